@@ -1,0 +1,260 @@
+"""Seeded synthetic inputs: graphs, source lists and target lists.
+
+Input generation only. Nothing here computes distances, path counts,
+dependencies or estimates; both the CPU oracle and the GPU library consume the
+CSR arrays built here byte for byte.
+
+CSR convention used everywhere in this repository:
+  row: int64[n+1] offsets, col: int32[nnz] neighbour ids,
+  symmetric (undirected), rows sorted ascending, no self-loops, no duplicates.
+
+Random streams: numpy's Philox4x64-10 bit generator keyed (seed, stream) with
+stream ids graph=2, sources=0, pairs=1, arrivals=3; the Barabasi-Albert
+generator runs in C (gen.c) with a SplitMix64 stream seeded from the same key.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgraphgen.so")
+_lib = None
+
+STREAM_SOURCES = 0
+STREAM_PAIRS = 1
+STREAM_GRAPH = 2
+STREAM_ARRIVALS = 3
+
+
+def build_native(force: bool = False) -> str:
+    """Compile gen.c into libgraphgen.so (gcc, -O2)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=c11",
+                               os.path.join(_HERE, "gen.c"), "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _native():
+    global _lib
+    if _lib is None:
+        build_native()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.graphgen_ba.restype = ctypes.c_int64
+        lib.graphgen_ba.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                    ctypes.c_void_p, ctypes.c_void_p]
+        lib.graphgen_csr.restype = ctypes.c_int64
+        lib.graphgen_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class CSR:
+    n: int
+    row: np.ndarray  # int64[n+1]
+    col: np.ndarray  # int32[nnz]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def m_undirected(self) -> int:
+        return self.nnz // 2
+
+    def degree(self) -> np.ndarray:
+        return np.diff(self.row)
+
+    def neighbours(self, v: int) -> np.ndarray:
+        return self.col[self.row[v]:self.row[v + 1]]
+
+
+def rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=np.array([seed, stream], dtype=np.uint64)))
+
+
+def from_edges(n: int, src, dst, name: str = "") -> CSR:
+    """Symmetric, sorted, deduplicated CSR from an undirected edge list."""
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.int32))
+    dst = np.ascontiguousarray(np.asarray(dst, dtype=np.int32))
+    assert src.shape == dst.shape
+    if n <= 0:
+        raise ValueError("n must be positive")
+    row = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(1, 2 * src.shape[0]), dtype=np.int32)
+    nnz = _native().graphgen_csr(n, src.shape[0], src.ctypes.data, dst.ctypes.data,
+                                 row.ctypes.data, col.ctypes.data)
+    if nnz < 0:
+        raise ValueError("edge list has an endpoint outside [0, n)")
+    return CSR(n, row, col[:nnz].copy(), name)
+
+
+def relabel_subgraph(g: CSR, keep: np.ndarray, name: str = "") -> CSR:
+    """Induced subgraph on the vertices where keep is True, ids renumbered in order."""
+    newid = -np.ones(g.n, dtype=np.int64)
+    idx = np.nonzero(keep)[0]
+    newid[idx] = np.arange(idx.shape[0])
+    src = np.repeat(np.arange(g.n), np.diff(g.row))
+    dst = g.col.astype(np.int64)
+    m = keep[src] & keep[dst] & (src < dst)
+    return from_edges(int(idx.shape[0]), newid[src[m]], newid[dst[m]], name)
+
+
+def largest_component(g: CSR) -> CSR:
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    a = sp.csr_matrix((np.ones(g.nnz, dtype=np.int8), g.col, g.row), shape=(g.n, g.n))
+    ncomp, lab = connected_components(a, directed=False)
+    if ncomp == 1:
+        return g
+    big = np.argmax(np.bincount(lab))
+    return relabel_subgraph(g, lab == big, g.name + "-lcc")
+
+
+# ----------------------------------------------------------------- families
+
+def path(n: int) -> CSR:
+    a = np.arange(n - 1)
+    return from_edges(n, a, a + 1, "path%d" % n)
+
+
+def star(n: int) -> CSR:
+    """Vertex 0 is the centre; leaves 1..n-1."""
+    a = np.arange(1, n)
+    return from_edges(n, np.zeros_like(a), a, "star%d" % n)
+
+
+def cycle(n: int) -> CSR:
+    a = np.arange(n)
+    return from_edges(n, a, (a + 1) % n, "cycle%d" % n)
+
+
+def complete(n: int) -> CSR:
+    i, j = np.triu_indices(n, 1)
+    return from_edges(n, i, j, "K%d" % n)
+
+
+def complete_bipartite(a: int, b: int) -> CSR:
+    """Part A = 0..a-1, part B = a..a+b-1."""
+    i, j = np.meshgrid(np.arange(a), np.arange(a, a + b), indexing="ij")
+    return from_edges(a + b, i.ravel(), j.ravel(), "K%d,%d" % (a, b))
+
+
+def grid(x: int, y: int) -> CSR:
+    """x-by-y 4-neighbour grid; vertex (i, j) has id i*y + j."""
+    ids = np.arange(x * y).reshape(x, y)
+    s = np.concatenate([ids[:, :-1].ravel(), ids[:-1, :].ravel()])
+    d = np.concatenate([ids[:, 1:].ravel(), ids[1:, :].ravel()])
+    return from_edges(x * y, s, d, "grid%dx%d" % (x, y))
+
+
+def er(n: int, p: float, seed: int) -> CSR:
+    """G(n, p): each unordered pair independently with probability p."""
+    r = rng(seed, STREAM_GRAPH)
+    i, j = np.triu_indices(n, 1)
+    keep = r.random(i.shape[0]) < p
+    return from_edges(n, i[keep], j[keep], "er%d" % n)
+
+
+def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) -> CSR:
+    """R-MAT (Chakrabarti et al. 2004): edge_factor * 2^scale generated edges,
+    quadrant probabilities a, b, c, d = 1-a-b-c at every bit, no noise, no
+    relabelling; symmetrised, self-loops and duplicates dropped, isolated
+    vertices kept (n = 2^scale)."""
+    r = rng(seed, STREAM_GRAPH)
+    n = 1 << scale
+    ne = edge_factor * n
+    src = np.zeros(ne, dtype=np.int64)
+    dst = np.zeros(ne, dtype=np.int64)
+    for bit in range(scale):
+        u = r.random(ne)
+        down = u >= a + b            # quadrants c or d set the row bit
+        right = ((u >= a) & (u < a + b)) | (u >= a + b + c)
+        src |= down.astype(np.int64) << bit
+        dst |= right.astype(np.int64) << bit
+    return from_edges(n, src, dst, "rmat%d_%d" % (scale, edge_factor))
+
+
+def ba(n: int, m: int, seed: int) -> CSR:
+    """Barabasi-Albert: K_{m+1} seed clique, then m degree-proportional distinct
+    targets per new vertex; m(m+1)/2 + m(n-m-1) undirected edges."""
+    ne = m * (m + 1) // 2 + m * (n - m - 1)
+    src = np.zeros(ne, dtype=np.int32)
+    dst = np.zeros(ne, dtype=np.int32)
+    key = (int(seed) * 0x100000001B3 + STREAM_GRAPH) & ((1 << 64) - 1)
+    got = _native().graphgen_ba(n, m, key, src.ctypes.data, dst.ctypes.data)
+    if got != ne:
+        raise RuntimeError("graphgen_ba failed")
+    return from_edges(n, src, dst, "ba%d_%d" % (n, m))
+
+
+def grid_percolated(side: int, frac: float, seed: int) -> CSR:
+    """side x side 4-neighbour grid with floor(frac*E) edges deleted uniformly
+    without replacement, reduced to its largest connected component."""
+    r = rng(seed, STREAM_GRAPH)
+    ids = np.arange(side * side, dtype=np.int64).reshape(side, side)
+    s = np.concatenate([ids[:, :-1].ravel(), ids[:-1, :].ravel()])
+    d = np.concatenate([ids[:, 1:].ravel(), ids[1:, :].ravel()])
+    ne = s.shape[0]
+    ndel = int(np.floor(frac * ne))
+    drop = r.choice(ne, size=ndel, replace=False)
+    keep = np.ones(ne, dtype=bool)
+    keep[drop] = False
+    g = from_edges(side * side, s[keep], d[keep], "grid%d_p%g" % (side, frac))
+    return largest_component(g)
+
+
+# ----------------------------------------------------------------- samples
+
+def philox_sources(seed: int, count: int, n: int, stream: int = STREAM_SOURCES) -> np.ndarray:
+    """Sources for a fixed-list run: word 0 of Philox4x64-10 block j (key
+    (seed, stream)) mapped to floor(w * n / 2^64), j = 0..count-1.
+
+    numpy's Philox emits block c+1 first when its counter is c, so the counter
+    starts at 2^256 - 1 (which wraps to block 0)."""
+    ones = np.full(4, np.iinfo(np.uint64).max, dtype=np.uint64)
+    bg = np.random.Philox(key=np.array([seed, stream], dtype=np.uint64), counter=ones)
+    raw = bg.random_raw(4 * count).reshape(count, 4)[:, 0]
+    hi = [(int(w) * n) >> 64 for w in raw]
+    return np.asarray(hi, dtype=np.int32)
+
+
+def top_degree(g: CSR, k: int) -> np.ndarray:
+    """k highest-degree vertices, ties broken by lower id."""
+    deg = g.degree()
+    order = np.lexsort((np.arange(g.n), -deg))
+    return order[:k].astype(np.int32)
+
+
+def degree_percentile_targets(g: CSR, k: int, min_degree: int = 2) -> np.ndarray:
+    """Vertices at degree percentiles (j + 1/2)/k, j = 0..k-1, among the
+    vertices of degree >= min_degree sorted by (degree, id)."""
+    deg = g.degree()
+    cand = np.nonzero(deg >= min_degree)[0]
+    order = cand[np.lexsort((cand, deg[cand]))]
+    pos = ((np.arange(k) + 0.5) / k * order.shape[0]).astype(np.int64)
+    return order[np.minimum(pos, order.shape[0] - 1)].astype(np.int32)
+
+
+# ----------------------------------------------------------------- configs
+
+def config_graph(name: str) -> CSR:
+    """The synthetic workloads, by name (sizes in the docstrings above)."""
+    if name == "er2000":
+        return er(2000, 8.0 / 1999.0, seed=1)
+    if name == "rmat16":
+        return rmat(16, 16, 0.57, 0.19, 0.19, seed=2)
+    if name == "ba1m":
+        return ba(1 << 20, 5, seed=7)
+    if name == "grid2048":
+        return grid_percolated(2048, 0.05, seed=3)
+    raise KeyError(name)

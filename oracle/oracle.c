@@ -1,0 +1,438 @@
+/*
+ * CPU oracle for sampled betweenness centrality.
+ *
+ * TEST INFRASTRUCTURE ONLY: plain, slow, obviously correct. Only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may call it; the GPU
+ * library never links or loads it and shares no code with it.
+ *
+ * Paper: S. Ji and Z. Yan, "Refining Approximating Betweenness Centrality
+ * Based on Samplings" (arXiv 1608.04472). Each function cites the passage it
+ * follows. Readings of silent or ambiguous points:
+ *   - graphs are undirected and unweighted, so the single-source shortest
+ *     paths of Brandes' first step are a breadth-first search;
+ *   - BC sums over ordered pairs (s, t), s, t, v pairwise distinct;
+ *   - the predecessor condition of Definition 3 is read as "if and only if";
+ *   - sampling is uniform with replacement over all n vertices (sources) or
+ *     all n(n-1) ordered pairs of distinct vertices (pairs);
+ *   - the loop runs while S <= c*n, so it stops at the first S > c*n, and the
+ *     sample that crosses the threshold is counted.
+ * Built with -ffp-contract=off: no fused multiply-add anywhere.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ Philox */
+
+/* Philox4x64-10 as published by Salmon et al. (SC'11): ten rounds of two
+ * 64x64->128 multiplies with the round keys bumped by the Weyl constants. */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, x0, &hi0, &lo0);
+        mulhilo64(M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static int64_t scale_draw(uint64_t w, int64_t range)
+{
+    unsigned __int128 p = (unsigned __int128)w * (uint64_t)range;
+    return (int64_t)(p >> 64);
+}
+
+int32_t oracle_draw_source(uint64_t seed, int64_t j, int64_t n)
+{
+    uint64_t ctr[4] = {(uint64_t)j, 0, 0, 0}, key[2] = {seed, 0}, w[4];
+    oracle_philox4x64_10(ctr, key, w);
+    return (int32_t)scale_draw(w[0], n);
+}
+
+void oracle_draw_pair(uint64_t seed, int64_t j, int64_t n, int32_t *u, int32_t *v)
+{
+    uint64_t ctr[4] = {(uint64_t)j, 0, 0, 0}, key[2] = {seed, 1}, w[4];
+    oracle_philox4x64_10(ctr, key, w);
+    int64_t a = scale_draw(w[0], n);
+    int64_t b = scale_draw(w[1], n - 1);
+    if (b >= a) b += 1;
+    *u = (int32_t)a;
+    *v = (int32_t)b;
+}
+
+/* ------------------------------------------- FP64 with unbounded exponent */
+
+typedef struct { double m; int32_t e; } xnum;   /* m * 2^e; m == 0 or 1 <= m < 2 */
+
+static xnum xnum_make(double m, int64_t e)
+{
+    xnum r = {0.0, 0};
+    if (m == 0.0) return r;
+    int k;
+    double f = frexp(m, &k);            /* m = f * 2^k, 0.5 <= f < 1 */
+    r.m = f * 2.0;
+    r.e = (int32_t)(e + k - 1);
+    return r;
+}
+
+static xnum xnum_add(xnum a, xnum b)
+{
+    if (a.m == 0.0) return b;
+    if (b.m == 0.0) return a;
+    int32_t e = a.e > b.e ? a.e : b.e;
+    return xnum_make(ldexp(a.m, a.e - e) + ldexp(b.m, b.e - e), e);
+}
+
+static xnum xnum_mul(xnum a, xnum b)
+{
+    return xnum_make(a.m * b.m, (int64_t)a.e + b.e);
+}
+
+/* a / b as a plain double (may underflow to 0 or a subnormal). */
+static double xnum_div(xnum a, xnum b)
+{
+    return ldexp(a.m / b.m, a.e - b.e);
+}
+
+/* ------------------------------------------------------------ Brandes pass */
+
+typedef struct {
+    int32_t *dist;
+    xnum *sig;
+    double *delta;
+    int32_t *order;     /* vertices in BFS order: non-decreasing distance */
+    int64_t reached;
+} pass_t;
+
+static int pass_alloc(pass_t *p, int64_t n)
+{
+    p->dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    p->sig = (xnum *)malloc(sizeof(xnum) * (size_t)n);
+    p->delta = (double *)malloc(sizeof(double) * (size_t)n);
+    p->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    p->reached = 0;
+    return (p->dist && p->sig && p->delta && p->order) ? 0 : -1;
+}
+
+static void pass_free(pass_t *p)
+{
+    free(p->dist); free(p->sig); free(p->delta); free(p->order);
+}
+
+static int check_graph(int64_t n, const int64_t *row, const int32_t *col)
+{
+    return (n > 0 && n < 0x7fffffffLL && row && (col || row[n] == 0)) ? 0 : -1;
+}
+
+/* Brandes' first step for an unweighted graph: breadth-first search from s
+ * giving d(s, .) and the visiting order. */
+static void bfs(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pass_t *p)
+{
+    for (int64_t v = 0; v < n; ++v) p->dist[v] = -1;
+    int64_t head = 0, tail = 0;
+    p->dist[s] = 0;
+    p->order[tail++] = s;
+    while (head < tail) {
+        int32_t u = p->order[head++];
+        for (int64_t e = row[u]; e < row[u + 1]; ++e) {
+            int32_t w = col[e];
+            if (p->dist[w] < 0) {
+                p->dist[w] = p->dist[u] + 1;
+                p->order[tail++] = w;
+            }
+        }
+    }
+    p->reached = tail;
+}
+
+/* sigma_sw = sum of sigma_su over the predecessors u of w (Definition 3:
+ * neighbours with d(s,u) = d(s,w) - 1), in BFS order so that every
+ * predecessor is final before it is read. */
+static void path_counts(const int64_t *row, const int32_t *col, int64_t n, pass_t *p)
+{
+    for (int64_t v = 0; v < n; ++v) { p->sig[v].m = 0.0; p->sig[v].e = 0; }
+    int32_t s = p->order[0];
+    p->sig[s] = xnum_make(1.0, 0);
+    for (int64_t i = 1; i < p->reached; ++i) {
+        int32_t w = p->order[i];
+        xnum acc = {0.0, 0};
+        for (int64_t e = row[w]; e < row[w + 1]; ++e) {
+            int32_t u = col[e];
+            if (p->dist[u] == p->dist[w] - 1) acc = xnum_add(acc, p->sig[u]);
+        }
+        p->sig[w] = acc;
+    }
+}
+
+/* Theorem 1: delta_s(v) = sum over t with v in P_s(t) of
+ * (sigma_sv / sigma_st) * (1 + delta_s(t)), evaluated in non-increasing
+ * distance (Brandes' second step) so every successor t is final. The source
+ * itself is excluded from its own dependency (s != t != v), so delta_s(s) = 0. */
+static void dependencies(const int64_t *row, const int32_t *col, int64_t n, pass_t *p)
+{
+    for (int64_t v = 0; v < n; ++v) p->delta[v] = 0.0;
+    for (int64_t i = p->reached - 1; i >= 1; --i) {
+        int32_t v = p->order[i];
+        double acc = 0.0;
+        for (int64_t e = row[v]; e < row[v + 1]; ++e) {
+            int32_t t = col[e];
+            if (p->dist[t] == p->dist[v] + 1) {
+                double q = xnum_div(p->sig[v], p->sig[t]);
+                double r = 1.0 + p->delta[t];
+                acc += q * r;
+            }
+        }
+        p->delta[v] = acc;
+    }
+}
+
+static void brandes_pass(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pass_t *p)
+{
+    bfs(n, row, col, s, p);
+    path_counts(row, col, n, p);
+    dependencies(row, col, n, p);
+}
+
+int oracle_brandes(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
+                   int32_t *dist, double *sig_m, int32_t *sig_e, double *delta)
+{
+    if (check_graph(n, row, col) || s < 0 || s >= n) return -1;
+    pass_t p;
+    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    brandes_pass(n, row, col, s, &p);
+    for (int64_t v = 0; v < n; ++v) {
+        if (dist) dist[v] = p.dist[v];
+        if (sig_m) sig_m[v] = p.sig[v].m;
+        if (sig_e) sig_e[v] = p.sig[v].e;
+        if (delta) delta[v] = p.delta[v];
+    }
+    pass_free(&p);
+    return 0;
+}
+
+/* Exact BC as the sum of source dependencies (Section 3). */
+int oracle_bc_exact(int64_t n, const int64_t *row, const int32_t *col, double *bc)
+{
+    if (check_graph(n, row, col) || !bc) return -1;
+    pass_t p;
+    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    for (int64_t v = 0; v < n; ++v) bc[v] = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        brandes_pass(n, row, col, (int32_t)s, &p);
+        for (int64_t v = 0; v < n; ++v) bc[v] += p.delta[v];
+    }
+    pass_free(&p);
+    return 0;
+}
+
+int oracle_dependencies(int64_t n, const int64_t *row, const int32_t *col,
+                        const int32_t *sources, int64_t k, double *full, double *sum)
+{
+    if (check_graph(n, row, col) || k < 0 || (k > 0 && !sources)) return -1;
+    for (int64_t i = 0; i < k; ++i)
+        if (sources[i] < 0 || sources[i] >= n) return -1;
+    pass_t p;
+    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    if (sum) for (int64_t v = 0; v < n; ++v) sum[v] = 0.0;
+    for (int64_t i = 0; i < k; ++i) {
+        brandes_pass(n, row, col, sources[i], &p);
+        for (int64_t v = 0; v < n; ++v) {
+            if (full) full[i * n + v] = p.delta[v];
+            if (sum) sum[v] += p.delta[v];
+        }
+    }
+    pass_free(&p);
+    return 0;
+}
+
+/* -------------------------------------------------------- pair dependency */
+
+static void pair_from_passes(int64_t n, int32_t u, int32_t v, const pass_t *pu,
+                             const pass_t *pv, double *y)
+{
+    for (int64_t t = 0; t < n; ++t) y[t] = 0.0;
+    int32_t duv = pu->dist[v];
+    if (duv < 0) return;
+    for (int64_t t = 0; t < n; ++t) {
+        if (t == u || t == v) continue;
+        if (pu->dist[t] < 0 || pv->dist[t] < 0) continue;
+        if (pu->dist[t] + pv->dist[t] != duv) continue;
+        xnum through = xnum_mul(pu->sig[t], pv->sig[t]);
+        y[t] = xnum_div(through, pu->sig[v]);
+    }
+}
+
+static void sssp_counts(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pass_t *p)
+{
+    bfs(n, row, col, s, p);
+    path_counts(row, col, n, p);
+}
+
+int oracle_pair_dependency(int64_t n, const int64_t *row, const int32_t *col,
+                           int32_t u, int32_t v, double *y)
+{
+    if (check_graph(n, row, col) || !y || u < 0 || v < 0 || u >= n || v >= n || u == v)
+        return -1;
+    pass_t pu, pv;
+    int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n);
+    if (bad) { pass_free(&pu); pass_free(&pv); return -2; }
+    sssp_counts(n, row, col, u, &pu);
+    sssp_counts(n, row, col, v, &pv);
+    pair_from_passes(n, u, v, &pu, &pv, y);
+    pass_free(&pu); pass_free(&pv);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- samplers */
+
+enum { ST_RUNNING = 255, ST_DONE = 0, ST_CAPPED = 1 };
+
+/* Section 4, Bader's loop as restated in the paper: S starts at 0; each
+ * iteration samples a vertex, runs the shortest paths from it and adds its
+ * dependency on the target; the loop repeats while S <= c*n; the estimate
+ * is n*S/k. Targets share the sample stream, so one pass per draw serves all
+ * targets that are still running. */
+int oracle_adaptive_source(int64_t n, const int64_t *row, const int32_t *col,
+                           const int32_t *targets, int32_t T, double c, uint64_t seed,
+                           int64_t k_max, double *est, int64_t *samples, double *S,
+                           uint8_t *status)
+{
+    if (check_graph(n, row, col) || T < 0 || (T > 0 && !targets) || !(c >= 1.0) ||
+        k_max < 1 || !est || !samples || !S || !status)
+        return -1;
+    for (int32_t i = 0; i < T; ++i)
+        if (targets[i] < 0 || targets[i] >= n) return -1;
+    pass_t p;
+    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    const double threshold = c * (double)n;
+    for (int32_t i = 0; i < T; ++i) { S[i] = 0.0; samples[i] = 0; status[i] = ST_RUNNING; }
+    int32_t running = T;
+    for (int64_t j = 0; running > 0; ++j) {
+        int32_t s = oracle_draw_source(seed, j, n);
+        brandes_pass(n, row, col, s, &p);
+        for (int32_t i = 0; i < T; ++i) {
+            if (status[i] != ST_RUNNING) continue;
+            S[i] += p.delta[targets[i]];
+            samples[i] += 1;
+            if (S[i] > threshold) { status[i] = ST_DONE; --running; }
+            else if (samples[i] == k_max) { status[i] = ST_CAPPED; --running; }
+        }
+    }
+    for (int32_t i = 0; i < T; ++i) est[i] = ((double)n * S[i]) / (double)samples[i];
+    pass_free(&p);
+    return 0;
+}
+
+/* Algorithm 1: pick an ordered pair of distinct vertices, count the share of
+ * its shortest paths through the target, add it to S, count the sample.
+ * Rule 0 keeps the loop's literal condition (repeat while S <= c*n). Rule 1
+ * stops once k reaches Lemma 5's sample count eps*(n^2(n-1)/A)^(2/3) with A
+ * read as the running estimate n(n-1)S/k, which rearranges to
+ * k*S^2 >= eps^3*n^2. */
+int oracle_adaptive_pair(int64_t n, const int64_t *row, const int32_t *col,
+                         const int32_t *targets, int32_t T, int rule, double eps, double c,
+                         uint64_t seed, int64_t k_max, double *est, int64_t *samples,
+                         double *S, uint8_t *status)
+{
+    if (check_graph(n, row, col) || n < 2 || T < 0 || (T > 0 && !targets) || k_max < 1 ||
+        !est || !samples || !S || !status)
+        return -1;
+    if (rule == 0 && !(c >= 1.0)) return -1;
+    if (rule == 1 && !(eps > 0.0 && eps < 0.5)) return -1;
+    if (rule != 0 && rule != 1) return -1;
+    for (int32_t i = 0; i < T; ++i)
+        if (targets[i] < 0 || targets[i] >= n) return -1;
+    pass_t pu, pv;
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n);
+    if (bad || !y) { pass_free(&pu); pass_free(&pv); free(y); return -2; }
+    const double threshold = c * (double)n;
+    const double eps_rhs = ((eps * eps) * eps) * ((double)n * (double)n);
+    for (int32_t i = 0; i < T; ++i) { S[i] = 0.0; samples[i] = 0; status[i] = ST_RUNNING; }
+    int32_t running = T;
+    for (int64_t j = 0; running > 0; ++j) {
+        int32_t u, v;
+        oracle_draw_pair(seed, j, n, &u, &v);
+        sssp_counts(n, row, col, u, &pu);
+        sssp_counts(n, row, col, v, &pv);
+        pair_from_passes(n, u, v, &pu, &pv, y);
+        for (int32_t i = 0; i < T; ++i) {
+            if (status[i] != ST_RUNNING) continue;
+            S[i] += y[targets[i]];
+            samples[i] += 1;
+            int stop;
+            if (rule == 0) stop = S[i] > threshold;
+            else stop = S[i] > 0.0 && ((double)samples[i] * (S[i] * S[i])) >= eps_rhs;
+            if (stop) { status[i] = ST_DONE; --running; }
+            else if (samples[i] == k_max) { status[i] = ST_CAPPED; --running; }
+        }
+    }
+    const double pairs = (double)n * (double)(n - 1);
+    for (int32_t i = 0; i < T; ++i) est[i] = (pairs * S[i]) / (double)samples[i];
+    pass_free(&pu); pass_free(&pv); free(y);
+    return 0;
+}
+
+/* ------------------------------------------------------------ work counts */
+
+int oracle_source_work(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
+                       int64_t *reached, int64_t *edges_undirected, int64_t *dag_edges)
+{
+    if (check_graph(n, row, col) || s < 0 || s >= n) return -1;
+    pass_t p;
+    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    bfs(n, row, col, s, &p);
+    int64_t deg = 0, dag = 0;
+    for (int64_t i = 0; i < p.reached; ++i) {
+        int32_t u = p.order[i];
+        deg += row[u + 1] - row[u];
+        for (int64_t e = row[u]; e < row[u + 1]; ++e)
+            if (p.dist[col[e]] == p.dist[u] + 1) ++dag;
+    }
+    if (reached) *reached = p.reached;
+    if (edges_undirected) *edges_undirected = deg / 2;
+    if (dag_edges) *dag_edges = dag;
+    pass_free(&p);
+    return 0;
+}
+
+int oracle_pair_work(int64_t n, const int64_t *row, const int32_t *col, int32_t u, int32_t v,
+                     int64_t *edges_undirected)
+{
+    if (check_graph(n, row, col) || u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
+    pass_t p;
+    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    bfs(n, row, col, u, &p);
+    int32_t limit = p.dist[v] < 0 ? 0x7fffffff : p.dist[v];
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < p.reached; ++i) {
+        int32_t a = p.order[i];
+        for (int64_t e = row[a]; e < row[a + 1]; ++e) {
+            int32_t b = col[e];
+            int32_t da = p.dist[a], db = p.dist[b];
+            /* count each undirected edge once, from its lower-distance end
+             * (ties: lower id) when that end lies below the limit */
+            int lead = (da < db) || (da == db && a < b);
+            if (lead && da < limit) ++cnt;
+        }
+    }
+    *edges_undirected = cnt;
+    pass_free(&p);
+    return 0;
+}

@@ -1,0 +1,156 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies oracle.c, applies one plausible slip (a dropped term, a
+wrong level, a wrong comparison, a wrong constant), builds it on the CPU, and
+runs a compact selection of the pins from test_oracle_*.py against it. The
+unmodified source must pass the same selection.
+"""
+import math
+import os
+import shutil
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import networkx as nx
+import pytest
+
+import graphgen as gg
+import oracle
+from bruteforce import Brute
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+HDR = os.path.join(os.path.dirname(oracle.__file__), "oracle.h")
+
+MUTANTS = {
+    "drop_one_in_recursion": ("double r = 1.0 + p->delta[t];", "double r = p->delta[t];"),
+    "sigma_from_same_level": ("if (p->dist[u] == p->dist[w] - 1) acc",
+                              "if (p->dist[u] == p->dist[w]) acc"),
+    "successor_level_wrong": ("if (p->dist[t] == p->dist[v] + 1) {",
+                              "if (p->dist[t] >= p->dist[v] && t != v) {"),
+    "source_keeps_own_dependency": ("for (int64_t i = p->reached - 1; i >= 1; --i)",
+                                    "for (int64_t i = p->reached - 1; i >= 0; --i)"),
+    "ratio_inverted": ("double q = xnum_div(p->sig[v], p->sig[t]);",
+                       "double q = xnum_div(p->sig[t], p->sig[v]);"),
+    "stop_on_equal": ("if (S[i] > threshold) { status[i] = ST_DONE;",
+                      "if (S[i] >= threshold) { status[i] = ST_DONE;"),
+    "pair_shift_missing": ("if (b >= a) b += 1;", "if (b > a) b += 1;"),
+    "source_range_excludes_one": ("return (int32_t)scale_draw(w[0], n);",
+                                  "return (int32_t)scale_draw(w[0], n - 1);"),
+    "estimate_scale_wrong": ("est[i] = ((double)n * S[i]) / (double)samples[i];",
+                             "est[i] = ((double)(n - 1) * S[i]) / (double)samples[i];"),
+    "philox_nine_rounds": ("for (int r = 0; r < 10; ++r) {", "for (int r = 0; r < 9; ++r) {"),
+    "philox_key_bump_swapped": ("k0 += W0; k1 += W1;", "k0 += W1; k1 += W0;"),
+    "exponent_align_wrong": ("ldexp(a.m, a.e - e) + ldexp(b.m, b.e - e)",
+                             "ldexp(a.m, a.e - e) + ldexp(b.m, e - b.e)"),
+    "pair_offpath_kept": ("if (pu->dist[t] + pv->dist[t] != duv) continue;",
+                          "if (pu->dist[t] + pv->dist[t] > duv + 1) continue;"),
+    "eps_rule_unsquared": ("((double)samples[i] * (S[i] * S[i])) >= eps_rhs",
+                           "((double)samples[i] * S[i]) >= eps_rhs"),
+    "pair_estimate_scale": ("const double pairs = (double)n * (double)(n - 1);",
+                            "const double pairs = (double)n * (double)n;"),
+}
+
+
+def build_variant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    d = tmp_path / name
+    d.mkdir()
+    shutil.copy(HDR, d / "oracle.h")
+    (d / "oracle.c").write_text(src.replace(old, new))
+    out = str(d / "lib.so")
+    subprocess.check_call(["gcc"] + oracle.CFLAGS + [str(d / "oracle.c"), "-o", out, "-lm"])
+    return oracle.load(out)
+
+
+def numpy_block(seed, stream, j):
+    c = (j - 1) % (1 << 256)
+    ctr = np.array([(c >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(key=np.array([seed, stream], dtype=np.uint64), counter=ctr)
+    return [int(x) for x in bg.random_raw(4)]
+
+
+def pins_pass(O):
+    """A compact selection of the pins; True when all of them hold."""
+    try:
+        # Philox and the draw maps against numpy
+        if [int(x) for x in O.philox([5, 0, 0, 0], [7, 0])] != numpy_block(7, 0, 5):
+            return False
+        for j in range(20):
+            w = numpy_block(3, 0, j)
+            if O.draw_source(3, j, 10) != (w[0] * 10) >> 64:
+                return False
+            w = numpy_block(3, 1, j)
+            u = (w[0] * 10) >> 64
+            v = (w[1] * 9) >> 64
+            if O.draw_pair(3, j, 10) != (u, v + (v >= u)):
+                return False
+        # brute force on small graphs
+        for G in nx.graph_atlas_g()[40:1253:37]:
+            n = G.number_of_nodes()
+            e = np.array(list(G.edges()), dtype=np.int64).reshape(-1, 2)
+            g = gg.from_edges(n, e[:, 0], e[:, 1])
+            b = Brute(g)
+            bc = O.bc_exact(g)
+            if not np.allclose(bc, [float(x) for x in b.bc()], rtol=1e-12, atol=1e-12):
+                return False
+            for u in range(n):
+                for v in range(n):
+                    if u != v:
+                        y = O.pair_dependency(g, u, v)
+                        if not np.allclose(y, [float(x) for x in b.pair_dep(u, v)],
+                                           rtol=1e-12, atol=1e-12):
+                            return False
+        # grid counts beyond the FP64 range
+        g = gg.grid(600, 600)
+        dist, (sm, se), de = O.brandes(g, 0)
+        for i, j in ((599, 599), (599, 3), (300, 200)):
+            v = i * 600 + j
+            got = Fraction(float(sm[v])) * Fraction(2) ** int(se[v])
+            want = math.comb(i + j, i)
+            if abs(got - want) > Fraction(want, 10 ** 12):
+                return False
+        # sampler loops: star closed form, path tie, EPS rule on a star
+        n, c, seed = 10, 3.0, 2
+        S, k = 0, 0
+        for j in range(4000):
+            s = (numpy_block(seed, 0, j)[0] * n) >> 64
+            S += 0 if s == 0 else n - 2
+            k += 1
+            if S > c * n:
+                break
+        est, kk, SS, st = O.adaptive_source(gg.star(n), [0], c, seed, 10 ** 6)
+        if (kk[0], SS[0], st[0], est[0]) != (k, S, 0, n * S / k):
+            return False
+        for seed in range(1, 6):
+            _, kk, SS, _ = O.adaptive_source(gg.path(5), [2], 2.0, seed, 10 ** 6)
+            if SS[0] != 12:
+                return False
+        for n, eps, seed in ((9, 0.1, 3), (30, 0.2, 4)):
+            S, k = 0, 0
+            for j in range(100000):
+                w = numpy_block(seed, 1, j)
+                u = (w[0] * n) >> 64
+                v = (w[1] * (n - 1)) >> 64
+                v += v >= u
+                S += 1 if (u != 0 and v != 0) else 0
+                k += 1
+                if S > 0 and k * S * S >= eps ** 3 * n * n:
+                    break
+            est, kk, SS, st = O.adaptive_pair(gg.star(n), [0], 1, eps, 1.0, seed, 10 ** 7)
+            if (kk[0], SS[0]) != (k, S) or est[0] != n * (n - 1) * S / k:
+                return False
+    except ValueError:
+        return False
+    return True
+
+
+def test_unmodified_oracle_passes_the_selection():
+    assert pins_pass(oracle.load())
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    assert not pins_pass(build_variant(tmp_path, name, old, new))
