@@ -1,0 +1,172 @@
+/*
+ * bcmi -- sampled betweenness centrality on an MI355X (gfx950), C ABI.
+ *
+ * Implements the computations of S. Ji and Z. Yan, "Refining Approximating
+ * Betweenness Centrality Based on Samplings" (arXiv 1608.04472):
+ *   - Brandes' pass (Section 3): breadth-first search from a source giving
+ *     distances and shortest-path counts sigma, then the dependency recursion
+ *     of Theorem 1 in non-increasing distance;
+ *   - exact BC as the sum of source dependencies (Section 3, Definition 1);
+ *   - Bader's adaptive source sampling as restated in Section 4;
+ *   - adaptive pair sampling (Algorithm 1, Section 6.1) with the early stop of
+ *     the pair's search once the destination's level is complete (Section 6.2).
+ *
+ * Conventions shared by every call:
+ *   - Graphs are undirected and unweighted: symmetric CSR with rows sorted
+ *     ascending, no self-loops, no duplicate edges, 0 <= col < n < 2^31.
+ *   - BC counts ordered pairs (s, t), s, t, v pairwise distinct, so
+ *     0 <= BC(v) < n^2 (Definition 1).
+ *   - Array arguments of compute calls (bc_exact, bc_dependencies,
+ *     bc_adaptive_*) are DEVICE pointers on the graph's device; the caller
+ *     owns them. bc_graph_create reads a HOST CSR and keeps its own device copy.
+ *   - All work is ordered on the graph's stream; a call returns once its
+ *     outputs are complete. One graph handle serves one host thread at a time.
+ *   - Errors: every argument is checked before any device work; on error the
+ *     outputs are untouched, the call returns a nonzero bc_status and
+ *     bc_last_error() describes it. No call throws or aborts.
+ *   - Arithmetic: FP64. Path counts use an FP64 significand with an int32
+ *     exponent once any count of a batch reaches 2^1000 (plain FP64 below).
+ *   - Random draws: Philox4x64-10 (Salmon et al., SC'11), key (seed, stream),
+ *     counter (j, 0, 0, 0) for sample j; stream 0 for sources, 1 for pairs.
+ *     Source j = floor(w0 * n / 2^64). Pair j: u = floor(w0 * n / 2^64),
+ *     v' = floor(w1 * (n-1) / 2^64), v = v' + (v' >= u).
+ */
+#ifndef BCMI_H
+#define BCMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BC_OK = 0,
+    BC_E_INVALID = 1,      /* bad argument or malformed CSR */
+    BC_E_NOMEM = 2,        /* device memory exhausted */
+    BC_E_DEVICE = 3,       /* HIP runtime error (message in bc_last_error) */
+    BC_E_UNSUPPORTED = 4   /* valid request this build cannot serve */
+} bc_status;
+
+typedef enum {
+    BC_DONE = 0,           /* the stopping rule was met */
+    BC_CAPPED = 1          /* k_max samples taken without meeting it */
+} bc_target_status;
+
+/* Output layouts of bc_dependencies. */
+typedef enum {
+    BC_OUT_FULL = 0,       /* out[i*n + v] = delta_{sources[i].}(v), k*n doubles */
+    BC_OUT_SUM = 1         /* out[v] = sum over i of delta_{sources[i].}(v), n doubles */
+} bc_out_mode;
+
+/* Stopping rules of bc_adaptive_pair. */
+typedef enum {
+    BC_PAIR_ALG1 = 0,      /* Algorithm 1 as printed: repeat while S <= c*n */
+    BC_PAIR_EPS = 1        /* stop at the first k with S > 0 and k*S^2 >= eps^3 n^2:
+                              Lemma 5's sample count eps*(n^2(n-1)/A)^(2/3) with A
+                              replaced by the running estimate n(n-1)S/k */
+} bc_pair_rule;
+
+/* Batch scheduling (the engine's knobs; results do not depend on them beyond
+ * FP64 summation order in BC_OUT_SUM and bc_exact). */
+typedef enum {
+    BC_SCHED_AUTO = 0,     /* batched, batch width and direction switch tuned */
+    BC_SCHED_BATCHED = 1,  /* many sources per launch: one wavefront per
+                              (vertex, 64-source word), lanes = sources */
+    BC_SCHED_PER_SOURCE = 2 /* one source per launch sequence, one thread per
+                              frontier vertex: the plain form, for comparison */
+} bc_schedule;
+
+typedef struct {
+    int32_t schedule;      /* bc_schedule */
+    int32_t batch;         /* sources per batch, multiple of 64 in [64, 4096]; 0 = auto */
+    double bottom_up;      /* run a level bottom-up when its frontier entries exceed
+                              bottom_up * (n * batch/64); 0 = auto, < 0 = never */
+} bc_config;
+
+/* Host CSR. row has n+1 entries, int64 if row_is_i64 else int32. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const void *row;
+    int32_t row_is_i64;
+    const int32_t *col;
+} bc_csr;
+
+typedef struct bc_graph bc_graph;
+
+/* Validate a host CSR and copy it to the current HIP device. hip_stream is a
+ * hipStream_t (NULL = the null stream). On success *out owns the device copy
+ * and a lazily grown workspace; release it with bc_graph_destroy. */
+bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out);
+void bc_graph_destroy(bc_graph *g);
+bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
+bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg);
+bc_status bc_graph_info(const bc_graph *g, int64_t *n, int64_t *nnz);
+
+/* Exact BC of every vertex (Section 3; Definition 1 over ordered pairs):
+ * out[v] = sum over s != v of delta_{s.}(v), all n sources. out: n doubles. */
+bc_status bc_exact(bc_graph *g, double *out);
+
+/* Brandes' pass from each of k given sources (Definition 2, Theorem 1).
+ * sources: k int32 in [0, n), repeats allowed. out: see bc_out_mode.
+ * dist_out (k*n int32, -1 = unreachable), sigma_mant and sigma_exp (k*n each,
+ * sigma = mant * 2^exp) are optional (NULL) per-source outputs, source-major;
+ * they require out_mode == BC_OUT_FULL. delta_{s.}(s) = 0. */
+bc_status bc_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_t out_mode,
+                          double *out, int32_t *dist_out, double *sigma_mant,
+                          int32_t *sigma_exp);
+
+/* Bader's adaptive source sampling as restated in Section 4, for T targets
+ * sharing one sample stream (target i's results equal a T = 1 call with the
+ * same seed). Per target: S = 0, k = 0; repeat { draw source s_k; S +=
+ * delta_{s_k.}(v); k += 1 } while S <= c*n and k < k_max; est = n*S/k.
+ * c >= 1, k_max >= 1. Outputs (device, T entries each): est (double),
+ * samples (int64), S (double), status (uint8, bc_target_status). */
+bc_status bc_adaptive_source(bc_graph *g, const int32_t *targets, int32_t T, double c,
+                             uint64_t seed, int64_t k_max, double *out_est,
+                             int64_t *out_samples, double *out_S, uint8_t *out_status);
+
+/* Adaptive pair sampling (Algorithm 1) for T targets sharing one stream.
+ * Per target: S = 0, k = 0; repeat { draw ordered pair (u, v), u != v;
+ * S += sigma_uv(t)/sigma_uv; k += 1 } until the rule stops or k = k_max;
+ * est = n(n-1)*S/k. The pair's search stops once v's level is complete.
+ * rule BC_PAIR_ALG1 needs c >= 1; BC_PAIR_EPS needs 0 < eps < 1/2. Outputs as
+ * in bc_adaptive_source. */
+bc_status bc_adaptive_pair(bc_graph *g, const int32_t *targets, int32_t T, int32_t rule,
+                           double eps, double c, uint64_t seed, int64_t k_max,
+                           double *out_est, int64_t *out_samples, double *out_S,
+                           uint8_t *out_status);
+
+/* Pair dependencies of k given pairs: out[i*n + t] = sigma_{u_i v_i}(t) /
+ * sigma_{u_i v_i} (0 for t in {u_i, v_i} or when v_i is unreachable).
+ * us, vs: k int32 each, u_i != v_i. out: k*n doubles (device). */
+bc_status bc_pair_dependencies(bc_graph *g, const int32_t *us, const int32_t *vs, int64_t k,
+                               double *out);
+
+/* Sample draws as the samplers take them (Philox4x64-10, maps above):
+ * out_u[i] (and out_v[i] for pairs) for j = j0 + i, i < count. Device outputs. */
+bc_status bc_draw_sources(bc_graph *g, uint64_t seed, int64_t j0, int64_t count,
+                          int32_t *out_u);
+bc_status bc_draw_pairs(bc_graph *g, uint64_t seed, int64_t j0, int64_t count,
+                        int32_t *out_u, int32_t *out_v);
+
+/* Statistics of the most recent compute call on g: samples (sources or pairs)
+ * executed, batches, levels, whether extended path counts were needed. */
+typedef struct {
+    int64_t samples_executed;
+    int64_t batches;
+    int64_t levels;
+    int32_t extended;
+    int32_t batch_width;
+} bc_stats;
+bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *bc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

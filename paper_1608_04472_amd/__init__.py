@@ -1,0 +1,307 @@
+"""bcmi: sampled betweenness centrality on an MI355X, Python binding.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library libbcmi.so (csrc/), reached through its C ABI (include/bcmi.h).
+PyTorch supplies device memory (tensors) and the stream. The binding raises
+if the library is missing; there is no fallback path.
+
+Names follow the C ABI: bc_graph_create, bc_exact, bc_dependencies,
+bc_pair_dependencies, bc_adaptive_source, bc_adaptive_pair, bc_draw_sources,
+bc_draw_pairs. Array arguments are CUDA (HIP) tensors on the graph's device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libbcmi.so")
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("bcmi.hip", "kernels.hpp", "philox.hpp")]
+HEADER = os.path.join(_ROOT, "include", "bcmi.h")
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+BC_OK, BC_E_INVALID, BC_E_NOMEM, BC_E_DEVICE, BC_E_UNSUPPORTED = 0, 1, 2, 3, 4
+BC_DONE, BC_CAPPED = 0, 1
+BC_OUT_FULL, BC_OUT_SUM = 0, 1
+BC_PAIR_ALG1, BC_PAIR_EPS = 0, 1
+BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE = 0, 1, 2
+
+EXPORTS = [
+    "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_configure",
+    "bc_graph_info", "bc_exact", "bc_dependencies", "bc_pair_dependencies",
+    "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
+    "bc_last_stats", "bc_last_error",
+]
+
+
+def build(force: bool = True) -> str:
+    """Compile csrc/bcmi.hip for gfx950 into libbcmi.so (hipcc)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-I" + os.path.join(_ROOT, "include"),
+                                     os.path.join(_HERE, "csrc", "bcmi.hip"), "-o", tmp]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class BcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("bcmi status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row", ctypes.c_void_p),
+                ("row_is_i64", ctypes.c_int32), ("col", ctypes.c_void_p)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("bottom_up", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("samples_executed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("levels", ctypes.c_int64), ("extended", ctypes.c_int32),
+                ("batch_width", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libbcmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError("libbcmi.so is not built (%s); run __graft_entry__.build()" % p)
+    lib = ctypes.CDLL(p)
+    c = ctypes
+    V = c.c_void_p
+    lib.bc_last_error.restype = c.c_char_p
+    lib.bc_last_error.argtypes = []
+    lib.bc_graph_destroy.restype = None
+    lib.bc_graph_destroy.argtypes = [V]
+    sigs = {
+        "bc_graph_create": [c.POINTER(_Csr), V, c.POINTER(V)],
+        "bc_graph_set_stream": [V, V],
+        "bc_graph_configure": [V, c.POINTER(_Config)],
+        "bc_graph_info": [V, c.POINTER(c.c_int64), c.POINTER(c.c_int64)],
+        "bc_exact": [V, V],
+        "bc_dependencies": [V, V, c.c_int64, c.c_int32, V, V, V, V],
+        "bc_pair_dependencies": [V, V, V, c.c_int64, V],
+        "bc_adaptive_source": [V, V, c.c_int32, c.c_double, c.c_uint64, c.c_int64, V, V, V, V],
+        "bc_adaptive_pair": [V, V, c.c_int32, c.c_int32, c.c_double, c.c_double, c.c_uint64,
+                             c.c_int64, V, V, V, V],
+        "bc_draw_sources": [V, c.c_uint64, c.c_int64, c.c_int64, V],
+        "bc_draw_pairs": [V, c.c_uint64, c.c_int64, c.c_int64, V, V],
+        "bc_last_stats": [V, c.POINTER(_Stats)],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.restype = c.c_int
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != BC_OK:
+        raise BcError(rc, _lib.bc_last_error().decode())
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Graph:
+    """Handle to a device-resident CSR graph (bc_graph)."""
+
+    def __init__(self, row, col):
+        import numpy as np
+        lib = load_library()
+        row = np.ascontiguousarray(row, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        self._keep = (row, col)
+        csr = _Csr(row.shape[0] - 1, col.shape[0], row.ctypes.data, 1,
+                   col.ctypes.data if col.shape[0] else None)
+        h = ctypes.c_void_p()
+        _check(lib.bc_graph_create(ctypes.byref(csr), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.n = int(csr.n)
+        self.nnz = int(csr.nnz)
+        self._keep = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph is closed")
+        _check(_lib.bc_graph_set_stream(self._h, _stream()))
+        return self._h
+
+    def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0):
+        cfg = _Config(int(schedule), int(batch), float(bottom_up))
+        _check(_lib.bc_graph_configure(self.handle, ctypes.byref(cfg)))
+
+    def stats(self):
+        st = _Stats()
+        _check(_lib.bc_last_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.bc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bc_graph_create(row, col) -> Graph:
+    return Graph(row, col)
+
+
+def bc_exact(g: Graph, out):
+    import torch
+    _check(_lib.bc_exact(g.handle, _ptr(out, torch.float64, g.n, "out")))
+
+
+def bc_dependencies(g: Graph, sources, out_mode, out, dist_out=None, sigma_mant=None,
+                    sigma_exp=None):
+    import torch
+    k = sources.numel()
+    need = k * g.n if out_mode == BC_OUT_FULL else g.n
+    _check(_lib.bc_dependencies(
+        g.handle, _ptr(sources, torch.int32, k, "sources"), k, int(out_mode),
+        _ptr(out, torch.float64, need, "out"), _ptr(dist_out, torch.int32, k * g.n, "dist_out"),
+        _ptr(sigma_mant, torch.float64, k * g.n, "sigma_mant"),
+        _ptr(sigma_exp, torch.int32, k * g.n, "sigma_exp")))
+
+
+def bc_pair_dependencies(g: Graph, us, vs, out):
+    import torch
+    k = us.numel()
+    if vs.numel() != k:
+        raise ValueError("us and vs differ in length")
+    _check(_lib.bc_pair_dependencies(g.handle, _ptr(us, torch.int32, k, "us"),
+                                     _ptr(vs, torch.int32, k, "vs"), k,
+                                     _ptr(out, torch.float64, k * g.n, "out")))
+
+
+def bc_adaptive_source(g: Graph, targets, c, seed, k_max, out_est, out_samples, out_S,
+                       out_status):
+    import torch
+    T = targets.numel()
+    _check(_lib.bc_adaptive_source(
+        g.handle, _ptr(targets, torch.int32, T, "targets"), T, float(c), int(seed), int(k_max),
+        _ptr(out_est, torch.float64, T, "out_est"), _ptr(out_samples, torch.int64, T, "out_samples"),
+        _ptr(out_S, torch.float64, T, "out_S"), _ptr(out_status, torch.uint8, T, "out_status")))
+
+
+def bc_adaptive_pair(g: Graph, targets, rule, eps, c, seed, k_max, out_est, out_samples, out_S,
+                     out_status):
+    import torch
+    T = targets.numel()
+    _check(_lib.bc_adaptive_pair(
+        g.handle, _ptr(targets, torch.int32, T, "targets"), T, int(rule), float(eps), float(c),
+        int(seed), int(k_max), _ptr(out_est, torch.float64, T, "out_est"),
+        _ptr(out_samples, torch.int64, T, "out_samples"), _ptr(out_S, torch.float64, T, "out_S"),
+        _ptr(out_status, torch.uint8, T, "out_status")))
+
+
+def bc_draw_sources(g: Graph, seed, j0, count, out_u):
+    import torch
+    _check(_lib.bc_draw_sources(g.handle, int(seed), int(j0), int(count),
+                                _ptr(out_u, torch.int32, count, "out_u")))
+
+
+def bc_draw_pairs(g: Graph, seed, j0, count, out_u, out_v):
+    import torch
+    _check(_lib.bc_draw_pairs(g.handle, int(seed), int(j0), int(count),
+                              _ptr(out_u, torch.int32, count, "out_u"),
+                              _ptr(out_v, torch.int32, count, "out_v")))
+
+
+# ---------------------------------------------------- allocating conveniences
+
+def _dev():
+    import torch
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def exact(g: Graph):
+    import torch
+    out = torch.empty(g.n, dtype=torch.float64, device=_dev())
+    bc_exact(g, out)
+    return out
+
+
+def dependencies(g: Graph, sources, mode=BC_OUT_FULL, dist=False, sigma=False):
+    import torch
+    k = sources.numel()
+    out = torch.empty(k * g.n if mode == BC_OUT_FULL else g.n, dtype=torch.float64, device=_dev())
+    d = torch.empty(k * g.n, dtype=torch.int32, device=_dev()) if dist else None
+    sm = torch.empty(k * g.n, dtype=torch.float64, device=_dev()) if sigma else None
+    se = torch.empty(k * g.n, dtype=torch.int32, device=_dev()) if sigma else None
+    bc_dependencies(g, sources, mode, out, d, sm, se)
+    if mode == BC_OUT_FULL:
+        out = out.view(k, g.n)
+    return out, (d.view(k, g.n) if dist else None), \
+        ((sm.view(k, g.n), se.view(k, g.n)) if sigma else None)
+
+
+def pair_dependencies(g: Graph, us, vs):
+    import torch
+    out = torch.empty(us.numel() * g.n, dtype=torch.float64, device=_dev())
+    bc_pair_dependencies(g, us, vs, out)
+    return out.view(us.numel(), g.n)
+
+
+def _sampler_outputs(T):
+    import torch
+    d = _dev()
+    return (torch.empty(T, dtype=torch.float64, device=d), torch.empty(T, dtype=torch.int64, device=d),
+            torch.empty(T, dtype=torch.float64, device=d), torch.empty(T, dtype=torch.uint8, device=d))
+
+
+def adaptive_source(g: Graph, targets, c, seed, k_max):
+    est, k, S, st = _sampler_outputs(targets.numel())
+    bc_adaptive_source(g, targets, c, seed, k_max, est, k, S, st)
+    return est, k, S, st
+
+
+def adaptive_pair(g: Graph, targets, rule, eps, c, seed, k_max):
+    est, k, S, st = _sampler_outputs(targets.numel())
+    bc_adaptive_pair(g, targets, rule, eps, c, seed, k_max, est, k, S, st)
+    return est, k, S, st

@@ -1,0 +1,793 @@
+// bcmi C ABI: graph handles, the batched level-synchronous Brandes engine,
+// the per-source plain form, and the two adaptive samplers.
+//
+// Engine (one batch of B = 64 * 2^logW sources or pairs):
+//   forward, level by level: discover the next level top-down (narrow
+//   frontiers) or bottom-up (wide ones), pull path counts from all
+//   predecessors, clear the retired frontier words;
+//   backward, from the deepest recorded level up to level 1: pull rho from
+//   successors (Theorem 1), write delta and the vertex's own rho.
+// The host reads one 64-byte control block per level (queue tail, flags).
+#include "../../include/bcmi.h"
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace bcmi;
+
+namespace {
+
+thread_local std::string tl_error;
+
+struct Failure {
+    bc_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(bc_status s, std::string m) { throw Failure{s, std::move(m)}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return;
+    fail(e == hipErrorOutOfMemory ? BC_E_NOMEM : BC_E_DEVICE,
+         std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPX(expr) hip_check((expr), #expr)
+
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    void ensure(size_t count)
+    {
+        if (count <= cap) return;
+        release();
+        HIPX(hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T)));
+        cap = count;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+int grid_for(int64_t threads)
+{
+    const int64_t b = (threads + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 20));
+}
+int grid_waves(int64_t waves) { return grid_for(waves * kWave); }
+
+template <class K, class... A>
+void launch(hipStream_t st, int grid, K kernel, A... args)
+{
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, st, args...);
+    HIPX(hipGetLastError());
+}
+
+}  // namespace
+
+struct bc_graph {
+    int64_t n = 0, nnz = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DBuf<int64_t> row;
+    DBuf<int32_t> col;
+    bc_config cfg{BC_SCHED_AUTO, 0, 0.0};
+    // batched workspace
+    DBuf<double> sig, dlt;
+    DBuf<int32_t> sige;
+    DBuf<uint64_t> vis, F0, F1, active, valid;
+    DBuf<uint32_t> ridx;
+    DBuf<uint64_t> rmask;
+    DBuf<unsigned long long> ctl;
+    DBuf<int32_t> srcs, dest;
+    // samplers
+    DBuf<double> X, S;
+    DBuf<int64_t> K;
+    DBuf<uint8_t> st;
+    // per-source plain form
+    DBuf<int32_t> ss_d, ss_q;
+    DBuf<double> ss_sig, ss_dlt;
+    unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
+    int64_t cap_hint = 0;
+    bc_stats stats{};
+
+    void release_all()
+    {
+        row.release(); col.release(); sig.release(); dlt.release(); sige.release();
+        vis.release(); F0.release(); F1.release(); active.release(); valid.release();
+        ridx.release(); rmask.release(); ctl.release(); srcs.release(); dest.release();
+        X.release(); S.release(); K.release(); st.release();
+        ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release();
+        if (h_ctl) (void)hipHostFree(h_ctl);
+        h_ctl = nullptr;
+    }
+};
+
+namespace {
+
+template <class F>
+bc_status guarded(F &&f)
+{
+    try {
+        f();
+        tl_error.clear();
+        return BC_OK;
+    } catch (const Failure &e) {
+        tl_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        tl_error = "host allocation failed";
+        return BC_E_NOMEM;
+    } catch (...) {
+        tl_error = "unexpected error";
+        return BC_E_DEVICE;
+    }
+}
+
+void need(bool ok, const char *msg)
+{
+    if (!ok) fail(BC_E_INVALID, msg);
+}
+
+void use_device(bc_graph *g) { HIPX(hipSetDevice(g->device)); }
+
+void read_ctl(bc_graph *g)
+{
+    HIPX(hipMemcpyAsync(g->h_ctl, g->ctl.p, 8 * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, g->stream));
+    HIPX(hipStreamSynchronize(g->stream));
+}
+
+void zero_ctl(bc_graph *g)
+{
+    HIPX(hipMemsetAsync(g->ctl.p, 0, 8 * sizeof(unsigned long long), g->stream));
+}
+
+// Device-side range check of an index array (sources, targets, pair ends).
+void check_indices(bc_graph *g, const int32_t *x, int64_t count, const char *what)
+{
+    if (count <= 0) return;
+    zero_ctl(g);
+    launch(g->stream, grid_for(count), k_check_range, x, count, g->n, &g->ctl.p[CTL_REC_OVERFLOW]);
+    read_ctl(g);
+    if (g->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_INVALID, std::string(what) + " outside [0, n)");
+}
+
+// ------------------------------------------------------------ batch planning
+
+struct Plan {
+    int logW = 0;
+    int B = 64;
+};
+
+size_t free_device_bytes()
+{
+    size_t fr = 0, tot = 0;
+    HIPX(hipMemGetInfo(&fr, &tot));
+    return fr;
+}
+
+Plan plan_batch(bc_graph *g, int64_t want, int default_cap)
+{
+    int B = g->cfg.batch;
+    if (B == 0) {
+        B = 64;
+        while (B < want && B < default_cap) B *= 2;
+    }
+    // (vertex, word) indices are 32-bit
+    while (B > 64 && g->n * (int64_t)(B / 64) >= (1ll << 32)) B /= 2;
+    // slabs: sig + dlt (+ exponents) per (vertex, source); keep within free memory
+    const size_t budget = free_device_bytes() / 10 * 7 + g->sig.cap * 8 + g->dlt.cap * 8;
+    while (B > 64 && (size_t)g->n * B * 20 > budget) B /= 2;
+    Plan p;
+    p.B = B;
+    p.logW = 0;
+    while ((64 << p.logW) < B) ++p.logW;
+    return p;
+}
+
+void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap)
+{
+    const int64_t n = g->n, W = 1ll << p.logW;
+    g->sig.ensure((size_t)(n * p.B));
+    g->dlt.ensure((size_t)(n * p.B));
+    if (ext) g->sige.ensure((size_t)(n * p.B));
+    g->vis.ensure((size_t)(n * W));
+    g->F0.ensure((size_t)(n * W));
+    g->F1.ensure((size_t)(n * W));
+    g->active.ensure((size_t)W);
+    g->valid.ensure((size_t)W);
+    g->srcs.ensure((size_t)p.B);
+    g->dest.ensure((size_t)p.B);
+    g->ridx.ensure((size_t)cap);
+    g->rmask.ensure((size_t)cap);
+}
+
+__global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32_t nvalid)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= W) return;
+    const int rest = nvalid - 64 * j;
+    const int lanes = rest < 0 ? 0 : (rest > 64 ? 64 : rest);
+    const uint64_t m = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
+    valid[j] = m;
+    active[j] = m;
+}
+
+BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair, int64_t cap)
+{
+    BatchArgs a;
+    a.row = g->row.p;
+    a.col = g->col.p;
+    a.n = g->n;
+    a.logW = p.logW;
+    a.B = p.B;
+    a.sig = g->sig.p;
+    a.sige = ext ? g->sige.p : nullptr;
+    a.dlt = g->dlt.p;
+    a.vis = g->vis.p;
+    a.ridx = g->ridx.p;
+    a.rmask = g->rmask.p;
+    a.cap = cap;
+    a.ctl = g->ctl.p;
+    a.active = g->active.p;
+    a.valid = g->valid.p;
+    a.srcs = g->srcs.p;
+    a.dest = pair ? g->dest.p : nullptr;
+    a.nvalid = nvalid;
+    return a;
+}
+
+struct Retry {
+    bool overflow_record;
+    bool overflow_sigma;
+};
+
+// Hook between the forward and backward passes (per-source path counts).
+struct SigmaOut {
+    double *mant = nullptr;
+    int32_t *ex = nullptr;
+    int32_t count = 0;
+    int64_t b0 = 0;
+};
+
+double bottom_up_fraction(const bc_graph *g)
+{
+    if (g->cfg.bottom_up < 0) return -1.0;
+    return g->cfg.bottom_up > 0 ? g->cfg.bottom_up : 0.04;
+}
+
+// Forward + backward for the nvalid sources (pair mode: u in srcs, v in
+// dest) already placed in g->srcs / g->dest. Returns the level offsets and
+// sets *ext_used. Grows the record and switches to extended path counts as
+// needed, redoing the batch.
+std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair, bool *ext_used,
+                               const SigmaOut *sigout)
+{
+    const int64_t n = g->n, W = 1ll << p.logW;
+    bool ext = false;
+    int64_t cap = std::max<int64_t>(g->cap_hint, std::max<int64_t>(4 * n * W, 1 << 16));
+    const double bu_frac = bottom_up_fraction(g);
+    for (;;) {
+        ensure_batch(g, p, ext, cap);
+        BatchArgs a = make_args(g, p, ext, nvalid, pair, cap);
+        hipStream_t s = g->stream;
+        HIPX(hipMemsetAsync(g->vis.p, 0, (size_t)(n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->F0.p, 0, (size_t)(n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->F1.p, 0, (size_t)(n * W) * 8, s));
+        zero_ctl(g);
+        launch(s, 1, k_lane_masks, g->valid.p, g->active.p, (int32_t)W, nvalid);
+        launch(s, grid_for(p.B), k_init_sources, a, g->F0.p);
+        read_ctl(g);
+        std::vector<int64_t> off{0, (int64_t)g->h_ctl[CTL_TAIL]};
+        if (g->h_ctl[CTL_REC_OVERFLOW]) { cap *= 2; continue; }
+        launch(s, grid_for(off[1]), k_fill_masks, a, (int64_t)0, off[1], (const uint64_t *)g->F0.p);
+
+        uint64_t *cur = g->F0.p, *nxt = g->F1.p;
+        bool redo = false;
+        for (int level = 0;; ++level) {
+            const int64_t e0 = off[level], e1 = off[level + 1];
+            const int64_t nent = e1 - e0;
+            if (bu_frac > 0 && (double)nent > bu_frac * (double)(n * W))
+                launch(s, grid_for(n * W), k_discover_bottomup, a, (const uint64_t *)cur, nxt);
+            else
+                launch(s, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
+            read_ctl(g);
+            const int64_t e2 = (int64_t)g->h_ctl[CTL_TAIL];
+            if (g->h_ctl[CTL_REC_OVERFLOW]) {
+                cap = std::max<int64_t>(cap * 2, e2 + (e2 >> 2));
+                redo = true;
+                break;
+            }
+            if (e2 == e1) break;
+            if (ext)
+                launch(s, grid_waves(e2 - e1), k_sigma_pull<true>, a, e1, e2,
+                       (const uint64_t *)cur, (const uint64_t *)nxt);
+            else
+                launch(s, grid_waves(e2 - e1), k_sigma_pull<false>, a, e1, e2,
+                       (const uint64_t *)cur, (const uint64_t *)nxt);
+            launch(s, grid_for(nent), k_clear, a, e0, e1, cur);
+            off.push_back(e2);
+            std::swap(cur, nxt);
+        }
+        if (redo) continue;
+        if (!ext) {
+            read_ctl(g);
+            if (g->h_ctl[CTL_SIG_OVERFLOW]) {
+                ext = true;
+                continue;
+            }
+        }
+        g->cap_hint = std::max<int64_t>(g->cap_hint, off.back() + off.back() / 4);
+        if (sigout && (sigout->mant || sigout->ex))
+            launch(s, grid_for(n * sigout->count), k_out_sigma, a, sigout->count, sigout->b0,
+                   sigout->mant, sigout->ex);
+
+        // backward: cur holds the deepest level's masks, nxt is clear
+        const int L = (int)off.size() - 1;
+        uint64_t *fnext = nxt, *fown = cur;
+        for (int level = L - 1; level >= 1; --level) {
+            const int64_t e0 = off[level], e1 = off[level + 1];
+            if (ext)
+                launch(s, grid_waves(e1 - e0), k_backward<true>, a, e0, e1,
+                       (const uint64_t *)fnext, fown);
+            else
+                launch(s, grid_waves(e1 - e0), k_backward<false>, a, e0, e1,
+                       (const uint64_t *)fnext, fown);
+            if (level + 1 < L)
+                launch(s, grid_for(off[level + 2] - e1), k_clear, a, e1, off[level + 2], fnext);
+            std::swap(fnext, fown);
+        }
+        *ext_used = ext;
+        g->stats.levels += L;
+        g->stats.extended |= ext ? 1 : 0;
+        return off;
+    }
+}
+
+// --------------------------------------------------------- per-source form
+
+void ensure_single(bc_graph *g)
+{
+    g->ss_d.ensure((size_t)g->n);
+    g->ss_q.ensure((size_t)g->n);
+    g->ss_sig.ensure((size_t)g->n);
+    g->ss_dlt.ensure((size_t)g->n);
+}
+
+__global__ void k_ss_start(int32_t *d, double *sig, double *dlt, int32_t *queue,
+                           const int32_t *src, unsigned long long *ctl)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t s = *src;
+        d[s] = 0;
+        sig[s] = 1.0;
+        dlt[s] = 0.0;
+        queue[0] = s;
+        ctl[CTL_TAIL] = 1ull;
+    }
+}
+
+// One source: level-synchronous BFS with one thread per frontier vertex,
+// sigma pull, then the dependency sweep, each level its own launch.
+std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    ensure_single(g);
+    HIPX(hipMemsetAsync(g->ss_d.p, 0xff, (size_t)n * 4, s));
+    zero_ctl(g);
+    launch(s, 1, k_ss_start, g->ss_d.p, g->ss_sig.p, g->ss_dlt.p, g->ss_q.p, src_dev, g->ctl.p);
+    std::vector<int64_t> off{0, 1};
+    for (int level = 0;; ++level) {
+        const int64_t q0 = off[level], q1 = off[level + 1];
+        launch(s, grid_for(q1 - q0), k_ss_topdown, (const int64_t *)g->row.p,
+               (const int32_t *)g->col.p, g->ss_d.p, g->ss_q.p, q0, q1, (int32_t)level, g->ctl.p);
+        read_ctl(g);
+        const int64_t q2 = (int64_t)g->h_ctl[CTL_TAIL];
+        if (q2 == q1) break;
+        launch(s, grid_for(q2 - q1), k_ss_sigma, (const int64_t *)g->row.p,
+               (const int32_t *)g->col.p, (const int32_t *)g->ss_d.p, g->ss_sig.p,
+               (const int32_t *)g->ss_q.p, q1, q2, (int32_t)level, g->ctl.p);
+        off.push_back(q2);
+    }
+    read_ctl(g);
+    if (g->h_ctl[CTL_SIG_OVERFLOW])
+        fail(BC_E_UNSUPPORTED, "path counts reach 2^1000: the per-source form has no "
+                               "extended counts; use the batched schedule");
+    const int L = (int)off.size() - 1;
+    for (int level = L - 1; level >= 1; --level)
+        launch(s, grid_for(off[level + 1] - off[level]), k_ss_backward, (const int64_t *)g->row.p,
+               (const int32_t *)g->col.p, (const int32_t *)g->ss_d.p,
+               (const double *)g->ss_sig.p, g->ss_dlt.p, (const int32_t *)g->ss_q.p, off[level],
+               off[level + 1], (int32_t)level);
+    g->stats.levels += L;
+    return off;
+}
+
+bool per_source_schedule(const bc_graph *g) { return g->cfg.schedule == BC_SCHED_PER_SOURCE; }
+
+// ------------------------------------------------------------ dependencies
+
+void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode, double *out,
+                       int32_t *dist_out, double *sig_m, int32_t *sig_e, bool pair,
+                       const int32_t *dests)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    g->stats = bc_stats{};
+    // the sum over an empty source list is zero
+    if (mode == BC_OUT_SUM && out) HIPX(hipMemsetAsync(out, 0, (size_t)n * 8, s));
+    if (k == 0) {
+        HIPX(hipStreamSynchronize(s));
+        return;
+    }
+    if (dist_out) launch(s, grid_for(k * n), k_fill_i32, dist_out, (int32_t)-1, k * n);
+
+    if (per_source_schedule(g) && !pair) {
+        for (int64_t i = 0; i < k; ++i) {
+            std::vector<int64_t> off = run_single(g, sources + i);
+            if (mode == BC_OUT_SUM)
+                launch(s, grid_for(off.back() - 1), k_ss_out_sum, (const double *)g->ss_dlt.p,
+                       (const int32_t *)g->ss_q.p, (int64_t)1, off.back(), out);
+            else
+                launch(s, grid_for(n), k_ss_out_full, (const int32_t *)g->ss_d.p,
+                       (const double *)g->ss_dlt.p, n, out + i * n);
+            if (dist_out)
+                HIPX(hipMemcpyAsync(dist_out + i * n, g->ss_d.p, (size_t)n * 4,
+                                    hipMemcpyDeviceToDevice, s));
+        }
+        g->stats.samples_executed = k;
+        g->stats.batches = k;
+        g->stats.batch_width = 1;
+        HIPX(hipStreamSynchronize(s));
+        return;
+    }
+
+    const Plan p = plan_batch(g, k, 1024);
+    g->stats.batch_width = p.B;
+    for (int64_t b0 = 0; b0 < k; b0 += p.B) {
+        const int count = (int)std::min<int64_t>(p.B, k - b0);
+        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16));
+        HIPX(hipMemcpyAsync(g->srcs.p, sources + b0, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
+        if (pair)
+            HIPX(hipMemcpyAsync(g->dest.p, dests + b0, (size_t)count * 4,
+                                hipMemcpyDeviceToDevice, s));
+        SigmaOut so;
+        so.mant = sig_m;
+        so.ex = sig_e;
+        so.count = count;
+        so.b0 = b0;
+        bool ext = false;
+        std::vector<int64_t> off = run_batch(g, p, count, pair, &ext, &so);
+        BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->ridx.cap);
+        if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_sum, a, out);
+        else launch(s, grid_for(n * count), k_out_full, a, (int32_t)count, b0, out);
+        if (dist_out)
+            for (size_t l = 0; l + 1 < off.size(); ++l)
+                launch(s, grid_for(off[l + 1] - off[l]), k_out_dist, a, off[l], off[l + 1],
+                       (int32_t)l, (int32_t)count, b0, dist_out);
+        g->stats.batches += 1;
+        g->stats.samples_executed += count;
+    }
+    HIPX(hipStreamSynchronize(s));
+}
+
+// --------------------------------------------------------------- samplers
+
+void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int32_t rule,
+                  double c, double eps, uint64_t seed, int64_t k_max, double *out_est,
+                  int64_t *out_samples, double *out_S, uint8_t *out_status)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    g->stats = bc_stats{};
+    if (T == 0) return;
+    const Plan p = plan_batch(g, k_max, 256);
+    g->stats.batch_width = p.B;
+    g->X.ensure((size_t)T * p.B);
+    g->S.ensure((size_t)T);
+    g->K.ensure((size_t)T);
+    g->st.ensure((size_t)T);
+    StopArgs sa;
+    sa.T = T;
+    sa.rule = rule;
+    sa.threshold = c * (double)n;
+    sa.eps_rhs = ((eps * eps) * eps) * ((double)n * (double)n);
+    sa.k_max = k_max;
+    sa.S = g->S.p;
+    sa.K = g->K.p;
+    sa.status = g->st.p;
+    launch(s, grid_for(T), k_stop_init, sa);
+    int64_t j0 = 0;
+    for (;;) {
+        const int nb = (int)std::min<int64_t>(p.B, k_max - j0);
+        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16));
+        if (pair)
+            launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->srcs.p, g->dest.p);
+        else
+            launch(s, grid_for(nb), k_draw_sources, seed, j0, (int64_t)nb, n, g->srcs.p);
+        bool ext = false;
+        run_batch(g, p, nb, pair, &ext, nullptr);
+        BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->ridx.cap);
+        launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->X.p);
+        launch(s, grid_for(T), k_stop_rule, sa, (const double *)g->X.p, (int32_t)p.B, (int32_t)nb,
+               g->ctl.p);
+        read_ctl(g);
+        j0 += nb;
+        g->stats.batches += 1;
+        if (g->h_ctl[CTL_RUNNING] == 0) break;
+        if (j0 >= k_max) fail(BC_E_DEVICE, "stop rule left targets running at k_max");
+    }
+    g->stats.samples_executed = j0;
+    const double scale = pair ? (double)n * (double)(n - 1) : (double)n;
+    launch(s, grid_for(T), k_stop_finish, sa, scale, out_est, out_samples, out_S, out_status);
+    HIPX(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------- CSR validation
+
+template <class R>
+void validate_csr(const bc_csr *c, const R *row)
+{
+    const int64_t n = c->n, nnz = c->nnz;
+    need(row[0] == 0, "row[0] must be 0");
+    need((int64_t)row[n] == nnz, "row[n] must equal nnz");
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t b = (int64_t)row[v], e = (int64_t)row[v + 1];
+        need(b <= e, "row offsets must be non-decreasing");
+        for (int64_t i = b; i < e; ++i) {
+            const int32_t w = c->col[i];
+            need(w >= 0 && w < n, "column index outside [0, n)");
+            need(w != v, "self-loop");
+            need(i == b || c->col[i - 1] < w, "rows must be sorted ascending without duplicates");
+        }
+    }
+    // symmetry: every (v, w) needs (w, v)
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t i = (int64_t)row[v]; i < (int64_t)row[v + 1]; ++i) {
+            const int32_t w = c->col[i];
+            const int32_t *lo = c->col + (int64_t)row[w], *hi = c->col + (int64_t)row[w + 1];
+            need(std::binary_search(lo, hi, (int32_t)v), "CSR is not symmetric");
+        }
+    }
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char *bc_last_error(void) { return tl_error.c_str(); }
+
+bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out)
+{
+    return guarded([&] {
+        need(csr && out, "null argument");
+        need(csr->n >= 1 && csr->n < 0x7fffffffll, "n must be in [1, 2^31 - 1)");
+        need(csr->nnz >= 0 && csr->row && (csr->col || csr->nnz == 0), "bad CSR arrays");
+        std::vector<int64_t> row((size_t)csr->n + 1);
+        if (csr->row_is_i64) {
+            const int64_t *r = (const int64_t *)csr->row;
+            validate_csr(csr, r);
+            std::copy(r, r + csr->n + 1, row.begin());
+        } else {
+            const int32_t *r = (const int32_t *)csr->row;
+            validate_csr(csr, r);
+            std::copy(r, r + csr->n + 1, row.begin());
+        }
+        bc_graph *g = new bc_graph();
+        try {
+            HIPX(hipGetDevice(&g->device));
+            g->n = csr->n;
+            g->nnz = csr->nnz;
+            g->stream = (hipStream_t)hip_stream;
+            g->row.ensure(row.size());
+            g->col.ensure((size_t)csr->nnz);
+            g->ctl.ensure(8);
+            HIPX(hipHostMalloc((void **)&g->h_ctl, 8 * sizeof(unsigned long long), 0));
+            HIPX(hipMemcpy(g->row.p, row.data(), row.size() * 8, hipMemcpyHostToDevice));
+            if (csr->nnz)
+                HIPX(hipMemcpy(g->col.p, csr->col, (size_t)csr->nnz * 4, hipMemcpyHostToDevice));
+        } catch (...) {
+            g->release_all();
+            delete g;
+            throw;
+        }
+        *out = g;
+    });
+}
+
+void bc_graph_destroy(bc_graph *g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    g->release_all();
+    delete g;
+}
+
+bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        g->stream = (hipStream_t)hip_stream;
+    });
+}
+
+bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg)
+{
+    return guarded([&] {
+        need(g && cfg, "null argument");
+        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_PER_SOURCE,
+             "unknown schedule");
+        const int b = cfg->batch;
+        need(b == 0 || (b >= 64 && b <= 4096 && (b & (b - 1)) == 0),
+             "batch must be 0 or a power of two in [64, 4096]");
+        need(cfg->bottom_up == cfg->bottom_up, "bottom_up is NaN");
+        g->cfg = *cfg;
+    });
+}
+
+bc_status bc_graph_info(const bc_graph *g, int64_t *n, int64_t *nnz)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        if (n) *n = g->n;
+        if (nnz) *nnz = g->nnz;
+    });
+}
+
+bc_status bc_last_stats(const bc_graph *g, bc_stats *out)
+{
+    return guarded([&] {
+        need(g && out, "null argument");
+        *out = g->stats;
+    });
+}
+
+bc_status bc_exact(bc_graph *g, double *out)
+{
+    return guarded([&] {
+        need(g && out, "null argument");
+        use_device(g);
+        DBuf<int32_t> all;
+        all.ensure((size_t)g->n);
+        try {
+            launch(g->stream, grid_for(g->n), k_iota, all.p, (int64_t)0, g->n);
+            dependencies_impl(g, all.p, g->n, BC_OUT_SUM, out, nullptr, nullptr, nullptr, false,
+                              nullptr);
+        } catch (...) {
+            (void)hipStreamSynchronize(g->stream);
+            all.release();
+            throw;
+        }
+        all.release();
+    });
+}
+
+bc_status bc_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_t out_mode,
+                          double *out, int32_t *dist_out, double *sigma_mant, int32_t *sigma_exp)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(k >= 0, "k must be >= 0");
+        need(k == 0 || (sources && out), "null argument");
+        need(out_mode == BC_OUT_FULL || out_mode == BC_OUT_SUM, "unknown out_mode");
+        need(out_mode == BC_OUT_FULL || (!dist_out && !sigma_mant && !sigma_exp),
+             "per-source outputs need BC_OUT_FULL");
+        use_device(g);
+        check_indices(g, sources, k, "source");
+        if (per_source_schedule(g) && (sigma_mant || sigma_exp))
+            fail(BC_E_UNSUPPORTED, "path-count output is served by the batched schedule");
+        dependencies_impl(g, sources, k, out_mode, out, dist_out, sigma_mant, sigma_exp, false,
+                          nullptr);
+    });
+}
+
+bc_status bc_pair_dependencies(bc_graph *g, const int32_t *us, const int32_t *vs, int64_t k,
+                               double *out)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(k >= 0, "k must be >= 0");
+        need(k == 0 || (us && vs && out), "null argument");
+        need(g->n >= 2, "pairs need n >= 2");
+        use_device(g);
+        check_indices(g, us, k, "pair start");
+        check_indices(g, vs, k, "pair end");
+        // u != v is checked on the host copy (k is small in practice)
+        if (k > 0) {
+            std::vector<int32_t> hu((size_t)k), hv((size_t)k);
+            HIPX(hipMemcpy(hu.data(), us, (size_t)k * 4, hipMemcpyDeviceToHost));
+            HIPX(hipMemcpy(hv.data(), vs, (size_t)k * 4, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < k; ++i) need(hu[i] != hv[i], "pair with u == v");
+        }
+        dependencies_impl(g, us, k, BC_OUT_FULL, out, nullptr, nullptr, nullptr, true, vs);
+    });
+}
+
+bc_status bc_adaptive_source(bc_graph *g, const int32_t *targets, int32_t T, double c,
+                             uint64_t seed, int64_t k_max, double *out_est, int64_t *out_samples,
+                             double *out_S, uint8_t *out_status)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(T >= 0, "T must be >= 0");
+        need(T == 0 || (targets && out_est && out_samples && out_S && out_status),
+             "null argument");
+        need(c >= 1.0, "c must be >= 1 (and not NaN)");
+        need(k_max >= 1, "k_max must be >= 1");
+        use_device(g);
+        check_indices(g, targets, T, "target");
+        if (per_source_schedule(g))
+            fail(BC_E_UNSUPPORTED, "samplers run on the batched schedule");
+        sampler_impl(g, targets, T, false, RULE_SOURCE, c, 0.0, seed, k_max, out_est,
+                     out_samples, out_S, out_status);
+    });
+}
+
+bc_status bc_adaptive_pair(bc_graph *g, const int32_t *targets, int32_t T, int32_t rule,
+                           double eps, double c, uint64_t seed, int64_t k_max, double *out_est,
+                           int64_t *out_samples, double *out_S, uint8_t *out_status)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(T >= 0, "T must be >= 0");
+        need(T == 0 || (targets && out_est && out_samples && out_S && out_status),
+             "null argument");
+        need(rule == BC_PAIR_ALG1 || rule == BC_PAIR_EPS, "unknown rule");
+        if (rule == BC_PAIR_ALG1) need(c >= 1.0, "c must be >= 1 (and not NaN)");
+        if (rule == BC_PAIR_EPS) need(eps > 0.0 && eps < 0.5, "eps must be in (0, 1/2)");
+        need(k_max >= 1, "k_max must be >= 1");
+        need(g->n >= 2, "pairs need n >= 2");
+        use_device(g);
+        check_indices(g, targets, T, "target");
+        if (per_source_schedule(g))
+            fail(BC_E_UNSUPPORTED, "samplers run on the batched schedule");
+        sampler_impl(g, targets, T, true, rule == BC_PAIR_EPS ? RULE_PAIR_EPS : RULE_PAIR_ALG1,
+                     c, eps, seed, k_max, out_est, out_samples, out_S, out_status);
+    });
+}
+
+bc_status bc_draw_sources(bc_graph *g, uint64_t seed, int64_t j0, int64_t count, int32_t *out_u)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(j0 >= 0 && count >= 0, "j0 and count must be >= 0");
+        need(count == 0 || out_u, "null argument");
+        use_device(g);
+        if (count == 0) return;
+        launch(g->stream, grid_for(count), k_draw_sources, seed, j0, count, g->n, out_u);
+        HIPX(hipStreamSynchronize(g->stream));
+    });
+}
+
+bc_status bc_draw_pairs(bc_graph *g, uint64_t seed, int64_t j0, int64_t count, int32_t *out_u,
+                        int32_t *out_v)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(j0 >= 0 && count >= 0, "j0 and count must be >= 0");
+        need(count == 0 || (out_u && out_v), "null argument");
+        need(g->n >= 2, "pairs need n >= 2");
+        use_device(g);
+        if (count == 0) return;
+        launch(g->stream, grid_for(count), k_draw_pairs, seed, j0, count, g->n, out_u, out_v);
+        HIPX(hipStreamSynchronize(g->stream));
+    });
+}
+
+}  // extern "C"

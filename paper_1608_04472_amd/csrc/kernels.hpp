@@ -1,0 +1,655 @@
+// Device kernels for Brandes' pass on an unweighted CSR graph, batched over
+// many sources, plus the per-source plain form, the sample draws and the
+// adaptive stopping rules.
+//
+// Batched layout ("slabs", vertex-major, source-minor):
+//   sig[v*B + b]  FP64 path count sigma_{s_b}(v); after the backward pass of
+//                 v's level it is overwritten in place by
+//                 rho = (1 + delta)/sigma (source mode) or
+//                 rho = ([v = dest_b] + delta')/sigma (pair mode), the only
+//                 quantity a predecessor needs from v (Theorem 1).
+//   sige[v*B + b] int32 exponent of sig when counts are extended (value =
+//                 sig * 2^sige); absent in plain FP64 mode.
+//   dlt[v*B + b]  FP64 dependency delta_{s_b.}(v) (Definition 2).
+//   vis[v*W + j]  bit l set once source b = 64j + l has reached v.
+//   F*[v*W + j]   dense frontier bitmap of one level (two rotating arrays).
+// Level record: entries (v, j) with a nonzero 64-bit mask, appended level
+// by level; level l occupies [off[l], off[l+1]). It replaces Brandes'
+// distance-ordered stack: the backward sweep walks it from the deepest level up.
+// One wavefront works on one entry: its 64 lanes are the 64 sources of word j,
+// so every neighbour's slab row is one contiguous, coalesced 512-byte access.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace bcmi {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+// control words shared with the host (one 64-byte block)
+enum : int { CTL_TAIL = 0, CTL_REC_OVERFLOW = 1, CTL_SIG_OVERFLOW = 2, CTL_RUNNING = 3 };
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return (uint64_t)__ballot(p); }
+
+__device__ __forceinline__ int32_t lane_read_i32(int32_t x, int l)
+{
+    return __builtin_amdgcn_readlane(x, l);
+}
+
+__device__ __forceinline__ uint64_t lane_read_u64(uint64_t x, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// number of set bits of bal below this lane
+__device__ __forceinline__ int rank_below(uint64_t bal)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+// Wave-aggregated append: one atomic per wavefront, slots by ballot rank.
+// Every lane of the wavefront must reach this call.
+__device__ __forceinline__ int64_t wave_append(bool want, unsigned long long *tail)
+{
+    const uint64_t bal = wave_ballot(want);
+    if (bal == 0) return -1;
+    const int leader = __ffsll((long long)bal) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(tail, (unsigned long long)__popcll(bal));
+    base = lane_read_u64(base, leader);
+    return want ? (int64_t)base + rank_below(bal) : -1;
+}
+
+struct BatchArgs {
+    const int64_t *row;
+    const int32_t *col;
+    int64_t n;
+    int32_t logW;        // words per batch = 1 << logW
+    int32_t B;           // sources per batch = 64 << logW
+    double *sig;
+    int32_t *sige;       // null in plain FP64 mode
+    double *dlt;
+    uint64_t *vis;
+    uint32_t *ridx;
+    uint64_t *rmask;
+    int64_t cap;
+    unsigned long long *ctl;
+    uint64_t *active;    // [W] sources still expanding (pair mode clears finished slots)
+    const uint64_t *valid;  // [W] lanes holding a real source
+    const int32_t *srcs; // [B] source (pair: u)
+    const int32_t *dest; // [B] pair destination v, or null in source mode
+    int32_t nvalid;
+};
+
+__device__ __forceinline__ void record_push(const BatchArgs &a, int64_t pos, uint32_t idx)
+{
+    if (pos < a.cap) a.ridx[pos] = idx;
+    else a.ctl[CTL_REC_OVERFLOW] = 1ull;
+}
+
+// ------------------------------------------------------------ extended FP64
+// value = m * 2^e with m normalised into [1, 2) once it leaves the plain range.
+struct XNum {
+    double m;
+    int32_t e;
+};
+
+__device__ __forceinline__ XNum xnorm(double m, int32_t e)
+{
+    XNum r{m, e};
+    if (m == 0.0) { r.e = 0; return r; }
+    const uint64_t bits = __double_as_longlong(m);
+    const int32_t ex = (int32_t)((bits >> 52) & 0x7ff) - 1023;
+    if (ex == 0) return r;
+    r.m = __longlong_as_double((long long)((bits & ~(0x7ffull << 52)) | (1023ull << 52)));
+    r.e = e + ex;
+    return r;
+}
+
+__device__ __forceinline__ XNum xadd(XNum a, XNum b)
+{
+    if (a.m == 0.0) return b;
+    if (b.m == 0.0) return a;
+    const int32_t e = a.e > b.e ? a.e : b.e;
+    return xnorm(ldexp(a.m, a.e - e) + ldexp(b.m, b.e - e), e);
+}
+
+// ------------------------------------------------------------------ level 0
+
+__global__ void k_init_sources(BatchArgs a, uint64_t *F0)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    bool want = false;
+    uint32_t idx = 0;
+    if (b < a.nvalid) {
+        const int32_t s = a.srcs[b];
+        const int j = b >> 6;
+        const uint64_t bit = 1ull << (b & 63);
+        const int64_t o = (int64_t)s * a.B + b;
+        a.sig[o] = 1.0;
+        if (a.sige) a.sige[o] = 0;
+        a.dlt[o] = 0.0;
+        idx = ((uint32_t)s << a.logW) + (uint32_t)j;
+        const uint64_t old = atomicOr((unsigned long long *)&F0[idx], (unsigned long long)bit);
+        atomicOr((unsigned long long *)&a.vis[idx], (unsigned long long)bit);
+        want = (old == 0);
+    }
+    const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
+    if (want) record_push(a, pos, idx);
+}
+
+__global__ void k_fill_masks(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F)
+{
+    for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
+         e += (int64_t)gridDim.x * blockDim.x)
+        a.rmask[e] = F[a.ridx[e]];
+}
+
+__global__ void k_clear(BatchArgs a, int64_t e0, int64_t e1, uint64_t *F)
+{
+    for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
+         e += (int64_t)gridDim.x * blockDim.x)
+        F[a.ridx[e]] = 0;
+}
+
+// ---------------------------------------------------------- forward: discover
+
+// Top-down: each frontier entry (u, j) offers its mask to every neighbour w;
+// bits not yet visited are OR-ed into w's next-level word, and the first
+// writer of a word appends (w, j) to the record.
+__global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t *nxt)
+{
+    const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    for (int64_t e = e0 + wave; e < e1; e += nwaves) {
+        const uint32_t idx = a.ridx[e];
+        const int64_t u = idx >> a.logW;
+        const uint32_t j = idx & wmask;
+        const uint64_t m = a.rmask[e] & a.active[j];
+        if (m == 0) continue;
+        const int64_t beg = a.row[u], end = a.row[u + 1];
+        for (int64_t base = beg; base < end; base += kWave) {
+            const int64_t p = base + lane;
+            bool want = false;
+            uint32_t widx = 0;
+            if (p < end) {
+                widx = ((uint32_t)a.col[p] << a.logW) + j;
+                const uint64_t fresh = m & ~a.vis[widx];
+                if (fresh) {
+                    const uint64_t old = atomicOr((unsigned long long *)&nxt[widx],
+                                                  (unsigned long long)fresh);
+                    want = (old == 0);
+                }
+            }
+            const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
+            if (want) record_push(a, pos, widx);
+        }
+    }
+}
+
+// Bottom-up: every (w, j) with unvisited live sources looks for frontier
+// neighbours and stops early once all its unvisited sources are found
+// (membership only: the path counts are pulled afterwards from all parents).
+__global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *nxt)
+{
+    const int64_t total = a.n << a.logW;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < total; i0 += stride) {
+        const int64_t idx = i0 + threadIdx.x;
+        bool app = false;
+        if (idx < total) {
+            const uint32_t j = (uint32_t)idx & wmask;
+            const uint64_t want = ~a.vis[idx] & a.valid[j] & a.active[j];
+            if (want) {
+                const int64_t v = idx >> a.logW;
+                uint64_t acc = 0;
+                for (int64_t e = a.row[v], end = a.row[v + 1]; e < end; ++e) {
+                    acc |= cur[((int64_t)a.col[e] << a.logW) + j];
+                    if ((acc & want) == want) break;
+                }
+                const uint64_t fresh = acc & want;
+                if (fresh) {
+                    nxt[idx] = fresh;
+                    app = true;
+                }
+            }
+        }
+        const int64_t pos = wave_append(app, &a.ctl[CTL_TAIL]);
+        if (app) record_push(a, pos, (uint32_t)idx);
+    }
+}
+
+// -------------------------------------------------------- forward: sigma pull
+
+// sigma_s(w) = sum over predecessors u (neighbours one level up, Definition 3)
+// of sigma_s(u), in ascending CSR order. Lanes are sources; the neighbour
+// words are gathered 64 at a time and the overlapping ones walked in order.
+template <bool kExt>
+__global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *cur,
+                             const uint64_t *nxt)
+{
+    const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    for (int64_t e = e0 + wave; e < e1; e += nwaves) {
+        const uint32_t idx = a.ridx[e];
+        const int64_t v = idx >> a.logW;
+        const uint32_t j = idx & wmask;
+        const uint64_t m = nxt[idx];
+        const int b = (int)(j << 6) + lane;
+        const bool mine = (m >> lane) & 1ull;
+        XNum acc{0.0, 0};
+        double accp = 0.0;
+        const int64_t beg = a.row[v], end = a.row[v + 1];
+        for (int64_t base = beg; base < end; base += kWave) {
+            const int64_t p = base + lane;
+            int32_t u = 0;
+            uint64_t f = 0;
+            if (p < end) {
+                u = a.col[p];
+                f = cur[((int64_t)u << a.logW) + j] & m;
+            }
+            uint64_t bal = wave_ballot(f != 0);
+            while (bal) {
+                const int k = __ffsll((long long)bal) - 1;
+                bal &= bal - 1;
+                const int32_t uk = lane_read_i32(u, k);
+                const uint64_t fk = lane_read_u64(f, k);
+                if ((fk >> lane) & 1ull) {
+                    const int64_t o = (int64_t)uk * a.B + b;
+                    if (kExt) acc = xadd(acc, XNum{a.sig[o], a.sige[o]});
+                    else accp += a.sig[o];
+                }
+            }
+        }
+        if (mine) {
+            const int64_t o = v * a.B + b;
+            if (kExt) {
+                a.sig[o] = acc.m;
+                a.sige[o] = acc.e;
+            } else {
+                a.sig[o] = accp;
+                if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
+            }
+            if (a.dest && a.dest[b] == (int32_t)v)
+                atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
+        }
+        if (lane == 0) {
+            a.vis[idx] |= m;
+            a.rmask[e] = m;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward
+
+// Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
+// rho(w), rho(w) = (1 + delta(w)) / sigma(w). Pair mode replaces the 1 by the
+// indicator of the pair's destination, which yields sigma_uv(t)/sigma_uv.
+// The entry's own mask is scattered into fown for the next (shallower) level.
+template <bool kExt>
+__global__ void k_backward(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *fnext,
+                           uint64_t *fown)
+{
+    const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    for (int64_t e = e0 + wave; e < e1; e += nwaves) {
+        const uint32_t idx = a.ridx[e];
+        const int64_t v = idx >> a.logW;
+        const uint32_t j = idx & wmask;
+        const uint64_t m = a.rmask[e];
+        const int b = (int)(j << 6) + lane;
+        const bool mine = (m >> lane) & 1ull;
+        XNum acc{0.0, 0};
+        double accp = 0.0;
+        const int64_t beg = a.row[v], end = a.row[v + 1];
+        for (int64_t base = beg; base < end; base += kWave) {
+            const int64_t p = base + lane;
+            int32_t w = 0;
+            uint64_t f = 0;
+            if (p < end) {
+                w = a.col[p];
+                f = fnext[((int64_t)w << a.logW) + j] & m;
+            }
+            uint64_t bal = wave_ballot(f != 0);
+            while (bal) {
+                const int k = __ffsll((long long)bal) - 1;
+                bal &= bal - 1;
+                const int32_t wk = lane_read_i32(w, k);
+                const uint64_t fk = lane_read_u64(f, k);
+                if ((fk >> lane) & 1ull) {
+                    const int64_t o = (int64_t)wk * a.B + b;
+                    if (kExt) acc = xadd(acc, XNum{a.sig[o], a.sige[o]});
+                    else accp += a.sig[o];
+                }
+            }
+        }
+        if (mine) {
+            const int64_t o = v * a.B + b;
+            const double term = a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
+            if (kExt) {
+                const XNum s{a.sig[o], a.sige[o]};
+                // delta = sigma(v) * sum(rho): exponents add back to the plain range
+                const double d = acc.m == 0.0 ? 0.0 : ldexp(s.m * acc.m, s.e + acc.e);
+                const XNum r = xnorm((term + d) / s.m, -s.e);
+                a.sig[o] = r.m;
+                a.sige[o] = r.e;
+                a.dlt[o] = d;
+            } else {
+                const double s = a.sig[o];
+                const double d = s * accp;
+                a.sig[o] = (term + d) / s;
+                a.dlt[o] = d;
+            }
+        }
+        if (lane == 0) fown[idx] = m;
+    }
+}
+
+// ------------------------------------------------------------------ outputs
+
+__device__ __forceinline__ bool reached(const BatchArgs &a, int64_t v, int b)
+{
+    return (a.vis[(v << a.logW) + (b >> 6)] >> (b & 63)) & 1ull;
+}
+
+// out[(b0 + b) * n + v] = delta_{s_b}(v) for b < count (0 where unreached)
+__global__ void k_out_full(BatchArgs a, int32_t count, int64_t b0, double *out)
+{
+    const int64_t total = a.n * count;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / count;
+        const int b = (int)(i - v * count);
+        out[(b0 + b) * a.n + v] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
+    }
+}
+
+// out[v] += sum over the batch's sources in ascending batch order
+__global__ void k_out_sum(BatchArgs a, double *out)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < a.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        double acc = out[v];
+        const int W = 1 << a.logW;
+        for (int j = 0; j < W; ++j) {
+            uint64_t live = a.vis[(v << a.logW) + j] & a.valid[j];
+            while (live) {
+                const int l = __ffsll((long long)live) - 1;
+                live &= live - 1;
+                acc += a.dlt[v * a.B + (j << 6) + l];
+            }
+        }
+        out[v] = acc;
+    }
+}
+
+// per-source distances from the level record: dist[(b0+b)*n + v] = level
+__global__ void k_out_dist(BatchArgs a, int64_t e0, int64_t e1, int32_t level, int32_t count,
+                           int64_t b0, int32_t *dist)
+{
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = a.ridx[e];
+        const int64_t v = idx >> a.logW;
+        const int j = (int)(idx & wmask);
+        uint64_t m = a.rmask[e];
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int b = (j << 6) + l;
+            if (b < count) dist[(b0 + b) * a.n + v] = level;
+        }
+    }
+}
+
+// per-source path counts (taken between the forward and backward passes)
+__global__ void k_out_sigma(BatchArgs a, int32_t count, int64_t b0, double *mant, int32_t *ex)
+{
+    const int64_t total = a.n * count;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / count;
+        const int b = (int)(i - v * count);
+        const bool r = reached(a, v, b);
+        const int64_t o = v * a.B + b;
+        double m = r ? a.sig[o] : 0.0;
+        int32_t e = (r && a.sige) ? a.sige[o] : 0;
+        if (mant) {
+            // report normalised extended values (m in [1, 2)) whatever the mode
+            const XNum x = xnorm(m, e);
+            mant[(b0 + b) * a.n + v] = x.m;
+            if (ex) ex[(b0 + b) * a.n + v] = x.e;
+        } else if (ex) {
+            ex[(b0 + b) * a.n + v] = e;
+        }
+    }
+}
+
+// X[t*B + b] = delta_{s_b}(target_t) (pair mode: sigma_{u_b v_b}(t)/sigma_{u_b v_b})
+__global__ void k_gather_targets(BatchArgs a, const int32_t *targets, int32_t T, double *X)
+{
+    const int64_t total = (int64_t)T * a.B;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(i / a.B);
+        const int b = (int)(i - (int64_t)t * a.B);
+        const int64_t v = targets[t];
+        X[i] = (b < a.nvalid && reached(a, v, b)) ? a.dlt[v * a.B + b] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------- draws
+
+__global__ void k_draw_sources(uint64_t seed, int64_t j0, int64_t count, int64_t n, int32_t *out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Block4 r = philox4x64_10((uint64_t)(j0 + i), 0, 0, 0, seed, 0);
+        out[i] = (int32_t)scale_to_range(r.w[0], (uint64_t)n);
+    }
+}
+
+__global__ void k_draw_pairs(uint64_t seed, int64_t j0, int64_t count, int64_t n, int32_t *us,
+                             int32_t *vs)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Block4 r = philox4x64_10((uint64_t)(j0 + i), 0, 0, 0, seed, 1);
+        const int64_t u = scale_to_range(r.w[0], (uint64_t)n);
+        int64_t v = scale_to_range(r.w[1], (uint64_t)(n - 1));
+        v += (v >= u) ? 1 : 0;
+        us[i] = (int32_t)u;
+        vs[i] = (int32_t)v;
+    }
+}
+
+// ------------------------------------------------------------- stop rules
+
+enum : uint8_t { ST_DONE = 0, ST_CAPPED = 1, ST_RUNNING = 255 };
+enum : int32_t { RULE_SOURCE = 0, RULE_PAIR_ALG1 = 1, RULE_PAIR_EPS = 2 };
+
+struct StopArgs {
+    int32_t T;
+    int32_t rule;
+    double threshold;   // c * n
+    double eps_rhs;     // eps^3 * n^2
+    int64_t k_max;
+    double *S;
+    int64_t *K;
+    uint8_t *status;
+};
+
+// One lane per target walks the round's samples in draw order, exactly as the
+// sequential loop would: add, count, then test (the crossing sample counts).
+__global__ void k_stop_rule(StopArgs s, const double *X, int32_t B, int32_t nb,
+                            unsigned long long *ctl)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.T) return;
+    double S = s.S[t];
+    int64_t k = s.K[t];
+    uint8_t st = s.status[t];
+    for (int b = 0; b < nb && st == ST_RUNNING; ++b) {
+        S = S + X[(int64_t)t * B + b];
+        k = k + 1;
+        bool stop;
+        if (s.rule == RULE_PAIR_EPS) stop = (S > 0.0) && (((double)k * (S * S)) >= s.eps_rhs);
+        else stop = S > s.threshold;
+        if (stop) st = ST_DONE;
+        else if (k == s.k_max) st = ST_CAPPED;
+    }
+    s.S[t] = S;
+    s.K[t] = k;
+    s.status[t] = st;
+    if (st == ST_RUNNING) atomicAdd(&ctl[CTL_RUNNING], 1ull);
+}
+
+__global__ void k_stop_init(StopArgs s)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.T) return;
+    s.S[t] = 0.0;
+    s.K[t] = 0;
+    s.status[t] = ST_RUNNING;
+}
+
+// est = n*S/k (sources) or n(n-1)*S/k (pairs)
+__global__ void k_stop_finish(StopArgs s, double scale, double *est, int64_t *samples,
+                              double *S_out, uint8_t *status)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.T) return;
+    est[t] = (scale * s.S[t]) / (double)s.K[t];
+    samples[t] = s.K[t];
+    S_out[t] = s.S[t];
+    status[t] = s.status[t];
+}
+
+// -------------------------------------------------- per-source plain form
+
+__global__ void k_ss_init(int32_t *d, double *sig, double *dlt, int32_t *queue, int32_t s)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d[s] = 0;
+        sig[s] = 1.0;
+        dlt[s] = 0.0;
+        queue[0] = s;
+    }
+}
+
+__global__ void k_ss_topdown(const int64_t *row, const int32_t *col, int32_t *d, int32_t *queue,
+                             int64_t q0, int64_t q1, int32_t level, unsigned long long *ctl)
+{
+    for (int64_t i = q0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = queue[i];
+        for (int64_t e = row[u]; e < row[u + 1]; ++e) {
+            const int32_t w = col[e];
+            if (d[w] < 0 && atomicCAS(&d[w], -1, level + 1) == -1) {
+                const unsigned long long pos = atomicAdd(&ctl[CTL_TAIL], 1ull);
+                queue[pos] = w;
+            }
+        }
+    }
+}
+
+__global__ void k_ss_sigma(const int64_t *row, const int32_t *col, const int32_t *d, double *sig,
+                           const int32_t *queue, int64_t q0, int64_t q1, int32_t level,
+                           unsigned long long *ctl)
+{
+    for (int64_t i = q0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t w = queue[i];
+        double acc = 0.0;
+        for (int64_t e = row[w]; e < row[w + 1]; ++e) {
+            const int32_t u = col[e];
+            if (d[u] == level) acc += sig[u];
+        }
+        sig[w] = acc;
+        if (!(acc < 0x1p1000)) ctl[CTL_SIG_OVERFLOW] = 1ull;
+    }
+}
+
+__global__ void k_ss_backward(const int64_t *row, const int32_t *col, const int32_t *d,
+                              const double *sig, double *dlt, const int32_t *queue, int64_t q0,
+                              int64_t q1, int32_t level)
+{
+    for (int64_t i = q0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = queue[i];
+        const double sv = sig[v];
+        double acc = 0.0;
+        for (int64_t e = row[v]; e < row[v + 1]; ++e) {
+            const int32_t w = col[e];
+            if (d[w] == level + 1) acc += (sv / sig[w]) * (1.0 + dlt[w]);
+        }
+        dlt[v] = acc;
+    }
+}
+
+__global__ void k_ss_out_sum(const double *dlt, const int32_t *queue, int64_t q0, int64_t q1,
+                             double *out)
+{
+    for (int64_t i = q0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = queue[i];
+        out[v] += dlt[v];
+    }
+}
+
+__global__ void k_ss_out_full(const int32_t *d, const double *dlt, int64_t n, double *out_row)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        out_row[v] = d[v] > 0 ? dlt[v] : 0.0;
+}
+
+// ------------------------------------------------------------------- misc
+
+__global__ void k_iota(int32_t *out, int64_t start, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)(start + i);
+}
+
+__global__ void k_fill_i32(int32_t *out, int32_t value, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = value;
+}
+
+__global__ void k_fill_f64(double *out, double value, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = value;
+}
+
+// check sources / targets lie in [0, n); ctl[CTL_REC_OVERFLOW] is reused as
+// the "bad index" flag by the host before any batch starts
+__global__ void k_check_range(const int32_t *x, int64_t count, int64_t n, unsigned long long *flag)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (x[i] < 0 || x[i] >= n) *flag = 1ull;
+}
+
+}  // namespace bcmi

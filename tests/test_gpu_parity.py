@@ -1,0 +1,362 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars: distances bit-exact; path counts bit-exact below 2^53 and within 1e-12
+relative above (extended values compared as m * 2^e); dependencies, BC, pair
+dependencies and estimates within 1e-9 relative (values below 1e-290 in
+magnitude on both sides count as equal); sample counts and statuses exact.
+Every case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1608_04472_amd as bc  # noqa: E402
+
+O = oracle.load()
+RTOL = 1e-9
+TINY = 1e-290
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def assert_close(got, want, rtol=RTOL, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    assert got.shape == want.shape, what
+    tiny = (np.abs(got) < TINY) & (np.abs(want) < TINY)
+    ok = tiny | (np.abs(got - want) <= rtol * np.abs(want))
+    if not ok.all():
+        i = np.flatnonzero(~ok.ravel())[:5]
+        raise AssertionError("%s: %d mismatches, e.g. idx %s got %s want %s" % (
+            what, int((~ok).sum()), i, got.ravel()[i], want.ravel()[i]))
+
+
+def assert_sigma(gm, ge, om, oe, what=""):
+    """Extended counts: identical below 2^53, 1e-12 relative above."""
+    gm, ge, om, oe = (np.asarray(x) for x in (gm, ge, om, oe))
+    small = (oe < 53) | (om == 0)
+    assert np.array_equal(gm[small], om[small]) and np.array_equal(ge[small], oe[small]), what
+    big = ~small
+    if big.any():
+        d = ge[big].astype(np.int64) - oe[big].astype(np.int64)
+        assert np.all(np.abs(d) <= 1), what
+        rel = np.abs(np.ldexp(gm[big], d) - om[big]) / om[big]
+        assert rel.max() <= 1e-12, (what, rel.max())
+
+
+def check_sources(G, g, src, dev, what):
+    say(what, "n=%d k=%d" % (g.n, len(src)))
+    full, dist, sig = bc.dependencies(G, T(src.astype(np.int32), dev), bc.BC_OUT_FULL,
+                                      dist=True, sigma=True)
+    full, dist = full.cpu().numpy(), dist.cpu().numpy()
+    sm, se = sig[0].cpu().numpy(), sig[1].cpu().numpy()
+    for i, s in enumerate(src):
+        d, (om, oe), de = O.brandes(g, int(s))
+        assert np.array_equal(dist[i], d), (what, "dist", i)
+        assert_sigma(sm[i], se[i], om, oe, "%s sigma %d" % (what, i))
+        assert_close(full[i], de, what="%s delta %d" % (what, i))
+    return full
+
+
+# ------------------------------------------------------------------ draws
+
+@pytest.mark.parametrize("n", [2, 3, 2000, 1 << 20, 4194274])
+def test_draws_bit_exact(dev, n):
+    say("draws", n)
+    g = gg.path(n)                       # draws depend only on n
+    G = bc.Graph(g.row, g.col)
+    for seed, j0, cnt in ((1, 0, 1000), (7, 123456789, 777), ((1 << 64) - 1, 5, 64)):
+        u = torch.empty(cnt, dtype=torch.int32, device=dev)
+        v = torch.empty(cnt, dtype=torch.int32, device=dev)
+        bc.bc_draw_sources(G, seed, j0, cnt, u)
+        want = [O.draw_source(seed, j0 + i, n) for i in range(cnt)]
+        assert u.cpu().tolist() == want
+        bc.bc_draw_pairs(G, seed, j0, cnt, u, v)
+        want = [O.draw_pair(seed, j0 + i, n) for i in range(cnt)]
+        assert list(zip(u.cpu().tolist(), v.cpu().tolist())) == want
+    G.close()
+
+
+def test_draws_bit_exact_large_n(dev):
+    say("draws large n")
+    g = gg.ba(1 << 20, 5, seed=7)
+    G = bc.Graph(g.row, g.col)
+    u = torch.empty(4096, dtype=torch.int32, device=dev)
+    v = torch.empty(4096, dtype=torch.int32, device=dev)
+    bc.bc_draw_sources(G, 7, 0, 4096, u)
+    assert u.cpu().numpy().tolist() == gg.philox_sources(7, 4096, g.n).tolist()
+    bc.bc_draw_pairs(G, 7, 99, 1000, u[:1000], v[:1000])
+    want = [O.draw_pair(7, 99 + i, g.n) for i in range(1000)]
+    assert list(zip(u[:1000].cpu().tolist(), v[:1000].cpu().tolist())) == want
+    G.close()
+
+
+# --------------------------------------------------------- Brandes passes
+
+SMALL = [
+    ("path17", lambda: gg.path(17)),
+    ("star40", lambda: gg.star(40)),
+    ("cycle9", lambda: gg.cycle(9)),
+    ("cycle12", lambda: gg.cycle(12)),
+    ("K12", lambda: gg.complete(12)),
+    ("K3,5", lambda: gg.complete_bipartite(3, 5)),
+    ("grid7x9", lambda: gg.grid(7, 9)),
+    ("single", lambda: gg.from_edges(1, [], [])),
+    ("edge", lambda: gg.path(2)),
+    ("split", lambda: gg.from_edges(9, [0, 1, 3, 5, 6], [1, 2, 4, 6, 7])),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_small_graphs_all_sources(dev, name, make):
+    g = make()
+    G = bc.Graph(g.row, g.col)
+    src = np.arange(g.n, dtype=np.int32)
+    check_sources(G, g, src, dev, name)
+    out = bc.exact(G).cpu().numpy()
+    assert_close(out, O.bc_exact(g), what=name + " bc")
+    G.close()
+
+
+@pytest.mark.parametrize("batch", [64, 128, 256])
+@pytest.mark.parametrize("bottom_up", [-1.0, 0.0, 1e-9])
+def test_er2000_batches_and_directions(dev, batch, bottom_up):
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_BATCHED, batch, bottom_up)
+    src = gg.philox_sources(1, 200, g.n)          # 200 = several batches + ragged tail
+    src[5] = src[77] = src[199] = 3               # repeats in and across batches
+    check_sources(G, g, src, dev, "er2000 B=%d bu=%g" % (batch, bottom_up))
+    G.close()
+
+
+def test_er2000_exact_bc(dev):
+    say("er2000 exact")
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    out = bc.exact(G).cpu().numpy()
+    assert_close(out, O.bc_exact(g), what="er2000 bc")
+    st = G.stats()
+    assert st["samples_executed"] == g.n
+    G.close()
+
+
+def test_sum_mode_matches_oracle(dev):
+    say("rmat12 sum")
+    g = gg.rmat(12, 8, 0.57, 0.19, 0.19, seed=5)
+    G = bc.Graph(g.row, g.col)
+    src = gg.philox_sources(3, 300, g.n)
+    out, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+    _, want = O.dependencies(g, src, full=False, total=True)
+    assert_close(out.cpu().numpy(), want, what="rmat12 sum")
+    G.close()
+
+
+@pytest.mark.parametrize("batch", [64, 512])
+def test_rmat_isolated_vertices_and_hubs(dev, batch):
+    g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
+    assert (g.degree() == 0).any()
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_BATCHED, batch, 0.0)
+    iso = np.flatnonzero(g.degree() == 0)[:3]
+    hubs = gg.top_degree(g, 3)
+    src = np.concatenate([iso, hubs, gg.philox_sources(2, 90, g.n)]).astype(np.int32)
+    check_sources(G, g, src, dev, "rmat12 B=%d" % batch)
+    G.close()
+
+
+def test_grid_counts_beyond_2_53(dev):
+    g = gg.grid(40, 40)
+    G = bc.Graph(g.row, g.col)
+    check_sources(G, g, np.array([0, 1599, 820, 41], dtype=np.int32), dev, "grid40")
+    assert G.stats()["extended"] == 0
+    G.close()
+
+
+def test_grid_counts_beyond_fp64_range(dev):
+    g = gg.grid(600, 600)
+    G = bc.Graph(g.row, g.col)
+    check_sources(G, g, np.array([0, 359999, 180300], dtype=np.int32), dev, "grid600")
+    assert G.stats()["extended"] == 1
+    G.close()
+
+
+def test_per_source_schedule(dev):
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_PER_SOURCE, 0, 0.0)
+    src = gg.philox_sources(4, 20, g.n)
+    say("per-source full")
+    full, dist, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL, dist=True)
+    want, _ = O.dependencies(g, src, full=True, total=False)
+    assert_close(full.cpu().numpy(), want, what="per-source full")
+    for i, s in enumerate(src):
+        assert np.array_equal(dist[i].cpu().numpy(), O.brandes(g, int(s))[0])
+    say("per-source sum")
+    out, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+    assert_close(out.cpu().numpy(), want.sum(0), what="per-source sum")
+    G.close()
+
+
+def test_bit_identical_reruns_and_batch_positions(dev):
+    g = gg.rmat(11, 8, 0.57, 0.19, 0.19, seed=1)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_BATCHED, 128, 0.0)
+    src = gg.philox_sources(5, 128, g.n)
+    say("determinism")
+    a = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+    b = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+    assert np.array_equal(a, b)
+    # the same source alone, and at the last position of a different batch
+    alone = bc.dependencies(G, T(src[:1], dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+    assert np.array_equal(alone[0], a[0])
+    mixed = np.concatenate([gg.philox_sources(6, 127, g.n), src[:1]]).astype(np.int32)
+    m = bc.dependencies(G, T(mixed, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+    assert np.array_equal(m[127], a[0])
+    G.close()
+
+
+def test_invalid_arguments(dev):
+    g = gg.path(6)
+    G = bc.Graph(g.row, g.col)
+    say("invalid args")
+    with pytest.raises(bc.BcError) as e:
+        bc.dependencies(G, T(np.array([0, 6], np.int32), dev))
+    assert e.value.status == bc.BC_E_INVALID
+    with pytest.raises(bc.BcError):
+        bc.adaptive_source(G, T(np.array([1], np.int32), dev), 0.5, 1, 10)
+    with pytest.raises(bc.BcError):
+        bc.adaptive_pair(G, T(np.array([1], np.int32), dev), bc.BC_PAIR_EPS, 0.5, 1.0, 1, 10)
+    with pytest.raises(bc.BcError):
+        bc.pair_dependencies(G, T(np.array([2], np.int32), dev), T(np.array([2], np.int32), dev))
+    with pytest.raises(bc.BcError):
+        G.configure(bc.BC_SCHED_BATCHED, 96, 0.0)
+    # empty source list is valid
+    out, _, _ = bc.dependencies(G, T(np.zeros(0, np.int32), dev), bc.BC_OUT_SUM)
+    assert np.all(out.cpu().numpy() == 0)
+    G.close()
+
+
+# --------------------------------------------------------- pair dependencies
+
+def test_pair_dependencies(dev):
+    g = gg.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)
+    G = bc.Graph(g.row, g.col)
+    r = np.random.default_rng(0)
+    us = r.integers(0, g.n, 150).astype(np.int32)
+    vs = r.integers(0, g.n - 1, 150).astype(np.int32)
+    vs = vs + (vs >= us)
+    nb = g.col[g.row[us[0]]:g.row[us[0] + 1]]
+    if nb.shape[0]:
+        vs[0] = nb[0]                                   # adjacent pair: no interior vertex
+    iso = np.flatnonzero(g.degree() == 0)
+    if iso.shape[0]:
+        vs[1] = iso[0] if iso[0] != us[1] else iso[-1]  # unreachable destination
+    say("pair deps")
+    got = bc.pair_dependencies(G, T(us, dev), T(vs.astype(np.int32), dev)).cpu().numpy()
+    for i in range(us.shape[0]):
+        assert_close(got[i], O.pair_dependency(g, int(us[i]), int(vs[i])), what="pair %d" % i)
+    G.close()
+
+
+def test_pair_dependencies_grid_extended(dev):
+    g = gg.grid(600, 600)
+    G = bc.Graph(g.row, g.col)
+    us = np.array([0, 1000, 5], dtype=np.int32)
+    vs = np.array([359999, 300000, 359000], dtype=np.int32)
+    say("pair deps grid600")
+    got = bc.pair_dependencies(G, T(us, dev), T(vs, dev)).cpu().numpy()
+    for i in range(3):
+        assert_close(got[i], O.pair_dependency(g, int(us[i]), int(vs[i])), what="gpair %d" % i)
+    G.close()
+
+
+# --------------------------------------------------------------- samplers
+
+def check_sampler(got, want, what):
+    est, k, S, st = (x.cpu().numpy() for x in got)
+    oest, ok, oS, ost = want
+    assert np.array_equal(k, ok), (what, k, ok)
+    assert np.array_equal(st, ost), what
+    assert_close(S, oS, what=what + " S")
+    assert_close(est, oest, what=what + " est")
+
+
+def test_adaptive_source_er2000(dev):
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    targets = gg.top_degree(g, 16)
+    say("adaptive source er2000")
+    got = bc.adaptive_source(G, T(targets, dev), 5.0, 1, g.n)
+    check_sampler(got, O.adaptive_source(g, targets, 5.0, 1, g.n), "source er2000")
+    G.close()
+
+
+@pytest.mark.parametrize("batch", [64, 256])
+def test_adaptive_source_capped_and_shared(dev, batch):
+    g = gg.rmat(10, 8, 0.57, 0.19, 0.19, seed=3)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_BATCHED, batch, 0.0)
+    deg = g.degree()
+    leaf = int(np.flatnonzero(deg == 1)[0])
+    targets = np.array([leaf] + gg.top_degree(g, 5).tolist() + [leaf], dtype=np.int32)
+    say("adaptive source capped B=%d" % batch)
+    got = bc.adaptive_source(G, T(targets, dev), 1.5, 9, 300)
+    want = O.adaptive_source(g, targets, 1.5, 9, 300)
+    check_sampler(got, want, "source capped")
+    assert want[3][0] == oracle.CAPPED
+    G.close()
+
+
+def test_adaptive_source_threshold_tie(dev):
+    g = gg.path(5)
+    G = bc.Graph(g.row, g.col)
+    for seed in range(1, 6):
+        say("tie seed", seed)
+        got = bc.adaptive_source(G, T(np.array([2], np.int32), dev), 2.0, seed, 10 ** 6)
+        check_sampler(got, O.adaptive_source(g, [2], 2.0, seed, 10 ** 6), "tie")
+        assert got[2].cpu().numpy()[0] == 12.0
+    G.close()
+
+
+def test_adaptive_pair_eps_er2000(dev):
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    targets = gg.top_degree(g, 16)
+    say("adaptive pair eps er2000")
+    got = bc.adaptive_pair(G, T(targets, dev), bc.BC_PAIR_EPS, 0.1, 1.0, 1, 1 << 20)
+    check_sampler(got, O.adaptive_pair(g, targets, oracle.RULE_EPS, 0.1, 1.0, 1, 1 << 20),
+                  "pair eps er2000")
+    G.close()
+
+
+def test_adaptive_pair_alg1_small(dev):
+    g = gg.er(150, 0.04, seed=2)
+    G = bc.Graph(g.row, g.col)
+    targets = gg.top_degree(g, 3)
+    say("adaptive pair alg1")
+    got = bc.adaptive_pair(G, T(targets, dev), bc.BC_PAIR_ALG1, 0.1, 1.0, 5, 1 << 20)
+    check_sampler(got, O.adaptive_pair(g, targets, oracle.RULE_ALG1, 0.1, 1.0, 5, 1 << 20),
+                  "pair alg1")
+    G.close()
