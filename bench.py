@@ -100,17 +100,44 @@ def main():
         torch.cuda.synchronize()
         log("warmup %d: %.1f ms" % (i, 1e3 * (time.time() - t)))
     st = G.stats()
+    G.profile(True)      # HIP events around every hot launch on the library's stream
     torch.cuda.synchronize()
     t = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
+    kern = G.profile_read()
+    G.profile(False)
     ms = 1e3 * elapsed / args.steps
     gteps = edges_per_step / (elapsed / args.steps) / 1e9
     st = G.stats()
     log("timed %d steps: %.2f ms/step, %.2f GTEPS, batch %d, levels %d" % (
         args.steps, ms, gteps, st["batch_width"], st["levels"]))
+    for k in kern:
+        if k["launches"]:
+            log("  %-18s %4d launches %9.2f ms  avg %8.1f us  %7.1f GB/s algorithmic" % (
+                k["name"], k["launches"], k["ms"], 1e3 * k["ms"] / k["launches"],
+                k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0))
+    dom = max(kern, key=lambda k: k["ms"])
+    achieved = dom["algo_bytes"] / (dom["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["name"],
+                "avg_launch_us": 1e3 * dom["ms"] / dom["launches"],
+                "algo_bytes_per_launch": dom["algo_bytes"] / dom["launches"]}
+    sig = next(k for k in kern if k["name"] == "sigma_pull")
+    csr_bytes = 8 * (g.n + 1) + 4 * g.nnz
+    batches = -(-K // st["batch_width"])
+    reach = sig["units_a"] + K * args.steps          # level-0 pairs are the sources
+    step_bytes = (2 * csr_bytes * batches * args.steps + 32 * reach + 16 * sig["units_b"]) \
+        / args.steps
+    step_model = {"algo_bytes": step_bytes, "GBs": step_bytes / (ms * 1e-3) / 1e9,
+                  "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "reached_pairs": reach / args.steps,
+                  "dag_edge_pairs": sig["units_b"] / args.steps}
+    log("dominant %s: %.1f GB/s (%.1f%% of HBM); whole step %.1f GB/s (%.1f%%)" % (
+        dom["name"], achieved, 100 * achieved / HBM_PEAK_GBS, step_model["GBs"],
+        100 * step_model["frac"]))
 
     # ---------------------------------------------------- per-source form
     per_source = None
@@ -179,7 +206,11 @@ def main():
                                    g.m_undirected, K, args.seed),
                    "graph": args.graph, "n": g.n, "nnz": g.nnz, "sources": K,
                    "batch": st["batch_width"], "parallelism": "single GPU"},
-        "per_source": per_source, "pair_leg": pair, "roofline": None, "cpu_baseline": cpu,
+        "per_source": per_source, "pair_leg": pair, "roofline": roofline, "cpu_baseline": cpu,
+        "step_model": step_model,
+        "kernels": [{"name": k["name"], "launches": k["launches"], "ms": k["ms"] / args.steps,
+                     "algo_GBs": k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] else 0.0}
+                    for k in kern],
     }
     print(json.dumps(res), flush=True)
     G.close()

@@ -163,6 +163,31 @@ typedef struct {
 } bc_stats;
 bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
 
+/* Per-kernel profile of the hot path, for roofline accounting. While enabled,
+ * every launch of the four hot kernels is bracketed by HIP events on the
+ * graph's stream, and the kernels count the work units they process:
+ *   units_a: (vertex, source) pairs (discovered, counted or swept),
+ *   units_b: DAG (edge, source) pairs read (predecessor or successor values).
+ * Algorithmic bytes per unit (8-byte path counts and rho, 4-byte levels):
+ *   discover_topdown / discover_bottomup: 4 per units_a (level write)
+ *   sigma_pull : 8 per units_a (count write) + 8 per units_b (count read)
+ *   backward   : 20 per units_a (count read, rho write, level read)
+ *                + 8 per units_b (rho read)
+ * Enabling resets the accumulators. Profiling adds one event pair per launch
+ * and one counter update per wavefront. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double ms;          /* sum of event-measured launch durations */
+    int64_t units_a;
+    int64_t units_b;
+    double algo_bytes;  /* from the per-unit figures above */
+} bc_kernel_profile;
+
+bc_status bc_profile_enable(bc_graph *g, int32_t enable);
+/* Writes up to max entries (one per kernel) to out; *count receives the number. */
+bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int32_t *count);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *bc_last_error(void);
 

@@ -36,7 +36,7 @@ EXPORTS = [
     "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_configure",
     "bc_graph_info", "bc_exact", "bc_dependencies", "bc_pair_dependencies",
     "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
-    "bc_last_stats", "bc_last_error",
+    "bc_last_stats", "bc_last_error", "bc_profile_enable", "bc_profile_read",
 ]
 
 
@@ -74,6 +74,12 @@ class _Stats(ctypes.Structure):
                 ("batch_width", ctypes.c_int32)]
 
 
+class _KProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("ms", ctypes.c_double), ("units_a", ctypes.c_int64),
+                ("units_b", ctypes.c_int64), ("algo_bytes", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -106,6 +112,8 @@ def load_library(path: str | None = None):
         "bc_draw_sources": [V, c.c_uint64, c.c_int64, c.c_int64, V],
         "bc_draw_pairs": [V, c.c_uint64, c.c_int64, c.c_int64, V, V],
         "bc_last_stats": [V, c.POINTER(_Stats)],
+        "bc_profile_enable": [V, c.c_int32],
+        "bc_profile_read": [V, c.POINTER(_KProf), c.c_int32, c.POINTER(c.c_int32)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -175,6 +183,17 @@ class Graph:
         st = _Stats()
         _check(_lib.bc_last_stats(self.handle, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+    def profile(self, enable: bool):
+        _check(_lib.bc_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        arr = (_KProf * 16)()
+        cnt = ctypes.c_int32()
+        _check(_lib.bc_profile_read(self.handle, arr, 16, ctypes.byref(cnt)))
+        return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "ms": arr[i].ms,
+                 "units_a": arr[i].units_a, "units_b": arr[i].units_b,
+                 "algo_bytes": arr[i].algo_bytes} for i in range(cnt.value)]
 
     def close(self):
         if getattr(self, "_h", None) is not None:

@@ -65,7 +65,11 @@ int grid_for(int64_t threads)
     const int64_t b = (threads + kBlock - 1) / kBlock;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 20));
 }
-int grid_waves(int64_t waves) { return grid_for(waves * kWave); }
+// wave-per-entry kernels stride over their entries with at most 64K wavefronts
+int grid_waves(int64_t waves)
+{
+    return std::min(grid_for(waves * kWave), 16384);
+}
 
 template <class K, class... A>
 void launch(hipStream_t st, int grid, K kernel, A... args)
@@ -87,6 +91,7 @@ struct bc_graph {
     DBuf<double> sig, dlt;
     DBuf<int32_t> sige;
     DBuf<uint64_t> vis, F0, F1, active, valid;
+    DBuf<double> vsum;
     DBuf<uint32_t> ridx;
     DBuf<uint64_t> rmask;
     DBuf<unsigned long long> ctl;
@@ -101,16 +106,36 @@ struct bc_graph {
     unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
     int64_t cap_hint = 0;
     bc_stats stats{};
+    // profiler: event pairs around hot launches, device work-unit counters
+    bool prof_on = false;
+    DBuf<unsigned long long> prof_dev;
+    double prof_ms[PROF_KERNELS] = {};
+    int64_t prof_launches[PROF_KERNELS] = {};
+    struct Pending {
+        int kernel;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> ev_free;
 
     void release_all()
     {
         row.release(); col.release(); sig.release(); dlt.release(); sige.release();
         vis.release(); F0.release(); F1.release(); active.release(); valid.release();
+        vsum.release();
         ridx.release(); rmask.release(); ctl.release(); srcs.release(); dest.release();
         X.release(); S.release(); K.release(); st.release();
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release();
         if (h_ctl) (void)hipHostFree(h_ctl);
         h_ctl = nullptr;
+        prof_dev.release();
+        for (auto &p : pending) {
+            (void)hipEventDestroy(p.start);
+            (void)hipEventDestroy(p.stop);
+        }
+        for (auto e : ev_free) (void)hipEventDestroy(e);
+        pending.clear();
+        ev_free.clear();
     }
 };
 
@@ -141,6 +166,52 @@ void need(bool ok, const char *msg)
 }
 
 void use_device(bc_graph *g) { HIPX(hipSetDevice(g->device)); }
+
+// ------------------------------------------------------------------ profiler
+
+hipEvent_t take_event(bc_graph *g)
+{
+    if (!g->ev_free.empty()) {
+        hipEvent_t e = g->ev_free.back();
+        g->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPX(hipEventCreate(&e));
+    return e;
+}
+
+// Collect the durations of finished profiled launches.
+void prof_flush(bc_graph *g)
+{
+    if (g->pending.empty()) return;
+    HIPX(hipStreamSynchronize(g->stream));
+    for (auto &p : g->pending) {
+        float ms = 0.f;
+        HIPX(hipEventElapsedTime(&ms, p.start, p.stop));
+        g->prof_ms[p.kernel] += ms;
+        g->prof_launches[p.kernel] += 1;
+        g->ev_free.push_back(p.start);
+        g->ev_free.push_back(p.stop);
+    }
+    g->pending.clear();
+}
+
+// Launch one of the hot kernels, bracketed by events while profiling.
+template <class K, class... A>
+void launch_hot(bc_graph *g, int kernel, int grid, K fn, A... args)
+{
+    if (!g->prof_on) {
+        launch(g->stream, grid, fn, args...);
+        return;
+    }
+    bc_graph::Pending p{kernel, take_event(g), take_event(g)};
+    HIPX(hipEventRecord(p.start, g->stream));
+    launch(g->stream, grid, fn, args...);
+    HIPX(hipEventRecord(p.stop, g->stream));
+    g->pending.push_back(p);
+    if (g->pending.size() >= 256) prof_flush(g);
+}
 
 void read_ctl(bc_graph *g)
 {
@@ -188,7 +259,8 @@ Plan plan_batch(bc_graph *g, int64_t want, int default_cap)
     // (vertex, word) indices are 32-bit
     while (B > 64 && g->n * (int64_t)(B / 64) >= (1ll << 32)) B /= 2;
     // slabs: sig + dlt (+ exponents) per (vertex, source); keep within free memory
-    const size_t budget = free_device_bytes() / 10 * 7 + g->sig.cap * 8 + g->dlt.cap * 8;
+    const size_t budget = free_device_bytes() / 10 * 7 + g->sig.cap * 8 + g->dlt.cap * 8 +
+                          g->sige.cap * 4;
     while (B > 64 && (size_t)g->n * B * 20 > budget) B /= 2;
     Plan p;
     p.B = B;
@@ -197,11 +269,16 @@ Plan plan_batch(bc_graph *g, int64_t want, int default_cap)
     return p;
 }
 
-void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap)
+// What the backward pass leaves behind: the full dependency slab (per-source
+// outputs, target gathers) or only per-(vertex, word) sums (BC_OUT_SUM).
+enum OutKind { OUT_DELTA = 0, OUT_VSUM = 1 };
+
+void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kind)
 {
     const int64_t n = g->n, W = 1ll << p.logW;
     g->sig.ensure((size_t)(n * p.B));
-    g->dlt.ensure((size_t)(n * p.B));
+    if (kind == OUT_DELTA) g->dlt.ensure((size_t)(n * p.B));
+    else g->vsum.ensure((size_t)(n * W));
     if (ext) g->sige.ensure((size_t)(n * p.B));
     g->vis.ensure((size_t)(n * W));
     g->F0.ensure((size_t)(n * W));
@@ -225,7 +302,8 @@ __global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32
     active[j] = m;
 }
 
-BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair, int64_t cap)
+BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair, int64_t cap,
+                    OutKind kind)
 {
     BatchArgs a;
     a.row = g->row.p;
@@ -235,7 +313,9 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     a.B = p.B;
     a.sig = g->sig.p;
     a.sige = ext ? g->sige.p : nullptr;
-    a.dlt = g->dlt.p;
+    a.dlt = kind == OUT_DELTA ? g->dlt.p : nullptr;
+    a.vsum = kind == OUT_VSUM ? g->vsum.p : nullptr;
+    a.prof = g->prof_on ? g->prof_dev.p : nullptr;
     a.vis = g->vis.p;
     a.ridx = g->ridx.p;
     a.rmask = g->rmask.p;
@@ -273,17 +353,18 @@ double bottom_up_fraction(const bc_graph *g)
 // sets *ext_used. Grows the record and switches to extended path counts as
 // needed, redoing the batch.
 std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair, bool *ext_used,
-                               const SigmaOut *sigout)
+                               const SigmaOut *sigout, OutKind kind)
 {
     const int64_t n = g->n, W = 1ll << p.logW;
     bool ext = false;
     int64_t cap = std::max<int64_t>(g->cap_hint, std::max<int64_t>(4 * n * W, 1 << 16));
     const double bu_frac = bottom_up_fraction(g);
     for (;;) {
-        ensure_batch(g, p, ext, cap);
-        BatchArgs a = make_args(g, p, ext, nvalid, pair, cap);
+        ensure_batch(g, p, ext, cap, kind);
+        BatchArgs a = make_args(g, p, ext, nvalid, pair, cap, kind);
         hipStream_t s = g->stream;
         HIPX(hipMemsetAsync(g->vis.p, 0, (size_t)(n * W) * 8, s));
+        if (kind == OUT_VSUM) HIPX(hipMemsetAsync(g->vsum.p, 0, (size_t)(n * W) * 8, s));
         HIPX(hipMemsetAsync(g->F0.p, 0, (size_t)(n * W) * 8, s));
         HIPX(hipMemsetAsync(g->F1.p, 0, (size_t)(n * W) * 8, s));
         zero_ctl(g);
@@ -300,9 +381,10 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             const int64_t e0 = off[level], e1 = off[level + 1];
             const int64_t nent = e1 - e0;
             if (bu_frac > 0 && (double)nent > bu_frac * (double)(n * W))
-                launch(s, grid_for(n * W), k_discover_bottomup, a, (const uint64_t *)cur, nxt);
+                launch_hot(g, PROF_BOTTOMUP, grid_for(n * W), k_discover_bottomup, a,
+                           (const uint64_t *)cur, nxt);
             else
-                launch(s, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
+                launch_hot(g, PROF_TOPDOWN, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
             read_ctl(g);
             const int64_t e2 = (int64_t)g->h_ctl[CTL_TAIL];
             if (g->h_ctl[CTL_REC_OVERFLOW]) {
@@ -312,11 +394,11 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             }
             if (e2 == e1) break;
             if (ext)
-                launch(s, grid_waves(e2 - e1), k_sigma_pull<true>, a, e1, e2,
-                       (const uint64_t *)cur, (const uint64_t *)nxt);
+                launch_hot(g, PROF_SIGMA, grid_waves(e2 - e1), k_sigma_pull<true>, a, e1, e2,
+                           (const uint64_t *)cur, (const uint64_t *)nxt);
             else
-                launch(s, grid_waves(e2 - e1), k_sigma_pull<false>, a, e1, e2,
-                       (const uint64_t *)cur, (const uint64_t *)nxt);
+                launch_hot(g, PROF_SIGMA, grid_waves(e2 - e1), k_sigma_pull<false>, a, e1, e2,
+                           (const uint64_t *)cur, (const uint64_t *)nxt);
             launch(s, grid_for(nent), k_clear, a, e0, e1, cur);
             off.push_back(e2);
             std::swap(cur, nxt);
@@ -340,11 +422,11 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         for (int level = L - 1; level >= 1; --level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
             if (ext)
-                launch(s, grid_waves(e1 - e0), k_backward<true>, a, e0, e1,
-                       (const uint64_t *)fnext, fown);
+                launch_hot(g, PROF_BACKWARD, grid_waves(e1 - e0), k_backward<true>, a, e0, e1,
+                           (const uint64_t *)fnext, fown);
             else
-                launch(s, grid_waves(e1 - e0), k_backward<false>, a, e0, e1,
-                       (const uint64_t *)fnext, fown);
+                launch_hot(g, PROF_BACKWARD, grid_waves(e1 - e0), k_backward<false>, a, e0, e1,
+                           (const uint64_t *)fnext, fown);
             if (level + 1 < L)
                 launch(s, grid_for(off[level + 2] - e1), k_clear, a, e1, off[level + 2], fnext);
             std::swap(fnext, fown);
@@ -459,7 +541,8 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     g->stats.batch_width = p.B;
     for (int64_t b0 = 0; b0 < k; b0 += p.B) {
         const int count = (int)std::min<int64_t>(p.B, k - b0);
-        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16));
+        const OutKind kind = mode == BC_OUT_SUM ? OUT_VSUM : OUT_DELTA;
+        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), kind);
         HIPX(hipMemcpyAsync(g->srcs.p, sources + b0, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
         if (pair)
             HIPX(hipMemcpyAsync(g->dest.p, dests + b0, (size_t)count * 4,
@@ -470,9 +553,9 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         so.count = count;
         so.b0 = b0;
         bool ext = false;
-        std::vector<int64_t> off = run_batch(g, p, count, pair, &ext, &so);
-        BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->ridx.cap);
-        if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_sum, a, out);
+        std::vector<int64_t> off = run_batch(g, p, count, pair, &ext, &so, kind);
+        BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->ridx.cap, kind);
+        if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_vsum, a, out);
         else launch(s, grid_for(n * count), k_out_full, a, (int32_t)count, b0, out);
         if (dist_out)
             for (size_t l = 0; l + 1 < off.size(); ++l)
@@ -482,6 +565,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         g->stats.samples_executed += count;
     }
     HIPX(hipStreamSynchronize(s));
+    prof_flush(g);
 }
 
 // --------------------------------------------------------------- samplers
@@ -513,14 +597,14 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     int64_t j0 = 0;
     for (;;) {
         const int nb = (int)std::min<int64_t>(p.B, k_max - j0);
-        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16));
+        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
         if (pair)
             launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->srcs.p, g->dest.p);
         else
             launch(s, grid_for(nb), k_draw_sources, seed, j0, (int64_t)nb, n, g->srcs.p);
         bool ext = false;
-        run_batch(g, p, nb, pair, &ext, nullptr);
-        BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->ridx.cap);
+        run_batch(g, p, nb, pair, &ext, nullptr, OUT_DELTA);
+        BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->ridx.cap, OUT_DELTA);
         launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->X.p);
         launch(s, grid_for(T), k_stop_rule, sa, (const double *)g->X.p, (int32_t)p.B, (int32_t)nb,
                g->ctl.p);
@@ -534,6 +618,7 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     const double scale = pair ? (double)n * (double)(n - 1) : (double)n;
     launch(s, grid_for(T), k_stop_finish, sa, scale, out_est, out_samples, out_S, out_status);
     HIPX(hipStreamSynchronize(s));
+    prof_flush(g);
 }
 
 // ---------------------------------------------------------- CSR validation
@@ -655,6 +740,51 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out)
     return guarded([&] {
         need(g && out, "null argument");
         *out = g->stats;
+    });
+}
+
+bc_status bc_profile_enable(bc_graph *g, int32_t enable)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        use_device(g);
+        prof_flush(g);
+        g->prof_dev.ensure(2 * PROF_KERNELS);
+        HIPX(hipMemsetAsync(g->prof_dev.p, 0, 2 * PROF_KERNELS * 8, g->stream));
+        HIPX(hipStreamSynchronize(g->stream));
+        for (int k = 0; k < PROF_KERNELS; ++k) {
+            g->prof_ms[k] = 0.0;
+            g->prof_launches[k] = 0;
+        }
+        g->prof_on = enable != 0;
+    });
+}
+
+bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int32_t *count)
+{
+    return guarded([&] {
+        need(g && count && (max <= 0 || out), "null argument");
+        use_device(g);
+        prof_flush(g);
+        unsigned long long units[2 * PROF_KERNELS] = {};
+        if (g->prof_dev.p)
+            HIPX(hipMemcpy(units, g->prof_dev.p, sizeof(units), hipMemcpyDeviceToHost));
+        static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
+                                                  "sigma_pull", "backward"};
+        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0};
+        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0};
+        int32_t c = 0;
+        for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
+            bc_kernel_profile &r = out[c];
+            std::memset(&r, 0, sizeof(r));
+            std::strncpy(r.name, names[k], sizeof(r.name) - 1);
+            r.launches = g->prof_launches[k];
+            r.ms = g->prof_ms[k];
+            r.units_a = (int64_t)units[2 * k];
+            r.units_b = (int64_t)units[2 * k + 1];
+            r.algo_bytes = per_a[k] * (double)r.units_a + per_b[k] * (double)r.units_b;
+        }
+        *count = c;
     });
 }
 

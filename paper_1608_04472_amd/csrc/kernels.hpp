@@ -86,8 +86,31 @@ struct BatchArgs {
     const uint64_t *valid;  // [W] lanes holding a real source
     const int32_t *srcs; // [B] source (pair: u)
     const int32_t *dest; // [B] pair destination v, or null in source mode
+    double *vsum;        // [n][W] per-(vertex, word) dependency sums, or null
+    unsigned long long *prof;  // work-unit counters [kernel][2], or null
     int32_t nvalid;
 };
+
+// kernel ids of the work-unit counters
+enum : int { PROF_TOPDOWN = 0, PROF_BOTTOMUP = 1, PROF_SIGMA = 2, PROF_BACKWARD = 3, PROF_KERNELS = 4 };
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// add per-wave unit counts to the profile counters (one atomic pair per wave)
+__device__ __forceinline__ void prof_add(const BatchArgs &a, int kernel, unsigned long long ua,
+                                         unsigned long long ub, int lane)
+{
+    if (!a.prof) return;
+    if (lane == 0) {
+        if (ua) atomicAdd(&a.prof[2 * kernel], ua);
+        if (ub) atomicAdd(&a.prof[2 * kernel + 1], ub);
+    }
+}
 
 __device__ __forceinline__ void record_push(const BatchArgs &a, int64_t pos, uint32_t idx)
 {
@@ -136,7 +159,7 @@ __global__ void k_init_sources(BatchArgs a, uint64_t *F0)
         const int64_t o = (int64_t)s * a.B + b;
         a.sig[o] = 1.0;
         if (a.sige) a.sige[o] = 0;
-        a.dlt[o] = 0.0;
+        if (a.dlt) a.dlt[o] = 0.0;
         idx = ((uint32_t)s << a.logW) + (uint32_t)j;
         const uint64_t old = atomicOr((unsigned long long *)&F0[idx], (unsigned long long)bit);
         atomicOr((unsigned long long *)&a.vis[idx], (unsigned long long)bit);
@@ -171,6 +194,7 @@ __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const uint32_t wmask = (1u << a.logW) - 1u;
+    unsigned long long found = 0;
     for (int64_t e = e0 + wave; e < e1; e += nwaves) {
         const uint32_t idx = a.ridx[e];
         const int64_t u = idx >> a.logW;
@@ -189,12 +213,14 @@ __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t
                     const uint64_t old = atomicOr((unsigned long long *)&nxt[widx],
                                                   (unsigned long long)fresh);
                     want = (old == 0);
+                    found += __popcll(fresh & ~old);
                 }
             }
             const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
             if (want) record_push(a, pos, widx);
         }
     }
+    if (a.prof) prof_add(a, PROF_TOPDOWN, wave_sum_u64(found), 0, lane);
 }
 
 // Bottom-up: every (w, j) with unvisited live sources looks for frontier
@@ -205,6 +231,7 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
     const int64_t total = a.n << a.logW;
     const uint32_t wmask = (1u << a.logW) - 1u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long found = 0;
     for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < total; i0 += stride) {
         const int64_t idx = i0 + threadIdx.x;
         bool app = false;
@@ -214,27 +241,94 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
             if (want) {
                 const int64_t v = idx >> a.logW;
                 uint64_t acc = 0;
-                for (int64_t e = a.row[v], end = a.row[v + 1]; e < end; ++e) {
-                    acc |= cur[((int64_t)a.col[e] << a.logW) + j];
+                const int64_t end = a.row[v + 1];
+                // four neighbours per step so their loads overlap
+                for (int64_t e = a.row[v]; e < end; e += 4) {
+                    uint64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+                    f0 = cur[((int64_t)a.col[e] << a.logW) + j];
+                    if (e + 1 < end) f1 = cur[((int64_t)a.col[e + 1] << a.logW) + j];
+                    if (e + 2 < end) f2 = cur[((int64_t)a.col[e + 2] << a.logW) + j];
+                    if (e + 3 < end) f3 = cur[((int64_t)a.col[e + 3] << a.logW) + j];
+                    acc |= f0 | f1 | f2 | f3;
                     if ((acc & want) == want) break;
                 }
                 const uint64_t fresh = acc & want;
                 if (fresh) {
                     nxt[idx] = fresh;
                     app = true;
+                    found += __popcll(fresh);
                 }
             }
         }
         const int64_t pos = wave_append(app, &a.ctl[CTL_TAIL]);
         if (app) record_push(a, pos, (uint32_t)idx);
     }
+    if (a.prof) prof_add(a, PROF_BOTTOMUP, wave_sum_u64(found), 0, lane_id());
+}
+
+// ------------------------------------------------- neighbour pull (shared)
+
+// Sum, over the neighbours x of v in ascending CSR order whose frontier word
+// F[x][j] shares a bit with `want`, of the slab value slab[x][64j + lane] for
+// the lanes whose bit is set in that word. Overlapping neighbours are taken
+// eight at a time so their slab loads are in flight together; lanes outside a
+// neighbour's word add zero, which leaves the running sum unchanged.
+template <bool kExt>
+__device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t j, uint64_t want,
+                                         const uint64_t *F, int lane, double &accp, XNum &accx,
+                                         unsigned long long &units)
+{
+    const int b = (int)(j << 6) + lane;
+    const int64_t beg = a.row[v], end = a.row[v + 1];
+    for (int64_t base = beg; base < end; base += kWave) {
+        const int64_t p = base + lane;
+        int32_t x = 0;
+        uint64_t f = 0;
+        if (p < end) {
+            x = a.col[p];
+            f = F[((int64_t)x << a.logW) + j] & want;
+        }
+        uint64_t bal = wave_ballot(f != 0);
+        while (bal) {
+            double vm[8];
+            int32_t ve[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                vm[q] = 0.0;
+                ve[q] = 0;
+                if (bal) {
+                    const int k = __ffsll((long long)bal) - 1;
+                    bal &= bal - 1;
+                    const int32_t xk = lane_read_i32(x, k);
+                    const uint64_t fk = lane_read_u64(f, k);
+                    units += __popcll(fk);
+                    if ((fk >> lane) & 1ull) {
+                        const int64_t o = (int64_t)xk * a.B + b;
+                        vm[q] = a.sig[o];
+                        if (kExt) ve[q] = a.sige[o];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
+                else accp += vm[q];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
 }
 
 // -------------------------------------------------------- forward: sigma pull
 
 // sigma_s(w) = sum over predecessors u (neighbours one level up, Definition 3)
-// of sigma_s(u), in ascending CSR order. Lanes are sources; the neighbour
-// words are gathered 64 at a time and the overlapping ones walked in order.
+// of sigma_s(u), in ascending CSR order. Lanes are sources.
 template <bool kExt>
 __global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *cur,
                              const uint64_t *nxt)
@@ -243,6 +337,7 @@ __global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const uint32_t wmask = (1u << a.logW) - 1u;
+    unsigned long long ua = 0, ub = 0;
     for (int64_t e = e0 + wave; e < e1; e += nwaves) {
         const uint32_t idx = a.ridx[e];
         const int64_t v = idx >> a.logW;
@@ -252,28 +347,8 @@ __global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t
         const bool mine = (m >> lane) & 1ull;
         XNum acc{0.0, 0};
         double accp = 0.0;
-        const int64_t beg = a.row[v], end = a.row[v + 1];
-        for (int64_t base = beg; base < end; base += kWave) {
-            const int64_t p = base + lane;
-            int32_t u = 0;
-            uint64_t f = 0;
-            if (p < end) {
-                u = a.col[p];
-                f = cur[((int64_t)u << a.logW) + j] & m;
-            }
-            uint64_t bal = wave_ballot(f != 0);
-            while (bal) {
-                const int k = __ffsll((long long)bal) - 1;
-                bal &= bal - 1;
-                const int32_t uk = lane_read_i32(u, k);
-                const uint64_t fk = lane_read_u64(f, k);
-                if ((fk >> lane) & 1ull) {
-                    const int64_t o = (int64_t)uk * a.B + b;
-                    if (kExt) acc = xadd(acc, XNum{a.sig[o], a.sige[o]});
-                    else accp += a.sig[o];
-                }
-            }
-        }
+        ua += __popcll(m);
+        pull_sum<kExt>(a, v, j, m, cur, lane, accp, acc, ub);
         if (mine) {
             const int64_t o = v * a.B + b;
             if (kExt) {
@@ -291,6 +366,7 @@ __global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t
             a.rmask[e] = m;
         }
     }
+    prof_add(a, PROF_SIGMA, ua, ub, lane);
 }
 
 // ------------------------------------------------------------------ backward
@@ -299,6 +375,9 @@ __global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t
 // rho(w), rho(w) = (1 + delta(w)) / sigma(w). Pair mode replaces the 1 by the
 // indicator of the pair's destination, which yields sigma_uv(t)/sigma_uv.
 // The entry's own mask is scattered into fown for the next (shallower) level.
+// With a.vsum set, the entry's dependencies are also summed over its lanes
+// (fixed tree order) into vsum[v][j]; each (v, j) appears once per level and
+// levels run in sequence, so the accumulation needs no atomics.
 template <bool kExt>
 __global__ void k_backward(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *fnext,
                            uint64_t *fown)
@@ -307,6 +386,7 @@ __global__ void k_backward(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const uint32_t wmask = (1u << a.logW) - 1u;
+    unsigned long long ua = 0, ub = 0;
     for (int64_t e = e0 + wave; e < e1; e += nwaves) {
         const uint32_t idx = a.ridx[e];
         const int64_t v = idx >> a.logW;
@@ -316,48 +396,33 @@ __global__ void k_backward(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *
         const bool mine = (m >> lane) & 1ull;
         XNum acc{0.0, 0};
         double accp = 0.0;
-        const int64_t beg = a.row[v], end = a.row[v + 1];
-        for (int64_t base = beg; base < end; base += kWave) {
-            const int64_t p = base + lane;
-            int32_t w = 0;
-            uint64_t f = 0;
-            if (p < end) {
-                w = a.col[p];
-                f = fnext[((int64_t)w << a.logW) + j] & m;
-            }
-            uint64_t bal = wave_ballot(f != 0);
-            while (bal) {
-                const int k = __ffsll((long long)bal) - 1;
-                bal &= bal - 1;
-                const int32_t wk = lane_read_i32(w, k);
-                const uint64_t fk = lane_read_u64(f, k);
-                if ((fk >> lane) & 1ull) {
-                    const int64_t o = (int64_t)wk * a.B + b;
-                    if (kExt) acc = xadd(acc, XNum{a.sig[o], a.sige[o]});
-                    else accp += a.sig[o];
-                }
-            }
-        }
+        ua += __popcll(m);
+        pull_sum<kExt>(a, v, j, m, fnext, lane, accp, acc, ub);
+        double d = 0.0;
         if (mine) {
             const int64_t o = v * a.B + b;
             const double term = a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
             if (kExt) {
                 const XNum s{a.sig[o], a.sige[o]};
                 // delta = sigma(v) * sum(rho): exponents add back to the plain range
-                const double d = acc.m == 0.0 ? 0.0 : ldexp(s.m * acc.m, s.e + acc.e);
+                d = acc.m == 0.0 ? 0.0 : ldexp(s.m * acc.m, s.e + acc.e);
                 const XNum r = xnorm((term + d) / s.m, -s.e);
                 a.sig[o] = r.m;
                 a.sige[o] = r.e;
-                a.dlt[o] = d;
             } else {
                 const double s = a.sig[o];
-                const double d = s * accp;
+                d = s * accp;
                 a.sig[o] = (term + d) / s;
-                a.dlt[o] = d;
             }
+            if (a.dlt) a.dlt[o] = d;
+        }
+        if (a.vsum) {
+            const double t = wave_sum(d);
+            if (lane == 0) a.vsum[idx] += t;
         }
         if (lane == 0) fown[idx] = m;
     }
+    prof_add(a, PROF_BACKWARD, ua, ub, lane);
 }
 
 // ------------------------------------------------------------------ outputs
@@ -379,21 +444,14 @@ __global__ void k_out_full(BatchArgs a, int32_t count, int64_t b0, double *out)
     }
 }
 
-// out[v] += sum over the batch's sources in ascending batch order
-__global__ void k_out_sum(BatchArgs a, double *out)
+// out[v] += sum over j ascending of vsum[v][j]
+__global__ void k_out_vsum(BatchArgs a, double *out)
 {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < a.n;
          v += (int64_t)gridDim.x * blockDim.x) {
         double acc = out[v];
         const int W = 1 << a.logW;
-        for (int j = 0; j < W; ++j) {
-            uint64_t live = a.vis[(v << a.logW) + j] & a.valid[j];
-            while (live) {
-                const int l = __ffsll((long long)live) - 1;
-                live &= live - 1;
-                acc += a.dlt[v * a.B + (j << 6) + l];
-            }
-        }
+        for (int j = 0; j < W; ++j) acc += a.vsum[(v << a.logW) + j];
         out[v] = acc;
     }
 }
