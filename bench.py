@@ -28,6 +28,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1608_04472_amd/csrc/kernels.hpp", "paper_1608_04472_amd/csrc/bcmi.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/hbm_traffic.md), or None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        line = line.strip()
+        if not line.startswith("{"):
+            continue
+        rec = json.loads(line)
+        if rec.get("kernel") == kernel and rec.get("workload") == workload and \
+                rec.get("source_hash") == kernel_source_hash():
+            return rec["hbm_bytes_per_launch"]
+    return None
 
 
 def log(*a):
@@ -55,6 +82,7 @@ def main():
     ap.add_argument("--sources", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--schedule", default="auto", choices=["auto", "wave", "pair"])
     ap.add_argument("--bottom-up", type=float, default=0.0)
     ap.add_argument("--per-source", type=int, default=16, help="sources for the per-source leg")
     ap.add_argument("--pair-targets", type=int, default=32)
@@ -62,6 +90,8 @@ def main():
     ap.add_argument("--no-pair", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy a 1 GiB device buffer once before timing (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -82,7 +112,9 @@ def main():
     log("graph %s n=%d nnz=%d built in %.1fs" % (args.graph, g.n, g.nnz, time.time() - t0))
     comp_edges = component_edges(g)
     G = bc.Graph(g.row, g.col)
-    G.configure(bc.BC_SCHED_BATCHED, args.batch, args.bottom_up)
+    sched = {"auto": bc.BC_SCHED_AUTO, "wave": bc.BC_SCHED_BATCHED,
+             "pair": bc.BC_SCHED_THREADED}[args.schedule]
+    G.configure(sched, args.batch, args.bottom_up)
 
     K = args.sources
     srcs = torch.empty(K, dtype=torch.int32, device=dev)
@@ -94,6 +126,15 @@ def main():
         bc.bc_draw_sources(G, args.seed, 0, K, srcs)
         bc.bc_dependencies(G, srcs, bc.BC_OUT_SUM, out)
 
+    if args.calibrate_copy:
+        # a plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # readings give the scale between those counters and bytes moved
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read + 1 GiB written")
     for i in range(args.warmup):
         t = time.time()
         step()
@@ -112,8 +153,8 @@ def main():
     ms = 1e3 * elapsed / args.steps
     gteps = edges_per_step / (elapsed / args.steps) / 1e9
     st = G.stats()
-    log("timed %d steps: %.2f ms/step, %.2f GTEPS, batch %d, levels %d" % (
-        args.steps, ms, gteps, st["batch_width"], st["levels"]))
+    log("timed %d steps: %.2f ms/step, %.2f GTEPS, schedule %d, batch %d, levels %d" % (
+        args.steps, ms, gteps, st["schedule"], st["batch_width"], st["levels"]))
     for k in kern:
         if k["launches"]:
             log("  %-18s %4d launches %9.2f ms  avg %8.1f us  %7.1f GB/s algorithmic" % (
@@ -121,8 +162,9 @@ def main():
                 k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0))
     dom = max(kern, key=lambda k: k["ms"])
     achieved = dom["algo_bytes"] / (dom["ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(dom["name"], "%s-%d-b%d" % (args.graph, K, st["batch_width"]))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["name"],
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["name"],
                 "avg_launch_us": 1e3 * dom["ms"] / dom["launches"],
                 "algo_bytes_per_launch": dom["algo_bytes"] / dom["launches"]}
     sig = next(k for k in kern if k["name"] == "sigma_pull")

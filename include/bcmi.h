@@ -71,11 +71,14 @@ typedef enum {
 /* Batch scheduling (the engine's knobs; results do not depend on them beyond
  * FP64 summation order in BC_OUT_SUM and bc_exact). */
 typedef enum {
-    BC_SCHED_AUTO = 0,     /* batched, batch width and direction switch tuned */
+    BC_SCHED_AUTO = 0,     /* BATCHED, or THREADED when a BFS from a highest-degree
+                              vertex is deeper than 32 levels; batch width auto */
     BC_SCHED_BATCHED = 1,  /* many sources per launch: one wavefront per
                               (vertex, 64-source word), lanes = sources */
-    BC_SCHED_PER_SOURCE = 2 /* one source per launch sequence, one thread per
+    BC_SCHED_PER_SOURCE = 2, /* one source per launch sequence, one thread per
                               frontier vertex: the plain form, for comparison */
+    BC_SCHED_THREADED = 3  /* many sources per launch, one thread per (vertex,
+                              source) pair: for graphs of large diameter */
 } bc_schedule;
 
 typedef struct {
@@ -160,6 +163,8 @@ typedef struct {
     int64_t levels;
     int32_t extended;
     int32_t batch_width;
+    int32_t schedule;      /* bc_schedule that ran (never BC_SCHED_AUTO) */
+    int32_t reserved;
 } bc_stats;
 bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
 

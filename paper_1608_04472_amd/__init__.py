@@ -30,7 +30,7 @@ BC_OK, BC_E_INVALID, BC_E_NOMEM, BC_E_DEVICE, BC_E_UNSUPPORTED = 0, 1, 2, 3, 4
 BC_DONE, BC_CAPPED = 0, 1
 BC_OUT_FULL, BC_OUT_SUM = 0, 1
 BC_PAIR_ALG1, BC_PAIR_EPS = 0, 1
-BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE = 0, 1, 2
+BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED = 0, 1, 2, 3
 
 EXPORTS = [
     "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_configure",
@@ -71,7 +71,8 @@ class _Config(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("samples_executed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("levels", ctypes.c_int64), ("extended", ctypes.c_int32),
-                ("batch_width", ctypes.c_int32)]
+                ("batch_width", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _KProf(ctypes.Structure):

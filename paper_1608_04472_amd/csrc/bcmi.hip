@@ -71,6 +71,12 @@ int grid_waves(int64_t waves)
     return std::min(grid_for(waves * kWave), 16384);
 }
 
+// tiled pull kernels: one workgroup per kTile entries, grid-strided
+int grid_tiles(int64_t entries)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((entries + kTile - 1) / kTile, 32768));
+}
+
 template <class K, class... A>
 void launch(hipStream_t st, int grid, K kernel, A... args)
 {
@@ -100,9 +106,16 @@ struct bc_graph {
     DBuf<double> X, S;
     DBuf<int64_t> K;
     DBuf<uint8_t> st;
+    // pair-per-thread engine (shares sig/dlt/sige/ridx with the wave engine)
+    DBuf<int32_t> lv;
+    DBuf<uint8_t> pactive;
     // per-source plain form
     DBuf<int32_t> ss_d, ss_q;
     DBuf<double> ss_sig, ss_dlt;
+    DBuf<int32_t> probe_src;
+    int32_t hub = 0;          // a highest-degree vertex (depth probe)
+    int32_t engine = -1;      // cached automatic engine choice
+    bool ext_sticky = false;  // an earlier batch on this graph needed extended counts
     unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
     int64_t cap_hint = 0;
     bc_stats stats{};
@@ -126,6 +139,7 @@ struct bc_graph {
         ridx.release(); rmask.release(); ctl.release(); srcs.release(); dest.release();
         X.release(); S.release(); K.release(); st.release();
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release();
+        lv.release(); pactive.release(); probe_src.release();
         if (h_ctl) (void)hipHostFree(h_ctl);
         h_ctl = nullptr;
         prof_dev.release();
@@ -356,7 +370,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
                                const SigmaOut *sigout, OutKind kind)
 {
     const int64_t n = g->n, W = 1ll << p.logW;
-    bool ext = false;
+    bool ext = g->ext_sticky;
     int64_t cap = std::max<int64_t>(g->cap_hint, std::max<int64_t>(4 * n * W, 1 << 16));
     const double bu_frac = bottom_up_fraction(g);
     for (;;) {
@@ -394,10 +408,10 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             }
             if (e2 == e1) break;
             if (ext)
-                launch_hot(g, PROF_SIGMA, grid_waves(e2 - e1), k_sigma_pull<true>, a, e1, e2,
+                launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<true>, a, e1, e2,
                            (const uint64_t *)cur, (const uint64_t *)nxt);
             else
-                launch_hot(g, PROF_SIGMA, grid_waves(e2 - e1), k_sigma_pull<false>, a, e1, e2,
+                launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<false>, a, e1, e2,
                            (const uint64_t *)cur, (const uint64_t *)nxt);
             launch(s, grid_for(nent), k_clear, a, e0, e1, cur);
             off.push_back(e2);
@@ -408,6 +422,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             read_ctl(g);
             if (g->h_ctl[CTL_SIG_OVERFLOW]) {
                 ext = true;
+                g->ext_sticky = true;
                 continue;
             }
         }
@@ -422,10 +437,10 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         for (int level = L - 1; level >= 1; --level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
             if (ext)
-                launch_hot(g, PROF_BACKWARD, grid_waves(e1 - e0), k_backward<true>, a, e0, e1,
+                launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<true>, a, e0, e1,
                            (const uint64_t *)fnext, fown);
             else
-                launch_hot(g, PROF_BACKWARD, grid_waves(e1 - e0), k_backward<false>, a, e0, e1,
+                launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<false>, a, e0, e1,
                            (const uint64_t *)fnext, fown);
             if (level + 1 < L)
                 launch(s, grid_for(off[level + 2] - e1), k_clear, a, e1, off[level + 2], fnext);
@@ -463,7 +478,7 @@ __global__ void k_ss_start(int32_t *d, double *sig, double *dlt, int32_t *queue,
 
 // One source: level-synchronous BFS with one thread per frontier vertex,
 // sigma pull, then the dependency sweep, each level its own launch.
-std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev)
+std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev, bool forward_only = false)
 {
     const int64_t n = g->n;
     hipStream_t s = g->stream;
@@ -484,6 +499,7 @@ std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev)
                (const int32_t *)g->ss_q.p, q1, q2, (int32_t)level, g->ctl.p);
         off.push_back(q2);
     }
+    if (forward_only) return off;
     read_ctl(g);
     if (g->h_ctl[CTL_SIG_OVERFLOW])
         fail(BC_E_UNSUPPORTED, "path counts reach 2^1000: the per-source form has no "
@@ -499,6 +515,151 @@ std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev)
 }
 
 bool per_source_schedule(const bc_graph *g) { return g->cfg.schedule == BC_SCHED_PER_SOURCE; }
+
+// ------------------------------------------------------ engine selection
+
+enum Engine { ENG_WAVE = 0, ENG_PAIR = 1 };
+constexpr int kDeepGraphLevels = 32;
+
+// Wave-per-word batching pays off when a vertex sits at few distinct levels
+// across a batch's sources (small-world graphs); for deep graphs each
+// (vertex, source) is on its own, so pairs get one thread each. The automatic
+// choice probes the BFS depth from a highest-degree vertex once per graph.
+Engine engine_for(bc_graph *g)
+{
+    if (g->cfg.schedule == BC_SCHED_BATCHED) return ENG_WAVE;
+    if (g->cfg.schedule == BC_SCHED_THREADED) return ENG_PAIR;
+    if (g->engine < 0) {
+        g->probe_src.ensure(1);
+        HIPX(hipMemcpy(g->probe_src.p, &g->hub, 4, hipMemcpyHostToDevice));
+        std::vector<int64_t> off = run_single(g, g->probe_src.p, true);
+        const int depth = (int)off.size() - 2;
+        g->engine = depth > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
+        g->stats.levels = 0;
+    }
+    return (Engine)g->engine;
+}
+
+// ------------------------------------------------------ pair-per-thread engine
+
+int plan_pairs(bc_graph *g, int64_t want, int default_cap)
+{
+    int B = g->cfg.batch;
+    if (B == 0) {
+        B = 64;
+        while (B < want && B < default_cap) B *= 2;
+    }
+    while (B > 1 && (int64_t)B * g->n >= (1ll << 32)) B /= 2;
+    // level, count, dependency, exponent, record: 28 bytes per pair
+    const size_t budget = free_device_bytes() / 10 * 7 + g->sig.cap * 8 + g->dlt.cap * 8 +
+                          g->lv.cap * 4 + g->sige.cap * 4 + g->ridx.cap * 4;
+    while (B > 1 && (size_t)g->n * B * 28 > budget) B /= 2;
+    return B;
+}
+
+PairArgs make_pair_args(bc_graph *g, int B, bool ext, int nvalid, bool pair)
+{
+    PairArgs a;
+    a.row = g->row.p;
+    a.col = g->col.p;
+    a.n = (uint32_t)g->n;
+    a.B = B;
+    a.lv = g->lv.p;
+    a.sig = g->sig.p;
+    a.sige = ext ? g->sige.p : nullptr;
+    a.dlt = g->dlt.p;
+    a.rec = g->ridx.p;
+    a.cap = (int64_t)B * g->n;
+    a.ctl = g->ctl.p;
+    a.active = g->pactive.p;
+    a.srcs = g->srcs.p;
+    a.dest = pair ? g->dest.p : nullptr;
+    a.nvalid = nvalid;
+    a.prof = g->prof_on ? g->prof_dev.p : nullptr;
+    return a;
+}
+
+void ensure_pairs(bc_graph *g, int B, bool ext)
+{
+    const size_t np = (size_t)B * g->n;
+    g->lv.ensure(np);
+    g->sig.ensure(np);
+    g->dlt.ensure(np);
+    if (ext) g->sige.ensure(np);
+    g->ridx.ensure(np);
+    g->pactive.ensure((size_t)B);
+    g->srcs.ensure((size_t)B);
+    g->dest.ensure((size_t)B);
+}
+
+struct PairSigmaOut {
+    double *mant = nullptr;
+    int32_t *ex = nullptr;
+    int32_t count = 0;
+    int64_t b0 = 0;
+};
+
+std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *ext_used,
+                               const PairSigmaOut *sigout)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    bool ext = g->ext_sticky;
+    for (;;) {
+        ensure_pairs(g, B, ext);
+        PairArgs a = make_pair_args(g, B, ext, nvalid, pair);
+        HIPX(hipMemsetAsync(g->lv.p, 0xff, (size_t)B * n * 4, s));
+        zero_ctl(g);
+        launch(s, grid_for(B), k_p_init, a);
+        read_ctl(g);
+        std::vector<int64_t> off{0, (int64_t)g->h_ctl[CTL_TAIL]};
+        bool redo = false;
+        for (int level = 0;; ++level) {
+            const int64_t e0 = off[level], e1 = off[level + 1];
+            launch_hot(g, PROF_TOPDOWN, grid_for(e1 - e0), k_p_topdown, a, e0, e1, (int32_t)level);
+            read_ctl(g);
+            const int64_t e2 = (int64_t)g->h_ctl[CTL_TAIL];
+            if (g->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_DEVICE, "pair record overflow");
+            if (!ext && g->h_ctl[CTL_SIG_OVERFLOW]) {
+                redo = true;
+                break;
+            }
+            if (e2 == e1) break;
+            if (ext)
+                launch_hot(g, PROF_SIGMA, grid_for(e2 - e1), k_p_sigma<true>, a, e1, e2,
+                           (int32_t)level);
+            else
+                launch_hot(g, PROF_SIGMA, grid_for(e2 - e1), k_p_sigma<false>, a, e1, e2,
+                           (int32_t)level);
+            off.push_back(e2);
+        }
+        if (!redo && !ext) {
+            read_ctl(g);
+            redo = g->h_ctl[CTL_SIG_OVERFLOW] != 0;
+        }
+        if (redo) {
+            ext = true;
+            g->ext_sticky = true;
+            continue;
+        }
+        if (sigout && (sigout->mant || sigout->ex))
+            launch(s, grid_for(n * sigout->count), k_p_out_sigma, a, sigout->count, sigout->b0,
+                   sigout->mant, sigout->ex);
+        const int L = (int)off.size() - 1;
+        for (int level = L - 1; level >= 1; --level) {
+            if (ext)
+                launch_hot(g, PROF_BACKWARD, grid_for(off[level + 1] - off[level]),
+                           k_p_backward<true>, a, off[level], off[level + 1], (int32_t)level);
+            else
+                launch_hot(g, PROF_BACKWARD, grid_for(off[level + 1] - off[level]),
+                           k_p_backward<false>, a, off[level], off[level + 1], (int32_t)level);
+        }
+        *ext_used = ext;
+        g->stats.levels += L;
+        g->stats.extended |= ext ? 1 : 0;
+        return off;
+    }
+}
 
 // ------------------------------------------------------------ dependencies
 
@@ -533,12 +694,47 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         g->stats.samples_executed = k;
         g->stats.batches = k;
         g->stats.batch_width = 1;
+        g->stats.schedule = BC_SCHED_PER_SOURCE;
         HIPX(hipStreamSynchronize(s));
+        return;
+    }
+
+    if (engine_for(g) == ENG_PAIR) {
+        const int B = plan_pairs(g, k, 512);
+        g->stats.batch_width = B;
+        g->stats.schedule = BC_SCHED_THREADED;
+        for (int64_t b0 = 0; b0 < k; b0 += B) {
+            const int count = (int)std::min<int64_t>(B, k - b0);
+            ensure_pairs(g, B, false);
+            HIPX(hipMemcpyAsync(g->srcs.p, sources + b0, (size_t)count * 4,
+                                hipMemcpyDeviceToDevice, s));
+            if (pair)
+                HIPX(hipMemcpyAsync(g->dest.p, dests + b0, (size_t)count * 4,
+                                    hipMemcpyDeviceToDevice, s));
+            PairSigmaOut so;
+            so.mant = sig_m;
+            so.ex = sig_e;
+            so.count = count;
+            so.b0 = b0;
+            bool ext = false;
+            run_pairs(g, B, count, pair, &ext, &so);
+            PairArgs a = make_pair_args(g, B, ext, count, pair);
+            if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_p_out_sum, a, out);
+            else launch(s, grid_for(n * count), k_p_out_full, a, (int32_t)count, b0, out);
+            if (dist_out)
+                HIPX(hipMemcpyAsync(dist_out + b0 * n, g->lv.p, (size_t)count * n * 4,
+                                    hipMemcpyDeviceToDevice, s));
+            g->stats.batches += 1;
+            g->stats.samples_executed += count;
+        }
+        HIPX(hipStreamSynchronize(s));
+        prof_flush(g);
         return;
     }
 
     const Plan p = plan_batch(g, k, 1024);
     g->stats.batch_width = p.B;
+    g->stats.schedule = BC_SCHED_BATCHED;
     for (int64_t b0 = 0; b0 < k; b0 += p.B) {
         const int count = (int)std::min<int64_t>(p.B, k - b0);
         const OutKind kind = mode == BC_OUT_SUM ? OUT_VSUM : OUT_DELTA;
@@ -578,8 +774,14 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     hipStream_t s = g->stream;
     g->stats = bc_stats{};
     if (T == 0) return;
-    const Plan p = plan_batch(g, k_max, 256);
+    const bool use_pairs = engine_for(g) == ENG_PAIR;
+    Plan p = plan_batch(g, k_max, 256);
+    if (use_pairs) {
+        // the pair engine takes any power-of-two width; keep the sampler's stride
+        p.B = plan_pairs(g, k_max, 256);
+    }
     g->stats.batch_width = p.B;
+    g->stats.schedule = use_pairs ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
     g->X.ensure((size_t)T * p.B);
     g->S.ensure((size_t)T);
     g->K.ensure((size_t)T);
@@ -597,15 +799,23 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     int64_t j0 = 0;
     for (;;) {
         const int nb = (int)std::min<int64_t>(p.B, k_max - j0);
-        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
+        if (use_pairs) ensure_pairs(g, p.B, false);
+        else ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
         if (pair)
             launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->srcs.p, g->dest.p);
         else
             launch(s, grid_for(nb), k_draw_sources, seed, j0, (int64_t)nb, n, g->srcs.p);
         bool ext = false;
-        run_batch(g, p, nb, pair, &ext, nullptr, OUT_DELTA);
-        BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->ridx.cap, OUT_DELTA);
-        launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->X.p);
+        if (use_pairs) {
+            run_pairs(g, p.B, nb, pair, &ext, nullptr);
+            PairArgs a = make_pair_args(g, p.B, ext, nb, pair);
+            launch(s, grid_for((int64_t)T * p.B), k_p_gather_targets, a, targets, T,
+                   (int32_t)p.B, g->X.p);
+        } else {
+            run_batch(g, p, nb, pair, &ext, nullptr, OUT_DELTA);
+            BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->ridx.cap, OUT_DELTA);
+            launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->X.p);
+        }
         launch(s, grid_for(T), k_stop_rule, sa, (const double *)g->X.p, (int32_t)p.B, (int32_t)nb,
                g->ctl.p);
         read_ctl(g);
@@ -678,6 +888,12 @@ bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out)
             HIPX(hipGetDevice(&g->device));
             g->n = csr->n;
             g->nnz = csr->nnz;
+            int64_t best = -1;
+            for (int64_t v = 0; v < csr->n; ++v)
+                if (row[v + 1] - row[v] > best) {
+                    best = row[v + 1] - row[v];
+                    g->hub = (int32_t)v;
+                }
             g->stream = (hipStream_t)hip_stream;
             g->row.ensure(row.size());
             g->col.ensure((size_t)csr->nnz);
@@ -716,7 +932,7 @@ bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg)
 {
     return guarded([&] {
         need(g && cfg, "null argument");
-        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_PER_SOURCE,
+        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_THREADED,
              "unknown schedule");
         const int b = cfg->batch;
         need(b == 0 || (b >= 64 && b <= 4096 && (b & (b - 1)) == 0),

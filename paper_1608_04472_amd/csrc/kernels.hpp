@@ -101,6 +101,16 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
+// add wave-summed unit counts (lane 0 of each wave adds)
+__device__ __forceinline__ void prof_add_raw(unsigned long long *prof, int kernel,
+                                             unsigned long long ua, unsigned long long ub)
+{
+    if ((threadIdx.x & 63) == 0) {
+        if (ua) atomicAdd(&prof[2 * kernel], ua);
+        if (ub) atomicAdd(&prof[2 * kernel + 1], ub);
+    }
+}
+
 // add per-wave unit counts to the profile counters (one atomic pair per wave)
 __device__ __forceinline__ void prof_add(const BatchArgs &a, int kernel, unsigned long long ua,
                                          unsigned long long ub, int lane)
@@ -325,51 +335,246 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// -------------------------------------------------------- forward: sigma pull
+// ------------------------------------------------------ tiled pull kernels
+//
+// A workgroup takes a tile of kTile consecutive record entries and works in
+// three phases, so that only the slab loads remain on each entry's critical
+// path:
+//   1. one thread per entry loads (vertex, word, mask) and the CSR row bounds;
+//   2. all threads walk the tile's concatenated adjacency rows in parallel,
+//      loading each neighbour id and its frontier word for the entry's word,
+//      and stage (neighbour, overlap mask) in LDS;
+//   3. each wavefront takes entries in turn: the overlap masks come from LDS,
+//      the slab values of overlapping neighbours are loaded eight at a time
+//      (lanes = sources) and summed in ascending CSR order.
+// Entries whose row is longer than kHub, or that no longer fit the tile's
+// edge budget, skip staging and gather their neighbours from global memory
+// in phase 3 (same order, same sums).
+constexpr int kTile = 32;
+constexpr int kEdgeCap = 1024;
+constexpr int kHub = 256;
 
-// sigma_s(w) = sum over predecessors u (neighbours one level up, Definition 3)
-// of sigma_s(u), in ascending CSR order. Lanes are sources.
+struct TileLds {
+    int32_t v[kTile];
+    uint32_t j[kTile];
+    uint64_t m[kTile];
+    int64_t beg[kTile];
+    int32_t deg[kTile];
+    int32_t start[kTile];   // first staged edge (entries not staged: start == end)
+    int32_t end[kTile];
+    int32_t staged[kTile];
+    int32_t total;
+    int32_t x[kEdgeCap];
+    uint64_t f[kEdgeCap];
+};
+
+// Sum over staged edges [s0, s1) of the tile (neighbour ids and overlap masks
+// already in LDS).
 template <bool kExt>
-__global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *cur,
-                             const uint64_t *nxt)
+__device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &t, int s0, int s1,
+                                             int b, int lane, double &accp, XNum &accx,
+                                             unsigned long long &units)
 {
-    const int lane = lane_id();
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const uint32_t wmask = (1u << a.logW) - 1u;
-    unsigned long long ua = 0, ub = 0;
-    for (int64_t e = e0 + wave; e < e1; e += nwaves) {
-        const uint32_t idx = a.ridx[e];
-        const int64_t v = idx >> a.logW;
-        const uint32_t j = idx & wmask;
-        const uint64_t m = nxt[idx];
-        const int b = (int)(j << 6) + lane;
-        const bool mine = (m >> lane) & 1ull;
-        XNum acc{0.0, 0};
-        double accp = 0.0;
-        ua += __popcll(m);
-        pull_sum<kExt>(a, v, j, m, cur, lane, accp, acc, ub);
-        if (mine) {
-            const int64_t o = v * a.B + b;
-            if (kExt) {
-                a.sig[o] = acc.m;
-                a.sige[o] = acc.e;
-            } else {
-                a.sig[o] = accp;
-                if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
-            }
-            if (a.dest && a.dest[b] == (int32_t)v)
-                atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
+    for (int base = s0; base < s1; base += kWave) {
+        const int p = base + lane;
+        int32_t x = 0;
+        uint64_t f = 0;
+        if (p < s1) {
+            x = t.x[p];
+            f = t.f[p];
         }
-        if (lane == 0) {
-            a.vis[idx] |= m;
-            a.rmask[e] = m;
+        uint64_t bal = wave_ballot(f != 0);
+        while (bal) {
+            double vm[8];
+            int32_t ve[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                vm[q] = 0.0;
+                ve[q] = 0;
+                if (bal) {
+                    const int k = __ffsll((long long)bal) - 1;
+                    bal &= bal - 1;
+                    const int32_t xk = lane_read_i32(x, k);
+                    const uint64_t fk = lane_read_u64(f, k);
+                    units += __popcll(fk);
+                    if ((fk >> lane) & 1ull) {
+                        const int64_t o = (int64_t)xk * a.B + b;
+                        vm[q] = a.sig[o];
+                        if (kExt) ve[q] = a.sige[o];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
+                else accp += vm[q];
+            }
         }
     }
-    prof_add(a, PROF_SIGMA, ua, ub, lane);
 }
 
-// ------------------------------------------------------------------ backward
+// kBackward = false: sigma pull for the new level (F = previous frontier,
+//   masks from the dense next-level words `nxt`).
+// kBackward = true: dependency sweep (F = next-deeper frontier, masks from the
+//   record; the entry's own mask is scattered into fown).
+template <bool kExt, bool kBackward>
+__device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F,
+                                           const uint64_t *nxt, uint64_t *fown)
+{
+    __shared__ TileLds t;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid >> 6;
+    const int nwv = blockDim.x >> 6;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    unsigned long long ua = 0, ub = 0;
+    for (int64_t tile = e0 + (int64_t)blockIdx.x * kTile; tile < e1;
+         tile += (int64_t)gridDim.x * kTile) {
+        // phase 1: entry headers
+        if (tid < kTile) {
+            const int64_t e = tile + tid;
+            int32_t v = 0, deg = 0;
+            uint32_t j = 0;
+            uint64_t m = 0;
+            int64_t beg = 0;
+            if (e < e1) {
+                const uint32_t idx = a.ridx[e];
+                v = (int32_t)(idx >> a.logW);
+                j = idx & wmask;
+                m = kBackward ? a.rmask[e] : nxt[idx];
+                beg = a.row[v];
+                deg = (int32_t)(a.row[v + 1] - beg);
+            }
+            t.v[tid] = v;
+            t.j[tid] = j;
+            t.m[tid] = m;
+            t.beg[tid] = beg;
+            t.deg[tid] = deg;
+        }
+        __syncthreads();
+        // staging plan (wave 0): inclusive prefix of the stageable degrees
+        if (wv == 0) {
+            const int d = (lane < kTile) ? t.deg[lane] : 0;
+            const int de = d <= kHub ? d : 0;
+            int incl = de;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            const bool fits = incl <= kEdgeCap;
+            // entries past the budget are not staged; the staged set keeps a
+            // monotone layout because the prefix only grows
+            const int endp = fits ? incl : kEdgeCap;
+            const int startp = fits ? incl - de : kEdgeCap;
+            if (lane < kTile) {
+                t.start[lane] = (fits && de == d) ? startp : endp;
+                t.end[lane] = endp;
+                t.staged[lane] = (fits && de == d) ? 1 : 0;
+            }
+            // staged edge count: the largest prefix that fits the budget
+            int maxfit = fits ? incl : 0;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const int y = __shfl_xor(maxfit, off, 64);
+                maxfit = maxfit > y ? maxfit : y;
+            }
+            if (lane == 0) t.total = maxfit;
+        }
+        __syncthreads();
+        // phase 2: stage neighbours and overlap masks
+        const int total = t.total;
+        for (int p = tid; p < total; p += blockDim.x) {
+            // owning entry: the staged entry with start <= p < end
+            int lo = 0, hi = kTile - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (t.end[mid] > p) hi = mid;
+                else lo = mid + 1;
+            }
+            const int i = lo;
+            const int32_t x = a.col[t.beg[i] + (p - t.start[i])];
+            t.x[p] = x;
+            t.f[p] = F[((int64_t)x << a.logW) + t.j[i]] & t.m[i];
+        }
+        __syncthreads();
+        // phase 3: slab sums, one entry per wavefront at a time
+        for (int i = wv; i < kTile; i += nwv) {
+            const int64_t e = tile + i;
+            if (e >= e1) break;
+            const int64_t v = t.v[i];
+            const uint32_t j = t.j[i];
+            const uint64_t m = t.m[i];
+            const int b = (int)(j << 6) + lane;
+            const bool mine = (m >> lane) & 1ull;
+            const int64_t o = v * a.B + b;
+            double own = 0.0;
+            int32_t owne = 0;
+            if (kBackward && mine) {
+                own = a.sig[o];
+                if (kExt) owne = a.sige[o];
+            }
+            XNum acc{0.0, 0};
+            double accp = 0.0;
+            ua += __popcll(m);
+            if (t.staged[i])
+                pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], b, lane, accp, acc, ub);
+            else
+                pull_sum<kExt>(a, v, j, m, F, lane, accp, acc, ub);
+            const uint32_t idx = ((uint32_t)v << a.logW) + j;
+            if (!kBackward) {
+                if (mine) {
+                    if (kExt) {
+                        a.sig[o] = acc.m;
+                        a.sige[o] = acc.e;
+                    } else {
+                        a.sig[o] = accp;
+                        if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
+                    }
+                    if (a.dest && a.dest[b] == (int32_t)v)
+                        atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
+                }
+                if (lane == 0) {
+                    a.vis[idx] |= m;
+                    a.rmask[e] = m;
+                }
+            } else {
+                double d = 0.0;
+                if (mine) {
+                    const double term =
+                        a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
+                    if (kExt) {
+                        // delta = sigma(v) * sum(rho): exponents add back to the plain range
+                        d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
+                        const XNum r = xnorm((term + d) / own, -owne);
+                        a.sig[o] = r.m;
+                        a.sige[o] = r.e;
+                    } else {
+                        d = own * accp;
+                        a.sig[o] = (term + d) / own;
+                    }
+                    if (a.dlt) a.dlt[o] = d;
+                }
+                if (a.vsum) {
+                    const double tsum = wave_sum(d);
+                    if (lane == 0) a.vsum[idx] += tsum;
+                }
+                if (lane == 0) fown[idx] = m;
+            }
+        }
+        __syncthreads();
+    }
+    prof_add(a, kBackward ? PROF_BACKWARD : PROF_SIGMA, ua, ub, lane);
+}
+
+// sigma_s(w) = sum over predecessors u (neighbours one level up, Definition 3)
+// of sigma_s(u), in ascending CSR order.
+template <bool kExt>
+__global__ __launch_bounds__(kBlock) void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1,
+                                                       const uint64_t *cur, const uint64_t *nxt)
+{
+    pull_tiles<kExt, false>(a, e0, e1, cur, nxt, nullptr);
+}
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
 // rho(w), rho(w) = (1 + delta(w)) / sigma(w). Pair mode replaces the 1 by the
@@ -379,50 +584,10 @@ __global__ void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1, const uint64_t
 // (fixed tree order) into vsum[v][j]; each (v, j) appears once per level and
 // levels run in sequence, so the accumulation needs no atomics.
 template <bool kExt>
-__global__ void k_backward(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *fnext,
-                           uint64_t *fown)
+__global__ __launch_bounds__(kBlock) void k_backward(BatchArgs a, int64_t e0, int64_t e1,
+                                                     const uint64_t *fnext, uint64_t *fown)
 {
-    const int lane = lane_id();
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const uint32_t wmask = (1u << a.logW) - 1u;
-    unsigned long long ua = 0, ub = 0;
-    for (int64_t e = e0 + wave; e < e1; e += nwaves) {
-        const uint32_t idx = a.ridx[e];
-        const int64_t v = idx >> a.logW;
-        const uint32_t j = idx & wmask;
-        const uint64_t m = a.rmask[e];
-        const int b = (int)(j << 6) + lane;
-        const bool mine = (m >> lane) & 1ull;
-        XNum acc{0.0, 0};
-        double accp = 0.0;
-        ua += __popcll(m);
-        pull_sum<kExt>(a, v, j, m, fnext, lane, accp, acc, ub);
-        double d = 0.0;
-        if (mine) {
-            const int64_t o = v * a.B + b;
-            const double term = a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
-            if (kExt) {
-                const XNum s{a.sig[o], a.sige[o]};
-                // delta = sigma(v) * sum(rho): exponents add back to the plain range
-                d = acc.m == 0.0 ? 0.0 : ldexp(s.m * acc.m, s.e + acc.e);
-                const XNum r = xnorm((term + d) / s.m, -s.e);
-                a.sig[o] = r.m;
-                a.sige[o] = r.e;
-            } else {
-                const double s = a.sig[o];
-                d = s * accp;
-                a.sig[o] = (term + d) / s;
-            }
-            if (a.dlt) a.dlt[o] = d;
-        }
-        if (a.vsum) {
-            const double t = wave_sum(d);
-            if (lane == 0) a.vsum[idx] += t;
-        }
-        if (lane == 0) fown[idx] = m;
-    }
-    prof_add(a, PROF_BACKWARD, ua, ub, lane);
+    pull_tiles<kExt, true>(a, e0, e1, fnext, nullptr, fown);
 }
 
 // ------------------------------------------------------------------ outputs
@@ -597,6 +762,254 @@ __global__ void k_stop_finish(StopArgs s, double scale, double *est, int64_t *sa
     samples[t] = s.K[t];
     S_out[t] = s.S[t];
     status[t] = s.status[t];
+}
+
+// ------------------------------------------------ pair-per-thread engine
+//
+// For graphs of large diameter the sources of a batch sit at unrelated levels
+// of most vertices, so one lane per (vertex, source) pair replaces one
+// wavefront per (vertex, 64-source word). Arrays are source-major ([B][n]):
+// source b's levels, counts and dependencies are contiguous, so neighbouring
+// vertices of one source share cache lines. The level record holds pair
+// indices o = b*n + v (32-bit), level by level.
+
+struct PairArgs {
+    const int64_t *row;
+    const int32_t *col;
+    uint32_t n;
+    int32_t B;
+    int32_t *lv;         // [B][n] level, -1 = unreached
+    double *sig;         // [B][n] sigma, then rho after the backward pass of its level
+    int32_t *sige;       // [B][n] exponents in extended mode, else null
+    double *dlt;         // [B][n] dependency
+    uint32_t *rec;       // level record of pair indices
+    int64_t cap;
+    unsigned long long *ctl;
+    uint8_t *active;     // [B] pair mode: slot still expanding
+    const int32_t *srcs;
+    const int32_t *dest; // [B] pair destinations, or null
+    int32_t nvalid;
+    unsigned long long *prof;
+};
+
+__device__ __forceinline__ void pair_split(const PairArgs &a, uint32_t o, uint32_t &b, uint32_t &v)
+{
+    b = o / a.n;
+    v = o - b * a.n;
+}
+
+__global__ void k_p_init(PairArgs a)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    bool want = false;
+    uint32_t o = 0;
+    if (b < a.nvalid) {
+        o = (uint32_t)b * a.n + (uint32_t)a.srcs[b];
+        a.lv[o] = 0;
+        a.sig[o] = 1.0;
+        if (a.sige) a.sige[o] = 0;
+        a.dlt[o] = 0.0;
+        a.active[b] = 1;
+        want = true;
+    }
+    const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
+    if (want) {
+        if (pos < a.cap) a.rec[pos] = o;
+        else a.ctl[CTL_REC_OVERFLOW] = 1ull;
+    }
+}
+
+// Top-down discovery: each pair (v, b) of the level claims its unreached
+// neighbours for source b (compare-and-swap on the level word).
+__global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long found = 0;
+    for (int64_t i0 = e0 + blockIdx.x * (int64_t)blockDim.x; i0 < e1; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        uint32_t b = 0, v = 0;
+        int64_t beg = 0;
+        int32_t deg = 0;
+        if (i < e1) {
+            pair_split(a, a.rec[i], b, v);
+            if (!a.dest || a.active[b]) {
+                beg = a.row[v];
+                deg = (int32_t)(a.row[v + 1] - beg);
+            }
+        }
+        for (int k = 0;; ++k) {
+            if (wave_ballot(k < deg) == 0) break;
+            bool want = false;
+            uint32_t ox = 0;
+            if (k < deg) {
+                ox = b * a.n + (uint32_t)a.col[beg + k];
+                if (a.lv[ox] < 0 && atomicCAS(&a.lv[ox], -1, level + 1) == -1) want = true;
+            }
+            found += want ? 1 : 0;
+            const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
+            if (want) {
+                if (pos < a.cap) a.rec[pos] = ox;
+                else a.ctl[CTL_REC_OVERFLOW] = 1ull;
+            }
+        }
+    }
+    if (a.prof) {
+        const unsigned long long t = wave_sum_u64(found);
+        if (lane_id() == 0 && t) atomicAdd(&a.prof[2 * PROF_TOPDOWN], t);
+    }
+}
+
+// sigma for the pairs discovered at level+1: sum over neighbours one level up
+// (ascending CSR order), four neighbour loads in flight.
+template <bool kExt>
+__global__ void k_p_sigma(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+{
+    unsigned long long ua = 0, ub = 0;
+    for (int64_t i = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < e1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t o = a.rec[i];
+        uint32_t b, x;
+        pair_split(a, o, b, x);
+        const uint32_t base = b * a.n;
+        double accp = 0.0;
+        XNum acc{0.0, 0};
+        const int64_t end = a.row[x + 1];
+        for (int64_t e = a.row[x]; e < end; e += 4) {
+            int32_t y[4];
+            bool par[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                y[q] = (e + q < end) ? a.col[e + q] : 0;
+                par[q] = (e + q < end) && a.lv[base + (uint32_t)y[q]] == level;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!par[q]) continue;
+                ++ub;
+                const uint32_t oy = base + (uint32_t)y[q];
+                if (kExt) acc = xadd(acc, XNum{a.sig[oy], a.sige[oy]});
+                else accp += a.sig[oy];
+            }
+        }
+        ++ua;
+        if (kExt) {
+            a.sig[o] = acc.m;
+            a.sige[o] = acc.e;
+        } else {
+            a.sig[o] = accp;
+            if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
+        }
+        if (a.dest && a.dest[b] == (int32_t)x) a.active[b] = 0;
+    }
+    if (a.prof) {
+        const unsigned long long ta = wave_sum_u64(ua), tb = wave_sum_u64(ub);
+        prof_add_raw(a.prof, PROF_SIGMA, ta, tb);
+    }
+}
+
+// Theorem 1 (rho form) for the pairs of one level.
+template <bool kExt>
+__global__ void k_p_backward(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+{
+    unsigned long long ua = 0, ub = 0;
+    for (int64_t i = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < e1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t o = a.rec[i];
+        uint32_t b, v;
+        pair_split(a, o, b, v);
+        const uint32_t base = b * a.n;
+        double accp = 0.0;
+        XNum acc{0.0, 0};
+        const int64_t end = a.row[v + 1];
+        for (int64_t e = a.row[v]; e < end; e += 4) {
+            int32_t w[4];
+            bool suc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w[q] = (e + q < end) ? a.col[e + q] : 0;
+                suc[q] = (e + q < end) && a.lv[base + (uint32_t)w[q]] == level + 1;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!suc[q]) continue;
+                ++ub;
+                const uint32_t ow = base + (uint32_t)w[q];
+                if (kExt) acc = xadd(acc, XNum{a.sig[ow], a.sige[ow]});
+                else accp += a.sig[ow];
+            }
+        }
+        ++ua;
+        const double term = a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
+        double d;
+        if (kExt) {
+            const XNum s{a.sig[o], a.sige[o]};
+            d = acc.m == 0.0 ? 0.0 : ldexp(s.m * acc.m, s.e + acc.e);
+            const XNum r = xnorm((term + d) / s.m, -s.e);
+            a.sig[o] = r.m;
+            a.sige[o] = r.e;
+        } else {
+            const double s = a.sig[o];
+            d = s * accp;
+            a.sig[o] = (term + d) / s;
+        }
+        a.dlt[o] = d;
+    }
+    if (a.prof) {
+        const unsigned long long ta = wave_sum_u64(ua), tb = wave_sum_u64(ub);
+        prof_add_raw(a.prof, PROF_BACKWARD, ta, tb);
+    }
+}
+
+// out[v] += sum over b ascending of the reached pairs' dependencies
+__global__ void k_p_out_sum(PairArgs a, double *out)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < a.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        double acc = out[v];
+        for (int b = 0; b < a.nvalid; ++b) {
+            const uint32_t o = (uint32_t)b * a.n + (uint32_t)v;
+            if (a.lv[o] >= 1) acc += a.dlt[o];
+        }
+        out[v] = acc;
+    }
+}
+
+__global__ void k_p_out_full(PairArgs a, int32_t count, int64_t b0, double *out)
+{
+    const int64_t total = (int64_t)a.n * count;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        out[b0 * a.n + i] = a.lv[i] >= 1 ? a.dlt[i] : 0.0;
+    }
+}
+
+__global__ void k_p_out_sigma(PairArgs a, int32_t count, int64_t b0, double *mant, int32_t *ex)
+{
+    const int64_t total = (int64_t)a.n * count;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const bool r = a.lv[i] >= 0;
+        const XNum x = xnorm(r ? a.sig[i] : 0.0, (r && a.sige) ? a.sige[i] : 0);
+        if (mant) mant[b0 * a.n + i] = x.m;
+        if (ex) ex[b0 * a.n + i] = x.e;
+    }
+}
+
+__global__ void k_p_gather_targets(PairArgs a, const int32_t *targets, int32_t T, int32_t stride,
+                                   double *X)
+{
+    const int64_t total = (int64_t)T * stride;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(i / stride);
+        const int b = (int)(i - (int64_t)t * stride);
+        double x = 0.0;
+        if (b < a.nvalid) {
+            const uint32_t o = (uint32_t)b * a.n + (uint32_t)targets[t];
+            if (a.lv[o] >= 1) x = a.dlt[o];
+        }
+        X[i] = x;
+    }
 }
 
 // -------------------------------------------------- per-source plain form

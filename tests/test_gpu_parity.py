@@ -128,12 +128,18 @@ SMALL = [
 ]
 
 
+SCHEDS = [bc.BC_SCHED_BATCHED, bc.BC_SCHED_THREADED]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
-def test_small_graphs_all_sources(dev, name, make):
+def test_small_graphs_all_sources(dev, name, make, sched):
     g = make()
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     src = np.arange(g.n, dtype=np.int32)
-    check_sources(G, g, src, dev, name)
+    check_sources(G, g, src, dev, name + " sched %d" % sched)
+    assert G.stats()["schedule"] == sched
     out = bc.exact(G).cpu().numpy()
     assert_close(out, O.bc_exact(g), what=name + " bc")
     G.close()
@@ -148,6 +154,45 @@ def test_er2000_batches_and_directions(dev, batch, bottom_up):
     src = gg.philox_sources(1, 200, g.n)          # 200 = several batches + ragged tail
     src[5] = src[77] = src[199] = 3               # repeats in and across batches
     check_sources(G, g, src, dev, "er2000 B=%d bu=%g" % (batch, bottom_up))
+    G.close()
+
+
+@pytest.mark.parametrize("batch", [64, 128])
+def test_er2000_threaded_batches(dev, batch):
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_THREADED, batch, 0.0)
+    src = gg.philox_sources(2, 150, g.n)
+    src[3] = src[140] = 11
+    check_sources(G, g, src, dev, "er2000 threaded B=%d" % batch)
+    G.close()
+
+
+def test_rmat_threaded_sum(dev):
+    g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_THREADED, 128, 0.0)
+    src = np.concatenate([np.flatnonzero(g.degree() == 0)[:2],
+                          gg.philox_sources(8, 200, g.n)]).astype(np.int32)
+    say("rmat12 threaded sum")
+    out, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+    _, want = O.dependencies(g, src, full=False, total=True)
+    assert_close(out.cpu().numpy(), want, what="rmat12 threaded sum")
+    G.close()
+
+
+def test_auto_engine_selection(dev):
+    say("auto engine")
+    g = gg.grid(300, 300)
+    G = bc.Graph(g.row, g.col)
+    src = np.array([0, 4500, 89999], dtype=np.int32)
+    check_sources(G, g, src, dev, "grid300 auto")
+    assert G.stats()["schedule"] == bc.BC_SCHED_THREADED
+    G.close()
+    g = gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    bc.dependencies(G, T(np.array([0, 1999], np.int32), dev), bc.BC_OUT_SUM)
+    assert G.stats()["schedule"] == bc.BC_SCHED_BATCHED
     G.close()
 
 
@@ -194,9 +239,11 @@ def test_grid_counts_beyond_2_53(dev):
     G.close()
 
 
-def test_grid_counts_beyond_fp64_range(dev):
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_grid_counts_beyond_fp64_range(dev, sched):
     g = gg.grid(600, 600)
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     check_sources(G, g, np.array([0, 359999, 180300], dtype=np.int32), dev, "grid600")
     assert G.stats()["extended"] == 1
     G.close()
@@ -260,9 +307,11 @@ def test_invalid_arguments(dev):
 
 # --------------------------------------------------------- pair dependencies
 
-def test_pair_dependencies(dev):
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_pair_dependencies(dev, sched):
     g = gg.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     r = np.random.default_rng(0)
     us = r.integers(0, g.n, 150).astype(np.int32)
     vs = r.integers(0, g.n - 1, 150).astype(np.int32)
@@ -280,9 +329,11 @@ def test_pair_dependencies(dev):
     G.close()
 
 
-def test_pair_dependencies_grid_extended(dev):
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_pair_dependencies_grid_extended(dev, sched):
     g = gg.grid(600, 600)
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     us = np.array([0, 1000, 5], dtype=np.int32)
     vs = np.array([359999, 300000, 359000], dtype=np.int32)
     say("pair deps grid600")
@@ -303,9 +354,11 @@ def check_sampler(got, want, what):
     assert_close(est, oest, what=what + " est")
 
 
-def test_adaptive_source_er2000(dev):
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_adaptive_source_er2000(dev, sched):
     g = gg.config_graph("er2000")
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     targets = gg.top_degree(g, 16)
     say("adaptive source er2000")
     got = bc.adaptive_source(G, T(targets, dev), 5.0, 1, g.n)
@@ -340,9 +393,11 @@ def test_adaptive_source_threshold_tie(dev):
     G.close()
 
 
-def test_adaptive_pair_eps_er2000(dev):
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_adaptive_pair_eps_er2000(dev, sched):
     g = gg.config_graph("er2000")
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     targets = gg.top_degree(g, 16)
     say("adaptive pair eps er2000")
     got = bc.adaptive_pair(G, T(targets, dev), bc.BC_PAIR_EPS, 0.1, 1.0, 1, 1 << 20)
@@ -351,9 +406,11 @@ def test_adaptive_pair_eps_er2000(dev):
     G.close()
 
 
-def test_adaptive_pair_alg1_small(dev):
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_adaptive_pair_alg1_small(dev, sched):
     g = gg.er(150, 0.04, seed=2)
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     targets = gg.top_degree(g, 3)
     say("adaptive pair alg1")
     got = bc.adaptive_pair(G, T(targets, dev), bc.BC_PAIR_ALG1, 0.1, 1.0, 5, 1 << 20)
