@@ -193,6 +193,70 @@ bc_status bc_profile_enable(bc_graph *g, int32_t enable);
 /* Writes up to max entries (one per kernel) to out; *count receives the number. */
 bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int32_t *count);
 
+/* ---------------------------------------------------------------- serving
+ * A query server over device-resident graphs with continuous batching: each
+ * round (bc_server_step) takes one graph and fills the sample slots of one
+ * batch with consecutive samples of the active queries on that graph (source
+ * and pair queries together), newly arrived queries joining as slots free
+ * up. A query's samples come from its own seed and each sample's arithmetic
+ * does not depend on its batch mates, so a query's result is bit-identical
+ * to running it alone, and to bc_adaptive_source / bc_adaptive_pair with T = 1
+ * on the same graph, seed and schedule.
+ * Admission by HBM budget: bc_server_add_graph fails with BC_E_NOMEM when the
+ * graph's CSR would exceed the budget; each graph's batch width is the widest
+ * (<= max_batch) whose engine workspace fits what the resident graphs leave.
+ * The round to run next belongs to the graph of the oldest unfinished query.
+ * Not thread-safe: one host thread drives a server. */
+typedef struct bc_server bc_server;
+
+typedef enum { BC_QUERY_SOURCE = 0, BC_QUERY_PAIR = 1 } bc_query_kind;
+
+typedef struct {
+    int32_t graph;        /* id from bc_server_add_graph */
+    int32_t target;       /* vertex whose BC is estimated */
+    int32_t kind;         /* bc_query_kind */
+    int32_t rule;         /* pair queries: bc_pair_rule */
+    double c;             /* source queries and BC_PAIR_ALG1: c >= 1 */
+    double eps;           /* BC_PAIR_EPS: 0 < eps < 1/2 */
+    uint64_t seed;
+    int64_t k_max;        /* >= 1 */
+    double arrival_s;     /* arrival on the server clock (bc_server_now); < 0 = now */
+} bc_query;
+
+typedef struct {
+    int64_t id;
+    int32_t graph;
+    int32_t status;       /* bc_target_status */
+    double est;
+    int64_t samples;
+    double S;
+    double arrival_s;     /* server clock, seconds */
+    double done_s;
+} bc_result;
+
+bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, void *hip_stream,
+                           bc_server **out);
+void bc_server_destroy(bc_server *s);
+bc_status bc_server_add_graph(bc_server *s, const bc_csr *csr, int32_t *graph_id);
+bc_status bc_server_submit(bc_server *s, const bc_query *q, int64_t *id);
+/* Run one round; *completed receives the number of queries it finished
+ * (0 and no device work when nothing is queued). */
+bc_status bc_server_step(bc_server *s, int32_t *completed);
+/* Move up to max finished results (completion order) into out. */
+bc_status bc_server_poll(bc_server *s, bc_result *out, int32_t max, int32_t *count);
+bc_status bc_server_now(const bc_server *s, double *now_s);
+typedef struct {
+    int64_t queued;           /* submitted, not yet admitted */
+    int64_t active;           /* admitted, still sampling */
+    int64_t finished;         /* results produced so far */
+    int64_t rounds;
+    int64_t samples_executed; /* slots run, including those past a query's stop */
+    int64_t samples_used;     /* samples counted by the stopping rules */
+    int64_t resident_bytes;   /* graphs' device CSR */
+    int64_t workspace_bytes;  /* shared engine workspace */
+} bc_server_stats;
+bc_status bc_server_stats_get(const bc_server *s, bc_server_stats *out);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *bc_last_error(void);
 

@@ -37,7 +37,10 @@ EXPORTS = [
     "bc_graph_info", "bc_exact", "bc_dependencies", "bc_pair_dependencies",
     "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
     "bc_last_stats", "bc_last_error", "bc_profile_enable", "bc_profile_read",
+    "bc_server_create", "bc_server_destroy", "bc_server_add_graph", "bc_server_submit",
+    "bc_server_step", "bc_server_poll", "bc_server_now", "bc_server_stats_get",
 ]
+BC_QUERY_SOURCE, BC_QUERY_PAIR = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -81,6 +84,25 @@ class _KProf(ctypes.Structure):
                 ("units_b", ctypes.c_int64), ("algo_bytes", ctypes.c_double)]
 
 
+class _Query(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("target", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("c", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("k_max", ctypes.c_int64),
+                ("arrival_s", ctypes.c_double)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("graph", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("est", ctypes.c_double), ("samples", ctypes.c_int64), ("S", ctypes.c_double),
+                ("arrival_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("queued", "active", "finished", "rounds",
+                                               "samples_executed", "samples_used",
+                                               "resident_bytes", "workspace_bytes")]
+
+
 _lib = None
 
 
@@ -99,6 +121,8 @@ def load_library(path: str | None = None):
     lib.bc_last_error.argtypes = []
     lib.bc_graph_destroy.restype = None
     lib.bc_graph_destroy.argtypes = [V]
+    lib.bc_server_destroy.restype = None
+    lib.bc_server_destroy.argtypes = [V]
     sigs = {
         "bc_graph_create": [c.POINTER(_Csr), V, c.POINTER(V)],
         "bc_graph_set_stream": [V, V],
@@ -114,6 +138,13 @@ def load_library(path: str | None = None):
         "bc_draw_pairs": [V, c.c_uint64, c.c_int64, c.c_int64, V, V],
         "bc_last_stats": [V, c.POINTER(_Stats)],
         "bc_profile_enable": [V, c.c_int32],
+        "bc_server_create": [c.c_size_t, c.c_int32, V, c.POINTER(V)],
+        "bc_server_add_graph": [V, c.POINTER(_Csr), c.POINTER(c.c_int32)],
+        "bc_server_submit": [V, c.POINTER(_Query), c.POINTER(c.c_int64)],
+        "bc_server_step": [V, c.POINTER(c.c_int32)],
+        "bc_server_poll": [V, c.POINTER(_Result), c.c_int32, c.POINTER(c.c_int32)],
+        "bc_server_now": [V, c.POINTER(c.c_double)],
+        "bc_server_stats_get": [V, c.POINTER(_ServerStats)],
         "bc_profile_read": [V, c.POINTER(_KProf), c.c_int32, c.POINTER(c.c_int32)],
     }
     for name, args in sigs.items():
@@ -199,6 +230,67 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None) is not None:
             _lib.bc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Query server with continuous batching over device-resident graphs."""
+
+    def __init__(self, hbm_budget_bytes, max_batch=256):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.bc_server_create(int(hbm_budget_bytes), int(max_batch), _stream(),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def add_graph(self, row, col) -> int:
+        import numpy as np
+        row = np.ascontiguousarray(row, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        csr = _Csr(row.shape[0] - 1, col.shape[0], row.ctypes.data, 1,
+                   col.ctypes.data if col.shape[0] else None)
+        gid = ctypes.c_int32()
+        _check(_lib.bc_server_add_graph(self._h, ctypes.byref(csr), ctypes.byref(gid)))
+        return gid.value
+
+    def submit(self, graph, target, kind, seed, k_max, c=1.0, eps=0.1, rule=BC_PAIR_EPS,
+               arrival_s=-1.0) -> int:
+        q = _Query(int(graph), int(target), int(kind), int(rule), float(c), float(eps),
+                   int(seed), int(k_max), float(arrival_s))
+        qid = ctypes.c_int64()
+        _check(_lib.bc_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid)))
+        return qid.value
+
+    def step(self) -> int:
+        done = ctypes.c_int32()
+        _check(_lib.bc_server_step(self._h, ctypes.byref(done)))
+        return done.value
+
+    def poll(self, max_results=4096):
+        arr = (_Result * max_results)()
+        cnt = ctypes.c_int32()
+        _check(_lib.bc_server_poll(self._h, arr, max_results, ctypes.byref(cnt)))
+        return [{f: getattr(arr[i], f) for f, _ in _Result._fields_} for i in range(cnt.value)]
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _check(_lib.bc_server_now(self._h, ctypes.byref(t)))
+        return t.value
+
+    def stats(self):
+        st = _ServerStats()
+        _check(_lib.bc_server_stats_get(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.bc_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

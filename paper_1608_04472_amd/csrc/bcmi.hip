@@ -14,7 +14,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <string>
 #include <utility>
@@ -86,14 +88,10 @@ void launch(hipStream_t st, int grid, K kernel, A... args)
 
 }  // namespace
 
-struct bc_graph {
-    int64_t n = 0, nnz = 0;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    DBuf<int64_t> row;
-    DBuf<int32_t> col;
-    bc_config cfg{BC_SCHED_AUTO, 0, 0.0};
-    // batched workspace
+// Device buffers of the engines. A graph owns one; graphs of a server share
+// the server's (rounds on a server run one at a time on one stream).
+struct Work {
+    // wave engine
     DBuf<double> sig, dlt;
     DBuf<int32_t> sige;
     DBuf<uint64_t> vis, F0, F1, active, valid;
@@ -113,12 +111,40 @@ struct bc_graph {
     DBuf<int32_t> ss_d, ss_q;
     DBuf<double> ss_sig, ss_dlt;
     DBuf<int32_t> probe_src;
+    unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
+
+    void init()
+    {
+        ctl.ensure(8);
+        if (!h_ctl) HIPX(hipHostMalloc((void **)&h_ctl, 8 * sizeof(unsigned long long), 0));
+    }
+    void release()
+    {
+        sig.release(); dlt.release(); sige.release();
+        vis.release(); F0.release(); F1.release(); active.release(); valid.release();
+        vsum.release(); ridx.release(); rmask.release(); ctl.release(); srcs.release();
+        dest.release(); X.release(); S.release(); K.release(); st.release();
+        lv.release(); pactive.release();
+        ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release(); probe_src.release();
+        if (h_ctl) (void)hipHostFree(h_ctl);
+        h_ctl = nullptr;
+    }
+};
+
+struct bc_graph {
+    int64_t n = 0, nnz = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DBuf<int64_t> row;
+    DBuf<int32_t> col;
+    bc_config cfg{BC_SCHED_AUTO, 0, 0.0};
+    Work own;
+    Work *w = &own;
+    int64_t cap_hint = 0;
+    bc_stats stats{};
     int32_t hub = 0;          // a highest-degree vertex (depth probe)
     int32_t engine = -1;      // cached automatic engine choice
     bool ext_sticky = false;  // an earlier batch on this graph needed extended counts
-    unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
-    int64_t cap_hint = 0;
-    bc_stats stats{};
     // profiler: event pairs around hot launches, device work-unit counters
     bool prof_on = false;
     DBuf<unsigned long long> prof_dev;
@@ -133,15 +159,8 @@ struct bc_graph {
 
     void release_all()
     {
-        row.release(); col.release(); sig.release(); dlt.release(); sige.release();
-        vis.release(); F0.release(); F1.release(); active.release(); valid.release();
-        vsum.release();
-        ridx.release(); rmask.release(); ctl.release(); srcs.release(); dest.release();
-        X.release(); S.release(); K.release(); st.release();
-        ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release();
-        lv.release(); pactive.release(); probe_src.release();
-        if (h_ctl) (void)hipHostFree(h_ctl);
-        h_ctl = nullptr;
+        row.release(); col.release();
+        own.release();
         prof_dev.release();
         for (auto &p : pending) {
             (void)hipEventDestroy(p.start);
@@ -229,14 +248,14 @@ void launch_hot(bc_graph *g, int kernel, int grid, K fn, A... args)
 
 void read_ctl(bc_graph *g)
 {
-    HIPX(hipMemcpyAsync(g->h_ctl, g->ctl.p, 8 * sizeof(unsigned long long),
+    HIPX(hipMemcpyAsync(g->w->h_ctl, g->w->ctl.p, 8 * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, g->stream));
     HIPX(hipStreamSynchronize(g->stream));
 }
 
 void zero_ctl(bc_graph *g)
 {
-    HIPX(hipMemsetAsync(g->ctl.p, 0, 8 * sizeof(unsigned long long), g->stream));
+    HIPX(hipMemsetAsync(g->w->ctl.p, 0, 8 * sizeof(unsigned long long), g->stream));
 }
 
 // Device-side range check of an index array (sources, targets, pair ends).
@@ -244,9 +263,9 @@ void check_indices(bc_graph *g, const int32_t *x, int64_t count, const char *wha
 {
     if (count <= 0) return;
     zero_ctl(g);
-    launch(g->stream, grid_for(count), k_check_range, x, count, g->n, &g->ctl.p[CTL_REC_OVERFLOW]);
+    launch(g->stream, grid_for(count), k_check_range, x, count, g->n, &g->w->ctl.p[CTL_REC_OVERFLOW]);
     read_ctl(g);
-    if (g->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_INVALID, std::string(what) + " outside [0, n)");
+    if (g->w->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_INVALID, std::string(what) + " outside [0, n)");
 }
 
 // ------------------------------------------------------------ batch planning
@@ -273,8 +292,8 @@ Plan plan_batch(bc_graph *g, int64_t want, int default_cap)
     // (vertex, word) indices are 32-bit
     while (B > 64 && g->n * (int64_t)(B / 64) >= (1ll << 32)) B /= 2;
     // slabs: sig + dlt (+ exponents) per (vertex, source); keep within free memory
-    const size_t budget = free_device_bytes() / 10 * 7 + g->sig.cap * 8 + g->dlt.cap * 8 +
-                          g->sige.cap * 4;
+    const size_t budget = free_device_bytes() / 10 * 7 + g->w->sig.cap * 8 + g->w->dlt.cap * 8 +
+                          g->w->sige.cap * 4;
     while (B > 64 && (size_t)g->n * B * 20 > budget) B /= 2;
     Plan p;
     p.B = B;
@@ -290,19 +309,19 @@ enum OutKind { OUT_DELTA = 0, OUT_VSUM = 1 };
 void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kind)
 {
     const int64_t n = g->n, W = 1ll << p.logW;
-    g->sig.ensure((size_t)(n * p.B));
-    if (kind == OUT_DELTA) g->dlt.ensure((size_t)(n * p.B));
-    else g->vsum.ensure((size_t)(n * W));
-    if (ext) g->sige.ensure((size_t)(n * p.B));
-    g->vis.ensure((size_t)(n * W));
-    g->F0.ensure((size_t)(n * W));
-    g->F1.ensure((size_t)(n * W));
-    g->active.ensure((size_t)W);
-    g->valid.ensure((size_t)W);
-    g->srcs.ensure((size_t)p.B);
-    g->dest.ensure((size_t)p.B);
-    g->ridx.ensure((size_t)cap);
-    g->rmask.ensure((size_t)cap);
+    g->w->sig.ensure((size_t)(n * p.B));
+    if (kind == OUT_DELTA) g->w->dlt.ensure((size_t)(n * p.B));
+    else g->w->vsum.ensure((size_t)(n * W));
+    if (ext) g->w->sige.ensure((size_t)(n * p.B));
+    g->w->vis.ensure((size_t)(n * W));
+    g->w->F0.ensure((size_t)(n * W));
+    g->w->F1.ensure((size_t)(n * W));
+    g->w->active.ensure((size_t)W);
+    g->w->valid.ensure((size_t)W);
+    g->w->srcs.ensure((size_t)p.B);
+    g->w->dest.ensure((size_t)p.B);
+    g->w->ridx.ensure((size_t)cap);
+    g->w->rmask.ensure((size_t)cap);
 }
 
 __global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32_t nvalid)
@@ -325,20 +344,20 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     a.n = g->n;
     a.logW = p.logW;
     a.B = p.B;
-    a.sig = g->sig.p;
-    a.sige = ext ? g->sige.p : nullptr;
-    a.dlt = kind == OUT_DELTA ? g->dlt.p : nullptr;
-    a.vsum = kind == OUT_VSUM ? g->vsum.p : nullptr;
+    a.sig = g->w->sig.p;
+    a.sige = ext ? g->w->sige.p : nullptr;
+    a.dlt = kind == OUT_DELTA ? g->w->dlt.p : nullptr;
+    a.vsum = kind == OUT_VSUM ? g->w->vsum.p : nullptr;
     a.prof = g->prof_on ? g->prof_dev.p : nullptr;
-    a.vis = g->vis.p;
-    a.ridx = g->ridx.p;
-    a.rmask = g->rmask.p;
+    a.vis = g->w->vis.p;
+    a.ridx = g->w->ridx.p;
+    a.rmask = g->w->rmask.p;
     a.cap = cap;
-    a.ctl = g->ctl.p;
-    a.active = g->active.p;
-    a.valid = g->valid.p;
-    a.srcs = g->srcs.p;
-    a.dest = pair ? g->dest.p : nullptr;
+    a.ctl = g->w->ctl.p;
+    a.active = g->w->active.p;
+    a.valid = g->w->valid.p;
+    a.srcs = g->w->srcs.p;
+    a.dest = pair ? g->w->dest.p : nullptr;
     a.nvalid = nvalid;
     return a;
 }
@@ -363,7 +382,7 @@ double bottom_up_fraction(const bc_graph *g)
 }
 
 // Forward + backward for the nvalid sources (pair mode: u in srcs, v in
-// dest) already placed in g->srcs / g->dest. Returns the level offsets and
+// dest) already placed in g->w->srcs / g->w->dest. Returns the level offsets and
 // sets *ext_used. Grows the record and switches to extended path counts as
 // needed, redoing the batch.
 std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair, bool *ext_used,
@@ -377,19 +396,19 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         ensure_batch(g, p, ext, cap, kind);
         BatchArgs a = make_args(g, p, ext, nvalid, pair, cap, kind);
         hipStream_t s = g->stream;
-        HIPX(hipMemsetAsync(g->vis.p, 0, (size_t)(n * W) * 8, s));
-        if (kind == OUT_VSUM) HIPX(hipMemsetAsync(g->vsum.p, 0, (size_t)(n * W) * 8, s));
-        HIPX(hipMemsetAsync(g->F0.p, 0, (size_t)(n * W) * 8, s));
-        HIPX(hipMemsetAsync(g->F1.p, 0, (size_t)(n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->w->vis.p, 0, (size_t)(n * W) * 8, s));
+        if (kind == OUT_VSUM) HIPX(hipMemsetAsync(g->w->vsum.p, 0, (size_t)(n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->w->F0.p, 0, (size_t)(n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->w->F1.p, 0, (size_t)(n * W) * 8, s));
         zero_ctl(g);
-        launch(s, 1, k_lane_masks, g->valid.p, g->active.p, (int32_t)W, nvalid);
-        launch(s, grid_for(p.B), k_init_sources, a, g->F0.p);
+        launch(s, 1, k_lane_masks, g->w->valid.p, g->w->active.p, (int32_t)W, nvalid);
+        launch(s, grid_for(p.B), k_init_sources, a, g->w->F0.p);
         read_ctl(g);
-        std::vector<int64_t> off{0, (int64_t)g->h_ctl[CTL_TAIL]};
-        if (g->h_ctl[CTL_REC_OVERFLOW]) { cap *= 2; continue; }
-        launch(s, grid_for(off[1]), k_fill_masks, a, (int64_t)0, off[1], (const uint64_t *)g->F0.p);
+        std::vector<int64_t> off{0, (int64_t)g->w->h_ctl[CTL_TAIL]};
+        if (g->w->h_ctl[CTL_REC_OVERFLOW]) { cap *= 2; continue; }
+        launch(s, grid_for(off[1]), k_fill_masks, a, (int64_t)0, off[1], (const uint64_t *)g->w->F0.p);
 
-        uint64_t *cur = g->F0.p, *nxt = g->F1.p;
+        uint64_t *cur = g->w->F0.p, *nxt = g->w->F1.p;
         bool redo = false;
         for (int level = 0;; ++level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
@@ -400,8 +419,8 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             else
                 launch_hot(g, PROF_TOPDOWN, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
             read_ctl(g);
-            const int64_t e2 = (int64_t)g->h_ctl[CTL_TAIL];
-            if (g->h_ctl[CTL_REC_OVERFLOW]) {
+            const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
+            if (g->w->h_ctl[CTL_REC_OVERFLOW]) {
                 cap = std::max<int64_t>(cap * 2, e2 + (e2 >> 2));
                 redo = true;
                 break;
@@ -420,7 +439,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         if (redo) continue;
         if (!ext) {
             read_ctl(g);
-            if (g->h_ctl[CTL_SIG_OVERFLOW]) {
+            if (g->w->h_ctl[CTL_SIG_OVERFLOW]) {
                 ext = true;
                 g->ext_sticky = true;
                 continue;
@@ -457,10 +476,10 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
 
 void ensure_single(bc_graph *g)
 {
-    g->ss_d.ensure((size_t)g->n);
-    g->ss_q.ensure((size_t)g->n);
-    g->ss_sig.ensure((size_t)g->n);
-    g->ss_dlt.ensure((size_t)g->n);
+    g->w->ss_d.ensure((size_t)g->n);
+    g->w->ss_q.ensure((size_t)g->n);
+    g->w->ss_sig.ensure((size_t)g->n);
+    g->w->ss_dlt.ensure((size_t)g->n);
 }
 
 __global__ void k_ss_start(int32_t *d, double *sig, double *dlt, int32_t *queue,
@@ -483,32 +502,32 @@ std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev, bool forwar
     const int64_t n = g->n;
     hipStream_t s = g->stream;
     ensure_single(g);
-    HIPX(hipMemsetAsync(g->ss_d.p, 0xff, (size_t)n * 4, s));
+    HIPX(hipMemsetAsync(g->w->ss_d.p, 0xff, (size_t)n * 4, s));
     zero_ctl(g);
-    launch(s, 1, k_ss_start, g->ss_d.p, g->ss_sig.p, g->ss_dlt.p, g->ss_q.p, src_dev, g->ctl.p);
+    launch(s, 1, k_ss_start, g->w->ss_d.p, g->w->ss_sig.p, g->w->ss_dlt.p, g->w->ss_q.p, src_dev, g->w->ctl.p);
     std::vector<int64_t> off{0, 1};
     for (int level = 0;; ++level) {
         const int64_t q0 = off[level], q1 = off[level + 1];
         launch(s, grid_for(q1 - q0), k_ss_topdown, (const int64_t *)g->row.p,
-               (const int32_t *)g->col.p, g->ss_d.p, g->ss_q.p, q0, q1, (int32_t)level, g->ctl.p);
+               (const int32_t *)g->col.p, g->w->ss_d.p, g->w->ss_q.p, q0, q1, (int32_t)level, g->w->ctl.p);
         read_ctl(g);
-        const int64_t q2 = (int64_t)g->h_ctl[CTL_TAIL];
+        const int64_t q2 = (int64_t)g->w->h_ctl[CTL_TAIL];
         if (q2 == q1) break;
         launch(s, grid_for(q2 - q1), k_ss_sigma, (const int64_t *)g->row.p,
-               (const int32_t *)g->col.p, (const int32_t *)g->ss_d.p, g->ss_sig.p,
-               (const int32_t *)g->ss_q.p, q1, q2, (int32_t)level, g->ctl.p);
+               (const int32_t *)g->col.p, (const int32_t *)g->w->ss_d.p, g->w->ss_sig.p,
+               (const int32_t *)g->w->ss_q.p, q1, q2, (int32_t)level, g->w->ctl.p);
         off.push_back(q2);
     }
     if (forward_only) return off;
     read_ctl(g);
-    if (g->h_ctl[CTL_SIG_OVERFLOW])
+    if (g->w->h_ctl[CTL_SIG_OVERFLOW])
         fail(BC_E_UNSUPPORTED, "path counts reach 2^1000: the per-source form has no "
                                "extended counts; use the batched schedule");
     const int L = (int)off.size() - 1;
     for (int level = L - 1; level >= 1; --level)
         launch(s, grid_for(off[level + 1] - off[level]), k_ss_backward, (const int64_t *)g->row.p,
-               (const int32_t *)g->col.p, (const int32_t *)g->ss_d.p,
-               (const double *)g->ss_sig.p, g->ss_dlt.p, (const int32_t *)g->ss_q.p, off[level],
+               (const int32_t *)g->col.p, (const int32_t *)g->w->ss_d.p,
+               (const double *)g->w->ss_sig.p, g->w->ss_dlt.p, (const int32_t *)g->w->ss_q.p, off[level],
                off[level + 1], (int32_t)level);
     g->stats.levels += L;
     return off;
@@ -530,9 +549,9 @@ Engine engine_for(bc_graph *g)
     if (g->cfg.schedule == BC_SCHED_BATCHED) return ENG_WAVE;
     if (g->cfg.schedule == BC_SCHED_THREADED) return ENG_PAIR;
     if (g->engine < 0) {
-        g->probe_src.ensure(1);
-        HIPX(hipMemcpy(g->probe_src.p, &g->hub, 4, hipMemcpyHostToDevice));
-        std::vector<int64_t> off = run_single(g, g->probe_src.p, true);
+        g->w->probe_src.ensure(1);
+        HIPX(hipMemcpy(g->w->probe_src.p, &g->hub, 4, hipMemcpyHostToDevice));
+        std::vector<int64_t> off = run_single(g, g->w->probe_src.p, true);
         const int depth = (int)off.size() - 2;
         g->engine = depth > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
         g->stats.levels = 0;
@@ -551,8 +570,8 @@ int plan_pairs(bc_graph *g, int64_t want, int default_cap)
     }
     while (B > 1 && (int64_t)B * g->n >= (1ll << 32)) B /= 2;
     // level, count, dependency, exponent, record: 28 bytes per pair
-    const size_t budget = free_device_bytes() / 10 * 7 + g->sig.cap * 8 + g->dlt.cap * 8 +
-                          g->lv.cap * 4 + g->sige.cap * 4 + g->ridx.cap * 4;
+    const size_t budget = free_device_bytes() / 10 * 7 + g->w->sig.cap * 8 + g->w->dlt.cap * 8 +
+                          g->w->lv.cap * 4 + g->w->sige.cap * 4 + g->w->ridx.cap * 4;
     while (B > 1 && (size_t)g->n * B * 28 > budget) B /= 2;
     return B;
 }
@@ -564,16 +583,16 @@ PairArgs make_pair_args(bc_graph *g, int B, bool ext, int nvalid, bool pair)
     a.col = g->col.p;
     a.n = (uint32_t)g->n;
     a.B = B;
-    a.lv = g->lv.p;
-    a.sig = g->sig.p;
-    a.sige = ext ? g->sige.p : nullptr;
-    a.dlt = g->dlt.p;
-    a.rec = g->ridx.p;
+    a.lv = g->w->lv.p;
+    a.sig = g->w->sig.p;
+    a.sige = ext ? g->w->sige.p : nullptr;
+    a.dlt = g->w->dlt.p;
+    a.rec = g->w->ridx.p;
     a.cap = (int64_t)B * g->n;
-    a.ctl = g->ctl.p;
-    a.active = g->pactive.p;
-    a.srcs = g->srcs.p;
-    a.dest = pair ? g->dest.p : nullptr;
+    a.ctl = g->w->ctl.p;
+    a.active = g->w->pactive.p;
+    a.srcs = g->w->srcs.p;
+    a.dest = pair ? g->w->dest.p : nullptr;
     a.nvalid = nvalid;
     a.prof = g->prof_on ? g->prof_dev.p : nullptr;
     return a;
@@ -582,14 +601,14 @@ PairArgs make_pair_args(bc_graph *g, int B, bool ext, int nvalid, bool pair)
 void ensure_pairs(bc_graph *g, int B, bool ext)
 {
     const size_t np = (size_t)B * g->n;
-    g->lv.ensure(np);
-    g->sig.ensure(np);
-    g->dlt.ensure(np);
-    if (ext) g->sige.ensure(np);
-    g->ridx.ensure(np);
-    g->pactive.ensure((size_t)B);
-    g->srcs.ensure((size_t)B);
-    g->dest.ensure((size_t)B);
+    g->w->lv.ensure(np);
+    g->w->sig.ensure(np);
+    g->w->dlt.ensure(np);
+    if (ext) g->w->sige.ensure(np);
+    g->w->ridx.ensure(np);
+    g->w->pactive.ensure((size_t)B);
+    g->w->srcs.ensure((size_t)B);
+    g->w->dest.ensure((size_t)B);
 }
 
 struct PairSigmaOut {
@@ -608,19 +627,19 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
     for (;;) {
         ensure_pairs(g, B, ext);
         PairArgs a = make_pair_args(g, B, ext, nvalid, pair);
-        HIPX(hipMemsetAsync(g->lv.p, 0xff, (size_t)B * n * 4, s));
+        HIPX(hipMemsetAsync(g->w->lv.p, 0xff, (size_t)B * n * 4, s));
         zero_ctl(g);
         launch(s, grid_for(B), k_p_init, a);
         read_ctl(g);
-        std::vector<int64_t> off{0, (int64_t)g->h_ctl[CTL_TAIL]};
+        std::vector<int64_t> off{0, (int64_t)g->w->h_ctl[CTL_TAIL]};
         bool redo = false;
         for (int level = 0;; ++level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
             launch_hot(g, PROF_TOPDOWN, grid_for(e1 - e0), k_p_topdown, a, e0, e1, (int32_t)level);
             read_ctl(g);
-            const int64_t e2 = (int64_t)g->h_ctl[CTL_TAIL];
-            if (g->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_DEVICE, "pair record overflow");
-            if (!ext && g->h_ctl[CTL_SIG_OVERFLOW]) {
+            const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
+            if (g->w->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_DEVICE, "pair record overflow");
+            if (!ext && g->w->h_ctl[CTL_SIG_OVERFLOW]) {
                 redo = true;
                 break;
             }
@@ -635,7 +654,7 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
         }
         if (!redo && !ext) {
             read_ctl(g);
-            redo = g->h_ctl[CTL_SIG_OVERFLOW] != 0;
+            redo = g->w->h_ctl[CTL_SIG_OVERFLOW] != 0;
         }
         if (redo) {
             ext = true;
@@ -682,13 +701,13 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         for (int64_t i = 0; i < k; ++i) {
             std::vector<int64_t> off = run_single(g, sources + i);
             if (mode == BC_OUT_SUM)
-                launch(s, grid_for(off.back() - 1), k_ss_out_sum, (const double *)g->ss_dlt.p,
-                       (const int32_t *)g->ss_q.p, (int64_t)1, off.back(), out);
+                launch(s, grid_for(off.back() - 1), k_ss_out_sum, (const double *)g->w->ss_dlt.p,
+                       (const int32_t *)g->w->ss_q.p, (int64_t)1, off.back(), out);
             else
-                launch(s, grid_for(n), k_ss_out_full, (const int32_t *)g->ss_d.p,
-                       (const double *)g->ss_dlt.p, n, out + i * n);
+                launch(s, grid_for(n), k_ss_out_full, (const int32_t *)g->w->ss_d.p,
+                       (const double *)g->w->ss_dlt.p, n, out + i * n);
             if (dist_out)
-                HIPX(hipMemcpyAsync(dist_out + i * n, g->ss_d.p, (size_t)n * 4,
+                HIPX(hipMemcpyAsync(dist_out + i * n, g->w->ss_d.p, (size_t)n * 4,
                                     hipMemcpyDeviceToDevice, s));
         }
         g->stats.samples_executed = k;
@@ -706,10 +725,10 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         for (int64_t b0 = 0; b0 < k; b0 += B) {
             const int count = (int)std::min<int64_t>(B, k - b0);
             ensure_pairs(g, B, false);
-            HIPX(hipMemcpyAsync(g->srcs.p, sources + b0, (size_t)count * 4,
+            HIPX(hipMemcpyAsync(g->w->srcs.p, sources + b0, (size_t)count * 4,
                                 hipMemcpyDeviceToDevice, s));
             if (pair)
-                HIPX(hipMemcpyAsync(g->dest.p, dests + b0, (size_t)count * 4,
+                HIPX(hipMemcpyAsync(g->w->dest.p, dests + b0, (size_t)count * 4,
                                     hipMemcpyDeviceToDevice, s));
             PairSigmaOut so;
             so.mant = sig_m;
@@ -722,7 +741,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
             if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_p_out_sum, a, out);
             else launch(s, grid_for(n * count), k_p_out_full, a, (int32_t)count, b0, out);
             if (dist_out)
-                HIPX(hipMemcpyAsync(dist_out + b0 * n, g->lv.p, (size_t)count * n * 4,
+                HIPX(hipMemcpyAsync(dist_out + b0 * n, g->w->lv.p, (size_t)count * n * 4,
                                     hipMemcpyDeviceToDevice, s));
             g->stats.batches += 1;
             g->stats.samples_executed += count;
@@ -739,9 +758,9 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         const int count = (int)std::min<int64_t>(p.B, k - b0);
         const OutKind kind = mode == BC_OUT_SUM ? OUT_VSUM : OUT_DELTA;
         ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), kind);
-        HIPX(hipMemcpyAsync(g->srcs.p, sources + b0, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
+        HIPX(hipMemcpyAsync(g->w->srcs.p, sources + b0, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
         if (pair)
-            HIPX(hipMemcpyAsync(g->dest.p, dests + b0, (size_t)count * 4,
+            HIPX(hipMemcpyAsync(g->w->dest.p, dests + b0, (size_t)count * 4,
                                 hipMemcpyDeviceToDevice, s));
         SigmaOut so;
         so.mant = sig_m;
@@ -750,7 +769,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         so.b0 = b0;
         bool ext = false;
         std::vector<int64_t> off = run_batch(g, p, count, pair, &ext, &so, kind);
-        BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->ridx.cap, kind);
+        BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->w->ridx.cap, kind);
         if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_vsum, a, out);
         else launch(s, grid_for(n * count), k_out_full, a, (int32_t)count, b0, out);
         if (dist_out)
@@ -782,19 +801,19 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     }
     g->stats.batch_width = p.B;
     g->stats.schedule = use_pairs ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
-    g->X.ensure((size_t)T * p.B);
-    g->S.ensure((size_t)T);
-    g->K.ensure((size_t)T);
-    g->st.ensure((size_t)T);
+    g->w->X.ensure((size_t)T * p.B);
+    g->w->S.ensure((size_t)T);
+    g->w->K.ensure((size_t)T);
+    g->w->st.ensure((size_t)T);
     StopArgs sa;
     sa.T = T;
     sa.rule = rule;
     sa.threshold = c * (double)n;
     sa.eps_rhs = ((eps * eps) * eps) * ((double)n * (double)n);
     sa.k_max = k_max;
-    sa.S = g->S.p;
-    sa.K = g->K.p;
-    sa.status = g->st.p;
+    sa.S = g->w->S.p;
+    sa.K = g->w->K.p;
+    sa.status = g->w->st.p;
     launch(s, grid_for(T), k_stop_init, sa);
     int64_t j0 = 0;
     for (;;) {
@@ -802,26 +821,26 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
         if (use_pairs) ensure_pairs(g, p.B, false);
         else ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
         if (pair)
-            launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->srcs.p, g->dest.p);
+            launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->w->srcs.p, g->w->dest.p);
         else
-            launch(s, grid_for(nb), k_draw_sources, seed, j0, (int64_t)nb, n, g->srcs.p);
+            launch(s, grid_for(nb), k_draw_sources, seed, j0, (int64_t)nb, n, g->w->srcs.p);
         bool ext = false;
         if (use_pairs) {
             run_pairs(g, p.B, nb, pair, &ext, nullptr);
             PairArgs a = make_pair_args(g, p.B, ext, nb, pair);
             launch(s, grid_for((int64_t)T * p.B), k_p_gather_targets, a, targets, T,
-                   (int32_t)p.B, g->X.p);
+                   (int32_t)p.B, g->w->X.p);
         } else {
             run_batch(g, p, nb, pair, &ext, nullptr, OUT_DELTA);
-            BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->ridx.cap, OUT_DELTA);
-            launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->X.p);
+            BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->w->ridx.cap, OUT_DELTA);
+            launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->w->X.p);
         }
-        launch(s, grid_for(T), k_stop_rule, sa, (const double *)g->X.p, (int32_t)p.B, (int32_t)nb,
-               g->ctl.p);
+        launch(s, grid_for(T), k_stop_rule, sa, (const double *)g->w->X.p, (int32_t)p.B, (int32_t)nb,
+               g->w->ctl.p);
         read_ctl(g);
         j0 += nb;
         g->stats.batches += 1;
-        if (g->h_ctl[CTL_RUNNING] == 0) break;
+        if (g->w->h_ctl[CTL_RUNNING] == 0) break;
         if (j0 >= k_max) fail(BC_E_DEVICE, "stop rule left targets running at k_max");
     }
     g->stats.samples_executed = j0;
@@ -897,8 +916,7 @@ bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out)
             g->stream = (hipStream_t)hip_stream;
             g->row.ensure(row.size());
             g->col.ensure((size_t)csr->nnz);
-            g->ctl.ensure(8);
-            HIPX(hipHostMalloc((void **)&g->h_ctl, 8 * sizeof(unsigned long long), 0));
+            g->own.init();
             HIPX(hipMemcpy(g->row.p, row.data(), row.size() * 8, hipMemcpyHostToDevice));
             if (csr->nnz)
                 HIPX(hipMemcpy(g->col.p, csr->col, (size_t)csr->nnz * 4, hipMemcpyHostToDevice));
@@ -1133,6 +1151,340 @@ bc_status bc_draw_pairs(bc_graph *g, uint64_t seed, int64_t j0, int64_t count, i
         if (count == 0) return;
         launch(g->stream, grid_for(count), k_draw_pairs, seed, j0, count, g->n, out_u, out_v);
         HIPX(hipStreamSynchronize(g->stream));
+    });
+}
+
+}  // extern "C"
+
+// ================================================================= serving
+
+namespace {
+
+struct ServerQuery {
+    int64_t id = 0;
+    bc_query q{};
+    double S = 0.0;
+    int64_t K = 0;
+    double arrival = 0.0;
+};
+
+}  // namespace
+
+struct bc_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    size_t resident = 0;
+    int max_batch = 256;
+    Work work;
+    std::vector<bc_graph *> graphs;
+    std::vector<int> width;            // batch width per graph
+    std::deque<ServerQuery> queued;    // arrival order
+    std::vector<std::vector<ServerQuery>> active;
+    std::deque<bc_result> done;
+    int64_t next_id = 0, finished = 0, rounds = 0, samples_exec = 0, samples_used = 0;
+    DBuf<QueryDesc> qd;
+    DBuf<int32_t> slotq, tgt;
+    DBuf<double> X;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    size_t workspace_bytes() const
+    {
+        const Work &w = work;
+        return w.sig.cap * 8 + w.dlt.cap * 8 + w.sige.cap * 4 + w.vis.cap * 8 + w.F0.cap * 8 +
+               w.F1.cap * 8 + w.vsum.cap * 8 + w.ridx.cap * 4 + w.rmask.cap * 8 + w.lv.cap * 4 +
+               qd.cap * sizeof(QueryDesc) + slotq.cap * 4 + tgt.cap * 4 + X.cap * 8;
+    }
+    void release()
+    {
+        for (auto g : graphs) bc_graph_destroy(g);
+        graphs.clear();
+        work.release();
+        qd.release();
+        slotq.release();
+        tgt.release();
+        X.release();
+    }
+};
+
+namespace {
+
+// Device bytes an engine needs for a batch of width B on n vertices.
+size_t engine_bytes(Engine e, int64_t n, int B)
+{
+    const size_t W = (size_t)std::max(1, B / 64);
+    if (e == ENG_PAIR) return (size_t)n * B * 28;
+    // slabs (count, dependency, exponent), bitmaps and sums, a record of ~4 entries
+    // per (vertex, word)
+    return (size_t)n * B * 20 + (size_t)n * W * 8 * 5 + (size_t)n * W * 4 * 12;
+}
+
+void server_round(bc_server *sv, int gi, int32_t *completed)
+{
+    bc_graph *g = sv->graphs[gi];
+    std::vector<ServerQuery> &act = sv->active[gi];
+    const int B = sv->width[gi];
+    // admit waiting queries of this graph in arrival order while slots remain
+    for (auto it = sv->queued.begin(); it != sv->queued.end() && (int)act.size() < B;) {
+        if (it->q.graph == gi) {
+            act.push_back(*it);
+            it = sv->queued.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    const int A = (int)act.size();
+    const int64_t n = g->n;
+    std::vector<QueryDesc> hd((size_t)A);
+    std::vector<int32_t> hslot;
+    hslot.reserve((size_t)B);
+    const int base = B / A, extra = B % A;
+    for (int i = 0; i < A; ++i) {
+        const ServerQuery &sq = act[(size_t)i];
+        const bool pairq = sq.q.kind == BC_QUERY_PAIR;
+        QueryDesc &d = hd[(size_t)i];
+        std::memset(&d, 0, sizeof(d));
+        d.seed = sq.q.seed;
+        d.j0 = sq.K;
+        d.k_max = sq.q.k_max;
+        d.threshold = sq.q.c * (double)n;
+        d.eps_rhs = ((sq.q.eps * sq.q.eps) * sq.q.eps) * ((double)n * (double)n);
+        d.scale = pairq ? (double)n * (double)(n - 1) : (double)n;
+        d.S = sq.S;
+        d.K = sq.K;
+        d.target = sq.q.target;
+        d.rule = !pairq ? RULE_SOURCE : (sq.q.rule == BC_PAIR_EPS ? RULE_PAIR_EPS : RULE_PAIR_ALG1);
+        d.slot0 = (int32_t)hslot.size();
+        const int64_t need = sq.q.k_max - sq.K;
+        d.nslots = (int32_t)std::min<int64_t>(need, base + (i < extra ? 1 : 0));
+        d.status = ST_RUNNING;
+        for (int k = 0; k < d.nslots; ++k) hslot.push_back(i);
+    }
+    const int nb = (int)hslot.size();
+    hipStream_t st = sv->stream;
+    g->stream = st;
+    sv->qd.ensure((size_t)A);
+    sv->slotq.ensure((size_t)B);
+    sv->tgt.ensure((size_t)B);
+    sv->X.ensure((size_t)B);
+    HIPX(hipMemcpyAsync(sv->qd.p, hd.data(), hd.size() * sizeof(QueryDesc),
+                        hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(sv->slotq.p, hslot.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st));
+    const Engine e = engine_for(g);
+    bool ext = false;
+    if (e == ENG_PAIR) {
+        ensure_pairs(g, B, false);
+        launch(st, grid_for(nb), k_serve_draw, (const QueryDesc *)sv->qd.p,
+               (const int32_t *)sv->slotq.p, (int32_t)nb, n, g->w->srcs.p, g->w->dest.p,
+               sv->tgt.p);
+        run_pairs(g, B, nb, true, &ext, nullptr);
+        PairArgs a = make_pair_args(g, B, ext, nb, true);
+        launch(st, grid_for(nb), k_p_gather_slots, a, (const int32_t *)sv->tgt.p, sv->X.p);
+    } else {
+        Plan p;
+        p.B = B;
+        while ((64 << p.logW) < B) ++p.logW;
+        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
+        launch(st, grid_for(nb), k_serve_draw, (const QueryDesc *)sv->qd.p,
+               (const int32_t *)sv->slotq.p, (int32_t)nb, n, g->w->srcs.p, g->w->dest.p,
+               sv->tgt.p);
+        run_batch(g, p, nb, true, &ext, nullptr, OUT_DELTA);
+        BatchArgs a = make_args(g, p, ext, nb, true, (int64_t)g->w->ridx.cap, OUT_DELTA);
+        launch(st, grid_for(nb), k_gather_slots, a, (const int32_t *)sv->tgt.p, sv->X.p);
+    }
+    launch(st, grid_for(A), k_stop_queries, sv->qd.p, (int32_t)A, (const double *)sv->X.p);
+    HIPX(hipMemcpyAsync(hd.data(), sv->qd.p, hd.size() * sizeof(QueryDesc),
+                        hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
+    const double t = sv->now();
+    int fin = 0;
+    std::vector<ServerQuery> keep;
+    keep.reserve(act.size());
+    for (int i = 0; i < A; ++i) {
+        ServerQuery sq = act[(size_t)i];
+        const QueryDesc &d = hd[(size_t)i];
+        sv->samples_used += d.K - sq.K;
+        sq.S = d.S;
+        sq.K = d.K;
+        if (d.status == ST_RUNNING) {
+            keep.push_back(sq);
+            continue;
+        }
+        bc_result r;
+        r.id = sq.id;
+        r.graph = gi;
+        r.status = d.status;
+        r.est = d.est;
+        r.samples = d.K;
+        r.S = d.S;
+        r.arrival_s = sq.arrival;
+        r.done_s = t;
+        sv->done.push_back(r);
+        ++fin;
+    }
+    act.swap(keep);
+    sv->finished += fin;
+    sv->rounds += 1;
+    sv->samples_exec += nb;
+    *completed = fin;
+}
+
+}  // namespace
+
+extern "C" {
+
+bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, void *hip_stream,
+                           bc_server **out)
+{
+    return guarded([&] {
+        need(out != nullptr, "null argument");
+        need(max_batch >= 64 && max_batch <= 4096 && (max_batch & (max_batch - 1)) == 0,
+             "max_batch must be a power of two in [64, 4096]");
+        need(hbm_budget_bytes > 0, "budget must be positive");
+        bc_server *sv = new bc_server();
+        try {
+            HIPX(hipGetDevice(&sv->device));
+            sv->stream = (hipStream_t)hip_stream;
+            sv->budget = hbm_budget_bytes;
+            sv->max_batch = max_batch;
+            sv->work.init();
+        } catch (...) {
+            sv->release();
+            delete sv;
+            throw;
+        }
+        *out = sv;
+    });
+}
+
+void bc_server_destroy(bc_server *sv)
+{
+    if (!sv) return;
+    (void)hipSetDevice(sv->device);
+    if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    sv->release();
+    delete sv;
+}
+
+bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_id)
+{
+    return guarded([&] {
+        need(sv && csr && graph_id, "null argument");
+        HIPX(hipSetDevice(sv->device));
+        const size_t csr_bytes = (size_t)(csr->n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4;
+        if (sv->resident + csr_bytes > sv->budget)
+            fail(BC_E_NOMEM, "graph does not fit the server's HBM budget");
+        bc_graph *g = nullptr;
+        const bc_status rc = bc_graph_create(csr, (void *)sv->stream, &g);
+        if (rc != BC_OK) fail(rc, tl_error);
+        g->w = &sv->work;
+        try {
+            const Engine e = engine_for(g);
+            const size_t room = sv->budget - sv->resident - csr_bytes;
+            int B = sv->max_batch;
+            while (B > 64 && engine_bytes(e, g->n, B) > room) B /= 2;
+            if (engine_bytes(e, g->n, B) > room)
+                fail(BC_E_NOMEM, "no batch width fits the server's HBM budget for this graph");
+            sv->graphs.push_back(g);
+            sv->width.push_back(B);
+            sv->active.emplace_back();
+            sv->resident += csr_bytes;
+        } catch (...) {
+            g->w = &g->own;
+            bc_graph_destroy(g);
+            throw;
+        }
+        *graph_id = (int32_t)sv->graphs.size() - 1;
+    });
+}
+
+bc_status bc_server_submit(bc_server *sv, const bc_query *q, int64_t *id)
+{
+    return guarded([&] {
+        need(sv && q && id, "null argument");
+        need(q->graph >= 0 && q->graph < (int32_t)sv->graphs.size(), "unknown graph id");
+        const bc_graph *g = sv->graphs[(size_t)q->graph];
+        need(q->target >= 0 && q->target < g->n, "target outside [0, n)");
+        need(q->kind == BC_QUERY_SOURCE || q->kind == BC_QUERY_PAIR, "unknown query kind");
+        need(q->k_max >= 1, "k_max must be >= 1");
+        if (q->kind == BC_QUERY_SOURCE) {
+            need(q->c >= 1.0, "c must be >= 1 (and not NaN)");
+        } else {
+            need(g->n >= 2, "pairs need n >= 2");
+            need(q->rule == BC_PAIR_ALG1 || q->rule == BC_PAIR_EPS, "unknown rule");
+            if (q->rule == BC_PAIR_ALG1) need(q->c >= 1.0, "c must be >= 1 (and not NaN)");
+            else need(q->eps > 0.0 && q->eps < 0.5, "eps must be in (0, 1/2)");
+        }
+        ServerQuery sq;
+        sq.id = sv->next_id++;
+        sq.q = *q;
+        sq.arrival = q->arrival_s >= 0.0 ? q->arrival_s : sv->now();
+        sv->queued.push_back(sq);
+        *id = sq.id;
+    });
+}
+
+bc_status bc_server_step(bc_server *sv, int32_t *completed)
+{
+    return guarded([&] {
+        need(sv && completed, "null argument");
+        HIPX(hipSetDevice(sv->device));
+        *completed = 0;
+        // the graph of the oldest unfinished query runs next
+        int gi = -1;
+        double oldest = 0.0;
+        for (size_t i = 0; i < sv->active.size(); ++i)
+            for (const auto &q : sv->active[i])
+                if (gi < 0 || q.arrival < oldest) {
+                    gi = (int)i;
+                    oldest = q.arrival;
+                }
+        if (!sv->queued.empty() && (gi < 0 || sv->queued.front().arrival < oldest))
+            gi = sv->queued.front().q.graph;
+        if (gi < 0) return;
+        server_round(sv, gi, completed);
+    });
+}
+
+bc_status bc_server_poll(bc_server *sv, bc_result *out, int32_t max, int32_t *count)
+{
+    return guarded([&] {
+        need(sv && count && (max <= 0 || out), "null argument");
+        int32_t c = 0;
+        while (c < max && !sv->done.empty()) {
+            out[c++] = sv->done.front();
+            sv->done.pop_front();
+        }
+        *count = c;
+    });
+}
+
+bc_status bc_server_now(const bc_server *sv, double *now_s)
+{
+    return guarded([&] {
+        need(sv && now_s, "null argument");
+        *now_s = sv->now();
+    });
+}
+
+bc_status bc_server_stats_get(const bc_server *sv, bc_server_stats *out)
+{
+    return guarded([&] {
+        need(sv && out, "null argument");
+        int64_t act = 0;
+        for (const auto &a : sv->active) act += (int64_t)a.size();
+        out->queued = (int64_t)sv->queued.size();
+        out->active = act;
+        out->finished = sv->finished;
+        out->rounds = sv->rounds;
+        out->samples_executed = sv->samples_exec;
+        out->samples_used = sv->samples_used;
+        out->resident_bytes = (int64_t)sv->resident;
+        out->workspace_bytes = (int64_t)sv->workspace_bytes();
     });
 }
 

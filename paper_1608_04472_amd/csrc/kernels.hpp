@@ -541,8 +541,9 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             } else {
                 double d = 0.0;
                 if (mine) {
-                    const double term =
-                        a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
+                    // a slot without a destination (< 0) is a source sample
+                    const double term = (a.dest && a.dest[b] >= 0)
+                                            ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
                     if (kExt) {
                         // delta = sigma(v) * sum(rho): exponents add back to the plain range
                         d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
@@ -718,8 +719,24 @@ struct StopArgs {
     uint8_t *status;
 };
 
+// One sample of the sequential loop: add, count, then test (the crossing
+// sample counts). Source sampling and the literal Algorithm 1 repeat while
+// S <= c*n; the epsilon rule stops at S > 0 and k*S^2 >= eps^3 n^2.
+__device__ __forceinline__ void stop_step(double &S, int64_t &k, uint8_t &st, double x,
+                                          int32_t rule, double threshold, double eps_rhs,
+                                          int64_t k_max)
+{
+    S = S + x;
+    k = k + 1;
+    bool stop;
+    if (rule == RULE_PAIR_EPS) stop = (S > 0.0) && (((double)k * (S * S)) >= eps_rhs);
+    else stop = S > threshold;
+    if (stop) st = ST_DONE;
+    else if (k == k_max) st = ST_CAPPED;
+}
+
 // One lane per target walks the round's samples in draw order, exactly as the
-// sequential loop would: add, count, then test (the crossing sample counts).
+// sequential loop would.
 __global__ void k_stop_rule(StopArgs s, const double *X, int32_t B, int32_t nb,
                             unsigned long long *ctl)
 {
@@ -728,15 +745,8 @@ __global__ void k_stop_rule(StopArgs s, const double *X, int32_t B, int32_t nb,
     double S = s.S[t];
     int64_t k = s.K[t];
     uint8_t st = s.status[t];
-    for (int b = 0; b < nb && st == ST_RUNNING; ++b) {
-        S = S + X[(int64_t)t * B + b];
-        k = k + 1;
-        bool stop;
-        if (s.rule == RULE_PAIR_EPS) stop = (S > 0.0) && (((double)k * (S * S)) >= s.eps_rhs);
-        else stop = S > s.threshold;
-        if (stop) st = ST_DONE;
-        else if (k == s.k_max) st = ST_CAPPED;
-    }
+    for (int b = 0; b < nb && st == ST_RUNNING; ++b)
+        stop_step(S, k, st, X[(int64_t)t * B + b], s.rule, s.threshold, s.eps_rhs, s.k_max);
     s.S[t] = S;
     s.K[t] = k;
     s.status[t] = st;
@@ -939,7 +949,8 @@ __global__ void k_p_backward(PairArgs a, int64_t e0, int64_t e1, int32_t level)
             }
         }
         ++ua;
-        const double term = a.dest ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
+        const double term =
+            (a.dest && a.dest[b] >= 0) ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
         double d;
         if (kExt) {
             const XNum s{a.sig[o], a.sige[o]};
@@ -1010,6 +1021,88 @@ __global__ void k_p_gather_targets(PairArgs a, const int32_t *targets, int32_t T
         }
         X[i] = x;
     }
+}
+
+// ---------------------------------------------------------------- serving
+//
+// A serving round fills the B sample slots of one batch with consecutive
+// samples of several queries on the same graph: query q owns slots
+// [slot0, slot0 + nslots) and draws its samples j0, j0 + 1, ... from its own
+// stream. Source and pair samples share the batch (a slot's destination is
+// -1 for a source sample). Each slot's value is taken at its own query's
+// target, and one lane per query then runs that query's stopping rule over
+// its slots in draw order.
+
+struct QueryDesc {
+    uint64_t seed;
+    int64_t j0;
+    int64_t k_max;
+    double threshold;
+    double eps_rhs;
+    double scale;       // n (sources) or n(n-1) (pairs)
+    double S;
+    int64_t K;
+    double est;
+    int32_t target;
+    int32_t rule;       // RULE_SOURCE, RULE_PAIR_ALG1, RULE_PAIR_EPS
+    int32_t slot0;
+    int32_t nslots;
+    int32_t status;
+    int32_t pad;
+};
+
+__global__ void k_serve_draw(const QueryDesc *q, const int32_t *slot_query, int32_t nb,
+                             int64_t n, int32_t *srcs, int32_t *dest, int32_t *tgt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const QueryDesc &d = q[slot_query[b]];
+    const int64_t j = d.j0 + (b - d.slot0);
+    if (d.rule == RULE_SOURCE) {
+        const Block4 r = philox4x64_10((uint64_t)j, 0, 0, 0, d.seed, 0);
+        srcs[b] = (int32_t)scale_to_range(r.w[0], (uint64_t)n);
+        dest[b] = -1;
+    } else {
+        const Block4 r = philox4x64_10((uint64_t)j, 0, 0, 0, d.seed, 1);
+        const int64_t u = scale_to_range(r.w[0], (uint64_t)n);
+        int64_t v = scale_to_range(r.w[1], (uint64_t)(n - 1));
+        v += (v >= u) ? 1 : 0;
+        srcs[b] = (int32_t)u;
+        dest[b] = (int32_t)v;
+    }
+    tgt[b] = d.target;
+}
+
+__global__ void k_gather_slots(BatchArgs a, const int32_t *tgt, double *X)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nvalid) return;
+    const int64_t v = tgt[b];
+    X[b] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
+}
+
+__global__ void k_p_gather_slots(PairArgs a, const int32_t *tgt, double *X)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nvalid) return;
+    const uint32_t o = (uint32_t)b * a.n + (uint32_t)tgt[b];
+    X[b] = a.lv[o] >= 1 ? a.dlt[o] : 0.0;
+}
+
+__global__ void k_stop_queries(QueryDesc *q, int32_t nq, const double *X)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    QueryDesc d = q[i];
+    double S = d.S;
+    int64_t k = d.K;
+    uint8_t st = (uint8_t)d.status;
+    for (int b = d.slot0; b < d.slot0 + d.nslots && st == ST_RUNNING; ++b)
+        stop_step(S, k, st, X[b], d.rule, d.threshold, d.eps_rhs, d.k_max);
+    q[i].S = S;
+    q[i].K = k;
+    q[i].status = st;
+    q[i].est = st == ST_RUNNING ? 0.0 : (d.scale * S) / (double)k;
 }
 
 // -------------------------------------------------- per-source plain form

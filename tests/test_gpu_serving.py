@@ -1,0 +1,176 @@
+"""GPU tests of the query server (continuous batching over resident graphs).
+
+A query's result must be bit-identical whether it runs alone or mixed with
+other queries (on the same and on other graphs), and identical to the
+single-target sampler calls with the same seed; sampled checks against the
+oracle pin the values themselves.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1608_04472_amd as bc  # noqa: E402
+
+O = oracle.load()
+GIB = 1 << 30
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+GRAPHS = [("er300", lambda: gg.er(300, 0.02, seed=5)),
+          ("rmat10", lambda: gg.rmat(10, 8, 0.57, 0.19, 0.19, seed=2)),
+          ("grid30", lambda: gg.grid(30, 30))]      # deep: served by the pair-per-thread engine
+
+
+def make_queries(graphs):
+    """(graph index, target, kind, rule, c, eps, seed, k_max) mixes."""
+    qs = []
+    r = np.random.default_rng(4)
+    for gi, g in enumerate(graphs):
+        tops = gg.top_degree(g, 3)
+        for t in tops:
+            qs.append((gi, int(t), bc.BC_QUERY_SOURCE, 0, float(r.choice([2.0, 5.0])), 0.1,
+                       int(r.integers(1, 1 << 40)), g.n))
+            qs.append((gi, int(t), bc.BC_QUERY_PAIR, bc.BC_PAIR_EPS, 1.0,
+                       float(r.choice([0.1, 0.2])), int(r.integers(1, 1 << 40)), 1 << 16))
+    leaf = int(np.flatnonzero(graphs[0].degree() == 1)[0])
+    qs.append((0, leaf, bc.BC_QUERY_SOURCE, 0, 1.0, 0.1, 99, 50))   # capped at k_max
+    qs.append((0, leaf, bc.BC_QUERY_PAIR, bc.BC_PAIR_ALG1, 1.0, 0.1, 98, 70))
+    return qs
+
+
+def new_server(graphs, budget=8 * GIB, max_batch=128):
+    S = bc.Server(budget, max_batch)
+    ids = [S.add_graph(g.row, g.col) for g in graphs]
+    assert ids == list(range(len(graphs)))
+    return S
+
+
+def run(S, qs):
+    ids = [S.submit(gi, t, kind, seed, kmax, c=c, eps=eps, rule=rule)
+           for gi, t, kind, rule, c, eps, seed, kmax in qs]
+    out = {}
+    steps = 0
+    while len(out) < len(qs):
+        S.step()
+        steps += 1
+        assert steps < 100000
+        for r in S.poll():
+            out[r["id"]] = r
+    return [out[i] for i in ids]
+
+
+def key(r):
+    return (r["est"], r["samples"], r["S"], r["status"])
+
+
+def test_mixed_equals_alone_equals_sampler(dev):
+    graphs = [m() for _, m in GRAPHS]
+    qs = make_queries(graphs)
+    say("serving mixed", len(qs))
+    S = new_server(graphs)
+    mixed = run(S, qs)
+    st = S.stats()
+    assert st["finished"] == len(qs) and st["queued"] == 0 and st["active"] == 0
+    assert st["samples_used"] == sum(r["samples"] for r in mixed)
+    S.close()
+    for i, q in enumerate(qs):
+        say("serving alone", i)
+        A = new_server(graphs)
+        alone = run(A, [q])[0]
+        A.close()
+        assert key(alone) == key(mixed[i]), (i, q, alone, mixed[i])
+    # the same queries through the single-target sampler calls
+    for i, (gi, t, kind, rule, c, eps, seed, kmax) in enumerate(qs):
+        g = graphs[gi]
+        G = bc.Graph(g.row, g.col)
+        tt = torch.tensor([t], dtype=torch.int32, device=dev)
+        if kind == bc.BC_QUERY_SOURCE:
+            est, k, Sx, stt = bc.adaptive_source(G, tt, c, seed, kmax)
+        else:
+            est, k, Sx, stt = bc.adaptive_pair(G, tt, rule, eps, c, seed, kmax)
+        G.close()
+        assert (est.item(), k.item(), Sx.item(), stt.item()) == key(mixed[i]), (i, q)
+
+
+def test_serving_against_oracle(dev):
+    g = gg.er(300, 0.02, seed=5)
+    S = new_server([g])
+    tops = gg.top_degree(g, 2)
+    qs = [(0, int(tops[0]), bc.BC_QUERY_SOURCE, 0, 3.0, 0.1, 17, g.n),
+          (0, int(tops[1]), bc.BC_QUERY_PAIR, bc.BC_PAIR_EPS, 1.0, 0.15, 23, 1 << 16)]
+    say("serving oracle")
+    res = run(S, qs)
+    S.close()
+    oe, ok, oS, ost = O.adaptive_source(g, [tops[0]], 3.0, 17, g.n)
+    assert res[0]["samples"] == ok[0] and res[0]["status"] == ost[0]
+    assert abs(res[0]["est"] - oe[0]) <= 1e-9 * oe[0]
+    oe, ok, oS, ost = O.adaptive_pair(g, [tops[1]], oracle.RULE_EPS, 0.15, 1.0, 23, 1 << 16)
+    assert res[1]["samples"] == ok[0] and res[1]["status"] == ost[0]
+    assert abs(res[1]["est"] - oe[0]) <= 1e-9 * oe[0]
+
+
+def test_continuous_admission_and_latency_fields(dev):
+    graphs = [gg.er(300, 0.02, seed=5), gg.rmat(10, 8, 0.57, 0.19, 0.19, seed=2)]
+    S = new_server(graphs, max_batch=64)
+    say("serving continuous")
+    t0 = S.now()
+    first = [S.submit(0, int(gg.top_degree(graphs[0], 1)[0]), bc.BC_QUERY_PAIR, 7 + i, 1 << 16,
+                      eps=0.1, rule=bc.BC_PAIR_EPS) for i in range(3)]
+    S.step()
+    # arrivals while the first queries are active join later rounds
+    later = [S.submit(i % 2, int(gg.top_degree(graphs[i % 2], 2)[1]), bc.BC_QUERY_SOURCE,
+                      50 + i, 5000, c=2.0) for i in range(6)]
+    got = {}
+    while len(got) < 9:
+        S.step()
+        for r in S.poll():
+            got[r["id"]] = r
+    for i in first + later:
+        r = got[i]
+        assert r["done_s"] >= r["arrival_s"] >= t0
+    st = S.stats()
+    assert st["rounds"] >= 2 and st["samples_executed"] >= st["samples_used"]
+    S.close()
+
+
+def test_budget_admission(dev):
+    g = gg.er(2000, 0.004, seed=1)
+    say("serving budget")
+    S = bc.Server(1 << 12, 64)             # 4 KiB: the CSR itself does not fit
+    with pytest.raises(bc.BcError) as e:
+        S.add_graph(g.row, g.col)
+    assert e.value.status == bc.BC_E_NOMEM
+    S.close()
+    S = bc.Server(200 << 10, 64)           # CSR fits, no engine workspace does
+    with pytest.raises(bc.BcError) as e:
+        S.add_graph(g.row, g.col)
+    assert e.value.status == bc.BC_E_NOMEM
+    S.close()
+    S = bc.Server(8 * GIB, 64)
+    gid = S.add_graph(g.row, g.col)
+    with pytest.raises(bc.BcError):
+        S.submit(gid + 1, 0, bc.BC_QUERY_SOURCE, 1, 10, c=2.0)
+    with pytest.raises(bc.BcError):
+        S.submit(gid, 2000, bc.BC_QUERY_SOURCE, 1, 10, c=2.0)
+    with pytest.raises(bc.BcError):
+        S.submit(gid, 0, bc.BC_QUERY_PAIR, 1, 10, eps=0.7, rule=bc.BC_PAIR_EPS)
+    assert S.step() == 0                   # nothing queued: no device work
+    S.close()
