@@ -73,6 +73,76 @@ def component_edges(g):
     return per_comp[lab]
 
 
+def serving_leg(args, bc, gg):
+    """200 resident R-MAT graphs (scales 10-18, edge factors 8-32), a Poisson
+    stream of queries (graph uniform, target degree-weighted, half source
+    queries with c in {2, 5, 10}, half pair queries with eps in {0.05, 0.1}),
+    served with continuous batching; latency = result time - arrival time."""
+    import numpy as np
+    t = time.time()
+    graphs = gg.serving_graphs(args.serve_graphs)
+    qs = gg.serving_queries(graphs, args.serve_queries, args.serve_rate)
+    for q in qs:
+        q["k_max"] = args.serve_kmax_pair if q["kind"] == 1 else args.serve_kmax_source
+    log("serving: %d graphs (%d CSR entries) and %d queries generated in %.1fs" % (
+        len(graphs), sum(g.nnz for g in graphs), len(qs), time.time() - t))
+    S = bc.Server(args.serve_budget_gib << 30, 256)
+    for g in graphs:
+        S.add_graph(g.row, g.col)
+    N = len(qs)
+    results = {}
+    i = 0
+    t0 = S.now()
+    last_log = time.time()
+    while len(results) < N:
+        now = S.now() - t0
+        while i < N and qs[i]["arrival"] <= now:
+            q = qs[i]
+            S.submit(q["graph"], q["target"], q["kind"], q["seed"], q["k_max"], c=q["c"],
+                     eps=q["eps"], rule=bc.BC_PAIR_EPS, arrival_s=t0 + q["arrival"])
+            i += 1
+        S.step()
+        for r in S.poll():
+            results[r["id"]] = r
+        st = S.stats()
+        if st["queued"] + st["active"] == 0 and i < N:
+            time.sleep(max(0.0, min(0.002, qs[i]["arrival"] - (S.now() - t0))))
+        if time.time() - last_log > 10:
+            last_log = time.time()
+            log("serving: %d/%d done, %d queued, %d active, %.1fs" % (
+                len(results), N, st["queued"], st["active"], S.now() - t0))
+    st = S.stats()
+    res = [results[k] for k in sorted(results)]
+    lat = np.array([(r["done_s"] - r["arrival_s"]) * 1e3 for r in res])
+    makespan = max(r["done_s"] for r in res) - t0
+    edges = sum(r["samples"] * graphs[q["graph"]].m_undirected for r, q in zip(res, qs))
+    out = {
+        "workload": "%d R-MAT graphs (scale 10-18, edge factor 8-32, seeds 100-%d), %d queries "
+                    "at %.0f q/s Poisson (seed 3), half source (c 2/5/10), half pair "
+                    "(eps 0.05/0.1)" % (len(graphs), 99 + len(graphs), N, args.serve_rate),
+        "queries": N, "arrival_rate_qps": args.serve_rate,
+        "achieved_qps": N / makespan, "makespan_s": makespan,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "max_ms": float(lat.max()), "rounds": st["rounds"],
+        "samples_executed": st["samples_executed"], "samples_used": st["samples_used"],
+        "batch_fill": st["samples_executed"] / max(1, 256 * st["rounds"]),
+        "capped": int(sum(r["status"] == bc.BC_CAPPED for r in res)),
+        "used_sample_gteps_full_search_equiv": edges / makespan / 1e9,
+        "resident_bytes": st["resident_bytes"], "workspace_bytes": st["workspace_bytes"],
+    }
+    if args.serve_dump:
+        with open(args.serve_dump, "w") as f:
+            for r, q in zip(res, qs):
+                g = graphs[q["graph"]]
+                f.write(json.dumps(dict(q, n=g.n, m=g.m_undirected, samples=r["samples"],
+                                        status=r["status"],
+                                        latency_ms=(r["done_s"] - r["arrival_s"]) * 1e3)) + "\n")
+    S.close()
+    log("serving: p50 %.1f ms, p99 %.1f ms, %.1f q/s achieved over %.1f s, %d rounds" % (
+        out["p50_ms"], out["p99_ms"], out["achieved_qps"], makespan, st["rounds"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +160,16 @@ def main():
     ap.add_argument("--no-pair", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-graphs", type=int, default=200)
+    ap.add_argument("--serve-queries", type=int, default=200,
+                    help="prefix of the 20,000-query stream to serve (the whole stream "
+                         "exceeds one GPU's capacity)")
+    ap.add_argument("--serve-rate", type=float, default=500.0)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-dump", default="", help="write per-query results (JSON lines)")
+    ap.add_argument("--serve-kmax-source", type=int, default=1024)
+    ap.add_argument("--serve-kmax-pair", type=int, default=4096)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy a 1 GiB device buffer once before timing (counter calibration)")
     args = ap.parse_args()
@@ -222,6 +302,11 @@ def main():
         log("pair leg: %.1f ms, %d pairs executed (%.0f pairs/s)" % (
             pair["ms"], pair["samples_executed"], pair["pairs_per_s"]))
 
+    # ------------------------------------------------------------ serving
+    serving = None
+    if not args.no_serve and args.serve_queries > 0:
+        serving = serving_leg(args, bc, gg)
+
     # ------------------------------------------------------- cpu baseline
     cpu = None
     if not args.no_cpu:
@@ -249,7 +334,8 @@ def main():
                    "graph": args.graph, "n": g.n, "nnz": g.nnz, "sources": K,
                    "batch": st["batch_width"], "parallelism": "single GPU"},
         "per_source": per_source, "pair_leg": pair, "roofline": roofline, "cpu_baseline": cpu,
-        "step_model": step_model,
+        "step_model": step_model, "serving": serving,
+        "p99_query_ms": serving["p99_ms"] if serving else None,
         "kernels": [{"name": k["name"], "launches": k["launches"], "ms": k["ms"] / args.steps,
                      "algo_GBs": k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] else 0.0}
                     for k in kern],

@@ -35,7 +35,7 @@ def build_native(force: bool = False) -> str:
     """Compile gen.c into libgraphgen.so (gcc, -O2)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=c11",
+        subprocess.check_call(["gcc", "-O3", "-shared", "-fPIC", "-std=c11",
                                os.path.join(_HERE, "gen.c"), "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -49,6 +49,10 @@ def _native():
         lib.graphgen_ba.restype = ctypes.c_int64
         lib.graphgen_ba.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                     ctypes.c_void_p, ctypes.c_void_p]
+        lib.graphgen_rmat.restype = ctypes.c_int64
+        lib.graphgen_rmat.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                      ctypes.c_void_p, ctypes.c_void_p]
         lib.graphgen_csr.restype = ctypes.c_int64
         lib.graphgen_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -169,18 +173,17 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) 
     """R-MAT (Chakrabarti et al. 2004): edge_factor * 2^scale generated edges,
     quadrant probabilities a, b, c, d = 1-a-b-c at every bit, no noise, no
     relabelling; symmetrised, self-loops and duplicates dropped, isolated
-    vertices kept (n = 2^scale)."""
-    r = rng(seed, STREAM_GRAPH)
+    vertices kept (n = 2^scale). Drawn in C from a SplitMix64 stream keyed by
+    (seed, graph stream)."""
     n = 1 << scale
     ne = edge_factor * n
-    src = np.zeros(ne, dtype=np.int64)
-    dst = np.zeros(ne, dtype=np.int64)
-    for bit in range(scale):
-        u = r.random(ne)
-        down = u >= a + b            # quadrants c or d set the row bit
-        right = ((u >= a) & (u < a + b)) | (u >= a + b + c)
-        src |= down.astype(np.int64) << bit
-        dst |= right.astype(np.int64) << bit
+    src = np.zeros(ne, dtype=np.int32)
+    dst = np.zeros(ne, dtype=np.int32)
+    key = (int(seed) * 0x100000001B3 + STREAM_GRAPH) & ((1 << 64) - 1)
+    got = _native().graphgen_rmat(scale, edge_factor, a, b, c, key, src.ctypes.data,
+                                  dst.ctypes.data)
+    if got != ne:
+        raise RuntimeError("graphgen_rmat failed")
     return from_edges(n, src, dst, "rmat%d_%d" % (scale, edge_factor))
 
 
@@ -243,6 +246,50 @@ def degree_percentile_targets(g: CSR, k: int, min_degree: int = 2) -> np.ndarray
     order = cand[np.lexsort((cand, deg[cand]))]
     pos = ((np.arange(k) + 0.5) / k * order.shape[0]).astype(np.int64)
     return order[np.minimum(pos, order.shape[0] - 1)].astype(np.int32)
+
+
+def serving_graph_params(seed: int):
+    """Scale in 10..18 and edge factor in 8..32, each uniform, from the graph's seed."""
+    r = rng(seed, 4)
+    scale = int(10 + np.floor(r.random() * 9))
+    ef = int(8 + np.floor(r.random() * 25))
+    return scale, ef
+
+
+def serving_graphs(count: int = 200, first_seed: int = 100, threads: int = 8):
+    """R-MAT graphs with seeds first_seed.. (parameters from serving_graph_params),
+    built on a thread pool (the C generators run without the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
+        seed = first_seed + i
+        scale, ef = serving_graph_params(seed)
+        return rmat(scale, ef, 0.57, 0.19, 0.19, seed=seed)
+
+    _native()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(one, range(count)))
+
+
+def serving_queries(graphs, count: int, rate_qps: float, seed: int = 3):
+    """Poisson arrivals at rate_qps; graph uniform; target degree-weighted;
+    half source queries (c in {2, 5, 10}, k_max 1024), half pair queries
+    (eps in {0.05, 0.1}, k_max 65536); query seed = query id."""
+    r = rng(seed, STREAM_ARRIVALS)
+    t = np.cumsum(r.exponential(1.0 / rate_qps, count))
+    out = []
+    for i in range(count):
+        gi = int(r.integers(0, len(graphs)))
+        deg = graphs[gi].degree().astype(np.float64)
+        target = int(np.searchsorted(np.cumsum(deg), r.random() * deg.sum(), side="right"))
+        target = min(target, graphs[gi].n - 1)
+        if r.random() < 0.5:
+            out.append(dict(arrival=float(t[i]), graph=gi, target=target, kind=0,
+                            c=float(r.choice([2.0, 5.0, 10.0])), eps=0.1, seed=i, k_max=1024))
+        else:
+            out.append(dict(arrival=float(t[i]), graph=gi, target=target, kind=1, c=1.0,
+                            eps=float(r.choice([0.05, 0.1])), seed=i, k_max=65536))
+    return out
 
 
 # ----------------------------------------------------------------- configs

@@ -68,47 +68,89 @@ int64_t graphgen_ba(int64_t n, int32_t m, uint64_t seed, int32_t *src, int32_t *
 }
 
 /*
- * Build a symmetric CSR from an undirected edge list: both directions are
- * inserted, self-loops dropped, duplicates merged, rows sorted ascending.
- * row has n+1 entries; col must hold 2*n_edges entries. Returns nnz or -1.
+ * R-MAT (Chakrabarti, Zhan and Faloutsos, SDM 2004): each of the
+ * edge_factor * 2^scale edges picks, bit by bit from the top, one of the four
+ * quadrants with probabilities a, b, c, 1-a-b-c (no noise, no relabelling).
+ * Quadrant b sets the column bit, c the row bit, d both.
  */
-static int cmp_i32(const void *a, const void *b)
+int64_t graphgen_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c,
+                      uint64_t seed, int32_t *src, int32_t *dst)
 {
-    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
-    return (x > y) - (x < y);
+    if (scale < 1 || scale > 30 || edge_factor < 1) return -1;
+    const int64_t ne = (int64_t)edge_factor << scale;
+    uint64_t st = seed;
+    /* quadrant thresholds on a 32-bit uniform draw (two draws per 64-bit word) */
+    const uint64_t ta = (uint64_t)(a * 4294967296.0);
+    const uint64_t tab = (uint64_t)((a + b) * 4294967296.0);
+    const uint64_t tabc = (uint64_t)((a + b + c) * 4294967296.0);
+    for (int64_t e = 0; e < ne; ++e) {
+        uint32_t r = 0, q = 0;
+        uint64_t word = 0;
+        for (int32_t bit = scale - 1, k = 0; bit >= 0; --bit, ++k) {
+            if ((k & 1) == 0) word = splitmix64_next(&st);
+            const uint64_t u = (k & 1) ? (word >> 32) : (word & 0xffffffffULL);
+            const uint32_t down = u >= tab;
+            const uint32_t right = (u >= ta && u < tab) || u >= tabc;
+            r |= down << bit;
+            q |= right << bit;
+        }
+        src[e] = (int32_t)r;
+        dst[e] = (int32_t)q;
+    }
+    return ne;
 }
 
+/*
+ * Build a symmetric CSR from an undirected edge list: both directions are
+ * inserted, self-loops dropped, duplicates merged, rows sorted ascending.
+ * Two stable counting-sort passes (by neighbour, then by row) order the
+ * directed entries; equal neighbours of a row become adjacent and are merged.
+ * row has n+1 entries; col must hold 2*n_edges entries. Returns nnz or -1.
+ */
 int64_t graphgen_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
                      int64_t *row, int32_t *col)
 {
-    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    if (!deg) return -1;
+    int64_t d = 0;
     for (int64_t e = 0; e < n_edges; ++e) {
         int32_t a = src[e], b = dst[e];
-        if (a < 0 || b < 0 || a >= n || b >= n) { free(deg); return -1; }
-        if (a == b) continue;
-        deg[a]++; deg[b]++;
+        if (a < 0 || b < 0 || a >= n || b >= n) return -1;
+        if (a != b) d += 2;
     }
-    row[0] = 0;
-    for (int64_t v = 0; v < n; ++v) row[v + 1] = row[v] + deg[v];
-    for (int64_t v = 0; v < n; ++v) deg[v] = row[v];
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *ra = (int32_t *)malloc(sizeof(int32_t) * (size_t)(d ? d : 1));
+    int32_t *rb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(d ? d : 1));
+    if (!cnt || !ra || !rb) { free(cnt); free(ra); free(rb); return -1; }
+    /* pass 1: bucket the directed entries (a -> b) by b */
     for (int64_t e = 0; e < n_edges; ++e) {
         int32_t a = src[e], b = dst[e];
         if (a == b) continue;
-        col[deg[a]++] = b;
-        col[deg[b]++] = a;
+        cnt[b + 1]++;
+        cnt[a + 1]++;
     }
-    /* sort + unique each row, compacting in place */
-    int64_t out = 0;
+    for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    for (int64_t e = 0; e < n_edges; ++e) {
+        int32_t a = src[e], b = dst[e];
+        if (a == b) continue;
+        int64_t p = cnt[b]++;
+        ra[p] = a; rb[p] = b;
+        p = cnt[a]++;
+        ra[p] = b; rb[p] = a;
+    }
+    /* pass 2: stable bucket by a; entries of a row come out ordered by b */
+    memset(cnt, 0, sizeof(int64_t) * ((size_t)n + 1));
+    for (int64_t i = 0; i < d; ++i) cnt[ra[i] + 1]++;
+    for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    for (int64_t i = 0; i < d; ++i) col[cnt[ra[i]]++] = rb[i];
+    /* cnt[v] now holds the end of row v; merge duplicates in place */
+    int64_t out = 0, lo = 0;
     for (int64_t v = 0; v < n; ++v) {
-        int64_t lo = row[v], hi = row[v + 1];
-        qsort(col + lo, (size_t)(hi - lo), sizeof(int32_t), cmp_i32);
-        int64_t start = out;
-        for (int64_t e = lo; e < hi; ++e)
-            if (e == lo || col[e] != col[e - 1]) col[out++] = col[e];
-        row[v] = start;
+        const int64_t hi = cnt[v];
+        row[v] = out;
+        for (int64_t i = lo; i < hi; ++i)
+            if (i == lo || col[i] != col[i - 1]) col[out++] = col[i];
+        lo = hi;
     }
     row[n] = out;
-    free(deg);
+    free(cnt); free(ra); free(rb);
     return out;
 }

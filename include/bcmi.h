@@ -205,7 +205,10 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
  * Admission by HBM budget: bc_server_add_graph fails with BC_E_NOMEM when the
  * graph's CSR would exceed the budget; each graph's batch width is the widest
  * (<= max_batch) whose engine workspace fits what the resident graphs leave.
- * The round to run next belongs to the graph of the oldest unfinished query.
+ * Scheduling: shortest job first at graph granularity (the graph whose
+ * cheapest unfinished query has the smallest bound (k_max - k) * nnz runs the
+ * next round), with every eighth round given to the graph of the oldest
+ * unfinished query so that no query starves.
  * Not thread-safe: one host thread drives a server. */
 typedef struct bc_server bc_server;
 

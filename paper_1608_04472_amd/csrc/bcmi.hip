@@ -1434,17 +1434,36 @@ bc_status bc_server_step(bc_server *sv, int32_t *completed)
         need(sv && completed, "null argument");
         HIPX(hipSetDevice(sv->device));
         *completed = 0;
-        // the graph of the oldest unfinished query runs next
+        // Shortest job first at graph granularity: the graph whose cheapest
+        // unfinished query has the least remaining work bound ((k_max - k)
+        // samples times the CSR size) runs next. Every eighth round goes to
+        // the graph of the oldest unfinished query, so no query starves.
+        const int G = (int)sv->graphs.size();
         int gi = -1;
-        double oldest = 0.0;
-        for (size_t i = 0; i < sv->active.size(); ++i)
-            for (const auto &q : sv->active[i])
-                if (gi < 0 || q.arrival < oldest) {
-                    gi = (int)i;
-                    oldest = q.arrival;
+        if (sv->rounds % 8 == 7) {
+            double oldest = 0.0;
+            for (int i = 0; i < G; ++i)
+                for (const auto &q : sv->active[(size_t)i])
+                    if (gi < 0 || q.arrival < oldest) {
+                        gi = i;
+                        oldest = q.arrival;
+                    }
+            if (!sv->queued.empty() && (gi < 0 || sv->queued.front().arrival < oldest))
+                gi = sv->queued.front().q.graph;
+        } else {
+            double best = 0.0;
+            auto consider = [&](const ServerQuery &q) {
+                const double work = (double)(q.q.k_max - q.K) *
+                                    (double)std::max<int64_t>(sv->graphs[(size_t)q.q.graph]->nnz, 1);
+                if (gi < 0 || work < best) {
+                    gi = q.q.graph;
+                    best = work;
                 }
-        if (!sv->queued.empty() && (gi < 0 || sv->queued.front().arrival < oldest))
-            gi = sv->queued.front().q.graph;
+            };
+            for (int i = 0; i < G; ++i)
+                for (const auto &q : sv->active[(size_t)i]) consider(q);
+            for (const auto &q : sv->queued) consider(q);
+        }
         if (gi < 0) return;
         server_round(sv, gi, completed);
     });
