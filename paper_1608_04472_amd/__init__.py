@@ -111,6 +111,9 @@ def load_library(path: str | None = None):
     global _lib
     if _lib is not None and path is None:
         return _lib
+    # torch ships its own HIP runtime under the same soname as ROCm's; loading
+    # torch first makes this library bind to that one runtime in the process
+    import torch  # noqa: F401
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError("libbcmi.so is not built (%s); run __graft_entry__.build()" % p)

@@ -94,10 +94,10 @@ struct Work {
     // wave engine
     DBuf<double> sig, dlt;
     DBuf<int32_t> sige;
-    DBuf<uint64_t> vis, F0, F1, active, valid;
+    DBuf<uint64_t> vis, F0, F1, SG0, SG1, active, valid;
     DBuf<double> vsum;
     DBuf<uint32_t> ridx;
-    DBuf<uint64_t> rmask;
+    DBuf<uint64_t> rmask, rseg;
     DBuf<unsigned long long> ctl;
     DBuf<int32_t> srcs, dest;
     // samplers
@@ -121,8 +121,10 @@ struct Work {
     void release()
     {
         sig.release(); dlt.release(); sige.release();
-        vis.release(); F0.release(); F1.release(); active.release(); valid.release();
-        vsum.release(); ridx.release(); rmask.release(); ctl.release(); srcs.release();
+        vis.release(); F0.release(); F1.release(); SG0.release(); SG1.release();
+        active.release(); valid.release();
+        vsum.release(); ridx.release(); rmask.release(); rseg.release(); ctl.release();
+        srcs.release();
         dest.release(); X.release(); S.release(); K.release(); st.release();
         lv.release(); pactive.release();
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release(); probe_src.release();
@@ -316,12 +318,15 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->vis.ensure((size_t)(n * W));
     g->w->F0.ensure((size_t)(n * W));
     g->w->F1.ensure((size_t)(n * W));
+    g->w->SG0.ensure((size_t)(n * W));
+    g->w->SG1.ensure((size_t)(n * W));
     g->w->active.ensure((size_t)W);
     g->w->valid.ensure((size_t)W);
     g->w->srcs.ensure((size_t)p.B);
     g->w->dest.ensure((size_t)p.B);
     g->w->ridx.ensure((size_t)cap);
     g->w->rmask.ensure((size_t)cap);
+    g->w->rseg.ensure((size_t)cap);
 }
 
 __global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32_t nvalid)
@@ -352,6 +357,7 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     a.vis = g->w->vis.p;
     a.ridx = g->w->ridx.p;
     a.rmask = g->w->rmask.p;
+    a.rseg = g->w->rseg.p;
     a.cap = cap;
     a.ctl = g->w->ctl.p;
     a.active = g->w->active.p;
@@ -406,9 +412,11 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         read_ctl(g);
         std::vector<int64_t> off{0, (int64_t)g->w->h_ctl[CTL_TAIL]};
         if (g->w->h_ctl[CTL_REC_OVERFLOW]) { cap *= 2; continue; }
-        launch(s, grid_for(off[1]), k_fill_masks, a, (int64_t)0, off[1], (const uint64_t *)g->w->F0.p);
+        launch(s, grid_for(off[1]), k_init_level0, a, (int64_t)0, off[1],
+               (const uint64_t *)g->w->F0.p, g->w->SG0.p);
 
         uint64_t *cur = g->w->F0.p, *nxt = g->w->F1.p;
+        uint64_t *sgcur = g->w->SG0.p, *sgnxt = g->w->SG1.p;
         bool redo = false;
         for (int level = 0;; ++level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
@@ -428,13 +436,16 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             if (e2 == e1) break;
             if (ext)
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<true>, a, e1, e2,
-                           (const uint64_t *)cur, (const uint64_t *)nxt);
+                           (const uint64_t *)cur, (const uint64_t *)sgcur,
+                           (const uint64_t *)nxt, sgnxt);
             else
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<false>, a, e1, e2,
-                           (const uint64_t *)cur, (const uint64_t *)nxt);
+                           (const uint64_t *)cur, (const uint64_t *)sgcur,
+                           (const uint64_t *)nxt, sgnxt);
             launch(s, grid_for(nent), k_clear, a, e0, e1, cur);
             off.push_back(e2);
             std::swap(cur, nxt);
+            std::swap(sgcur, sgnxt);
         }
         if (redo) continue;
         if (!ext) {
@@ -446,24 +457,33 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             }
         }
         g->cap_hint = std::max<int64_t>(g->cap_hint, off.back() + off.back() / 4);
-        if (sigout && (sigout->mant || sigout->ex))
-            launch(s, grid_for(n * sigout->count), k_out_sigma, a, sigout->count, sigout->b0,
-                   sigout->mant, sigout->ex);
+        if (sigout && (sigout->mant || sigout->ex)) {
+            const int64_t cells = n * sigout->count;
+            if (sigout->mant)
+                launch(s, grid_for(cells), k_fill_f64, sigout->mant + sigout->b0 * n, 0.0, cells);
+            if (sigout->ex)
+                launch(s, grid_for(cells), k_fill_i32, sigout->ex + sigout->b0 * n, (int32_t)0,
+                       cells);
+            launch(s, grid_for(off.back()), k_out_sigma, a, (int64_t)0, off.back(),
+                   sigout->count, sigout->b0, sigout->mant, sigout->ex);
+        }
 
         // backward: cur holds the deepest level's masks, nxt is clear
         const int L = (int)off.size() - 1;
         uint64_t *fnext = nxt, *fown = cur;
+        uint64_t *sgnext = sgnxt, *sgown = sgcur;
         for (int level = L - 1; level >= 1; --level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
             if (ext)
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<true>, a, e0, e1,
-                           (const uint64_t *)fnext, fown);
+                           (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
             else
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<false>, a, e0, e1,
-                           (const uint64_t *)fnext, fown);
+                           (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
             if (level + 1 < L)
                 launch(s, grid_for(off[level + 2] - e1), k_clear, a, e1, off[level + 2], fnext);
             std::swap(fnext, fown);
+            std::swap(sgnext, sgown);
         }
         *ext_used = ext;
         g->stats.levels += L;
@@ -1196,7 +1216,8 @@ struct bc_server {
     {
         const Work &w = work;
         return w.sig.cap * 8 + w.dlt.cap * 8 + w.sige.cap * 4 + w.vis.cap * 8 + w.F0.cap * 8 +
-               w.F1.cap * 8 + w.vsum.cap * 8 + w.ridx.cap * 4 + w.rmask.cap * 8 + w.lv.cap * 4 +
+               w.F1.cap * 8 + w.SG0.cap * 8 + w.SG1.cap * 8 + w.vsum.cap * 8 + w.ridx.cap * 4 +
+               w.rmask.cap * 8 + w.rseg.cap * 8 + w.lv.cap * 4 +
                qd.cap * sizeof(QueryDesc) + slotq.cap * 4 + tgt.cap * 4 + X.cap * 8;
     }
     void release()
@@ -1220,7 +1241,7 @@ size_t engine_bytes(Engine e, int64_t n, int B)
     if (e == ENG_PAIR) return (size_t)n * B * 28;
     // slabs (count, dependency, exponent), bitmaps and sums, a record of ~4 entries
     // per (vertex, word)
-    return (size_t)n * B * 20 + (size_t)n * W * 8 * 5 + (size_t)n * W * 4 * 12;
+    return (size_t)n * B * 20 + (size_t)n * W * 8 * 7 + (size_t)n * W * 4 * 20;
 }
 
 void server_round(bc_server *sv, int gi, int32_t *completed)

@@ -2,22 +2,22 @@
 // many sources, plus the per-source plain form, the sample draws and the
 // adaptive stopping rules.
 //
-// Batched layout ("slabs", vertex-major, source-minor):
-//   sig[v*B + b]  FP64 path count sigma_{s_b}(v); after the backward pass of
-//                 v's level it is overwritten in place by
-//                 rho = (1 + delta)/sigma (source mode) or
-//                 rho = ([v = dest_b] + delta')/sigma (pair mode), the only
-//                 quantity a predecessor needs from v (Theorem 1).
-//   sige[v*B + b] int32 exponent of sig when counts are extended (value =
-//                 sig * 2^sige); absent in plain FP64 mode.
-//   dlt[v*B + b]  FP64 dependency delta_{s_b.}(v) (Definition 2).
+// Wave engine layout (a batch of B = 64 * W sources, W = 2^logW words):
 //   vis[v*W + j]  bit l set once source b = 64j + l has reached v.
-//   F*[v*W + j]   dense frontier bitmap of one level (two rotating arrays).
-// Level record: entries (v, j) with a nonzero 64-bit mask, appended level
-// by level; level l occupies [off[l], off[l+1]). It replaces Brandes'
-// distance-ordered stack: the backward sweep walks it from the deepest level up.
-// One wavefront works on one entry: its 64 lanes are the 64 sources of word j,
-// so every neighbour's slab row is one contiguous, coalesced 512-byte access.
+//   F*[v*W + j]   dense frontier bitmap of one level (two rotating arrays);
+//   SG*[v*W + j]  beside it, the first pool slot of that (v, j) entry.
+//   Level record: entries (v, j) with a nonzero 64-bit mask m, appended level
+//   by level; level l occupies [off[l], off[l+1]). It replaces Brandes'
+//   distance-ordered stack: the backward sweep walks it from the deepest level.
+//   Value pool: entry e owns popcount(m_e) consecutive FP64 slots starting at
+//   rseg[e]; lane l of the entry's word (source 64j + l, bit l of m_e) lives at
+//   rseg[e] + (number of bits of m_e below l). It holds sigma_{s_b}(v), replaced
+//   in place by rho = (1 + delta)/sigma (pair mode: ([v = dest_b] + delta')/sigma)
+//   when the backward sweep reaches v's level, the only quantity a predecessor
+//   needs from v (Theorem 1). A level's values are one dense region, and the
+//   lanes a reader needs from one owner are consecutive slots.
+//   dlt[v*B + b]  FP64 dependency, written only for per-source outputs.
+// One wavefront works on one entry: its 64 lanes are the 64 sources of word j.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,9 +28,16 @@ namespace bcmi {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+constexpr int kInFlight = 8;   // overlapping neighbours whose value loads are issued together
 
 // control words shared with the host (one 64-byte block)
-enum : int { CTL_TAIL = 0, CTL_REC_OVERFLOW = 1, CTL_SIG_OVERFLOW = 2, CTL_RUNNING = 3 };
+enum : int {
+    CTL_TAIL = 0,         // level-record tail
+    CTL_REC_OVERFLOW = 1,
+    CTL_SIG_OVERFLOW = 2, // some path count reached 2^1000 in plain FP64
+    CTL_RUNNING = 3,      // targets still sampling
+    CTL_POOL = 4          // value-pool tail
+};
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -55,6 +62,13 @@ __device__ __forceinline__ int rank_below(uint64_t bal)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
 }
 
+// number of set bits of m below this lane: the lane's slot in its owner's segment
+__device__ __forceinline__ uint32_t slot_rank(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Wave-aggregated append: one atomic per wavefront, slots by ballot rank.
 // Every lane of the wavefront must reach this call.
 __device__ __forceinline__ int64_t wave_append(bool want, unsigned long long *tail)
@@ -74,12 +88,13 @@ struct BatchArgs {
     int64_t n;
     int32_t logW;        // words per batch = 1 << logW
     int32_t B;           // sources per batch = 64 << logW
-    double *sig;
-    int32_t *sige;       // null in plain FP64 mode
+    double *sig;         // value pool: sigma, then rho, per entry segment
+    int32_t *sige;       // pool exponents (extended mode), else null
     double *dlt;
     uint64_t *vis;
     uint32_t *ridx;
     uint64_t *rmask;
+    uint64_t *rseg;      // first pool slot of each record entry
     int64_t cap;
     unsigned long long *ctl;
     uint64_t *active;    // [W] sources still expanding (pair mode clears finished slots)
@@ -167,8 +182,6 @@ __global__ void k_init_sources(BatchArgs a, uint64_t *F0)
         const int j = b >> 6;
         const uint64_t bit = 1ull << (b & 63);
         const int64_t o = (int64_t)s * a.B + b;
-        a.sig[o] = 1.0;
-        if (a.sige) a.sige[o] = 0;
         if (a.dlt) a.dlt[o] = 0.0;
         idx = ((uint32_t)s << a.logW) + (uint32_t)j;
         const uint64_t old = atomicOr((unsigned long long *)&F0[idx], (unsigned long long)bit);
@@ -179,11 +192,24 @@ __global__ void k_init_sources(BatchArgs a, uint64_t *F0)
     if (want) record_push(a, pos, idx);
 }
 
-__global__ void k_fill_masks(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F)
+// Level 0: each source entry's final mask, its pool segment and sigma = 1.
+__global__ void k_init_level0(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F0,
+                              uint64_t *SG0)
 {
     for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
-         e += (int64_t)gridDim.x * blockDim.x)
-        a.rmask[e] = F[a.ridx[e]];
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = a.ridx[e];
+        const uint64_t m = F0[idx];
+        const int c = __popcll(m);
+        const uint64_t seg = atomicAdd(&a.ctl[CTL_POOL], (unsigned long long)c);
+        for (int r = 0; r < c; ++r) {
+            a.sig[seg + r] = 1.0;
+            if (a.sige) a.sige[seg + r] = 0;
+        }
+        a.rmask[e] = m;
+        a.rseg[e] = seg;
+        SG0[idx] = seg;
+    }
 }
 
 __global__ void k_clear(BatchArgs a, int64_t e0, int64_t e1, uint64_t *F)
@@ -281,46 +307,46 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
 // Sum, over the neighbours x of v in ascending CSR order whose frontier word
 // F[x][j] shares a bit with `want`, of the slab value slab[x][64j + lane] for
 // the lanes whose bit is set in that word. Overlapping neighbours are taken
-// eight at a time so their slab loads are in flight together; lanes outside a
+// kInFlight at a time so their slab loads are in flight together; lanes outside a
 // neighbour's word add zero, which leaves the running sum unchanged.
 template <bool kExt>
 __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t j, uint64_t want,
-                                         const uint64_t *F, int lane, double &accp, XNum &accx,
-                                         unsigned long long &units)
+                                         const uint64_t *F, const uint64_t *SG, int lane,
+                                         double &accp, XNum &accx, unsigned long long &units)
 {
-    const int b = (int)(j << 6) + lane;
     const int64_t beg = a.row[v], end = a.row[v + 1];
     for (int64_t base = beg; base < end; base += kWave) {
         const int64_t p = base + lane;
-        int32_t x = 0;
-        uint64_t f = 0;
+        uint64_t fm = 0, sx = 0;
         if (p < end) {
-            x = a.col[p];
-            f = F[((int64_t)x << a.logW) + j] & want;
+            const int64_t xi = ((int64_t)a.col[p] << a.logW) + j;
+            fm = F[xi];
+            if (fm & want) sx = SG[xi];
         }
-        uint64_t bal = wave_ballot(f != 0);
+        uint64_t bal = wave_ballot((fm & want) != 0);
         while (bal) {
-            double vm[8];
-            int32_t ve[8];
+            double vm[kInFlight];
+            int32_t ve[kInFlight];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < kInFlight; ++q) {
                 vm[q] = 0.0;
                 ve[q] = 0;
                 if (bal) {
                     const int k = __ffsll((long long)bal) - 1;
                     bal &= bal - 1;
-                    const int32_t xk = lane_read_i32(x, k);
-                    const uint64_t fk = lane_read_u64(f, k);
+                    const uint64_t mk = lane_read_u64(fm, k);
+                    const uint64_t sk = lane_read_u64(sx, k);
+                    const uint64_t fk = mk & want;
                     units += __popcll(fk);
                     if ((fk >> lane) & 1ull) {
-                        const int64_t o = (int64_t)xk * a.B + b;
+                        const uint64_t o = sk + slot_rank(mk);
                         vm[q] = a.sig[o];
                         if (kExt) ve[q] = a.sige[o];
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < kInFlight; ++q) {
                 if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
                 else accp += vm[q];
             }
@@ -358,54 +384,56 @@ struct TileLds {
     int32_t v[kTile];
     uint32_t j[kTile];
     uint64_t m[kTile];
+    uint64_t seg[kTile];
     int64_t beg[kTile];
     int32_t deg[kTile];
     int32_t start[kTile];   // first staged edge (entries not staged: start == end)
     int32_t end[kTile];
     int32_t staged[kTile];
     int32_t total;
-    int32_t x[kEdgeCap];
-    uint64_t f[kEdgeCap];
+    int32_t x[kEdgeCap];    // neighbour id
+    uint64_t fm[kEdgeCap];  // the neighbour's full frontier word for the entry's word
+    uint64_t fs[kEdgeCap];  // the neighbour's pool segment for that word
 };
 
-// Sum over staged edges [s0, s1) of the tile (neighbour ids and overlap masks
-// already in LDS).
+// Sum over staged edges [s0, s1) of the tile: for each neighbour whose
+// frontier word shares bits with `want`, the values of the shared lanes.
 template <bool kExt>
 __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &t, int s0, int s1,
-                                             int b, int lane, double &accp, XNum &accx,
+                                             uint64_t want, int lane, double &accp, XNum &accx,
                                              unsigned long long &units)
 {
     for (int base = s0; base < s1; base += kWave) {
         const int p = base + lane;
-        int32_t x = 0;
-        uint64_t f = 0;
+        uint64_t fm = 0, sx = 0;
         if (p < s1) {
-            x = t.x[p];
-            f = t.f[p];
+            fm = t.fm[p];
+            sx = t.fs[p];
         }
-        uint64_t bal = wave_ballot(f != 0);
+        uint64_t bal = wave_ballot((fm & want) != 0);
         while (bal) {
-            double vm[8];
-            int32_t ve[8];
+            double vm[kInFlight];
+            int32_t ve[kInFlight];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < kInFlight; ++q) {
                 vm[q] = 0.0;
                 ve[q] = 0;
                 if (bal) {
                     const int k = __ffsll((long long)bal) - 1;
                     bal &= bal - 1;
-                    const int32_t xk = lane_read_i32(x, k);
-                    const uint64_t fk = lane_read_u64(f, k);
+                    const uint64_t mk = lane_read_u64(fm, k);
+                    const uint64_t sk = lane_read_u64(sx, k);
+                    const uint64_t fk = mk & want;
                     units += __popcll(fk);
                     if ((fk >> lane) & 1ull) {
-                        const int64_t o = (int64_t)xk * a.B + b;
+                        const uint64_t o = sk + slot_rank(mk);
                         vm[q] = a.sig[o];
                         if (kExt) ve[q] = a.sige[o];
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < kInFlight; ++q) {
                 if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
                 else accp += vm[q];
             }
@@ -413,13 +441,16 @@ __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &
     }
 }
 
-// kBackward = false: sigma pull for the new level (F = previous frontier,
-//   masks from the dense next-level words `nxt`).
-// kBackward = true: dependency sweep (F = next-deeper frontier, masks from the
-//   record; the entry's own mask is scattered into fown).
+// kBackward = false: sigma pull for the new level (F/SG = previous frontier,
+//   masks from the dense next-level words `nxt`; new segments are allocated
+//   from the pool, one atomic per tile, and published in SGo).
+// kBackward = true: dependency sweep (F/SG = next-deeper frontier, masks and
+//   segments from the record; the entry's own word and segment are scattered
+//   into Fo/SGo for the next, shallower level).
 template <bool kExt, bool kBackward>
 __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F,
-                                           const uint64_t *nxt, uint64_t *fown)
+                                           const uint64_t *SG, const uint64_t *nxt, uint64_t *Fo,
+                                           uint64_t *SGo)
 {
     __shared__ TileLds t;
     const int tid = threadIdx.x;
@@ -430,32 +461,38 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
     unsigned long long ua = 0, ub = 0;
     for (int64_t tile = e0 + (int64_t)blockIdx.x * kTile; tile < e1;
          tile += (int64_t)gridDim.x * kTile) {
-        // phase 1: entry headers
-        if (tid < kTile) {
-            const int64_t e = tile + tid;
+        // phase 1 (wave 0): entry headers, pool segments, staging plan
+        if (wv == 0) {
+            const int64_t e = tile + lane;
             int32_t v = 0, deg = 0;
             uint32_t j = 0;
-            uint64_t m = 0;
+            uint64_t m = 0, seg = 0;
             int64_t beg = 0;
-            if (e < e1) {
+            if (lane < kTile && e < e1) {
                 const uint32_t idx = a.ridx[e];
                 v = (int32_t)(idx >> a.logW);
                 j = idx & wmask;
                 m = kBackward ? a.rmask[e] : nxt[idx];
+                if (kBackward) seg = a.rseg[e];
                 beg = a.row[v];
                 deg = (int32_t)(a.row[v + 1] - beg);
             }
-            t.v[tid] = v;
-            t.j[tid] = j;
-            t.m[tid] = m;
-            t.beg[tid] = beg;
-            t.deg[tid] = deg;
-        }
-        __syncthreads();
-        // staging plan (wave 0): inclusive prefix of the stageable degrees
-        if (wv == 0) {
-            const int d = (lane < kTile) ? t.deg[lane] : 0;
-            const int de = d <= kHub ? d : 0;
+            if (!kBackward) {
+                // allocate this tile's segments: one atomic, offsets by prefix sum
+                const int c = __popcll(m);
+                int incl = c;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += y;
+                }
+                const int tot = __shfl(incl, 63, 64);
+                unsigned long long base = 0;
+                if (lane == 0 && tot) base = atomicAdd(&a.ctl[CTL_POOL], (unsigned long long)tot);
+                base = lane_read_u64(base, 0);
+                seg = base + (uint64_t)(incl - c);
+            }
+            const int de = deg <= kHub ? deg : 0;
             int incl = de;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -463,29 +500,31 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 if (lane >= off) incl += y;
             }
             const bool fits = incl <= kEdgeCap;
-            // entries past the budget are not staged; the staged set keeps a
-            // monotone layout because the prefix only grows
             const int endp = fits ? incl : kEdgeCap;
             const int startp = fits ? incl - de : kEdgeCap;
-            if (lane < kTile) {
-                t.start[lane] = (fits && de == d) ? startp : endp;
-                t.end[lane] = endp;
-                t.staged[lane] = (fits && de == d) ? 1 : 0;
-            }
-            // staged edge count: the largest prefix that fits the budget
             int maxfit = fits ? incl : 0;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 const int y = __shfl_xor(maxfit, off, 64);
                 maxfit = maxfit > y ? maxfit : y;
             }
+            if (lane < kTile) {
+                t.v[lane] = v;
+                t.j[lane] = j;
+                t.m[lane] = m;
+                t.seg[lane] = seg;
+                t.beg[lane] = beg;
+                t.deg[lane] = deg;
+                t.start[lane] = (fits && de == deg) ? startp : endp;
+                t.end[lane] = endp;
+                t.staged[lane] = (fits && de == deg) ? 1 : 0;
+            }
             if (lane == 0) t.total = maxfit;
         }
         __syncthreads();
-        // phase 2: stage neighbours and overlap masks
+        // phase 2: stage neighbours with their frontier words and segments
         const int total = t.total;
         for (int p = tid; p < total; p += blockDim.x) {
-            // owning entry: the staged entry with start <= p < end
             int lo = 0, hi = kTile - 1;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
@@ -494,41 +533,45 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             }
             const int i = lo;
             const int32_t x = a.col[t.beg[i] + (p - t.start[i])];
+            const int64_t xi = ((int64_t)x << a.logW) + t.j[i];
+            const uint64_t fm = F[xi];
             t.x[p] = x;
-            t.f[p] = F[((int64_t)x << a.logW) + t.j[i]] & t.m[i];
+            t.fm[p] = fm;
+            t.fs[p] = (fm & t.m[i]) ? SG[xi] : 0;
         }
         __syncthreads();
-        // phase 3: slab sums, one entry per wavefront at a time
+        // phase 3: value sums, one entry per wavefront at a time
         for (int i = wv; i < kTile; i += nwv) {
             const int64_t e = tile + i;
             if (e >= e1) break;
             const int64_t v = t.v[i];
             const uint32_t j = t.j[i];
             const uint64_t m = t.m[i];
+            const uint64_t seg = t.seg[i];
             const int b = (int)(j << 6) + lane;
             const bool mine = (m >> lane) & 1ull;
-            const int64_t o = v * a.B + b;
+            const uint64_t own_slot = seg + slot_rank(m);
             double own = 0.0;
             int32_t owne = 0;
             if (kBackward && mine) {
-                own = a.sig[o];
-                if (kExt) owne = a.sige[o];
+                own = a.sig[own_slot];
+                if (kExt) owne = a.sige[own_slot];
             }
             XNum acc{0.0, 0};
             double accp = 0.0;
             ua += __popcll(m);
             if (t.staged[i])
-                pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], b, lane, accp, acc, ub);
+                pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
             else
-                pull_sum<kExt>(a, v, j, m, F, lane, accp, acc, ub);
+                pull_sum<kExt>(a, v, j, m, F, SG, lane, accp, acc, ub);
             const uint32_t idx = ((uint32_t)v << a.logW) + j;
             if (!kBackward) {
                 if (mine) {
                     if (kExt) {
-                        a.sig[o] = acc.m;
-                        a.sige[o] = acc.e;
+                        a.sig[own_slot] = acc.m;
+                        a.sige[own_slot] = acc.e;
                     } else {
-                        a.sig[o] = accp;
+                        a.sig[own_slot] = accp;
                         if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
                     }
                     if (a.dest && a.dest[b] == (int32_t)v)
@@ -537,6 +580,8 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 if (lane == 0) {
                     a.vis[idx] |= m;
                     a.rmask[e] = m;
+                    a.rseg[e] = seg;
+                    SGo[idx] = seg;
                 }
             } else {
                 double d = 0.0;
@@ -548,19 +593,22 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                         // delta = sigma(v) * sum(rho): exponents add back to the plain range
                         d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
                         const XNum r = xnorm((term + d) / own, -owne);
-                        a.sig[o] = r.m;
-                        a.sige[o] = r.e;
+                        a.sig[own_slot] = r.m;
+                        a.sige[own_slot] = r.e;
                     } else {
                         d = own * accp;
-                        a.sig[o] = (term + d) / own;
+                        a.sig[own_slot] = (term + d) / own;
                     }
-                    if (a.dlt) a.dlt[o] = d;
+                    if (a.dlt) a.dlt[v * a.B + b] = d;
                 }
                 if (a.vsum) {
                     const double tsum = wave_sum(d);
                     if (lane == 0) a.vsum[idx] += tsum;
                 }
-                if (lane == 0) fown[idx] = m;
+                if (lane == 0) {
+                    Fo[idx] = m;
+                    SGo[idx] = seg;
+                }
             }
         }
         __syncthreads();
@@ -572,23 +620,24 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
 // of sigma_s(u), in ascending CSR order.
 template <bool kExt>
 __global__ __launch_bounds__(kBlock) void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1,
-                                                       const uint64_t *cur, const uint64_t *nxt)
+                                                       const uint64_t *cur, const uint64_t *sgcur,
+                                                       const uint64_t *nxt, uint64_t *sgnxt)
 {
-    pull_tiles<kExt, false>(a, e0, e1, cur, nxt, nullptr);
+    pull_tiles<kExt, false>(a, e0, e1, cur, sgcur, nxt, nullptr, sgnxt);
 }
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
 // rho(w), rho(w) = (1 + delta(w)) / sigma(w). Pair mode replaces the 1 by the
 // indicator of the pair's destination, which yields sigma_uv(t)/sigma_uv.
-// The entry's own mask is scattered into fown for the next (shallower) level.
 // With a.vsum set, the entry's dependencies are also summed over its lanes
 // (fixed tree order) into vsum[v][j]; each (v, j) appears once per level and
 // levels run in sequence, so the accumulation needs no atomics.
 template <bool kExt>
 __global__ __launch_bounds__(kBlock) void k_backward(BatchArgs a, int64_t e0, int64_t e1,
-                                                     const uint64_t *fnext, uint64_t *fown)
+                                                     const uint64_t *fnext, const uint64_t *sgnext,
+                                                     uint64_t *fown, uint64_t *sgown)
 {
-    pull_tiles<kExt, true>(a, e0, e1, fnext, nullptr, fown);
+    pull_tiles<kExt, true>(a, e0, e1, fnext, sgnext, nullptr, fown, sgown);
 }
 
 // ------------------------------------------------------------------ outputs
@@ -642,25 +691,27 @@ __global__ void k_out_dist(BatchArgs a, int64_t e0, int64_t e1, int32_t level, i
     }
 }
 
-// per-source path counts (taken between the forward and backward passes)
-__global__ void k_out_sigma(BatchArgs a, int32_t count, int64_t b0, double *mant, int32_t *ex)
+// per-source path counts from the record (between the forward and backward
+// passes): mant[(b0+b)*n + v], ex[...] for b < count, normalised to [1, 2)
+__global__ void k_out_sigma(BatchArgs a, int64_t e0, int64_t e1, int32_t count, int64_t b0,
+                            double *mant, int32_t *ex)
 {
-    const int64_t total = a.n * count;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = i / count;
-        const int b = (int)(i - v * count);
-        const bool r = reached(a, v, b);
-        const int64_t o = v * a.B + b;
-        double m = r ? a.sig[o] : 0.0;
-        int32_t e = (r && a.sige) ? a.sige[o] : 0;
-        if (mant) {
-            // report normalised extended values (m in [1, 2)) whatever the mode
-            const XNum x = xnorm(m, e);
-            mant[(b0 + b) * a.n + v] = x.m;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = a.ridx[e];
+        const int64_t v = idx >> a.logW;
+        const int j = (int)(idx & wmask);
+        uint64_t m = a.rmask[e];
+        const uint64_t seg = a.rseg[e];
+        for (int r = 0; m; ++r) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int b = (j << 6) + l;
+            if (b >= count) continue;
+            const XNum x = xnorm(a.sig[seg + r], a.sige ? a.sige[seg + r] : 0);
+            if (mant) mant[(b0 + b) * a.n + v] = x.m;
             if (ex) ex[(b0 + b) * a.n + v] = x.e;
-        } else if (ex) {
-            ex[(b0 + b) * a.n + v] = e;
         }
     }
 }
