@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <new>
@@ -145,6 +146,7 @@ struct bc_graph {
     int64_t cap_hint = 0;
     bc_stats stats{};
     int32_t hub = 0;          // a highest-degree vertex (depth probe)
+    int64_t hub_degree = 0;
     int32_t engine = -1;      // cached automatic engine choice
     bool ext_sticky = false;  // an earlier batch on this graph needed extended counts
     // profiler: event pairs around hot launches, device work-unit counters
@@ -575,6 +577,11 @@ Engine engine_for(bc_graph *g)
         const int depth = (int)off.size() - 2;
         g->engine = depth > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
         g->stats.levels = 0;
+        // A path count is at most maxdeg^distance and distances are at most
+        // twice the probe depth: start in extended counts when that bound
+        // reaches 2^1000 (they agree bit for bit with plain FP64 in range).
+        const double bound = 2.0 * depth * std::log2(std::max<double>(2.0, (double)g->hub_degree));
+        if (bound >= 1000.0) g->ext_sticky = true;
     }
     return (Engine)g->engine;
 }
@@ -771,7 +778,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         return;
     }
 
-    const Plan p = plan_batch(g, k, 1024);
+    const Plan p = plan_batch(g, k, 2048);
     g->stats.batch_width = p.B;
     g->stats.schedule = BC_SCHED_BATCHED;
     for (int64_t b0 = 0; b0 < k; b0 += p.B) {
@@ -933,6 +940,7 @@ bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out)
                     best = row[v + 1] - row[v];
                     g->hub = (int32_t)v;
                 }
+            g->hub_degree = best;
             g->stream = (hipStream_t)hip_stream;
             g->row.ensure(row.size());
             g->col.ensure((size_t)csr->nnz);

@@ -881,9 +881,12 @@ __global__ void k_p_init(PairArgs a)
 }
 
 // Top-down discovery: each pair (v, b) of the level claims its unreached
-// neighbours for source b (compare-and-swap on the level word).
+// neighbours for source b (compare-and-swap on the level word). A lane looks
+// at four neighbours per step and the wavefront appends all its claims of
+// that step with one atomic.
 __global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
 {
+    const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long found = 0;
     for (int64_t i0 = e0 + blockIdx.x * (int64_t)blockDim.x; i0 < e1; i0 += stride) {
@@ -898,25 +901,48 @@ __global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
                 deg = (int32_t)(a.row[v + 1] - beg);
             }
         }
-        for (int k = 0;; ++k) {
-            if (wave_ballot(k < deg) == 0) break;
-            bool want = false;
-            uint32_t ox = 0;
-            if (k < deg) {
-                ox = b * a.n + (uint32_t)a.col[beg + k];
-                if (a.lv[ox] < 0 && atomicCAS(&a.lv[ox], -1, level + 1) == -1) want = true;
+        for (int k0 = 0;; k0 += 4) {
+            if (wave_ballot(k0 < deg) == 0) break;
+            uint32_t c[4];
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = 0;
+                if (k0 + q < deg) {
+                    const uint32_t ox = b * a.n + (uint32_t)a.col[beg + k0 + q];
+                    if (a.lv[ox] < 0 && atomicCAS(&a.lv[ox], -1, level + 1) == -1) {
+                        c[q] = ox + 1u;   // 0 = no claim
+                        ++cnt;
+                    }
+                }
             }
-            found += want ? 1 : 0;
-            const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
-            if (want) {
-                if (pos < a.cap) a.rec[pos] = ox;
-                else a.ctl[CTL_REC_OVERFLOW] = 1ull;
+            found += cnt;
+            // exclusive prefix of the claim counts across the wavefront
+            int incl = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            const int tot = __shfl(incl, 63, 64);
+            if (tot == 0) continue;
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&a.ctl[CTL_TAIL], (unsigned long long)tot);
+            base = lane_read_u64(base, 0);
+            int64_t pos = (int64_t)base + (incl - cnt);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (c[q]) {
+                    if (pos < a.cap) a.rec[pos] = c[q] - 1u;
+                    else a.ctl[CTL_REC_OVERFLOW] = 1ull;
+                    ++pos;
+                }
             }
         }
     }
     if (a.prof) {
         const unsigned long long t = wave_sum_u64(found);
-        if (lane_id() == 0 && t) atomicAdd(&a.prof[2 * PROF_TOPDOWN], t);
+        if (lane == 0 && t) atomicAdd(&a.prof[2 * PROF_TOPDOWN], t);
     }
 }
 
