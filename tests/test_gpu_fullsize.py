@@ -1,0 +1,123 @@
+"""Full-size GPU parity in the benchmarks' launch configurations.
+
+At these sizes the oracle cannot replay whole runs in seconds, so the checks
+take outputs it can compute one at a time (sampled sources and pairs) and
+properties that hold at any size (the per-vertex sum equals the sum of the
+per-source rows; the per-source dependency sum equals the distance sum).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1608_04472_amd as bc  # noqa: E402
+from test_gpu_parity import assert_close, assert_sigma  # noqa: E402
+
+O = oracle.load()
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def ba(dev):
+    g = gg.config_graph("ba1m")
+    G = bc.Graph(g.row, g.col)
+    yield g, G
+    G.close()
+
+
+def test_ba1m_bench_batch_sampled_rows(dev, ba):
+    """The benchmark's 4096 sources (seed 7) in its batch width (automatic:
+    2048 on this graph); rows 0, 777 and 2047 of the first batch against the
+    oracle; the per-vertex sum of both batches against the per-source rows."""
+    g, G = ba
+    src = gg.philox_sources(7, 4096, g.n)
+    t = torch.from_numpy(src).to(dev)
+    say("ba1m full batch 1")
+    full, dist, _ = bc.dependencies(G, t[:2048].contiguous(), bc.BC_OUT_FULL, dist=True)
+    assert G.stats()["batch_width"] == 2048 and G.stats()["schedule"] == bc.BC_SCHED_BATCHED
+    for i in (0, 777, 2047):
+        d, _, de = O.brandes(g, int(src[i]))
+        assert np.array_equal(dist[i].cpu().numpy(), d), i
+        got = full[i].cpu().numpy()
+        assert_close(got, de, what="ba1m row %d" % i)
+        assert abs(got.sum() - float(np.sum(d[d > 0] - 1))) <= 1e-9 * got.sum()
+    acc = full.sum(0)
+    del full, dist
+    say("ba1m full batch 2")
+    full2, _, _ = bc.dependencies(G, t[2048:].contiguous(), bc.BC_OUT_FULL)
+    acc += full2.sum(0)
+    del full2
+    say("ba1m sum")
+    out, _, _ = bc.dependencies(G, t, bc.BC_OUT_SUM)
+    assert_close(out.cpu().numpy(), acc.cpu().numpy(), rtol=1e-9, what="ba1m sum vs rows")
+
+
+def test_ba1m_pair_dependencies_from_the_stream(dev, ba):
+    """Pairs 0, 1 and 5000 of the pair stream (seed 7), as the pair sampler
+    draws them, against the oracle's two-search definition."""
+    g, G = ba
+    us = torch.empty(5001, dtype=torch.int32, device=dev)
+    vs = torch.empty(5001, dtype=torch.int32, device=dev)
+    bc.bc_draw_pairs(G, 7, 0, 5001, us, vs)
+    pick = [0, 1, 5000]
+    u = us[pick].contiguous()
+    v = vs[pick].contiguous()
+    say("ba1m pairs")
+    got = bc.pair_dependencies(G, u, v).cpu().numpy()
+    for r, j in enumerate(pick):
+        assert (int(u[r]), int(v[r])) == O.draw_pair(7, j, g.n)
+        assert_close(got[r], O.pair_dependency(g, int(u[r]), int(v[r])), what="pair %d" % j)
+
+
+def test_grid2048_sampled_rows(dev):
+    """The percolated 2048^2 grid with its 1024 benchmark sources (seed 3):
+    automatic schedule (pair-per-thread, extended counts), rows 0 and 511 of
+    the first batch of 512 against the oracle."""
+    g = gg.config_graph("grid2048")
+    G = bc.Graph(g.row, g.col)
+    src = gg.philox_sources(3, 1024, g.n)
+    t = torch.from_numpy(src[:512]).to(dev)
+    say("grid2048 full")
+    full, dist, sig = bc.dependencies(G, t, bc.BC_OUT_FULL, dist=True, sigma=True)
+    st = G.stats()
+    assert st["schedule"] == bc.BC_SCHED_THREADED and st["extended"] == 1
+    for i in (0, 511):
+        d, (om, oe), de = O.brandes(g, int(src[i]))
+        assert np.array_equal(dist[i].cpu().numpy(), d)
+        assert_sigma(sig[0][i].cpu().numpy(), sig[1][i].cpu().numpy(), om, oe, "grid row %d" % i)
+        assert_close(full[i].cpu().numpy(), de, what="grid row %d" % i)
+        assert (oe > 1024).any()           # counts beyond the FP64 range occur on this row
+    G.close()
+
+
+def test_rmat16_adaptive_source_hubs(dev):
+    """C2's graph and batch width (256 per round), c = 5, seed 2, on its four
+    highest-degree vertices (targets that stop after a few hundred samples)."""
+    g = gg.config_graph("rmat16")
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_AUTO, 256, 0.0)
+    targets = gg.top_degree(g, 4)
+    say("rmat16 sampler")
+    est, k, S, st = bc.adaptive_source(G, torch.from_numpy(targets).to(dev), 5.0, 2, g.n)
+    oest, ok, oS, ost = O.adaptive_source(g, targets, 5.0, 2, g.n)
+    assert np.array_equal(k.cpu().numpy(), ok) and np.array_equal(st.cpu().numpy(), ost)
+    assert_close(est.cpu().numpy(), oest, what="rmat16 est")
+    assert G.stats()["batch_width"] == 256
+    G.close()
