@@ -366,10 +366,13 @@ __device__ __forceinline__ double wave_sum(double x)
 // A workgroup takes a tile of kTile consecutive record entries and works in
 // three phases, so that only the slab loads remain on each entry's critical
 // path:
-//   1. one thread per entry loads (vertex, word, mask) and the CSR row bounds;
+//   1. one thread per entry loads (vertex, word, mask) and the CSR row bounds
+//      and makes the entry's read-modify-write updates (visited word, frontier
+//      word and segment for the next sweep, running dependency sum), so that
+//      no entry waits on them one after another in phase 3;
 //   2. all threads walk the tile's concatenated adjacency rows in parallel,
 //      loading each neighbour id and its frontier word for the entry's word,
-//      and stage (neighbour, overlap mask) in LDS;
+//      and stage (frontier word, pool segment) in LDS;
 //   3. each wavefront takes entries in turn: the overlap masks come from LDS,
 //      the slab values of overlapping neighbours are loaded eight at a time
 //      (lanes = sources) and summed in ascending CSR order.
@@ -391,7 +394,7 @@ struct TileLds {
     int32_t end[kTile];
     int32_t staged[kTile];
     int32_t total;
-    int32_t x[kEdgeCap];    // neighbour id
+    double vs[kTile];       // the entry's running dependency sum before this level
     uint64_t fm[kEdgeCap];  // the neighbour's full frontier word for the entry's word
     uint64_t fs[kEdgeCap];  // the neighbour's pool segment for that word
 };
@@ -520,6 +523,21 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 t.staged[lane] = (fits && de == deg) ? 1 : 0;
             }
             if (lane == 0) t.total = maxfit;
+            // per-entry bookkeeping, one lane per entry (each (v, j) occurs
+            // once per level, so these updates do not race)
+            if (lane < kTile && e < e1) {
+                const uint32_t idx = ((uint32_t)v << a.logW) + j;
+                if (!kBackward) {
+                    a.vis[idx] |= m;
+                    a.rmask[e] = m;
+                    a.rseg[e] = seg;
+                    SGo[idx] = seg;
+                } else {
+                    Fo[idx] = m;
+                    SGo[idx] = seg;
+                    if (a.vsum) t.vs[lane] = a.vsum[idx];
+                }
+            }
         }
         __syncthreads();
         // phase 2: stage neighbours with their frontier words and segments
@@ -535,7 +553,6 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             const int32_t x = a.col[t.beg[i] + (p - t.start[i])];
             const int64_t xi = ((int64_t)x << a.logW) + t.j[i];
             const uint64_t fm = F[xi];
-            t.x[p] = x;
             t.fm[p] = fm;
             t.fs[p] = (fm & t.m[i]) ? SG[xi] : 0;
         }
@@ -564,7 +581,6 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
             else
                 pull_sum<kExt>(a, v, j, m, F, SG, lane, accp, acc, ub);
-            const uint32_t idx = ((uint32_t)v << a.logW) + j;
             if (!kBackward) {
                 if (mine) {
                     if (kExt) {
@@ -576,12 +592,6 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                     }
                     if (a.dest && a.dest[b] == (int32_t)v)
                         atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
-                }
-                if (lane == 0) {
-                    a.vis[idx] |= m;
-                    a.rmask[e] = m;
-                    a.rseg[e] = seg;
-                    SGo[idx] = seg;
                 }
             } else {
                 double d = 0.0;
@@ -603,11 +613,7 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 }
                 if (a.vsum) {
                     const double tsum = wave_sum(d);
-                    if (lane == 0) a.vsum[idx] += tsum;
-                }
-                if (lane == 0) {
-                    Fo[idx] = m;
-                    SGo[idx] = seg;
+                    if (lane == 0) a.vsum[((uint32_t)v << a.logW) + j] = t.vs[i] + tsum;
                 }
             }
         }
