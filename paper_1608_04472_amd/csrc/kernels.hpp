@@ -55,6 +55,20 @@ __device__ __forceinline__ uint64_t lane_read_u64(uint64_t x, int l)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// the value of x in the first active lane, as a wave-uniform (scalar) value
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// true in the lanes whose bit is set in the wave-uniform mask m
+__device__ __forceinline__ bool lane_in(uint64_t m)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+
 // number of set bits of bal below this lane
 __device__ __forceinline__ int rank_below(uint64_t bal)
 {
@@ -304,11 +318,57 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
 
 // ------------------------------------------------- neighbour pull (shared)
 
+// Issue the value loads of up to kInFlight overlapping neighbours, taken from
+// bal (bit k: the neighbour staged in lane k, whose frontier word and pool
+// segment are this lane's fm and sx) in ascending order. fk[q] receives the
+// q-th neighbour's overlap with the wave-uniform `want`; only its lanes load.
+template <bool kExt>
+__device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uint64_t sx,
+                                            uint64_t want, uint64_t &bal,
+                                            double (&vm)[kInFlight], int32_t (&ve)[kInFlight],
+                                            uint64_t (&fk)[kInFlight], unsigned long long &units)
+{
+#pragma unroll
+    for (int q = 0; q < kInFlight; ++q) {
+        fk[q] = 0;
+        if (bal) {
+            const int k = __ffsll((long long)bal) - 1;
+            bal &= bal - 1;
+            const uint64_t mk = lane_read_u64(fm, k);
+            const uint64_t sk = lane_read_u64(sx, k);
+            fk[q] = mk & want;
+            units += __popcll(fk[q]);
+            if (lane_in(fk[q])) {
+                const uint64_t o = sk + slot_rank(mk);
+                vm[q] = a.sig[o];
+                if (kExt) ve[q] = a.sige[o];
+            }
+        }
+    }
+}
+
+// Add a batch in issue order; lanes outside a neighbour's overlap add nothing.
+template <bool kExt>
+__device__ __forceinline__ void add_batch(const double (&vm)[kInFlight],
+                                          const int32_t (&ve)[kInFlight],
+                                          const uint64_t (&fk)[kInFlight], double &accp,
+                                          XNum &accx)
+{
+#pragma unroll
+    for (int q = 0; q < kInFlight; ++q) {
+        if (lane_in(fk[q])) {
+            if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
+            else accp += vm[q];
+        }
+    }
+}
+
 // Sum, over the neighbours x of v in ascending CSR order whose frontier word
 // F[x][j] shares a bit with `want`, of the slab value slab[x][64j + lane] for
 // the lanes whose bit is set in that word. Overlapping neighbours are taken
-// kInFlight at a time so their slab loads are in flight together; lanes outside a
-// neighbour's word add zero, which leaves the running sum unchanged.
+// kInFlight at a time so their slab loads are in flight together; only the
+// lanes inside a neighbour's overlap load and add (the overlap is wave-uniform,
+// so it serves directly as the execution mask).
 template <bool kExt>
 __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t j, uint64_t want,
                                          const uint64_t *F, const uint64_t *SG, int lane,
@@ -327,29 +387,9 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t
         while (bal) {
             double vm[kInFlight];
             int32_t ve[kInFlight];
-#pragma unroll
-            for (int q = 0; q < kInFlight; ++q) {
-                vm[q] = 0.0;
-                ve[q] = 0;
-                if (bal) {
-                    const int k = __ffsll((long long)bal) - 1;
-                    bal &= bal - 1;
-                    const uint64_t mk = lane_read_u64(fm, k);
-                    const uint64_t sk = lane_read_u64(sx, k);
-                    const uint64_t fk = mk & want;
-                    units += __popcll(fk);
-                    if ((fk >> lane) & 1ull) {
-                        const uint64_t o = sk + slot_rank(mk);
-                        vm[q] = a.sig[o];
-                        if (kExt) ve[q] = a.sige[o];
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kInFlight; ++q) {
-                if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
-                else accp += vm[q];
-            }
+            uint64_t fk[kInFlight];
+            issue_batch<kExt>(a, fm, sx, want, bal, vm, ve, fk, units);
+            add_batch<kExt>(vm, ve, fk, accp, accx);
         }
     }
 }
@@ -417,29 +457,9 @@ __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &
         while (bal) {
             double vm[kInFlight];
             int32_t ve[kInFlight];
-#pragma unroll
-            for (int q = 0; q < kInFlight; ++q) {
-                vm[q] = 0.0;
-                ve[q] = 0;
-                if (bal) {
-                    const int k = __ffsll((long long)bal) - 1;
-                    bal &= bal - 1;
-                    const uint64_t mk = lane_read_u64(fm, k);
-                    const uint64_t sk = lane_read_u64(sx, k);
-                    const uint64_t fk = mk & want;
-                    units += __popcll(fk);
-                    if ((fk >> lane) & 1ull) {
-                        const uint64_t o = sk + slot_rank(mk);
-                        vm[q] = a.sig[o];
-                        if (kExt) ve[q] = a.sige[o];
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kInFlight; ++q) {
-                if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
-                else accp += vm[q];
-            }
+            uint64_t fk[kInFlight];
+            issue_batch<kExt>(a, fm, sx, want, bal, vm, ve, fk, units);
+            add_batch<kExt>(vm, ve, fk, accp, accx);
         }
     }
 }
@@ -458,8 +478,8 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
     __shared__ TileLds t;
     const int tid = threadIdx.x;
     const int lane = lane_id();
-    const int wv = tid >> 6;
-    const int nwv = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwv = kBlock / kWave;
     const uint32_t wmask = (1u << a.logW) - 1u;
     unsigned long long ua = 0, ub = 0;
     for (int64_t tile = e0 + (int64_t)blockIdx.x * kTile; tile < e1;
@@ -561,12 +581,12 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
         for (int i = wv; i < kTile; i += nwv) {
             const int64_t e = tile + i;
             if (e >= e1) break;
-            const int64_t v = t.v[i];
-            const uint32_t j = t.j[i];
-            const uint64_t m = t.m[i];
-            const uint64_t seg = t.seg[i];
+            const int64_t v = __builtin_amdgcn_readfirstlane(t.v[i]);
+            const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
+            const uint64_t m = uniform_u64(t.m[i]);
+            const uint64_t seg = uniform_u64(t.seg[i]);
             const int b = (int)(j << 6) + lane;
-            const bool mine = (m >> lane) & 1ull;
+            const bool mine = lane_in(m);
             const uint64_t own_slot = seg + slot_rank(m);
             double own = 0.0;
             int32_t owne = 0;
