@@ -12,6 +12,7 @@
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hipcub/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -91,6 +92,11 @@ void launch(hipStream_t st, int grid, K kernel, A... args)
 
 // Device buffers of the engines. A graph owns one; graphs of a server share
 // the server's (rounds on a server run one at a time on one stream).
+// landmark vertices of the lane-order key (8 bits of distance each)
+constexpr int kLandmarks = 8;
+// batches of at least this many samples are reordered by the key
+constexpr int64_t kOrderMin = 128;
+
 struct Work {
     // wave engine
     DBuf<double> sig, dlt;
@@ -112,6 +118,10 @@ struct Work {
     DBuf<int32_t> ss_d, ss_q;
     DBuf<double> ss_sig, ss_dlt;
     DBuf<int32_t> probe_src;
+    // lane order: sort keys and permutation of the requested samples
+    DBuf<uint64_t> okey_in, okey_out;
+    DBuf<int32_t> oidx_in, operm, lane_row;
+    DBuf<uint8_t> sort_tmp;
     unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
 
     void init()
@@ -129,6 +139,8 @@ struct Work {
         dest.release(); X.release(); S.release(); K.release(); st.release();
         lv.release(); pactive.release();
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release(); probe_src.release();
+        okey_in.release(); okey_out.release(); oidx_in.release(); operm.release();
+        lane_row.release(); sort_tmp.release();
         if (h_ctl) (void)hipHostFree(h_ctl);
         h_ctl = nullptr;
     }
@@ -149,6 +161,10 @@ struct bc_graph {
     int64_t hub_degree = 0;
     int32_t engine = -1;      // cached automatic engine choice
     bool ext_sticky = false;  // an earlier batch on this graph needed extended counts
+    // lane-order key: distances to up to kLandmarks highest-degree vertices
+    std::vector<int32_t> landmarks;
+    DBuf<uint64_t> skey;
+    bool skey_ready = false;
     // profiler: event pairs around hot launches, device work-unit counters
     bool prof_on = false;
     DBuf<unsigned long long> prof_dev;
@@ -164,6 +180,7 @@ struct bc_graph {
     void release_all()
     {
         row.release(); col.release();
+        skey.release();
         own.release();
         prof_dev.release();
         for (auto &p : pending) {
@@ -366,6 +383,7 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     a.valid = g->w->valid.p;
     a.srcs = g->w->srcs.p;
     a.dest = pair ? g->w->dest.p : nullptr;
+    a.lane_row = nullptr;
     a.nvalid = nvalid;
     return a;
 }
@@ -381,6 +399,7 @@ struct SigmaOut {
     int32_t *ex = nullptr;
     int32_t count = 0;
     int64_t b0 = 0;
+    const int32_t *lane_row = nullptr;   // caller's row of each lane, or null
 };
 
 double bottom_up_fraction(const bc_graph *g)
@@ -459,14 +478,11 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             }
         }
         g->cap_hint = std::max<int64_t>(g->cap_hint, off.back() + off.back() / 4);
+        // (the caller has zeroed the output rows: unreached vertices stay 0)
         if (sigout && (sigout->mant || sigout->ex)) {
-            const int64_t cells = n * sigout->count;
-            if (sigout->mant)
-                launch(s, grid_for(cells), k_fill_f64, sigout->mant + sigout->b0 * n, 0.0, cells);
-            if (sigout->ex)
-                launch(s, grid_for(cells), k_fill_i32, sigout->ex + sigout->b0 * n, (int32_t)0,
-                       cells);
-            launch(s, grid_for(off.back()), k_out_sigma, a, (int64_t)0, off.back(),
+            BatchArgs ao = a;
+            ao.lane_row = sigout->lane_row;
+            launch(s, grid_for(off.back()), k_out_sigma, ao, (int64_t)0, off.back(),
                    sigout->count, sigout->b0, sigout->mant, sigout->ex);
         }
 
@@ -707,6 +723,49 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
     }
 }
 
+// ------------------------------------------------------------ lane order
+
+// key[v] packs the BFS distances from the landmarks (first landmark in the
+// top byte), computed once per graph with the per-source form.
+void ensure_source_keys(bc_graph *g)
+{
+    if (g->skey_ready) return;
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    g->skey.ensure((size_t)n);
+    HIPX(hipMemsetAsync(g->skey.p, 0, (size_t)n * 8, s));
+    g->w->probe_src.ensure(1);
+    for (int32_t l : g->landmarks) {
+        HIPX(hipMemcpyAsync(g->w->probe_src.p, &l, 4, hipMemcpyHostToDevice, s));
+        run_single(g, g->w->probe_src.p, true);
+        launch(s, grid_for(n), k_key_push, g->skey.p, (const int32_t *)g->w->ss_d.p, n);
+        HIPX(hipStreamSynchronize(s));   // `l` is read by the copy above
+    }
+    g->skey_ready = true;
+}
+
+// g->w->operm[0..k) = the sample indices in ascending (key of source, index)
+// order (a stable radix sort: deterministic for a given graph and input).
+void order_samples(bc_graph *g, const int32_t *sources, int64_t k)
+{
+    ensure_source_keys(g);
+    hipStream_t s = g->stream;
+    Work &w = *g->w;
+    w.okey_in.ensure((size_t)k);
+    w.okey_out.ensure((size_t)k);
+    w.oidx_in.ensure((size_t)k);
+    w.operm.ensure((size_t)k);
+    launch(s, grid_for(k), k_key_gather, (const uint64_t *)g->skey.p, sources, k, w.okey_in.p,
+           w.oidx_in.p);
+    size_t bytes = 0;
+    HIPX(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, w.okey_in.p, w.okey_out.p, w.oidx_in.p,
+                                            w.operm.p, (int)k, 0, 8 * (int)sizeof(uint64_t), s));
+    w.sort_tmp.ensure(std::max<size_t>(bytes, 1));
+    HIPX(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp.p, bytes, w.okey_in.p, w.okey_out.p,
+                                            w.oidx_in.p, w.operm.p, (int)k, 0,
+                                            8 * (int)sizeof(uint64_t), s));
+}
+
 // ------------------------------------------------------------ dependencies
 
 void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode, double *out,
@@ -723,6 +782,8 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         return;
     }
     if (dist_out) launch(s, grid_for(k * n), k_fill_i32, dist_out, (int32_t)-1, k * n);
+    if (sig_m) launch(s, grid_for(k * n), k_fill_f64, sig_m, 0.0, k * n);
+    if (sig_e) launch(s, grid_for(k * n), k_fill_i32, sig_e, (int32_t)0, k * n);
 
     if (per_source_schedule(g) && !pair) {
         for (int64_t i = 0; i < k; ++i) {
@@ -781,22 +842,36 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     const Plan p = plan_batch(g, k, 2048);
     g->stats.batch_width = p.B;
     g->stats.schedule = BC_SCHED_BATCHED;
+    // samples sorted by the clustering key, cut into batches, rows mapped back
+    const bool ordered = k >= kOrderMin && !g->landmarks.empty();
+    if (ordered) order_samples(g, sources, k);
     for (int64_t b0 = 0; b0 < k; b0 += p.B) {
         const int count = (int)std::min<int64_t>(p.B, k - b0);
         const OutKind kind = mode == BC_OUT_SUM ? OUT_VSUM : OUT_DELTA;
         ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), kind);
-        HIPX(hipMemcpyAsync(g->w->srcs.p, sources + b0, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
-        if (pair)
-            HIPX(hipMemcpyAsync(g->w->dest.p, dests + b0, (size_t)count * 4,
+        if (ordered) {
+            g->w->lane_row.ensure((size_t)p.B);
+            launch(s, grid_for(count), k_take_batch, (const int32_t *)g->w->operm.p, b0, count,
+                   sources, pair ? dests : (const int32_t *)nullptr, g->w->srcs.p, g->w->dest.p,
+                   g->w->lane_row.p);
+        } else {
+            HIPX(hipMemcpyAsync(g->w->srcs.p, sources + b0, (size_t)count * 4,
                                 hipMemcpyDeviceToDevice, s));
+            if (pair)
+                HIPX(hipMemcpyAsync(g->w->dest.p, dests + b0, (size_t)count * 4,
+                                    hipMemcpyDeviceToDevice, s));
+        }
+        const int32_t *lane_row = ordered ? (const int32_t *)g->w->lane_row.p : nullptr;
         SigmaOut so;
         so.mant = sig_m;
         so.ex = sig_e;
         so.count = count;
         so.b0 = b0;
+        so.lane_row = lane_row;
         bool ext = false;
         std::vector<int64_t> off = run_batch(g, p, count, pair, &ext, &so, kind);
         BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->w->ridx.cap, kind);
+        a.lane_row = lane_row;
         if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_vsum, a, out);
         else launch(s, grid_for(n * count), k_out_full, a, (int32_t)count, b0, out);
         if (dist_out)
@@ -941,6 +1016,18 @@ bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out)
                     g->hub = (int32_t)v;
                 }
             g->hub_degree = best;
+            {
+                // landmarks: the kLandmarks highest degrees (ties by vertex id)
+                std::vector<int32_t> ids((size_t)csr->n);
+                for (int64_t v = 0; v < csr->n; ++v) ids[(size_t)v] = (int32_t)v;
+                const size_t nl = std::min<size_t>(kLandmarks, ids.size());
+                std::partial_sort(ids.begin(), ids.begin() + nl, ids.end(), [&](int32_t x, int32_t y) {
+                    const int64_t dx = row[x + 1] - row[x], dy = row[y + 1] - row[y];
+                    return dx != dy ? dx > dy : x < y;
+                });
+                for (size_t i = 0; i < nl; ++i)
+                    if (row[ids[i] + 1] > row[ids[i]]) g->landmarks.push_back(ids[i]);
+            }
             g->stream = (hipStream_t)hip_stream;
             g->row.ensure(row.size());
             g->col.ensure((size_t)csr->nnz);

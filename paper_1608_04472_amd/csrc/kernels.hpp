@@ -117,8 +117,15 @@ struct BatchArgs {
     const int32_t *dest; // [B] pair destination v, or null in source mode
     double *vsum;        // [n][W] per-(vertex, word) dependency sums, or null
     unsigned long long *prof;  // work-unit counters [kernel][2], or null
+    const int32_t *lane_row;   // [B] caller's row of each lane, or null (row b0 + lane)
     int32_t nvalid;
 };
+
+// output row of lane b in a batch whose first sample is b0
+__device__ __forceinline__ int64_t out_row(const BatchArgs &a, int64_t b0, int b)
+{
+    return a.lane_row ? (int64_t)a.lane_row[b] : b0 + b;
+}
 
 // kernel ids of the work-unit counters
 enum : int { PROF_TOPDOWN = 0, PROF_BOTTOMUP = 1, PROF_SIGMA = 2, PROF_BACKWARD = 3, PROF_KERNELS = 4 };
@@ -666,6 +673,51 @@ __global__ __launch_bounds__(kBlock) void k_backward(BatchArgs a, int64_t e0, in
     pull_tiles<kExt, true>(a, e0, e1, fnext, sgnext, nullptr, fown, sgown);
 }
 
+// ------------------------------------------------------------- lane order
+//
+// Which sample sits in which lane does not change any per-sample value, but it
+// decides how many (vertex, word) entries and overlapping neighbours a batch
+// has: a word whose 64 sources are close to each other meets each vertex at
+// fewer distinct levels. Sources are therefore sorted by a clustering key
+// (distances to a few landmark vertices) before they are cut into batches.
+
+// key[v] = (key[v] << 8) | min(d[v], 255), an unreached vertex counting as 255
+__global__ void k_key_push(uint64_t *key, const int32_t *d, int64_t n)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = d[v];
+        const uint64_t c = (x < 0 || x > 255) ? 255u : (uint64_t)x;
+        key[v] = (key[v] << 8) | c;
+    }
+}
+
+// sort input: out[i] = key[src[i]], idx[i] = i
+__global__ void k_key_gather(const uint64_t *key, const int32_t *src, int64_t k, uint64_t *out,
+                             int32_t *idx)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        out[i] = key[src[i]];
+        idx[i] = (int32_t)i;
+    }
+}
+
+// Batch starting at b0 of the sorted order: lane b takes sample perm[b0 + b]
+// (its source, its destination in pair mode, and its caller's row).
+__global__ void k_take_batch(const int32_t *perm, int64_t b0, int32_t count, const int32_t *src,
+                             const int32_t *dst, int32_t *lane_src, int32_t *lane_dst,
+                             int32_t *lane_row)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < count) {
+        const int32_t r = perm[b0 + b];
+        lane_src[b] = src[r];
+        if (dst) lane_dst[b] = dst[r];
+        lane_row[b] = r;
+    }
+}
+
 // ------------------------------------------------------------------ outputs
 
 __device__ __forceinline__ bool reached(const BatchArgs &a, int64_t v, int b)
@@ -673,7 +725,7 @@ __device__ __forceinline__ bool reached(const BatchArgs &a, int64_t v, int b)
     return (a.vis[(v << a.logW) + (b >> 6)] >> (b & 63)) & 1ull;
 }
 
-// out[(b0 + b) * n + v] = delta_{s_b}(v) for b < count (0 where unreached)
+// out[row(b) * n + v] = delta_{s_b}(v) for b < count (0 where unreached)
 __global__ void k_out_full(BatchArgs a, int32_t count, int64_t b0, double *out)
 {
     const int64_t total = a.n * count;
@@ -681,7 +733,7 @@ __global__ void k_out_full(BatchArgs a, int32_t count, int64_t b0, double *out)
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = i / count;
         const int b = (int)(i - v * count);
-        out[(b0 + b) * a.n + v] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
+        out[out_row(a, b0, b) * a.n + v] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
     }
 }
 
@@ -697,7 +749,7 @@ __global__ void k_out_vsum(BatchArgs a, double *out)
     }
 }
 
-// per-source distances from the level record: dist[(b0+b)*n + v] = level
+// per-source distances from the level record: dist[row(b)*n + v] = level
 __global__ void k_out_dist(BatchArgs a, int64_t e0, int64_t e1, int32_t level, int32_t count,
                            int64_t b0, int32_t *dist)
 {
@@ -712,13 +764,13 @@ __global__ void k_out_dist(BatchArgs a, int64_t e0, int64_t e1, int32_t level, i
             const int l = __ffsll((long long)m) - 1;
             m &= m - 1;
             const int b = (j << 6) + l;
-            if (b < count) dist[(b0 + b) * a.n + v] = level;
+            if (b < count) dist[out_row(a, b0, b) * a.n + v] = level;
         }
     }
 }
 
 // per-source path counts from the record (between the forward and backward
-// passes): mant[(b0+b)*n + v], ex[...] for b < count, normalised to [1, 2)
+// passes): mant[row(b)*n + v], ex[...] for b < count, normalised to [1, 2)
 __global__ void k_out_sigma(BatchArgs a, int64_t e0, int64_t e1, int32_t count, int64_t b0,
                             double *mant, int32_t *ex)
 {
@@ -736,8 +788,9 @@ __global__ void k_out_sigma(BatchArgs a, int64_t e0, int64_t e1, int32_t count, 
             const int b = (j << 6) + l;
             if (b >= count) continue;
             const XNum x = xnorm(a.sig[seg + r], a.sige ? a.sige[seg + r] : 0);
-            if (mant) mant[(b0 + b) * a.n + v] = x.m;
-            if (ex) ex[(b0 + b) * a.n + v] = x.e;
+            const int64_t row = out_row(a, b0, b);
+            if (mant) mant[row * a.n + v] = x.m;
+            if (ex) ex[row * a.n + v] = x.e;
         }
     }
 }
