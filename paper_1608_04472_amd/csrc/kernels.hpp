@@ -651,8 +651,11 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
 
 // sigma_s(w) = sum over predecessors u (neighbours one level up, Definition 3)
 // of sigma_s(u), in ascending CSR order.
+// The plain-FP64 pull kernels are latency bound: they are held to 64 VGPRs so
+// that eight wavefronts share each SIMD (the scalar registers that do not fit
+// are kept in vector-register lanes).
 template <bool kExt>
-__global__ __launch_bounds__(kBlock) void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1 : 8, 8))) void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1,
                                                        const uint64_t *cur, const uint64_t *sgcur,
                                                        const uint64_t *nxt, uint64_t *sgnxt)
 {
@@ -666,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_sigma_pull(BatchArgs a, int64_t e0, 
 // (fixed tree order) into vsum[v][j]; each (v, j) appears once per level and
 // levels run in sequence, so the accumulation needs no atomics.
 template <bool kExt>
-__global__ __launch_bounds__(kBlock) void k_backward(BatchArgs a, int64_t e0, int64_t e1,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1 : 8, 8))) void k_backward(BatchArgs a, int64_t e0, int64_t e1,
                                                      const uint64_t *fnext, const uint64_t *sgnext,
                                                      uint64_t *fown, uint64_t *sgown)
 {
