@@ -90,13 +90,13 @@ void launch(hipStream_t st, int grid, K kernel, A... args)
 
 }  // namespace
 
-// Device buffers of the engines. A graph owns one; graphs of a server share
-// the server's (rounds on a server run one at a time on one stream).
 // landmark vertices of the lane-order key (8 bits of distance each)
 constexpr int kLandmarks = 8;
 // batches of at least this many samples are reordered by the key
 constexpr int64_t kOrderMin = 128;
 
+// Device buffers of the engines. A graph owns one; graphs of a server share
+// the server's (rounds on a server run one at a time on one stream).
 struct Work {
     // wave engine
     DBuf<double> sig, dlt;
@@ -105,6 +105,7 @@ struct Work {
     DBuf<double> vsum;
     DBuf<uint32_t> ridx;
     DBuf<uint64_t> rmask, rseg;
+    DBuf<unsigned long long> bsum;   // per-block pool offsets of one level
     DBuf<unsigned long long> ctl;
     DBuf<int32_t> srcs, dest;
     // samplers
@@ -135,6 +136,7 @@ struct Work {
         vis.release(); F0.release(); F1.release(); SG0.release(); SG1.release();
         active.release(); valid.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release(); ctl.release();
+        bsum.release();
         srcs.release();
         dest.release(); X.release(); S.release(); K.release(); st.release();
         lv.release(); pactive.release();
@@ -346,6 +348,7 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->ridx.ensure((size_t)cap);
     g->w->rmask.ensure((size_t)cap);
     g->w->rseg.ensure((size_t)cap);
+    g->w->bsum.ensure((size_t)((cap >> kSegShift) + 2));
 }
 
 __global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32_t nvalid)
@@ -455,14 +458,17 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
                 break;
             }
             if (e2 == e1) break;
+            const int64_t nb = ((e2 - e1) + (1 << kSegShift) - 1) >> kSegShift;
+            launch(s, (int)nb, k_seg_count, a, e1, e2, (const uint64_t *)nxt, g->w->bsum.p);
+            hipLaunchKernelGGL(k_seg_base, dim3(1), dim3(1024), 0, s, g->w->bsum.p, nb, g->w->ctl.p);
+            HIPX(hipGetLastError());
+            const unsigned long long *bb = g->w->bsum.p;
             if (ext)
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<true>, a, e1, e2,
-                           (const uint64_t *)cur, (const uint64_t *)sgcur,
-                           (const uint64_t *)nxt, sgnxt);
+                           (const uint64_t *)cur, (const uint64_t *)sgcur, bb, sgnxt);
             else
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<false>, a, e1, e2,
-                           (const uint64_t *)cur, (const uint64_t *)sgcur,
-                           (const uint64_t *)nxt, sgnxt);
+                           (const uint64_t *)cur, (const uint64_t *)sgcur, bb, sgnxt);
             launch(s, grid_for(nent), k_clear, a, e0, e1, cur);
             off.push_back(e2);
             std::swap(cur, nxt);

@@ -323,6 +323,90 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
     if (a.prof) prof_add(a, PROF_BOTTOMUP, wave_sum_u64(found), 0, lane_id());
 }
 
+// ------------------------------------------------ pool segment allocation
+//
+// A new level's entries receive consecutive pool segments in record order,
+// entry e owning popcount(mask) slots. The offsets come from a two-pass
+// prefix sum (no contended counter): k_seg_count scans blocks of
+// 2^kSegShift entries, k_seg_base scans the block totals from the pool tail.
+constexpr int kSegShift = 10;   // 256 threads x 4 entries
+
+// Also moves each entry's final mask into the record and the visited words.
+__global__ __launch_bounds__(256) void k_seg_count(BatchArgs a, int64_t e0, int64_t e1,
+                                                   const uint64_t *nxt, unsigned long long *bsum)
+{
+    __shared__ int wsum[4];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid >> 6;
+    const int64_t base = e0 + ((int64_t)blockIdx.x << kSegShift) + (int64_t)tid * 4;
+    int c[4];
+    int tsum = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t e = base + r;
+        c[r] = 0;
+        if (e < e1) {
+            const uint32_t idx = a.ridx[e];
+            const uint64_t m = nxt[idx];
+            a.rmask[e] = m;
+            a.vis[idx] |= m;   // each (v, j) occurs once per level
+            c[r] = __popcll(m);
+        }
+        tsum += c[r];
+    }
+    int incl = tsum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - tsum;
+    for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t e = base + r;
+        if (e < e1) a.rseg[e] = (uint64_t)run;
+        run += c[r];
+    }
+    if (tid == 255) bsum[blockIdx.x] = (unsigned long long)run;
+}
+
+// One workgroup of 1024 threads: bsum[b] becomes the pool tail plus the sum
+// of the totals of blocks before b; the tail advances past the level.
+__global__ __launch_bounds__(1024) void k_seg_base(unsigned long long *bsum, int64_t nb,
+                                                   unsigned long long *ctl)
+{
+    __shared__ unsigned long long wsum[16];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid >> 6;
+    unsigned long long carry = ctl[CTL_POOL];
+    for (int64_t i0 = 0; i0 < nb; i0 += 1024) {
+        const int64_t i = i0 + tid;
+        const unsigned long long x = i < nb ? bsum[i] : 0ull;
+        unsigned long long incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wv) before += wsum[w];
+            total += wsum[w];
+        }
+        if (i < nb) bsum[i] = carry + before + incl - x;
+        carry += total;
+        __syncthreads();
+    }
+    if (tid == 0) ctl[CTL_POOL] = carry;
+}
+
 // ------------------------------------------------- neighbour pull (shared)
 
 // Issue the value loads of up to kInFlight overlapping neighbours, taken from
@@ -471,16 +555,16 @@ __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &
     }
 }
 
-// kBackward = false: sigma pull for the new level (F/SG = previous frontier,
-//   masks from the dense next-level words `nxt`; new segments are allocated
-//   from the pool, one atomic per tile, and published in SGo).
+// kBackward = false: sigma pull for the new level (F/SG = previous frontier;
+//   masks and in-block segment offsets from k_seg_count, block bases from
+//   k_seg_base; the absolute segments are published in the record and SGo).
 // kBackward = true: dependency sweep (F/SG = next-deeper frontier, masks and
 //   segments from the record; the entry's own word and segment are scattered
 //   into Fo/SGo for the next, shallower level).
 template <bool kExt, bool kBackward>
 __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F,
-                                           const uint64_t *SG, const uint64_t *nxt, uint64_t *Fo,
-                                           uint64_t *SGo)
+                                           const uint64_t *SG, const unsigned long long *bbase,
+                                           uint64_t *Fo, uint64_t *SGo)
 {
     __shared__ TileLds t;
     const int tid = threadIdx.x;
@@ -502,25 +586,10 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 const uint32_t idx = a.ridx[e];
                 v = (int32_t)(idx >> a.logW);
                 j = idx & wmask;
-                m = kBackward ? a.rmask[e] : nxt[idx];
-                if (kBackward) seg = a.rseg[e];
+                m = a.rmask[e];
+                seg = a.rseg[e] + (kBackward ? 0ull : bbase[(e - e0) >> kSegShift]);
                 beg = a.row[v];
                 deg = (int32_t)(a.row[v + 1] - beg);
-            }
-            if (!kBackward) {
-                // allocate this tile's segments: one atomic, offsets by prefix sum
-                const int c = __popcll(m);
-                int incl = c;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int y = __shfl_up(incl, off, 64);
-                    if (lane >= off) incl += y;
-                }
-                const int tot = __shfl(incl, 63, 64);
-                unsigned long long base = 0;
-                if (lane == 0 && tot) base = atomicAdd(&a.ctl[CTL_POOL], (unsigned long long)tot);
-                base = lane_read_u64(base, 0);
-                seg = base + (uint64_t)(incl - c);
             }
             const int de = deg <= kHub ? deg : 0;
             int incl = de;
@@ -555,8 +624,6 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             if (lane < kTile && e < e1) {
                 const uint32_t idx = ((uint32_t)v << a.logW) + j;
                 if (!kBackward) {
-                    a.vis[idx] |= m;
-                    a.rmask[e] = m;
                     a.rseg[e] = seg;
                     SGo[idx] = seg;
                 } else {
@@ -657,9 +724,10 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
 template <bool kExt>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1 : 8, 8))) void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1,
                                                        const uint64_t *cur, const uint64_t *sgcur,
-                                                       const uint64_t *nxt, uint64_t *sgnxt)
+                                                       const unsigned long long *bbase,
+                                                       uint64_t *sgnxt)
 {
-    pull_tiles<kExt, false>(a, e0, e1, cur, sgcur, nxt, nullptr, sgnxt);
+    pull_tiles<kExt, false>(a, e0, e1, cur, sgcur, bbase, nullptr, sgnxt);
 }
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
