@@ -532,8 +532,8 @@ struct TileLds {
 
 // Sum over staged edges [s0, s1) of the tile: for each neighbour whose
 // frontier word shares bits with `want`, the values of the shared lanes.
-template <bool kExt>
-__device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &t, int s0, int s1,
+template <bool kExt, class Lds>
+__device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const Lds &t, int s0, int s1,
                                              uint64_t want, int lane, double &accp, XNum &accx,
                                              unsigned long long &units)
 {
@@ -551,6 +551,71 @@ __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const TileLds &
             uint64_t fk[kInFlight];
             issue_batch<kExt>(a, fm, sx, want, bal, vm, ve, fk, units);
             add_batch<kExt>(vm, ve, fk, accp, accx);
+        }
+    }
+}
+
+// Phase 3 for entry i of a staged tile: the sum over its overlapping
+// neighbours in ascending CSR order, then sigma (forward) or rho and the
+// dependency (backward) for the entry's lanes.
+template <bool kExt, bool kBackward, class Lds>
+__device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int i, int lane,
+                                          const uint64_t *F, const uint64_t *SG,
+                                          unsigned long long &ua, unsigned long long &ub)
+{
+    const int64_t v = __builtin_amdgcn_readfirstlane(t.v[i]);
+    const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
+    const uint64_t m = uniform_u64(t.m[i]);
+    const uint64_t seg = uniform_u64(t.seg[i]);
+    const int b = (int)(j << 6) + lane;
+    const bool mine = lane_in(m);
+    const uint64_t own_slot = seg + slot_rank(m);
+    double own = 0.0;
+    int32_t owne = 0;
+    if (kBackward && mine) {
+        own = a.sig[own_slot];
+        if (kExt) owne = a.sige[own_slot];
+    }
+    XNum acc{0.0, 0};
+    double accp = 0.0;
+    ua += __popcll(m);
+    if (t.staged[i])
+        pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
+    else
+        pull_sum<kExt>(a, v, j, m, F, SG, lane, accp, acc, ub);
+    if (!kBackward) {
+        if (mine) {
+            if (kExt) {
+                a.sig[own_slot] = acc.m;
+                a.sige[own_slot] = acc.e;
+            } else {
+                a.sig[own_slot] = accp;
+                if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
+            }
+            if (a.dest && a.dest[b] == (int32_t)v)
+                atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
+        }
+    } else {
+        double d = 0.0;
+        if (mine) {
+            // a slot without a destination (< 0) is a source sample
+            const double term = (a.dest && a.dest[b] >= 0)
+                                    ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
+            if (kExt) {
+                // delta = sigma(v) * sum(rho): exponents add back to the plain range
+                d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
+                const XNum r = xnorm((term + d) / own, -owne);
+                a.sig[own_slot] = r.m;
+                a.sige[own_slot] = r.e;
+            } else {
+                d = own * accp;
+                a.sig[own_slot] = (term + d) / own;
+            }
+            if (a.dlt) a.dlt[v * a.B + b] = d;
+        }
+        if (a.vsum) {
+            const double tsum = wave_sum(d);
+            if (lane == 0) a.vsum[((uint32_t)v << a.logW) + j] = t.vs[i] + tsum;
         }
     }
 }
@@ -653,63 +718,8 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
         __syncthreads();
         // phase 3: value sums, one entry per wavefront at a time
         for (int i = wv; i < kTile; i += nwv) {
-            const int64_t e = tile + i;
-            if (e >= e1) break;
-            const int64_t v = __builtin_amdgcn_readfirstlane(t.v[i]);
-            const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
-            const uint64_t m = uniform_u64(t.m[i]);
-            const uint64_t seg = uniform_u64(t.seg[i]);
-            const int b = (int)(j << 6) + lane;
-            const bool mine = lane_in(m);
-            const uint64_t own_slot = seg + slot_rank(m);
-            double own = 0.0;
-            int32_t owne = 0;
-            if (kBackward && mine) {
-                own = a.sig[own_slot];
-                if (kExt) owne = a.sige[own_slot];
-            }
-            XNum acc{0.0, 0};
-            double accp = 0.0;
-            ua += __popcll(m);
-            if (t.staged[i])
-                pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
-            else
-                pull_sum<kExt>(a, v, j, m, F, SG, lane, accp, acc, ub);
-            if (!kBackward) {
-                if (mine) {
-                    if (kExt) {
-                        a.sig[own_slot] = acc.m;
-                        a.sige[own_slot] = acc.e;
-                    } else {
-                        a.sig[own_slot] = accp;
-                        if (!(accp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
-                    }
-                    if (a.dest && a.dest[b] == (int32_t)v)
-                        atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
-                }
-            } else {
-                double d = 0.0;
-                if (mine) {
-                    // a slot without a destination (< 0) is a source sample
-                    const double term = (a.dest && a.dest[b] >= 0)
-                                            ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
-                    if (kExt) {
-                        // delta = sigma(v) * sum(rho): exponents add back to the plain range
-                        d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
-                        const XNum r = xnorm((term + d) / own, -owne);
-                        a.sig[own_slot] = r.m;
-                        a.sige[own_slot] = r.e;
-                    } else {
-                        d = own * accp;
-                        a.sig[own_slot] = (term + d) / own;
-                    }
-                    if (a.dlt) a.dlt[v * a.B + b] = d;
-                }
-                if (a.vsum) {
-                    const double tsum = wave_sum(d);
-                    if (lane == 0) a.vsum[((uint32_t)v << a.logW) + j] = t.vs[i] + tsum;
-                }
-            }
+            if (tile + i >= e1) break;
+            entry_sum<kExt, kBackward>(a, t, i, lane, F, SG, ua, ub);
         }
         __syncthreads();
     }
