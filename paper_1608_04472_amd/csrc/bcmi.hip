@@ -105,7 +105,7 @@ struct Work {
     DBuf<double> vsum;
     DBuf<uint32_t> ridx;
     DBuf<uint64_t> rmask, rseg;
-    DBuf<unsigned long long> bsum;   // per-block pool offsets of one level
+    DBuf<unsigned long long> bcnt, bpop;   // per-block record / pool offsets of a level
     DBuf<unsigned long long> ctl;
     DBuf<int32_t> srcs, dest;
     // samplers
@@ -136,7 +136,7 @@ struct Work {
         vis.release(); F0.release(); F1.release(); SG0.release(); SG1.release();
         active.release(); valid.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release(); ctl.release();
-        bsum.release();
+        bcnt.release(); bpop.release();
         srcs.release();
         dest.release(); X.release(); S.release(); K.release(); st.release();
         lv.release(); pactive.release();
@@ -172,6 +172,7 @@ struct bc_graph {
     DBuf<unsigned long long> prof_dev;
     double prof_ms[PROF_KERNELS] = {};
     int64_t prof_launches[PROF_KERNELS] = {};
+    int64_t prof_host_units[2 * PROF_KERNELS] = {};   // work units counted on the host
     struct Pending {
         int kernel;
         hipEvent_t start, stop;
@@ -269,6 +270,33 @@ void launch_hot(bc_graph *g, int kernel, int grid, K fn, A... args)
     if (g->pending.size() >= 256) prof_flush(g);
 }
 
+// Lay out the record entries and pool segments of the level now in `nxt`
+// (one profiled unit: count, scan, write).
+void build_level(bc_graph *g, const BatchArgs &a, const uint64_t *nxt, int64_t cap)
+{
+    hipStream_t s = g->stream;
+    const int64_t total = g->n << a.logW;
+    const int64_t nb = (total + (1 << kLevelShift) - 1) >> kLevelShift;
+    bc_graph::Pending p{PROF_LEVEL, nullptr, nullptr};
+    if (g->prof_on) {
+        p.start = take_event(g);
+        p.stop = take_event(g);
+        HIPX(hipEventRecord(p.start, s));
+    }
+    launch(s, (int)nb, k_level_count, nxt, total, g->w->bcnt.p, g->w->bpop.p);
+    hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, g->w->bcnt.p, g->w->bpop.p, nb,
+                       g->w->ctl.p, cap);
+    HIPX(hipGetLastError());
+    launch(s, (int)nb, k_level_write, a, nxt, (const unsigned long long *)g->w->bcnt.p,
+           (const unsigned long long *)g->w->bpop.p);
+    if (g->prof_on) {
+        HIPX(hipEventRecord(p.stop, s));
+        g->pending.push_back(p);
+        g->prof_host_units[2 * PROF_LEVEL] += total;
+        if (g->pending.size() >= 256) prof_flush(g);
+    }
+}
+
 void read_ctl(bc_graph *g)
 {
     HIPX(hipMemcpyAsync(g->w->h_ctl, g->w->ctl.p, 8 * sizeof(unsigned long long),
@@ -348,7 +376,8 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->ridx.ensure((size_t)cap);
     g->w->rmask.ensure((size_t)cap);
     g->w->rseg.ensure((size_t)cap);
-    g->w->bsum.ensure((size_t)((cap >> kSegShift) + 2));
+    g->w->bcnt.ensure((size_t)(((n * W) >> kLevelShift) + 2));
+    g->w->bpop.ensure((size_t)(((n * W) >> kLevelShift) + 2));
 }
 
 __global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32_t nvalid)
@@ -450,25 +479,22 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
                            (const uint64_t *)cur, nxt);
             else
                 launch_hot(g, PROF_TOPDOWN, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
+            build_level(g, a, nxt, cap);
             read_ctl(g);
             const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
+            if (g->prof_on) g->prof_host_units[2 * PROF_LEVEL + 1] += e2 - e1;
             if (g->w->h_ctl[CTL_REC_OVERFLOW]) {
                 cap = std::max<int64_t>(cap * 2, e2 + (e2 >> 2));
                 redo = true;
                 break;
             }
             if (e2 == e1) break;
-            const int64_t nb = ((e2 - e1) + (1 << kSegShift) - 1) >> kSegShift;
-            launch(s, (int)nb, k_seg_count, a, e1, e2, (const uint64_t *)nxt, g->w->bsum.p);
-            hipLaunchKernelGGL(k_seg_base, dim3(1), dim3(1024), 0, s, g->w->bsum.p, nb, g->w->ctl.p);
-            HIPX(hipGetLastError());
-            const unsigned long long *bb = g->w->bsum.p;
             if (ext)
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<true>, a, e1, e2,
-                           (const uint64_t *)cur, (const uint64_t *)sgcur, bb, sgnxt);
+                           (const uint64_t *)cur, (const uint64_t *)sgcur, sgnxt);
             else
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<false>, a, e1, e2,
-                           (const uint64_t *)cur, (const uint64_t *)sgcur, bb, sgnxt);
+                           (const uint64_t *)cur, (const uint64_t *)sgcur, sgnxt);
             launch(s, grid_for(nent), k_clear, a, e0, e1, cur);
             off.push_back(e2);
             std::swap(cur, nxt);
@@ -1110,6 +1136,8 @@ bc_status bc_profile_enable(bc_graph *g, int32_t enable)
         for (int k = 0; k < PROF_KERNELS; ++k) {
             g->prof_ms[k] = 0.0;
             g->prof_launches[k] = 0;
+            g->prof_host_units[2 * k] = 0;
+            g->prof_host_units[2 * k + 1] = 0;
         }
         g->prof_on = enable != 0;
     });
@@ -1124,10 +1152,13 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         unsigned long long units[2 * PROF_KERNELS] = {};
         if (g->prof_dev.p)
             HIPX(hipMemcpy(units, g->prof_dev.p, sizeof(units), hipMemcpyDeviceToHost));
+        for (int k = 0; k < 2 * PROF_KERNELS; ++k) units[k] += (unsigned long long)g->prof_host_units[k];
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
-                                                  "sigma_pull", "backward"};
-        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0};
-        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0};
+                                                  "sigma_pull", "backward", "level_record"};
+        // level_record: each word read once (8 B); per entry the record
+        // (4 + 8 + 8 B) and the visited word read and written (16 B)
+        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0};
+        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];

@@ -128,7 +128,14 @@ __device__ __forceinline__ int64_t out_row(const BatchArgs &a, int64_t b0, int b
 }
 
 // kernel ids of the work-unit counters
-enum : int { PROF_TOPDOWN = 0, PROF_BOTTOMUP = 1, PROF_SIGMA = 2, PROF_BACKWARD = 3, PROF_KERNELS = 4 };
+enum : int {
+    PROF_TOPDOWN = 0,
+    PROF_BOTTOMUP = 1,
+    PROF_SIGMA = 2,
+    PROF_BACKWARD = 3,
+    PROF_LEVEL = 4,   // record layout of a level (k_level_*), counted on the host
+    PROF_KERNELS = 5
+};
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 {
@@ -243,8 +250,8 @@ __global__ void k_clear(BatchArgs a, int64_t e0, int64_t e1, uint64_t *F)
 // ---------------------------------------------------------- forward: discover
 
 // Top-down: each frontier entry (u, j) offers its mask to every neighbour w;
-// bits not yet visited are OR-ed into w's next-level word, and the first
-// writer of a word appends (w, j) to the record.
+// bits not yet visited are OR-ed into w's next-level word (the level's record
+// is built from the words afterwards, by k_level_*).
 __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t *nxt)
 {
     const int lane = lane_id();
@@ -259,22 +266,14 @@ __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t
         const uint64_t m = a.rmask[e] & a.active[j];
         if (m == 0) continue;
         const int64_t beg = a.row[u], end = a.row[u + 1];
-        for (int64_t base = beg; base < end; base += kWave) {
-            const int64_t p = base + lane;
-            bool want = false;
-            uint32_t widx = 0;
-            if (p < end) {
-                widx = ((uint32_t)a.col[p] << a.logW) + j;
-                const uint64_t fresh = m & ~a.vis[widx];
-                if (fresh) {
-                    const uint64_t old = atomicOr((unsigned long long *)&nxt[widx],
-                                                  (unsigned long long)fresh);
-                    want = (old == 0);
-                    found += __popcll(fresh & ~old);
-                }
+        for (int64_t p = beg + lane; p < end; p += kWave) {
+            const uint32_t widx = ((uint32_t)a.col[p] << a.logW) + j;
+            const uint64_t fresh = m & ~a.vis[widx];
+            if (fresh) {
+                const uint64_t old = atomicOr((unsigned long long *)&nxt[widx],
+                                              (unsigned long long)fresh);
+                found += __popcll(fresh & ~old);
             }
-            const int64_t pos = wave_append(want, &a.ctl[CTL_TAIL]);
-            if (want) record_push(a, pos, widx);
         }
     }
     if (a.prof) prof_add(a, PROF_TOPDOWN, wave_sum_u64(found), 0, lane);
@@ -282,7 +281,8 @@ __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t
 
 // Bottom-up: every (w, j) with unvisited live sources looks for frontier
 // neighbours and stops early once all its unvisited sources are found
-// (membership only: the path counts are pulled afterwards from all parents).
+// (membership only: the path counts are pulled afterwards from all parents;
+// the level's record is built from the words by k_level_*).
 __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *nxt)
 {
     const int64_t total = a.n << a.logW;
@@ -291,7 +291,6 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
     unsigned long long found = 0;
     for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < total; i0 += stride) {
         const int64_t idx = i0 + threadIdx.x;
-        bool app = false;
         if (idx < total) {
             const uint32_t j = (uint32_t)idx & wmask;
             const uint64_t want = ~a.vis[idx] & a.valid[j] & a.active[j];
@@ -312,99 +311,170 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
                 const uint64_t fresh = acc & want;
                 if (fresh) {
                     nxt[idx] = fresh;
-                    app = true;
                     found += __popcll(fresh);
                 }
             }
         }
-        const int64_t pos = wave_append(app, &a.ctl[CTL_TAIL]);
-        if (app) record_push(a, pos, (uint32_t)idx);
     }
     if (a.prof) prof_add(a, PROF_BOTTOMUP, wave_sum_u64(found), 0, lane_id());
 }
 
-// ------------------------------------------------ pool segment allocation
+// ------------------------------------------------------- level record
 //
-// A new level's entries receive consecutive pool segments in record order,
-// entry e owning popcount(mask) slots. The offsets come from a two-pass
-// prefix sum (no contended counter): k_seg_count scans blocks of
-// 2^kSegShift entries, k_seg_base scans the block totals from the pool tail.
-constexpr int kSegShift = 10;   // 256 threads x 4 entries
+// After discovery the new level exists only as dense words nxt[v][j]. The
+// record entries (one per non-zero word, in (vertex, word) order) and their
+// pool segments (popcount(word) consecutive slots each, same order) are laid
+// out by a prefix sum: k_level_count totals blocks of 2^kLevelShift words,
+// k_level_scan turns the totals into block offsets from the record and pool
+// tails, and k_level_write emits the entries. No contended counter is used.
+constexpr int kLevelShift = 10;   // 256 threads x 4 words
 
-// Also moves each entry's final mask into the record and the visited words.
-__global__ __launch_bounds__(256) void k_seg_count(BatchArgs a, int64_t e0, int64_t e1,
-                                                   const uint64_t *nxt, unsigned long long *bsum)
+// scan of (entries, slots) over the block's threads; returns this thread's
+// exclusive offsets and leaves the block totals in tot_e / tot_s
+__device__ __forceinline__ void block_scan2(int ce, int cs, int &pe, int &ps, int &tot_e,
+                                            int &tot_s)
 {
-    __shared__ int wsum[4];
-    const int tid = threadIdx.x;
+    __shared__ int we[4], ws[4];
     const int lane = lane_id();
-    const int wv = tid >> 6;
-    const int64_t base = e0 + ((int64_t)blockIdx.x << kSegShift) + (int64_t)tid * 4;
-    int c[4];
-    int tsum = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t e = base + r;
-        c[r] = 0;
-        if (e < e1) {
-            const uint32_t idx = a.ridx[e];
-            const uint64_t m = nxt[idx];
-            a.rmask[e] = m;
-            a.vis[idx] |= m;   // each (v, j) occurs once per level
-            c[r] = __popcll(m);
-        }
-        tsum += c[r];
-    }
-    int incl = tsum;
+    const int wv = threadIdx.x >> 6;
+    int ie = ce, is = cs;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
+        const int ye = __shfl_up(ie, off, 64);
+        const int ys = __shfl_up(is, off, 64);
+        if (lane >= off) {
+            ie += ye;
+            is += ys;
+        }
     }
-    if (lane == 63) wsum[wv] = incl;
+    if (lane == 63) {
+        we[wv] = ie;
+        ws[wv] = is;
+    }
     __syncthreads();
-    int run = incl - tsum;
-    for (int w = 0; w < wv; ++w) run += wsum[w];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t e = base + r;
-        if (e < e1) a.rseg[e] = (uint64_t)run;
-        run += c[r];
+    pe = ie - ce;
+    ps = is - cs;
+    tot_e = 0;
+    tot_s = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wv) {
+            pe += we[w];
+            ps += ws[w];
+        }
+        tot_e += we[w];
+        tot_s += ws[w];
     }
-    if (tid == 255) bsum[blockIdx.x] = (unsigned long long)run;
 }
 
-// One workgroup of 1024 threads: bsum[b] becomes the pool tail plus the sum
-// of the totals of blocks before b; the tail advances past the level.
-__global__ __launch_bounds__(1024) void k_seg_base(unsigned long long *bsum, int64_t nb,
-                                                   unsigned long long *ctl)
+__global__ __launch_bounds__(256) void k_level_count(const uint64_t *nxt, int64_t total,
+                                                     unsigned long long *bcnt,
+                                                     unsigned long long *bpop)
 {
-    __shared__ unsigned long long wsum[16];
+    const int64_t base = ((int64_t)blockIdx.x << kLevelShift) + (int64_t)threadIdx.x * 4;
+    int ce = 0, cs = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t m = base + r < total ? nxt[base + r] : 0ull;
+        ce += m != 0;
+        cs += __popcll(m);
+    }
+    int pe, ps, te, ts;
+    block_scan2(ce, cs, pe, ps, te, ts);
+    if (threadIdx.x == 0) {
+        bcnt[blockIdx.x] = (unsigned long long)te;
+        bpop[blockIdx.x] = (unsigned long long)ts;
+    }
+}
+
+// One workgroup of 1024 threads: exclusive scan of the block totals from the
+// record tail (ctl[CTL_TAIL]) and the pool tail (ctl[CTL_POOL]); both tails
+// advance past the level, and a record beyond `cap` raises the overflow flag.
+__global__ __launch_bounds__(1024) void k_level_scan(unsigned long long *bcnt,
+                                                     unsigned long long *bpop, int64_t nb,
+                                                     unsigned long long *ctl, int64_t cap)
+{
+    __shared__ unsigned long long we[16], ws[16];
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wv = tid >> 6;
-    unsigned long long carry = ctl[CTL_POOL];
+    unsigned long long ce = ctl[CTL_TAIL], cs = ctl[CTL_POOL];
     for (int64_t i0 = 0; i0 < nb; i0 += 1024) {
         const int64_t i = i0 + tid;
-        const unsigned long long x = i < nb ? bsum[i] : 0ull;
-        unsigned long long incl = x;
+        const unsigned long long xe = i < nb ? bcnt[i] : 0ull;
+        const unsigned long long xs = i < nb ? bpop[i] : 0ull;
+        unsigned long long ie = xe, is = xs;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const unsigned long long y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
+            const unsigned long long ye = __shfl_up(ie, off, 64);
+            const unsigned long long ys = __shfl_up(is, off, 64);
+            if (lane >= off) {
+                ie += ye;
+                is += ys;
+            }
         }
-        if (lane == 63) wsum[wv] = incl;
+        if (lane == 63) {
+            we[wv] = ie;
+            ws[wv] = is;
+        }
         __syncthreads();
-        unsigned long long before = 0, total = 0;
+        unsigned long long be = 0, bs = 0, te = 0, ts = 0;
         for (int w = 0; w < 16; ++w) {
-            if (w < wv) before += wsum[w];
-            total += wsum[w];
+            if (w < wv) {
+                be += we[w];
+                bs += ws[w];
+            }
+            te += we[w];
+            ts += ws[w];
         }
-        if (i < nb) bsum[i] = carry + before + incl - x;
-        carry += total;
+        if (i < nb) {
+            bcnt[i] = ce + be + ie - xe;
+            bpop[i] = cs + bs + is - xs;
+        }
+        ce += te;
+        cs += ts;
         __syncthreads();
     }
-    if (tid == 0) ctl[CTL_POOL] = carry;
+    if (tid == 0) {
+        ctl[CTL_TAIL] = ce;
+        ctl[CTL_POOL] = cs;
+        if (ce > (unsigned long long)cap) ctl[CTL_REC_OVERFLOW] = 1ull;
+    }
+}
+
+// Entries of the level in (vertex, word) order with their masks and pool
+// segments; the words join the visited set.
+__global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t *nxt,
+                                                     const unsigned long long *bcnt,
+                                                     const unsigned long long *bpop)
+{
+    const int64_t total = a.n << a.logW;
+    const int64_t base = ((int64_t)blockIdx.x << kLevelShift) + (int64_t)threadIdx.x * 4;
+    uint64_t m[4];
+    int ce = 0, cs = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        m[r] = base + r < total ? nxt[base + r] : 0ull;
+        ce += m[r] != 0;
+        cs += __popcll(m[r]);
+    }
+    int pe, ps, te, ts;
+    block_scan2(ce, cs, pe, ps, te, ts);
+    uint64_t pos = bcnt[blockIdx.x] + (uint64_t)pe;
+    uint64_t seg = bpop[blockIdx.x] + (uint64_t)ps;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (m[r]) {
+            const int64_t idx = base + r;
+            if ((int64_t)pos < a.cap) {
+                a.ridx[pos] = (uint32_t)idx;
+                a.rmask[pos] = m[r];
+                a.rseg[pos] = seg;
+            }
+            a.vis[idx] |= m[r];
+            pos += 1;
+            seg += (uint64_t)__popcll(m[r]);
+        }
+    }
 }
 
 // ------------------------------------------------- neighbour pull (shared)
@@ -621,15 +691,14 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
 }
 
 // kBackward = false: sigma pull for the new level (F/SG = previous frontier;
-//   masks and in-block segment offsets from k_seg_count, block bases from
-//   k_seg_base; the absolute segments are published in the record and SGo).
+//   masks and pool segments from the record written by k_level_write; the
+//   segments are published in SGo for the next level's pull).
 // kBackward = true: dependency sweep (F/SG = next-deeper frontier, masks and
 //   segments from the record; the entry's own word and segment are scattered
 //   into Fo/SGo for the next, shallower level).
 template <bool kExt, bool kBackward>
 __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F,
-                                           const uint64_t *SG, const unsigned long long *bbase,
-                                           uint64_t *Fo, uint64_t *SGo)
+                                           const uint64_t *SG, uint64_t *Fo, uint64_t *SGo)
 {
     __shared__ TileLds t;
     const int tid = threadIdx.x;
@@ -652,7 +721,7 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 v = (int32_t)(idx >> a.logW);
                 j = idx & wmask;
                 m = a.rmask[e];
-                seg = a.rseg[e] + (kBackward ? 0ull : bbase[(e - e0) >> kSegShift]);
+                seg = a.rseg[e];
                 beg = a.row[v];
                 deg = (int32_t)(a.row[v + 1] - beg);
             }
@@ -689,7 +758,6 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             if (lane < kTile && e < e1) {
                 const uint32_t idx = ((uint32_t)v << a.logW) + j;
                 if (!kBackward) {
-                    a.rseg[e] = seg;
                     SGo[idx] = seg;
                 } else {
                     Fo[idx] = m;
@@ -734,10 +802,9 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
 template <bool kExt>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1 : 8, 8))) void k_sigma_pull(BatchArgs a, int64_t e0, int64_t e1,
                                                        const uint64_t *cur, const uint64_t *sgcur,
-                                                       const unsigned long long *bbase,
                                                        uint64_t *sgnxt)
 {
-    pull_tiles<kExt, false>(a, e0, e1, cur, sgcur, bbase, nullptr, sgnxt);
+    pull_tiles<kExt, false>(a, e0, e1, cur, sgcur, nullptr, sgnxt);
 }
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
@@ -751,7 +818,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
                                                      const uint64_t *fnext, const uint64_t *sgnext,
                                                      uint64_t *fown, uint64_t *sgown)
 {
-    pull_tiles<kExt, true>(a, e0, e1, fnext, sgnext, nullptr, fown, sgown);
+    pull_tiles<kExt, true>(a, e0, e1, fnext, sgnext, fown, sgown);
 }
 
 // ------------------------------------------------------------- lane order
