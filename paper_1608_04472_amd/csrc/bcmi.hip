@@ -758,21 +758,44 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
 // ------------------------------------------------------------ lane order
 
 // key[v] packs the BFS distances from the landmarks (first landmark in the
-// top byte), computed once per graph with the per-source form.
+// top byte), computed once per graph by one multi-source BFS.
 void ensure_source_keys(bc_graph *g)
 {
     if (g->skey_ready) return;
     const int64_t n = g->n;
+    const int nl = (int)g->landmarks.size();
     hipStream_t s = g->stream;
     g->skey.ensure((size_t)n);
-    HIPX(hipMemsetAsync(g->skey.p, 0, (size_t)n * 8, s));
-    g->w->probe_src.ensure(1);
-    for (int32_t l : g->landmarks) {
-        HIPX(hipMemcpyAsync(g->w->probe_src.p, &l, 4, hipMemcpyHostToDevice, s));
-        run_single(g, g->w->probe_src.p, true);
-        launch(s, grid_for(n), k_key_push, g->skey.p, (const int32_t *)g->w->ss_d.p, n);
-        HIPX(hipStreamSynchronize(s));   // `l` is read by the copy above
+    DBuf<uint8_t> f0, f1, seen;
+    DBuf<int32_t> lm;
+    DBuf<unsigned long long> grew;
+    f0.ensure((size_t)n);
+    f1.ensure((size_t)n);
+    seen.ensure((size_t)n);
+    lm.ensure((size_t)std::max(nl, 1));
+    grew.ensure(1);
+    try {
+        HIPX(hipMemcpy(lm.p, g->landmarks.data(), (size_t)nl * 4, hipMemcpyHostToDevice));
+        launch(s, grid_for(n), k_key_init, (const int32_t *)lm.p, (int32_t)nl, n, f0.p, seen.p,
+               g->skey.p);
+        const uint8_t all = (uint8_t)((1u << nl) - 1u);
+        uint8_t *f = f0.p, *fn = f1.p;
+        for (int32_t level = 1;; ++level) {
+            HIPX(hipMemsetAsync(grew.p, 0, 8, s));
+            launch(s, grid_for(n), k_key_level, (const int64_t *)g->row.p, (const int32_t *)g->col.p,
+                   n, all, level, (const uint8_t *)f, fn, seen.p, g->skey.p, grew.p);
+            unsigned long long h = 0;
+            HIPX(hipMemcpyAsync(&h, grew.p, 8, hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            if (!h) break;
+            std::swap(f, fn);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        f0.release(); f1.release(); seen.release(); lm.release(); grew.release();
+        throw;
     }
+    f0.release(); f1.release(); seen.release(); lm.release(); grew.release();
     g->skey_ready = true;
 }
 

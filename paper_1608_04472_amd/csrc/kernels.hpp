@@ -555,10 +555,29 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t
     }
 }
 
-__device__ __forceinline__ double wave_sum(double x)
+// x from the lane DPP control `Ctrl` selects (0 where no lane is selected or
+// the row is masked off)
+template <int Ctrl, int RowMask, bool BoundCtrl>
+__device__ __forceinline__ double dpp_f64(double x)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, Ctrl, RowMask, 0xf, BoundCtrl);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), Ctrl, RowMask, 0xf,
+                                               BoundCtrl);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sum over the 64 lanes in a fixed tree (pairs, quads, half rows, rows, then
+// rows 0+1 and 2+3, then all four); the total lands in lane 63. All lanes
+// must be active.
+__device__ __forceinline__ double wave_sum_to_last(double x)
+{
+    x += dpp_f64<0xB1, 0xF, true>(x);    // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E, 0xF, true>(x);    // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141, 0xF, true>(x);   // row_half_mirror
+    x += dpp_f64<0x140, 0xF, true>(x);   // row_mirror
+    x += dpp_f64<0x142, 0xA, false>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_f64<0x143, 0xC, false>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 
@@ -684,8 +703,8 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
             if (a.dlt) a.dlt[v * a.B + b] = d;
         }
         if (a.vsum) {
-            const double tsum = wave_sum(d);
-            if (lane == 0) a.vsum[((uint32_t)v << a.logW) + j] = t.vs[i] + tsum;
+            const double tsum = wave_sum_to_last(d);
+            if (lane == kWave - 1) a.vsum[((uint32_t)v << a.logW) + j] = t.vs[i] + tsum;
         }
     }
 }
@@ -829,14 +848,57 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
 // fewer distinct levels. Sources are therefore sorted by a clustering key
 // (distances to a few landmark vertices) before they are cut into batches.
 
-// key[v] = (key[v] << 8) | min(d[v], 255), an unreached vertex counting as 255
-__global__ void k_key_push(uint64_t *key, const int32_t *d, int64_t n)
+// The key packs the BFS distance of v from landmark l (capped at 255; 255
+// when unreached) into byte 7 - l. All landmarks advance together: bit l of
+// a frontier byte marks v as on landmark l's current level.
+
+// level 0: key bytes 255, the landmarks themselves at distance 0
+__global__ void k_key_init(const int32_t *lm, int32_t nl, int64_t n, uint8_t *f, uint8_t *seen,
+                           uint64_t *key)
 {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t x = d[v];
-        const uint64_t c = (x < 0 || x > 255) ? 255u : (uint64_t)x;
-        key[v] = (key[v] << 8) | c;
+        uint8_t bits = 0;
+        uint64_t k = ~0ull;
+        for (int l = 0; l < nl; ++l)
+            if (lm[l] == v) {
+                bits |= (uint8_t)(1u << l);
+                k &= ~(0xffull << (8 * (7 - l)));
+            }
+        f[v] = bits;
+        seen[v] = bits;
+        key[v] = k;
+    }
+}
+
+// one level (bottom-up): v joins landmark l's next level when a neighbour is
+// on its current one; `grew` is set when any vertex joins
+__global__ void k_key_level(const int64_t *row, const int32_t *col, int64_t n, uint8_t all,
+                            int32_t level, const uint8_t *f, uint8_t *fn, uint8_t *seen,
+                            uint64_t *key, unsigned long long *grew)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t want = (uint8_t)(all & ~seen[v]);
+        uint8_t fresh = 0;
+        if (want) {
+            uint8_t acc = 0;
+            for (int64_t e = row[v], end = row[v + 1]; e < end; ++e) {
+                acc |= f[col[e]];
+                if ((acc & want) == want) break;
+            }
+            fresh = acc & want;
+        }
+        fn[v] = fresh;
+        if (fresh) {
+            seen[v] |= fresh;
+            uint64_t k = key[v];
+            const uint64_t d = level < 255 ? (uint64_t)level : 255u;
+            for (int l = 0; l < 8; ++l)
+                if ((fresh >> l) & 1u) k = (k & ~(0xffull << (8 * (7 - l)))) | (d << (8 * (7 - l)));
+            key[v] = k;
+            *grew = 1ull;
+        }
     }
 }
 
