@@ -757,8 +757,8 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
 
 // ------------------------------------------------------------ lane order
 
-// key[v] packs the BFS distances from the landmarks (first landmark in the
-// top byte), computed once per graph by one multi-source BFS.
+// key[v]: the BFS distances from the landmarks interleaved in Morton order,
+// computed once per graph by one multi-source BFS.
 void ensure_source_keys(bc_graph *g)
 {
     if (g->skey_ready) return;
@@ -780,6 +780,7 @@ void ensure_source_keys(bc_graph *g)
                g->skey.p);
         const uint8_t all = (uint8_t)((1u << nl) - 1u);
         uint8_t *f = f0.p, *fn = f1.p;
+        int32_t depth = 0;
         for (int32_t level = 1;; ++level) {
             HIPX(hipMemsetAsync(grew.p, 0, 8, s));
             launch(s, grid_for(n), k_key_level, (const int64_t *)g->row.p, (const int32_t *)g->col.p,
@@ -788,8 +789,13 @@ void ensure_source_keys(bc_graph *g)
             HIPX(hipMemcpyAsync(&h, grew.p, 8, hipMemcpyDeviceToHost, s));
             HIPX(hipStreamSynchronize(s));
             if (!h) break;
+            depth = level;
             std::swap(f, fn);
         }
+        // bits per landmark: enough for the deepest level (unreached clamps)
+        int32_t bits = 1;
+        while (bits < 8 && (1 << bits) <= depth) ++bits;
+        launch(s, grid_for(n), k_key_morton, g->skey.p, n, bits);
     } catch (...) {
         (void)hipStreamSynchronize(s);
         f0.release(); f1.release(); seen.release(); lm.release(); grew.release();
@@ -1153,8 +1159,8 @@ bc_status bc_profile_enable(bc_graph *g, int32_t enable)
         need(g, "null graph");
         use_device(g);
         prof_flush(g);
-        g->prof_dev.ensure(2 * PROF_KERNELS);
-        HIPX(hipMemsetAsync(g->prof_dev.p, 0, 2 * PROF_KERNELS * 8, g->stream));
+        g->prof_dev.ensure(2 * PROF_KERNELS * kProfSlots);
+        HIPX(hipMemsetAsync(g->prof_dev.p, 0, 2 * PROF_KERNELS * kProfSlots * 8, g->stream));
         HIPX(hipStreamSynchronize(g->stream));
         for (int k = 0; k < PROF_KERNELS; ++k) {
             g->prof_ms[k] = 0.0;
@@ -1173,8 +1179,12 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         use_device(g);
         prof_flush(g);
         unsigned long long units[2 * PROF_KERNELS] = {};
-        if (g->prof_dev.p)
-            HIPX(hipMemcpy(units, g->prof_dev.p, sizeof(units), hipMemcpyDeviceToHost));
+        if (g->prof_dev.p) {
+            std::vector<unsigned long long> slots((size_t)2 * PROF_KERNELS * kProfSlots);
+            HIPX(hipMemcpy(slots.data(), g->prof_dev.p, slots.size() * 8, hipMemcpyDeviceToHost));
+            for (int k = 0; k < 2 * PROF_KERNELS; ++k)
+                for (int q = 0; q < kProfSlots; ++q) units[k] += slots[(size_t)k * kProfSlots + q];
+        }
         for (int k = 0; k < 2 * PROF_KERNELS; ++k) units[k] += (unsigned long long)g->prof_host_units[k];
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
                                                   "sigma_pull", "backward", "level_record"};

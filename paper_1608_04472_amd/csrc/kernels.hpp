@@ -144,13 +144,25 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
+// Work-unit counters: prof[(2 * kernel + c) * kProfSlots + slot], c = 0 for
+// units a, 1 for units b. A workgroup adds into slot blockIdx % kProfSlots,
+// so the counters' atomics spread over kProfSlots addresses (one address
+// would serialise every wavefront's add); the host sums the slots.
+constexpr int kProfSlots = 64;
+
+__device__ __forceinline__ unsigned long long *prof_slot(unsigned long long *prof, int kernel,
+                                                         int c)
+{
+    return prof + (2 * kernel + c) * kProfSlots + (blockIdx.x & (kProfSlots - 1));
+}
+
 // add wave-summed unit counts (lane 0 of each wave adds)
 __device__ __forceinline__ void prof_add_raw(unsigned long long *prof, int kernel,
                                              unsigned long long ua, unsigned long long ub)
 {
     if ((threadIdx.x & 63) == 0) {
-        if (ua) atomicAdd(&prof[2 * kernel], ua);
-        if (ub) atomicAdd(&prof[2 * kernel + 1], ub);
+        if (ua) atomicAdd(prof_slot(prof, kernel, 0), ua);
+        if (ub) atomicAdd(prof_slot(prof, kernel, 1), ub);
     }
 }
 
@@ -160,8 +172,8 @@ __device__ __forceinline__ void prof_add(const BatchArgs &a, int kernel, unsigne
 {
     if (!a.prof) return;
     if (lane == 0) {
-        if (ua) atomicAdd(&a.prof[2 * kernel], ua);
-        if (ub) atomicAdd(&a.prof[2 * kernel + 1], ub);
+        if (ua) atomicAdd(prof_slot(a.prof, kernel, 0), ua);
+        if (ub) atomicAdd(prof_slot(a.prof, kernel, 1), ub);
     }
 }
 
@@ -902,6 +914,26 @@ __global__ void k_key_level(const int64_t *row, const int32_t *col, int64_t n, u
     }
 }
 
+// Final key: the distance bytes interleaved bit by bit (Morton order), most
+// significant bits first, each distance clamped to `bits` bits: sources whose
+// distances to all landmarks are close get close keys.
+__global__ void k_key_morton(uint64_t *key, int64_t n, int32_t bits)
+{
+    const uint64_t top = (1ull << bits) - 1ull;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = key[v];
+        uint64_t m = 0;
+        for (int b = bits - 1; b >= 0; --b)
+            for (int l = 0; l < 8; ++l) {
+                uint64_t d = (k >> (8 * (7 - l))) & 0xffull;
+                d = d > top ? top : d;
+                m = (m << 1) | ((d >> b) & 1ull);
+            }
+        key[v] = m;
+    }
+}
+
 // sort input: out[i] = key[src[i]], idx[i] = i
 __global__ void k_key_gather(const uint64_t *key, const int32_t *src, int64_t k, uint64_t *out,
                              int32_t *idx)
@@ -1231,7 +1263,7 @@ __global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
     }
     if (a.prof) {
         const unsigned long long t = wave_sum_u64(found);
-        if (lane == 0 && t) atomicAdd(&a.prof[2 * PROF_TOPDOWN], t);
+        if (lane == 0 && t) atomicAdd(prof_slot(a.prof, PROF_TOPDOWN, 0), t);
     }
 }
 

@@ -284,6 +284,41 @@ def test_bit_identical_reruns_and_batch_positions(dev):
     G.close()
 
 
+def test_lane_order_maps_rows_back(dev):
+    """Samples are sorted by a clustering key before batching (from 128 on):
+    per-source rows, distances and path counts must come back in the caller's
+    order, bit-identical whatever the order of the list; sums may differ only
+    by summation order. Pair mode maps (u, v) rows the same way."""
+    g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_BATCHED, 128, 0.0)
+    src = gg.philox_sources(11, 300, g.n)
+    say("lane order rmat12 k=300")
+    f1, d1, s1 = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL, dist=True, sigma=True)
+    rev = np.ascontiguousarray(src[::-1])
+    f2, d2, s2 = bc.dependencies(G, T(rev, dev), bc.BC_OUT_FULL, dist=True, sigma=True)
+    assert torch.equal(f1, f2.flip(0)) and torch.equal(d1, d2.flip(0))
+    assert torch.equal(s1[0], s2[0].flip(0)) and torch.equal(s1[1], s2[1].flip(0))
+    for i in (0, 150, 299):
+        dd, _, de = O.brandes(g, int(src[i]))
+        assert np.array_equal(d1[i].cpu().numpy(), dd)
+        assert_close(f1[i].cpu().numpy(), de, what="lane order row %d" % i)
+    a, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+    b, _, _ = bc.dependencies(G, T(rev, dev), bc.BC_OUT_SUM)
+    assert_close(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-12, what="sum in both orders")
+    assert_close(a.cpu().numpy(), f1.sum(0).cpu().numpy(), rtol=1e-12, what="sum vs rows")
+    us = torch.empty(200, dtype=torch.int32, device=dev)
+    vs = torch.empty(200, dtype=torch.int32, device=dev)
+    bc.bc_draw_pairs(G, 5, 0, 200, us, vs)
+    p1 = bc.pair_dependencies(G, us, vs)
+    p2 = bc.pair_dependencies(G, us.flip(0).contiguous(), vs.flip(0).contiguous())
+    assert torch.equal(p1, p2.flip(0))
+    for i in (0, 199):
+        assert_close(p1[i].cpu().numpy(), O.pair_dependency(g, int(us[i]), int(vs[i])),
+                     what="lane order pair %d" % i)
+    G.close()
+
+
 def test_invalid_arguments(dev):
     g = gg.path(6)
     G = bc.Graph(g.row, g.col)
