@@ -309,15 +309,21 @@ __global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *
             if (want) {
                 const int64_t v = idx >> a.logW;
                 uint64_t acc = 0;
-                const int64_t end = a.row[v + 1];
-                // four neighbours per step so their loads overlap
-                for (int64_t e = a.row[v]; e < end; e += 4) {
-                    uint64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-                    f0 = cur[((int64_t)a.col[e] << a.logW) + j];
-                    if (e + 1 < end) f1 = cur[((int64_t)a.col[e + 1] << a.logW) + j];
-                    if (e + 2 < end) f2 = cur[((int64_t)a.col[e + 2] << a.logW) + j];
-                    if (e + 3 < end) f3 = cur[((int64_t)a.col[e + 3] << a.logW) + j];
-                    acc |= f0 | f1 | f2 | f3;
+                const int64_t beg = a.row[v], end = a.row[v + 1];
+                // eight neighbours per step; the next step's neighbour ids are
+                // loaded while this step's frontier words are in flight
+                int32_t c[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) c[k] = beg + k < end ? a.col[beg + k] : -1;
+                for (int64_t e = beg; e < end; e += 8) {
+                    uint64_t f[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        f[k] = c[k] >= 0 ? cur[((int64_t)c[k] << a.logW) + j] : 0ull;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) c[k] = e + 8 + k < end ? a.col[e + 8 + k] : -1;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc |= f[k];
                     if ((acc & want) == want) break;
                 }
                 const uint64_t fresh = acc & want;
