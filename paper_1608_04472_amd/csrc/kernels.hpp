@@ -500,7 +500,10 @@ __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t
 // Issue the value loads of up to kInFlight overlapping neighbours, taken from
 // bal (bit k: the neighbour staged in lane k, whose frontier word and pool
 // segment are this lane's fm and sx) in ascending order. fk[q] receives the
-// q-th neighbour's overlap with the wave-uniform `want`; only its lanes load.
+// q-th neighbour's overlap with the wave-uniform `want` (0 for an unused
+// slot). Every lane loads, so the loads are straight-line code and all of a
+// batch is in flight together: lanes outside the overlap read the segment's
+// first slot (always valid) and add_batch discards it.
 template <bool kExt>
 __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uint64_t sx,
                                             uint64_t want, uint64_t &bal,
@@ -510,6 +513,8 @@ __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uin
 #pragma unroll
     for (int q = 0; q < kInFlight; ++q) {
         fk[q] = 0;
+        vm[q] = 0.0;
+        ve[q] = 0;
         if (bal) {
             const int k = __ffsll((long long)bal) - 1;
             bal &= bal - 1;
@@ -517,16 +522,17 @@ __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uin
             const uint64_t sk = lane_read_u64(sx, k);
             fk[q] = mk & want;
             units += __popcll(fk[q]);
-            if (lane_in(fk[q])) {
-                const uint64_t o = sk + slot_rank(mk);
-                vm[q] = a.sig[o];
-                if (kExt) ve[q] = a.sige[o];
-            }
+            const uint64_t o = sk + (lane_in(fk[q]) ? slot_rank(mk) : 0u);
+            vm[q] = a.sig[o];
+            if (kExt) ve[q] = a.sige[o];
         }
     }
 }
 
 // Add a batch in issue order; lanes outside a neighbour's overlap add nothing.
+// In plain FP64 every slot is consumed by every lane without a branch, so no
+// load of a batch can be pending when its register is reused by the next one
+// (the compiler would otherwise wait for all memory operations first).
 template <bool kExt>
 __device__ __forceinline__ void add_batch(const double (&vm)[kInFlight],
                                           const int32_t (&ve)[kInFlight],
@@ -535,9 +541,14 @@ __device__ __forceinline__ void add_batch(const double (&vm)[kInFlight],
 {
 #pragma unroll
     for (int q = 0; q < kInFlight; ++q) {
-        if (lane_in(fk[q])) {
-            if (kExt) accx = xadd(accx, XNum{vm[q], ve[q]});
-            else accp += vm[q];
+        const bool on = lane_in(fk[q]);
+        if (kExt) {
+            if (fk[q]) {
+                const XNum y = xadd(accx, XNum{vm[q], ve[q]});
+                accx = on ? y : accx;
+            }
+        } else {
+            accp += on ? vm[q] : 0.0;
         }
     }
 }
