@@ -687,12 +687,18 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
     const uint64_t seg = uniform_u64(t.seg[i]);
     const int b = (int)(j << 6) + lane;
     const bool mine = lane_in(m);
-    const uint64_t own_slot = seg + slot_rank(m);
-    double own = 0.0;
+    // backward: every lane loads its slot (the segment's first slot outside the
+    // entry) and computes rho, only the entry's lanes store (a load under a
+    // per-lane branch makes the compiler wait for all outstanding memory
+    // operations, the previous entry's stores included, before the next one)
+    const uint64_t own_slot = seg + ((kBackward && !mine) ? 0u : slot_rank(m));
+    double own = 1.0;
     int32_t owne = 0;
-    if (kBackward && mine) {
+    int32_t dstb = -1;
+    if (kBackward) {
         own = a.sig[own_slot];
         if (kExt) owne = a.sige[own_slot];
+        if (a.dest) dstb = a.dest[b];
     }
     XNum acc{0.0, 0};
     double accp = 0.0;
@@ -714,23 +720,24 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
                 atomicAnd((unsigned long long *)&a.active[j], ~(1ull << lane));
         }
     } else {
-        double d = 0.0;
-        if (mine) {
-            // a slot without a destination (< 0) is a source sample
-            const double term = (a.dest && a.dest[b] >= 0)
-                                    ? (a.dest[b] == (int32_t)v ? 1.0 : 0.0) : 1.0;
-            if (kExt) {
-                // delta = sigma(v) * sum(rho): exponents add back to the plain range
-                d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
-                const XNum r = xnorm((term + d) / own, -owne);
+        // a slot without a destination (< 0) is a source sample
+        const double term = dstb >= 0 ? (dstb == (int32_t)v ? 1.0 : 0.0) : 1.0;
+        double d;
+        if (kExt) {
+            // delta = sigma(v) * sum(rho): exponents add back to the plain range
+            d = acc.m == 0.0 ? 0.0 : ldexp(own * acc.m, owne + acc.e);
+            const XNum r = xnorm((term + d) / own, -owne);
+            if (mine) {
                 a.sig[own_slot] = r.m;
                 a.sige[own_slot] = r.e;
-            } else {
-                d = own * accp;
-                a.sig[own_slot] = (term + d) / own;
             }
-            if (a.dlt) a.dlt[v * a.B + b] = d;
+        } else {
+            d = own * accp;
+            const double rho = (term + d) / own;
+            if (mine) a.sig[own_slot] = rho;
         }
+        d = mine ? d : 0.0;
+        if (mine && a.dlt) a.dlt[v * a.B + b] = d;
         if (a.vsum) {
             const double tsum = wave_sum_to_last(d);
             if (lane == kWave - 1) a.vsum[((uint32_t)v << a.logW) + j] = t.vs[i] + tsum;
