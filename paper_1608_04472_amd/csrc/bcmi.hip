@@ -3,8 +3,9 @@
 //
 // Engine (one batch of B = 64 * 2^logW sources or pairs):
 //   forward, level by level: discover the next level top-down (narrow
-//   frontiers) or bottom-up (wide ones), pull path counts from all
-//   predecessors, clear the retired frontier words;
+//   frontiers) or bottom-up (wide ones) as dense words, lay out the level's
+//   record entries and pool segments by a prefix sum, pull path counts from
+//   all predecessors, clear the retired frontier words;
 //   backward, from the deepest recorded level up to level 1: pull rho from
 //   successors (Theorem 1), write delta and the vertex's own rho.
 // The host reads one 64-byte control block per level (queue tail, flags).

@@ -6,9 +6,11 @@
 //   vis[v*W + j]  bit l set once source b = 64j + l has reached v.
 //   F*[v*W + j]   dense frontier bitmap of one level (two rotating arrays);
 //   SG*[v*W + j]  beside it, the first pool slot of that (v, j) entry.
-//   Level record: entries (v, j) with a nonzero 64-bit mask m, appended level
-//   by level; level l occupies [off[l], off[l+1]). It replaces Brandes'
-//   distance-ordered stack: the backward sweep walks it from the deepest level.
+//   Level record: entries (v, j) with a nonzero 64-bit mask m, level after
+//   level, in (v, j) order within a level (laid out by a prefix sum over the
+//   level's dense words); level l occupies [off[l], off[l+1]). It replaces
+//   Brandes' distance-ordered stack: the backward sweep walks it from the
+//   deepest level.
 //   Value pool: entry e owns popcount(m_e) consecutive FP64 slots starting at
 //   rseg[e]; lane l of the entry's word (source 64j + l, bit l of m_e) lives at
 //   rseg[e] + (number of bits of m_e below l). It holds sigma_{s_b}(v), replaced
