@@ -86,7 +86,7 @@ def serving_leg(args, bc, gg):
         q["k_max"] = args.serve_kmax_pair if q["kind"] == 1 else args.serve_kmax_source
     log("serving: %d graphs (%d CSR entries) and %d queries generated in %.1fs" % (
         len(graphs), sum(g.nnz for g in graphs), len(qs), time.time() - t))
-    S = bc.Server(args.serve_budget_gib << 30, 256)
+    S = bc.Server(args.serve_budget_gib << 30, args.serve_batch)
     for g in graphs:
         S.add_graph(g.row, g.col)
     N = len(qs)
@@ -125,7 +125,7 @@ def serving_leg(args, bc, gg):
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "max_ms": float(lat.max()), "rounds": st["rounds"],
         "samples_executed": st["samples_executed"], "samples_used": st["samples_used"],
-        "batch_fill": st["samples_executed"] / max(1, 256 * st["rounds"]),
+        "batch_fill": st["samples_executed"] / max(1, args.serve_batch * st["rounds"]),
         "capped": int(sum(r["status"] == bc.BC_CAPPED for r in res)),
         "used_sample_gteps_full_search_equiv": edges / makespan / 1e9,
         "resident_bytes": st["resident_bytes"], "workspace_bytes": st["workspace_bytes"],
@@ -166,6 +166,8 @@ def main():
                          "exceeds one GPU's capacity)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--serve-batch", type=int, default=2048,
+                    help="samples per server round (power of two, 64..4096)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-dump", default="", help="write per-query results (JSON lines)")
     ap.add_argument("--serve-kmax-source", type=int, default=1024)
