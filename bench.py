@@ -166,7 +166,7 @@ def main():
                          "exceeds one GPU's capacity)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
-    ap.add_argument("--serve-batch", type=int, default=2048,
+    ap.add_argument("--serve-batch", type=int, default=4096,
                     help="samples per server round (power of two, 64..4096)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-dump", default="", help="write per-query results (JSON lines)")

@@ -123,6 +123,7 @@ struct Work {
     // lane order: sort keys and permutation of the requested samples
     DBuf<uint64_t> okey_in, okey_out;
     DBuf<int32_t> oidx_in, operm, lane_row;
+    DBuf<int32_t> draw_src, draw_dst;   // a round's draws in draw order
     DBuf<uint8_t> sort_tmp;
     unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
 
@@ -143,7 +144,7 @@ struct Work {
         lv.release(); pactive.release();
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release(); probe_src.release();
         okey_in.release(); okey_out.release(); oidx_in.release(); operm.release();
-        lane_row.release(); sort_tmp.release();
+        lane_row.release(); sort_tmp.release(); draw_src.release(); draw_dst.release();
         if (h_ctl) (void)hipHostFree(h_ctl);
         h_ctl = nullptr;
     }
@@ -828,6 +829,29 @@ void order_samples(bc_graph *g, const int32_t *sources, int64_t k)
                                             8 * (int)sizeof(uint64_t), s));
 }
 
+// Lane order inside a sampler or server round: the nb samples drawn into
+// g->w->srcs (and g->w->dest for pairs) are sorted by the lane-order key in
+// place; lane_row[b] is lane b's position in draw order, so gathers can hand
+// the stop rule its values in draw order. Returns null when the round keeps
+// draw order (small rounds, graphs without edges).
+const int32_t *order_round(bc_graph *g, int nb, bool pair, int B)
+{
+    if (nb < kOrderMin || g->landmarks.empty()) return nullptr;
+    Work &w = *g->w;
+    hipStream_t s = g->stream;
+    w.draw_src.ensure((size_t)nb);
+    w.draw_dst.ensure((size_t)nb);
+    w.lane_row.ensure((size_t)B);
+    HIPX(hipMemcpyAsync(w.draw_src.p, w.srcs.p, (size_t)nb * 4, hipMemcpyDeviceToDevice, s));
+    if (pair)
+        HIPX(hipMemcpyAsync(w.draw_dst.p, w.dest.p, (size_t)nb * 4, hipMemcpyDeviceToDevice, s));
+    order_samples(g, w.draw_src.p, nb);
+    launch(s, grid_for(nb), k_take_batch, (const int32_t *)w.operm.p, (int64_t)0, (int32_t)nb,
+           (const int32_t *)w.draw_src.p, pair ? (const int32_t *)w.draw_dst.p : nullptr,
+           w.srcs.p, w.dest.p, w.lane_row.p);
+    return w.lane_row.p;
+}
+
 // ------------------------------------------------------------ dependencies
 
 void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode, double *out,
@@ -995,8 +1019,10 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
             launch(s, grid_for((int64_t)T * p.B), k_p_gather_targets, a, targets, T,
                    (int32_t)p.B, g->w->X.p);
         } else {
+            const int32_t *lane_row = order_round(g, nb, pair, p.B);
             run_batch(g, p, nb, pair, &ext, nullptr, OUT_DELTA);
             BatchArgs a = make_args(g, p, ext, nb, pair, (int64_t)g->w->ridx.cap, OUT_DELTA);
+            a.lane_row = lane_row;
             launch(s, grid_for((int64_t)T * p.B), k_gather_targets, a, targets, T, g->w->X.p);
         }
         launch(s, grid_for(T), k_stop_rule, sa, (const double *)g->w->X.p, (int32_t)p.B, (int32_t)nb,
@@ -1479,8 +1505,10 @@ void server_round(bc_server *sv, int gi, int32_t *completed)
         launch(st, grid_for(nb), k_serve_draw, (const QueryDesc *)sv->qd.p,
                (const int32_t *)sv->slotq.p, (int32_t)nb, n, g->w->srcs.p, g->w->dest.p,
                sv->tgt.p);
+        const int32_t *lane_row = order_round(g, nb, true, B);
         run_batch(g, p, nb, true, &ext, nullptr, OUT_DELTA);
         BatchArgs a = make_args(g, p, ext, nb, true, (int64_t)g->w->ridx.cap, OUT_DELTA);
+        a.lane_row = lane_row;
         launch(st, grid_for(nb), k_gather_slots, a, (const int32_t *)sv->tgt.p, sv->X.p);
     }
     launch(st, grid_for(A), k_stop_queries, sv->qd.p, (int32_t)A, (const double *)sv->X.p);

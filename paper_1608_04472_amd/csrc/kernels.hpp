@@ -1072,7 +1072,9 @@ __global__ void k_gather_targets(BatchArgs a, const int32_t *targets, int32_t T,
         const int t = (int)(i / a.B);
         const int b = (int)(i - (int64_t)t * a.B);
         const int64_t v = targets[t];
-        X[i] = (b < a.nvalid && reached(a, v, b)) ? a.dlt[v * a.B + b] : 0.0;
+        // lanes may hold the round's samples in another order: write sample order
+        const int64_t r = (a.lane_row && b < a.nvalid) ? (int64_t)a.lane_row[b] : (int64_t)b;
+        X[(int64_t)t * a.B + r] = (b < a.nvalid && reached(a, v, b)) ? a.dlt[v * a.B + b] : 0.0;
     }
 }
 
@@ -1501,8 +1503,9 @@ __global__ void k_gather_slots(BatchArgs a, const int32_t *tgt, double *X)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.nvalid) return;
-    const int64_t v = tgt[b];
-    X[b] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
+    const int r = a.lane_row ? a.lane_row[b] : b;   // the lane's slot
+    const int64_t v = tgt[r];
+    X[r] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
 }
 
 __global__ void k_p_gather_slots(PairArgs a, const int32_t *tgt, double *X)
