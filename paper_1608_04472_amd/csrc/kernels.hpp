@@ -567,14 +567,26 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t
                                          double &accp, XNum &accx, unsigned long long &units)
 {
     const int64_t beg = a.row[v], end = a.row[v + 1];
-    for (int64_t base = beg; base < end; base += kWave) {
+    if (beg >= end) return;
+    // Pipelined over chunks of kWave neighbours: while chunk c's values are
+    // summed, chunk c+1's frontier words and segments and chunk c+2's
+    // neighbour ids are in flight. Every lane loads (clamped to the row's last
+    // neighbour) so no load sits under a per-lane branch.
+    auto nb_at = [&](int64_t base) {
         const int64_t p = base + lane;
-        uint64_t fm = 0, sx = 0;
-        if (p < end) {
-            const int64_t xi = ((int64_t)a.col[p] << a.logW) + j;
-            fm = F[xi];
-            if (fm & want) sx = SG[xi];
-        }
+        return a.col[p < end ? p : end - 1];
+    };
+    int32_t x_next = nb_at(beg + kWave);          // ids of chunk c+1
+    int64_t xi = ((int64_t)nb_at(beg) << a.logW) + j;
+    uint64_t f_cur = F[xi], s_cur = SG[xi];       // words of chunk c
+    for (int64_t base = beg; base < end; base += kWave) {
+        const bool in = base + lane < end;
+        const uint64_t fm = in ? f_cur : 0ull;
+        const uint64_t sx = (fm & want) ? s_cur : 0ull;
+        // issue the next chunk's words and the one after's ids
+        const int64_t xin = ((int64_t)x_next << a.logW) + j;
+        const uint64_t f_nxt = F[xin], s_nxt = SG[xin];
+        x_next = nb_at(base + 2 * kWave);
         uint64_t bal = wave_ballot((fm & want) != 0);
         while (bal) {
             double vm[kInFlight];
@@ -583,6 +595,8 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t
             issue_batch<kExt>(a, fm, sx, want, bal, vm, ve, fk, units);
             add_batch<kExt>(vm, ve, fk, accp, accx);
         }
+        f_cur = f_nxt;
+        s_cur = s_nxt;
     }
 }
 
