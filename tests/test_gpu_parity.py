@@ -249,6 +249,29 @@ def test_grid_counts_beyond_fp64_range(dev, sched):
     G.close()
 
 
+@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+def test_hub_rows_with_extended_counts(dev, sched):
+    # A 600x600 grid plus one hub joined to the 15x20 block of vertices in the
+    # far corner: from the near corner the hub sits ~1166 levels deep, where
+    # path counts are far beyond FP64's range, and its row (300 neighbours) is
+    # longer than a tile stages, so its sums take the global gather path.
+    x = y = 600
+    ids = np.arange(x * y).reshape(x, y)
+    s = np.concatenate([ids[:, :-1].ravel(), ids[:-1, :].ravel()])
+    d = np.concatenate([ids[:, 1:].ravel(), ids[1:, :].ravel()])
+    hub = x * y
+    block = ids[585:600, 580:600].ravel()
+    g = gg.from_edges(x * y + 1, np.concatenate([s, np.full(block.size, hub)]),
+                      np.concatenate([d, block]), "grid600+hub")
+    assert g.degree()[hub] == 300
+    G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
+    check_sources(G, g, np.array([0, hub, 359999, 180300], dtype=np.int32), dev,
+                  "grid600+hub")
+    assert G.stats()["extended"] == 1
+    G.close()
+
+
 def test_per_source_schedule(dev):
     g = gg.config_graph("er2000")
     G = bc.Graph(g.row, g.col)
