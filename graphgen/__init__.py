@@ -200,6 +200,88 @@ def ba(n: int, m: int, seed: int) -> CSR:
     return from_edges(n, src, dst, "ba%d_%d" % (n, m))
 
 
+def powerlaw_cluster(n: int, m: int, p: float, seed: int) -> CSR:
+    """Holme-Kim growth: preferential attachment with triad formation. Each new
+    vertex makes m edges; the first goes to a degree-proportional target, and
+    each later one, with probability p, to a random neighbour of the previous
+    target that is not yet linked (a triangle), else to another
+    degree-proportional target. Starts from the clique K_{m+1}."""
+    r = rng(seed, STREAM_GRAPH)
+    adj = [set() for _ in range(n)]
+    ends = []                       # every edge endpoint: degree-proportional draws
+    src, dst = [], []
+
+    def link(a, b):
+        adj[a].add(b)
+        adj[b].add(a)
+        ends.extend((a, b))
+        src.append(a)
+        dst.append(b)
+
+    for a in range(m + 1):
+        for b in range(a + 1, m + 1):
+            link(a, b)
+    for v in range(m + 1, n):
+        made = 0
+        last = -1
+        while made < m:
+            u = -1
+            if last >= 0 and made > 0 and r.random() < p:
+                cand = [w for w in adj[last] if w != v and w not in adj[v]]
+                if cand:
+                    u = cand[int(r.integers(len(cand)))]
+            if u < 0:
+                while True:
+                    u = ends[int(r.integers(len(ends)))]
+                    if u != v and u not in adj[v]:
+                        break
+            link(v, u)
+            last = u
+            made += 1
+    return from_edges(n, np.array(src), np.array(dst), "plc%d_%d" % (n, m))
+
+
+def small_world(n: int, k: int, p: float, seed: int) -> CSR:
+    """Watts-Strogatz: the ring lattice where each vertex links to its k/2
+    nearest vertices on either side, then each lattice edge (i, i+j), taken in
+    order of j and then i, moves its far end with probability p to a uniform
+    vertex that is neither i nor already linked to it."""
+    r = rng(seed, STREAM_GRAPH)
+    adj = [set() for _ in range(n)]
+    for i in range(n):
+        for j in range(1, k // 2 + 1):
+            b = (i + j) % n
+            adj[i].add(b)
+            adj[b].add(i)
+    for j in range(1, k // 2 + 1):
+        for i in range(n):
+            b = (i + j) % n
+            if b not in adj[i] or r.random() >= p or len(adj[i]) >= n - 1:
+                continue
+            while True:
+                w = int(r.integers(n))
+                if w != i and w not in adj[i]:
+                    break
+            adj[i].discard(b)
+            adj[b].discard(i)
+            adj[i].add(w)
+            adj[w].add(i)
+    src = [a for a in range(n) for b in adj[a] if a < b]
+    dst = [b for a in range(n) for b in adj[a] if a < b]
+    return from_edges(n, np.array(src), np.array(dst), "ws%d_%d" % (n, k))
+
+
+def average_clustering(g: CSR) -> float:
+    """Mean over vertices of the local clustering coefficient (0 below degree 2)."""
+    import scipy.sparse as sp
+    a = sp.csr_matrix((np.ones(g.nnz, dtype=np.float64), g.col, g.row), shape=(g.n, g.n))
+    tri = np.asarray((a @ a).multiply(a).sum(axis=1)).ravel() / 2.0
+    d = np.diff(g.row).astype(np.float64)
+    pairs = d * (d - 1) / 2.0
+    c = np.divide(tri, pairs, out=np.zeros_like(tri), where=pairs > 0)
+    return float(c.mean())
+
+
 def grid_percolated(side: int, frac: float, seed: int) -> CSR:
     """side x side 4-neighbour grid with floor(frac*E) edges deleted uniformly
     without replacement, reduced to its largest connected component."""

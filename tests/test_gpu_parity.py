@@ -475,3 +475,30 @@ def test_adaptive_pair_alg1_small(dev, sched):
     check_sampler(got, O.adaptive_pair(g, targets, oracle.RULE_ALG1, 0.1, 1.0, 5, 1 << 20),
                   "pair alg1")
     G.close()
+
+
+def test_accuracy_sweep_settings_match_the_oracle(dev):
+    # the sweep's settings run through the library's samplers: the same
+    # streams give the oracle's sample counts and estimates
+    import paper_1608_04472_amd.accuracy as acc
+    g = gg.powerlaw_cluster(700, 2, 0.4, seed=5)
+    G = bc.Graph(g.row, g.col)
+    exact = bc.exact(G).cpu().numpy()
+    _, want_bc = O.dependencies(g, np.arange(g.n, dtype=np.int32), full=False, total=True)
+    assert_close(exact, want_bc, what="sweep exact")
+    tg = acc.top_targets(exact, 6)
+    say("accuracy sweep settings")
+    for kind, prm in (("source", 1.5), ("pair-eps", 0.2), ("pair-alg1", 1.0)):
+        K, D, capped, _ = acc.run_setting(bc, G, T(tg, dev), exact[tg], kind, prm, 2, 1 << 20)
+        for inst in range(2):
+            if kind == "source":
+                est, k, _, _ = O.adaptive_source(g, tg, prm, 1 + inst, 1 << 20)
+            elif kind == "pair-eps":
+                est, k, _, _ = O.adaptive_pair(g, tg, oracle.RULE_EPS, prm, 1.0, 1 + inst, 1 << 20)
+            else:
+                est, k, _, _ = O.adaptive_pair(g, tg, oracle.RULE_ALG1, 0.1, prm, 1 + inst,
+                                               1 << 20)
+            assert np.array_equal(K[inst], k), (kind, inst)
+            assert_close(D[inst], np.abs(est / want_bc[tg] - 1.0), what=kind)
+        assert capped == 0
+    G.close()
