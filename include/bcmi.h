@@ -169,7 +169,7 @@ typedef struct {
 bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
 
 /* Per-kernel profile of the hot path, for roofline accounting. While enabled,
- * every launch of the four hot kernels is bracketed by HIP events on the
+ * every launch of the hot kernels is bracketed by HIP events on the
  * graph's stream, and the kernels count the work units they process:
  *   units_a: (vertex, source) pairs (discovered, counted or swept),
  *   units_b: DAG (edge, source) pairs read (predecessor or successor values).
@@ -178,6 +178,10 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *   sigma_pull : 8 per units_a (count write) + 8 per units_b (count read)
  *   backward   : 20 per units_a (count read, rho write, level read)
  *                + 8 per units_b (rho read)
+ *   backward_split: the backward of levels with fewer than 2^20 record
+ *                entries, whose rows longer than 256 are summed by a whole
+ *                workgroup (same units and bytes as backward)
+ *   level_record: 8 per (vertex, word) read + 36 per record entry written
  * Enabling resets the accumulators. Profiling adds one event pair per launch
  * and one counter update per wavefront. */
 typedef struct {

@@ -77,6 +77,10 @@ int grid_waves(int64_t waves)
 }
 
 // tiled pull kernels: one workgroup per kTile entries, grid-strided
+// backward levels with fewer record entries than this are narrow enough for
+// their longest rows to set their time: they take the split form
+constexpr int64_t kSplitEntries = 1ll << 20;
+
 int grid_tiles(int64_t entries)
 {
     return (int)std::max<int64_t>(1, std::min<int64_t>((entries + kTile - 1) / kTile, 32768));
@@ -528,6 +532,9 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             const int64_t e0 = off[level], e1 = off[level + 1];
             if (ext)
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<true>, a, e0, e1,
+                           (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
+            else if (e1 - e0 < kSplitEntries)
+                launch_hot(g, PROF_BACKWARD_SPLIT, grid_tiles(e1 - e0), k_backward_split, a, e0, e1,
                            (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
             else
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<false>, a, e0, e1,
@@ -1214,11 +1221,12 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         }
         for (int k = 0; k < 2 * PROF_KERNELS; ++k) units[k] += (unsigned long long)g->prof_host_units[k];
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
-                                                  "sigma_pull", "backward", "level_record"};
+                                                  "sigma_pull", "backward", "level_record",
+                                                  "backward_split"};
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
-        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0};
-        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0};
+        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0};
+        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];

@@ -136,7 +136,8 @@ enum : int {
     PROF_SIGMA = 2,
     PROF_BACKWARD = 3,
     PROF_LEVEL = 4,   // record layout of a level (k_level_*), counted on the host
-    PROF_KERNELS = 5
+    PROF_BACKWARD_SPLIT = 5,
+    PROF_KERNELS = 6
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
@@ -499,6 +500,10 @@ __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t
 
 // ------------------------------------------------- neighbour pull (shared)
 
+// Rows longer than kHub are never staged in LDS: their neighbours are gathered
+// from global memory.
+constexpr int kHub = 256;
+
 // Issue the value loads of up to kInFlight overlapping neighbours, taken from
 // bal (bit k: the neighbour staged in lane k, whose frontier word and pool
 // segment are this lane's fm and sx) in ascending order. fk[q] receives the
@@ -555,18 +560,18 @@ __device__ __forceinline__ void add_batch(const double (&vm)[kInFlight],
     }
 }
 
-// Sum, over the neighbours x of v in ascending CSR order whose frontier word
-// F[x][j] shares a bit with `want`, of the slab value slab[x][64j + lane] for
-// the lanes whose bit is set in that word. Overlapping neighbours are taken
+// Sum, over the neighbours x at row positions [beg, end), in ascending CSR
+// order, whose frontier word F[x][j] shares a bit with `want`, of the slab
+// value slab[x][64j + lane] for the lanes whose bit is set in that word. Overlapping neighbours are taken
 // kInFlight at a time so their slab loads are in flight together; only the
 // lanes inside a neighbour's overlap load and add (the overlap is wave-uniform,
 // so it serves directly as the execution mask).
 template <bool kExt>
-__device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t j, uint64_t want,
-                                         const uint64_t *F, const uint64_t *SG, int lane,
-                                         double &accp, XNum &accx, unsigned long long &units)
+__device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t beg, int64_t end, uint32_t j,
+                                         uint64_t want, const uint64_t *F, const uint64_t *SG,
+                                         int lane, double &accp, XNum &accx,
+                                         unsigned long long &units)
 {
-    const int64_t beg = a.row[v], end = a.row[v + 1];
     if (beg >= end) return;
     // Pipelined over chunks of kWave neighbours: while chunk c's values are
     // summed, chunk c+1's frontier words and segments and chunk c+2's
@@ -597,6 +602,42 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t v, uint32_t
         }
         f_cur = f_nxt;
         s_cur = s_nxt;
+    }
+}
+
+// Rows longer than kHub are summed in kQuarters parts, each in ascending CSR
+// order, and the part sums are added in part order. The backward of a narrow
+// level spreads the parts of such a row over the workgroup's wavefronts; the
+// grouping is the same in both forms, so a vertex's sums are bit-identical
+// whichever form its level takes.
+constexpr int kQuarters = 4;
+
+__device__ __forceinline__ int64_t part_begin(int64_t beg, int64_t deg, int q, int parts)
+{
+    return beg + deg * q / parts;
+}
+
+template <bool kExt>
+__device__ __forceinline__ void row_sum(const BatchArgs &a, int64_t beg, int64_t deg, uint32_t j,
+                                        uint64_t want, const uint64_t *F, const uint64_t *SG,
+                                        int lane, double &accp, XNum &accx,
+                                        unsigned long long &units)
+{
+    const int parts = deg > kHub ? kQuarters : 1;
+#pragma unroll 1
+    for (int q = 0; q < parts; ++q) {
+        double p = 0.0;
+        XNum x{0.0, 0};
+        pull_sum<kExt>(a, part_begin(beg, deg, q, parts), part_begin(beg, deg, q + 1, parts), j,
+                       want, F, SG, lane, p, x, units);
+        if (q == 0) {
+            accp = p;
+            accx = x;
+        } else if (kExt) {
+            accx = xadd(accx, x);
+        } else {
+            accp += p;
+        }
     }
 }
 
@@ -643,10 +684,9 @@ __device__ __forceinline__ double wave_sum_to_last(double x)
 //      (lanes = sources) and summed in ascending CSR order.
 // Entries whose row is longer than kHub, or that no longer fit the tile's
 // edge budget, skip staging and gather their neighbours from global memory
-// in phase 3 (same order, same sums).
+// in phase 3 (the same sums; rows longer than kHub are summed in parts).
 constexpr int kTile = 32;
 constexpr int kEdgeCap = 1024;
-constexpr int kHub = 256;
 
 struct TileLds {
     int32_t v[kTile];
@@ -659,6 +699,7 @@ struct TileLds {
     int32_t end[kTile];
     int32_t staged[kTile];
     int32_t total;
+    int32_t nsplit;         // the tile has rows longer than kHub
     double vs[kTile];       // the entry's running dependency sum before this level
     uint64_t fm[kEdgeCap];  // the neighbour's full frontier word for the entry's word
     uint64_t fs[kEdgeCap];  // the neighbour's pool segment for that word
@@ -692,10 +733,11 @@ __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const Lds &t, i
 // Phase 3 for entry i of a staged tile: the sum over its overlapping
 // neighbours in ascending CSR order, then sigma (forward) or rho and the
 // dependency (backward) for the entry's lanes.
-template <bool kExt, bool kBackward, class Lds>
+template <bool kExt, bool kBackward, bool kPre, class Lds>
 __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int i, int lane,
                                           const uint64_t *F, const uint64_t *SG,
-                                          unsigned long long &ua, unsigned long long &ub)
+                                          unsigned long long &ua, unsigned long long &ub,
+                                          double pre_p = 0.0, XNum pre_x = XNum{0.0, 0})
 {
     const int64_t v = __builtin_amdgcn_readfirstlane(t.v[i]);
     const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
@@ -719,10 +761,14 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
     XNum acc{0.0, 0};
     double accp = 0.0;
     ua += __popcll(m);
-    if (t.staged[i])
+    if (kPre) {
+        accp = pre_p;
+        acc = pre_x;
+    } else if (t.staged[i]) {
         pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
-    else
-        pull_sum<kExt>(a, v, j, m, F, SG, lane, accp, acc, ub);
+    } else {
+        row_sum<kExt>(a, t.beg[i], t.deg[i], j, m, F, SG, lane, accp, acc, ub);
+    }
     if (!kBackward) {
         if (mine) {
             if (kExt) {
@@ -767,7 +813,7 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
 // kBackward = true: dependency sweep (F/SG = next-deeper frontier, masks and
 //   segments from the record; the entry's own word and segment are scattered
 //   into Fo/SGo for the next, shallower level).
-template <bool kExt, bool kBackward>
+template <bool kExt, bool kBackward, bool kSplit>
 __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F,
                                            const uint64_t *SG, uint64_t *Fo, uint64_t *SGo)
 {
@@ -823,7 +869,11 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 t.end[lane] = endp;
                 t.staged[lane] = (fits && de == deg) ? 1 : 0;
             }
-            if (lane == 0) t.total = maxfit;
+            const uint64_t sp = wave_ballot(deg > kHub);
+            if (lane == 0) {
+                t.total = maxfit;
+                t.nsplit = sp != 0ull;
+            }
             // per-entry bookkeeping, one lane per entry (each (v, j) occurs
             // once per level, so these updates do not race)
             if (lane < kTile && e < e1) {
@@ -855,14 +905,48 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             t.fs[p] = (fm & t.m[i]) ? SG[xi] : 0;
         }
         __syncthreads();
-        // phase 3: value sums, one entry per wavefront at a time
+        // phase 3: value sums, one entry per wavefront at a time (with kSplit,
+        // rows longer than kHub are left to the whole workgroup)
         for (int i = wv; i < kTile; i += nwv) {
             if (tile + i >= e1) break;
-            entry_sum<kExt, kBackward>(a, t, i, lane, F, SG, ua, ub);
+            if (kSplit && t.deg[i] > kHub) continue;
+            entry_sum<kExt, kBackward, false>(a, t, i, lane, F, SG, ua, ub);
+        }
+        if (kSplit && t.nsplit) {
+            // wavefront q sums part q of the row; the part sums meet in LDS,
+            // where the staged words are no longer needed once every wavefront
+            // is past its own entries, and wavefront 0 adds them in part order
+            double *pm = reinterpret_cast<double *>(t.fm);
+            int32_t *pe = reinterpret_cast<int32_t *>(t.fs);
+            for (int i = 0; i < kTile; ++i) {
+                if (tile + i >= e1) break;
+                const int64_t deg = t.deg[i];
+                if (deg <= kHub) continue;
+                const int64_t beg = t.beg[i];
+                const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
+                const uint64_t m = uniform_u64(t.m[i]);
+                double p = 0.0;
+                XNum x{0.0, 0};
+                pull_sum<kExt>(a, part_begin(beg, deg, wv, kQuarters),
+                               part_begin(beg, deg, wv + 1, kQuarters), j, m, F, SG, lane, p, x,
+                               ub);
+                __syncthreads();
+                pm[wv * kWave + lane] = kExt ? x.m : p;
+                if (kExt) pe[wv * kWave + lane] = x.e;
+                __syncthreads();
+                if (wv == 0) {
+                    for (int q = 1; q < kQuarters; ++q) {
+                        if (kExt) x = xadd(x, XNum{pm[q * kWave + lane], pe[q * kWave + lane]});
+                        else p += pm[q * kWave + lane];
+                    }
+                    entry_sum<kExt, kBackward, true>(a, t, i, lane, F, SG, ua, ub, p, x);
+                }
+            }
         }
         __syncthreads();
     }
-    prof_add(a, kBackward ? PROF_BACKWARD : PROF_SIGMA, ua, ub, lane);
+    prof_add(a, kBackward ? (kSplit ? PROF_BACKWARD_SPLIT : PROF_BACKWARD) : PROF_SIGMA, ua, ub,
+             lane);
 }
 
 // sigma_s(w) = sum over predecessors u (neighbours one level up, Definition 3)
@@ -875,7 +959,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
                                                        const uint64_t *cur, const uint64_t *sgcur,
                                                        uint64_t *sgnxt)
 {
-    pull_tiles<kExt, false>(a, e0, e1, cur, sgcur, nullptr, sgnxt);
+    pull_tiles<kExt, false, false>(a, e0, e1, cur, sgcur, nullptr, sgnxt);
 }
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
@@ -889,7 +973,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
                                                      const uint64_t *fnext, const uint64_t *sgnext,
                                                      uint64_t *fown, uint64_t *sgown)
 {
-    pull_tiles<kExt, true>(a, e0, e1, fnext, sgnext, fown, sgown);
+    pull_tiles<kExt, true, false>(a, e0, e1, fnext, sgnext, fown, sgown);
+}
+
+// The same sweep for a narrow level, whose time is set by its longest rows:
+// each row longer than kHub is summed by all wavefronts of the workgroup.
+__global__ __launch_bounds__(kBlock) void k_backward_split(BatchArgs a, int64_t e0, int64_t e1,
+                                                          const uint64_t *fnext,
+                                                          const uint64_t *sgnext, uint64_t *fown,
+                                                          uint64_t *sgown)
+{
+    pull_tiles<false, true, true>(a, e0, e1, fnext, sgnext, fown, sgown);
 }
 
 // ------------------------------------------------------------- lane order
