@@ -86,6 +86,10 @@ typedef struct {
     int32_t batch;         /* sources per batch, multiple of 64 in [64, 4096]; 0 = auto */
     double bottom_up;      /* run a level bottom-up when its frontier entries exceed
                               bottom_up * (n * batch/64); 0 = auto, < 0 = never */
+    int64_t split_entries; /* a backward level with fewer (vertex, 64-source word)
+                              entries than this sums its rows longer than 256 with a
+                              whole workgroup; 0 = auto (2^20), < 0 = never. Values
+                              are identical either way. */
 } bc_config;
 
 /* Host CSR. row has n+1 entries, int64 if row_is_i64 else int32. */

@@ -68,7 +68,7 @@ class _Csr(ctypes.Structure):
 
 class _Config(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("bottom_up", ctypes.c_double)]
+                ("bottom_up", ctypes.c_double), ("split_entries", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
@@ -210,8 +210,8 @@ class Graph:
         _check(_lib.bc_graph_set_stream(self._h, _stream()))
         return self._h
 
-    def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0):
-        cfg = _Config(int(schedule), int(batch), float(bottom_up))
+    def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0, split_entries=0):
+        cfg = _Config(int(schedule), int(batch), float(bottom_up), int(split_entries))
         _check(_lib.bc_graph_configure(self.handle, ctypes.byref(cfg)))
 
     def stats(self):

@@ -160,7 +160,7 @@ struct bc_graph {
     hipStream_t stream = nullptr;
     DBuf<int64_t> row;
     DBuf<int32_t> col;
-    bc_config cfg{BC_SCHED_AUTO, 0, 0.0};
+    bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0};
     Work own;
     Work *w = &own;
     int64_t cap_hint = 0;
@@ -526,6 +526,8 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
 
         // backward: cur holds the deepest level's masks, nxt is clear
         const int L = (int)off.size() - 1;
+        const int64_t split_entries =
+            g->cfg.split_entries == 0 ? kSplitEntries : g->cfg.split_entries;
         uint64_t *fnext = nxt, *fown = cur;
         uint64_t *sgnext = sgnxt, *sgown = sgcur;
         for (int level = L - 1; level >= 1; --level) {
@@ -533,7 +535,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             if (ext)
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<true>, a, e0, e1,
                            (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
-            else if (e1 - e0 < kSplitEntries)
+            else if (e1 - e0 < split_entries)
                 launch_hot(g, PROF_BACKWARD_SPLIT, grid_tiles(e1 - e0), k_backward_split, a, e0, e1,
                            (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
             else

@@ -502,3 +502,25 @@ def test_accuracy_sweep_settings_match_the_oracle(dev):
             assert_close(D[inst], np.abs(est / want_bc[tg] - 1.0), what=kind)
         assert capped == 0
     G.close()
+
+
+def test_backward_forms_bit_identical(dev):
+    # the wide-level backward (one wavefront per row) and the narrow-level form
+    # (a workgroup per row longer than 256) sum the same parts in the same
+    # order: forcing either form everywhere gives identical bits, and both
+    # match the oracle
+    g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
+    assert (g.degree() > 256).sum() > 20
+    src = np.concatenate([gg.top_degree(g, 4), gg.philox_sources(4, 250, g.n)]).astype(np.int32)
+    outs = {}
+    for split in (-1, 0, 1 << 40):
+        G = bc.Graph(g.row, g.col)
+        G.configure(bc.BC_SCHED_BATCHED, 128, 0.0, split)
+        if split == -1:
+            outs[split] = check_sources(G, g, src, dev, "rmat12 backward never split")
+        else:
+            say("rmat12 backward split_entries=%d" % split)
+            outs[split] = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+        G.close()
+    assert np.array_equal(outs[-1], outs[0])
+    assert np.array_equal(outs[-1], outs[1 << 40])
