@@ -76,11 +76,11 @@ int grid_waves(int64_t waves)
     return std::min(grid_for(waves * kWave), 16384);
 }
 
-// tiled pull kernels: one workgroup per kTile entries, grid-strided
 // backward levels with fewer record entries than this are narrow enough for
 // their longest rows to set their time: they take the split form
 constexpr int64_t kSplitEntries = 1ll << 20;
 
+// tiled pull kernels: one workgroup per kTile entries, grid-strided
 int grid_tiles(int64_t entries)
 {
     return (int)std::max<int64_t>(1, std::min<int64_t>((entries + kTile - 1) / kTile, 32768));

@@ -912,6 +912,7 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             if (kSplit && t.deg[i] > kHub) continue;
             entry_sum<kExt, kBackward, false>(a, t, i, lane, F, SG, ua, ub);
         }
+        static_assert(kBlock / kWave == kQuarters, "one part per wavefront");
         if (kSplit && t.nsplit) {
             // wavefront q sums part q of the row; the part sums meet in LDS,
             // where the staged words are no longer needed once every wavefront
