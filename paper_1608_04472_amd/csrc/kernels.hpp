@@ -504,21 +504,21 @@ __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t
 // from global memory.
 constexpr int kHub = 256;
 
-// Issue the value loads of up to kInFlight overlapping neighbours, taken from
+// Issue the value loads of up to kIF overlapping neighbours, taken from
 // bal (bit k: the neighbour staged in lane k, whose frontier word and pool
 // segment are this lane's fm and sx) in ascending order. fk[q] receives the
 // q-th neighbour's overlap with the wave-uniform `want` (0 for an unused
 // slot). Every lane loads, so the loads are straight-line code and all of a
 // batch is in flight together: lanes outside the overlap read the segment's
 // first slot (always valid) and add_batch discards it.
-template <bool kExt>
+template <bool kExt, int kIF = kInFlight>
 __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uint64_t sx,
-                                            uint64_t want, uint64_t &bal,
-                                            double (&vm)[kInFlight], int32_t (&ve)[kInFlight],
-                                            uint64_t (&fk)[kInFlight], unsigned long long &units)
+                                            uint64_t want, uint64_t &bal, double (&vm)[kIF],
+                                            int32_t (&ve)[kIF], uint64_t (&fk)[kIF],
+                                            unsigned long long &units)
 {
 #pragma unroll
-    for (int q = 0; q < kInFlight; ++q) {
+    for (int q = 0; q < kIF; ++q) {
         fk[q] = 0;
         vm[q] = 0.0;
         ve[q] = 0;
@@ -540,14 +540,12 @@ __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uin
 // In plain FP64 every slot is consumed by every lane without a branch, so no
 // load of a batch can be pending when its register is reused by the next one
 // (the compiler would otherwise wait for all memory operations first).
-template <bool kExt>
-__device__ __forceinline__ void add_batch(const double (&vm)[kInFlight],
-                                          const int32_t (&ve)[kInFlight],
-                                          const uint64_t (&fk)[kInFlight], double &accp,
-                                          XNum &accx)
+template <bool kExt, int kIF = kInFlight>
+__device__ __forceinline__ void add_batch(const double (&vm)[kIF], const int32_t (&ve)[kIF],
+                                          const uint64_t (&fk)[kIF], double &accp, XNum &accx)
 {
 #pragma unroll
-    for (int q = 0; q < kInFlight; ++q) {
+    for (int q = 0; q < kIF; ++q) {
         const bool on = lane_in(fk[q]);
         if (kExt) {
             if (fk[q]) {
@@ -563,10 +561,10 @@ __device__ __forceinline__ void add_batch(const double (&vm)[kInFlight],
 // Sum, over the neighbours x at row positions [beg, end), in ascending CSR
 // order, whose frontier word F[x][j] shares a bit with `want`, of the slab
 // value slab[x][64j + lane] for the lanes whose bit is set in that word. Overlapping neighbours are taken
-// kInFlight at a time so their slab loads are in flight together; only the
+// kIF at a time so their slab loads are in flight together; only the
 // lanes inside a neighbour's overlap load and add (the overlap is wave-uniform,
 // so it serves directly as the execution mask).
-template <bool kExt>
+template <bool kExt, int kIF = kInFlight>
 __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t beg, int64_t end, uint32_t j,
                                          uint64_t want, const uint64_t *F, const uint64_t *SG,
                                          int lane, double &accp, XNum &accx,
@@ -594,11 +592,11 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t beg, int64_
         x_next = nb_at(base + 2 * kWave);
         uint64_t bal = wave_ballot((fm & want) != 0);
         while (bal) {
-            double vm[kInFlight];
-            int32_t ve[kInFlight];
-            uint64_t fk[kInFlight];
-            issue_batch<kExt>(a, fm, sx, want, bal, vm, ve, fk, units);
-            add_batch<kExt>(vm, ve, fk, accp, accx);
+            double vm[kIF];
+            int32_t ve[kIF];
+            uint64_t fk[kIF];
+            issue_batch<kExt, kIF>(a, fm, sx, want, bal, vm, ve, fk, units);
+            add_batch<kExt, kIF>(vm, ve, fk, accp, accx);
         }
         f_cur = f_nxt;
         s_cur = s_nxt;
@@ -611,6 +609,9 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t beg, int64_
 // grouping is the same in both forms, so a vertex's sums are bit-identical
 // whichever form its level takes.
 constexpr int kQuarters = 4;
+// value loads in flight per wavefront in the split form, whose rows are long
+// and whose levels are narrow (the additions stay in neighbour order)
+constexpr int kSplitInFlight = 16;
 
 __device__ __forceinline__ int64_t part_begin(int64_t beg, int64_t deg, int q, int parts)
 {
@@ -928,7 +929,7 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 const uint64_t m = uniform_u64(t.m[i]);
                 double p = 0.0;
                 XNum x{0.0, 0};
-                pull_sum<kExt>(a, part_begin(beg, deg, wv, kQuarters),
+                pull_sum<kExt, kSplitInFlight>(a, part_begin(beg, deg, wv, kQuarters),
                                part_begin(beg, deg, wv + 1, kQuarters), j, m, F, SG, lane, p, x,
                                ub);
                 __syncthreads();
