@@ -46,7 +46,7 @@ typedef enum {
     BC_E_INVALID = 1,      /* bad argument or malformed CSR */
     BC_E_NOMEM = 2,        /* device memory exhausted */
     BC_E_DEVICE = 3,       /* HIP runtime error (message in bc_last_error) */
-    BC_E_UNSUPPORTED = 4   /* valid request this build cannot serve */
+    BC_E_UNSUPPORTED = 4   /* valid request that the library does not serve */
 } bc_status;
 
 typedef enum {
