@@ -768,7 +768,8 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
     } else if (t.staged[i]) {
         pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
     } else {
-        row_sum<kExt>(a, t.beg[i], t.deg[i], j, m, F, SG, lane, accp, acc, ub);
+        row_sum<kExt>(a, (int64_t)uniform_u64((uint64_t)t.beg[i]),
+                      __builtin_amdgcn_readfirstlane(t.deg[i]), j, m, F, SG, lane, accp, acc, ub);
     }
     if (!kBackward) {
         if (mine) {
