@@ -17,6 +17,11 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
                       Accuracy of the adaptive estimate itself: parity unpinned
   adaptive_pair       same checks as adaptive_source on its own rules.
                       Accuracy of the adaptive estimate: parity unpinned
+  source_work         closed forms (paths, stars, cycles, complete, bipartite,
+                      grids, trees), scipy BFS distances with numpy edge
+                      counts, planted mistakes
+  pair_work           closed forms (paths, stars, adjacent and unreachable
+                      pairs), scipy BFS distances, planted mistakes
 """
 from __future__ import annotations
 

@@ -52,6 +52,19 @@ MUTANTS = {
 }
 
 
+# slips in the work counters (the throughput metric's numerators)
+WORK_MUTANTS = {
+    "dag_counts_same_level": ("if (p.dist[col[e]] == p.dist[u] + 1) ++dag;",
+                              "if (p.dist[col[e]] >= p.dist[u] && col[e] != u) ++dag;"),
+    "component_edges_doubled": ("*edges_undirected = deg / 2;", "*edges_undirected = deg;"),
+    "pair_limit_inclusive": ("if (lead && da < limit) ++cnt;", "if (lead && da <= limit) ++cnt;"),
+    "pair_same_level_twice": ("int lead = (da < db) || (da == db && a < b);",
+                              "int lead = (da <= db);"),
+    "reached_without_source": ("if (reached) *reached = p.reached;",
+                               "if (reached) *reached = p.reached - 1;"),
+}
+
+
 def build_variant(tmp_path, name, old, new):
     src = open(SRC).read()
     assert src.count(old) == 1, name
@@ -146,11 +159,57 @@ def pins_pass(O):
     return True
 
 
+def work_pins_pass(O):
+    """A compact selection of the work-counter pins (tests/test_oracle_work.py)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+    try:
+        if O.source_work(gg.cycle(7), 0) != (7, 7, 6):
+            return False
+        if O.source_work(gg.grid(5, 9), 0) != (45, 76, 76):
+            return False
+        g = gg.from_edges(8, [0, 1, 0, 3, 4, 5], [1, 2, 2, 4, 5, 6])
+        if O.source_work(g, 0) != (3, 3, 2) or O.pair_work(g, 0, 5) != 3:
+            return False
+        n = 12
+        p = gg.path(n)
+        for u, v in ((0, 5), (7, 2), (3, 4)):
+            k = abs(u - v)
+            if O.pair_work(p, u, v) != min(u, k) + min(k, n - 1 - u):
+                return False
+        g = gg.er(300, 0.012, seed=3)
+        a = sp.csr_matrix((np.ones(g.nnz), g.col, g.row), shape=(g.n, g.n))
+        src = np.repeat(np.arange(g.n), np.diff(g.row))
+        dst = g.col.astype(np.int64)
+        for u, v in ((0, 1), (5, 200), (17, 299)):
+            d = shortest_path(a, unweighted=True, directed=False, indices=[u])[0]
+            d = np.where(np.isinf(d), -1, d).astype(np.int64)
+            dag = int(((d[src] >= 0) & (d[dst] == d[src] + 1)).sum())
+            if O.source_work(g, u) != (int((d >= 0).sum()), int((d[src] >= 0).sum()) // 2, dag):
+                return False
+            lim = d[v] if d[v] >= 0 else 1 << 40
+            keep = src < dst
+            da, db = d[src[keep]], d[dst[keep]]
+            if O.pair_work(g, u, v) != int(((da >= 0) & (np.minimum(da, db) < lim)).sum()):
+                return False
+    except ValueError:
+        return False
+    return True
+
+
 def test_unmodified_oracle_passes_the_selection():
-    assert pins_pass(oracle.load())
+    O = oracle.load()
+    assert pins_pass(O)
+    assert work_pins_pass(O)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     assert not pins_pass(build_variant(tmp_path, name, old, new))
+
+
+@pytest.mark.parametrize("name", sorted(WORK_MUTANTS))
+def test_planted_work_counter_mistake_is_caught(tmp_path, name):
+    old, new = WORK_MUTANTS[name]
+    assert not work_pins_pass(build_variant(tmp_path, name, old, new))
