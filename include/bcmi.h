@@ -17,13 +17,19 @@
  *   - BC counts ordered pairs (s, t), s, t, v pairwise distinct, so
  *     0 <= BC(v) < n^2 (Definition 1).
  *   - Array arguments of compute calls (bc_exact, bc_dependencies,
- *     bc_adaptive_*) are DEVICE pointers on the graph's device; the caller
- *     owns them. bc_graph_create reads a HOST CSR and keeps its own device copy.
+ *     bc_pair_dependencies, bc_adaptive_*, bc_draw_*) are DEVICE pointers on
+ *     the graph's device, or HOST pointers once bc_graph_set_io(g, BC_IO_HOST)
+ *     has been called; the caller owns them either way. bc_graph_create reads
+ *     a HOST CSR and keeps its own device copy.
+ *   - Device memory the library needs (the graph's copy, its workspace) comes
+ *     from the caller's bc_allocator when one is given, else from hipMalloc.
  *   - All work is ordered on the graph's stream; a call returns once its
  *     outputs are complete. One graph handle serves one host thread at a time.
- *   - Errors: every argument is checked before any device work; on error the
- *     outputs are untouched, the call returns a nonzero bc_status and
- *     bc_last_error() describes it. No call throws or aborts.
+ *   - Errors: no call throws or aborts. Arguments are checked before any
+ *     device work: a bad argument returns BC_E_INVALID and leaves the outputs
+ *     untouched. A failure found during the computation (BC_E_NOMEM,
+ *     BC_E_DEVICE, BC_E_UNSUPPORTED) leaves the outputs unspecified. Either
+ *     way bc_last_error() describes it.
  *   - Arithmetic: FP64. Path counts use an FP64 significand with an int32
  *     exponent once any count of a batch reaches 2^1000 (plain FP64 below).
  *   - Random draws: Philox4x64-10 (Salmon et al., SC'11), key (seed, stream),
@@ -57,8 +63,17 @@ typedef enum {
 /* Output layouts of bc_dependencies. */
 typedef enum {
     BC_OUT_FULL = 0,       /* out[i*n + v] = delta_{sources[i].}(v), k*n doubles */
-    BC_OUT_SUM = 1         /* out[v] = sum over i of delta_{sources[i].}(v), n doubles */
+    BC_OUT_SUM = 1,        /* out[v] = sum over i of delta_{sources[i].}(v), n doubles */
+    BC_OUT_TARGETS = 2     /* out[i*T + t] = delta_{sources[i].}(targets[t]), k*T doubles:
+                              the values a sampler takes from each sample (Section 4) */
 } bc_out_mode;
+
+/* Where the array arguments of compute calls live (bc_graph_set_io). */
+typedef enum {
+    BC_IO_DEVICE = 0,      /* device pointers on the graph's device (default) */
+    BC_IO_HOST = 1         /* host pointers: the library stages them through
+                              device memory from the graph's allocator */
+} bc_io;
 
 /* Stopping rules of bc_adaptive_pair. */
 typedef enum {
@@ -83,7 +98,7 @@ typedef enum {
 
 typedef struct {
     int32_t schedule;      /* bc_schedule */
-    int32_t batch;         /* sources per batch, multiple of 64 in [64, 4096]; 0 = auto */
+    int32_t batch;         /* sources per batch, a power of two in [64, 4096]; 0 = auto */
     double bottom_up;      /* run a level bottom-up when its frontier entries exceed
                               bottom_up * (n * batch/64); 0 = auto, < 0 = never */
     int64_t split_entries; /* a backward level with fewer (vertex, 64-source word)
@@ -103,12 +118,29 @@ typedef struct {
 
 typedef struct bc_graph bc_graph;
 
-/* Validate a host CSR and copy it to the current HIP device. hip_stream is a
- * hipStream_t (NULL = the null stream). On success *out owns the device copy
- * and a lazily grown workspace; release it with bc_graph_destroy. */
-bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out);
+/* Device memory provider. alloc returns `bytes` of device memory on the
+ * current device (aligned to at least 256 bytes), or NULL when it has none;
+ * free releases what alloc returned. Both may be called from any library
+ * call on the handle that was created with it, on the calling host thread;
+ * the memory is used on the handle's stream. The struct is copied: ctx must
+ * stay valid until the handle is destroyed. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} bc_allocator;
+
+/* Validate a host CSR and copy it to the current HIP device. alloc supplies
+ * all device memory of the handle (NULL = hipMalloc / hipFree). hip_stream is
+ * a hipStream_t (NULL = the null stream). On success *out owns the device
+ * copy and a lazily grown workspace; release it with bc_graph_destroy.
+ * row_is_i64 = 0 takes int32 row offsets (nnz < 2^31). */
+bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream,
+                          bc_graph **out);
 void bc_graph_destroy(bc_graph *g);
 bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
+/* bc_io: where the array arguments of later compute calls on g live. */
+bc_status bc_graph_set_io(bc_graph *g, int32_t io);
 bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg);
 bc_status bc_graph_info(const bc_graph *g, int64_t *n, int64_t *nnz);
 
@@ -120,10 +152,12 @@ bc_status bc_exact(bc_graph *g, double *out);
  * sources: k int32 in [0, n), repeats allowed. out: see bc_out_mode.
  * dist_out (k*n int32, -1 = unreachable), sigma_mant and sigma_exp (k*n each,
  * sigma = mant * 2^exp) are optional (NULL) per-source outputs, source-major;
- * they require out_mode == BC_OUT_FULL. delta_{s.}(s) = 0. */
+ * they require out_mode == BC_OUT_FULL. targets (T int32 in [0, n)) are read
+ * only in BC_OUT_TARGETS mode (else they may be NULL, T = 0).
+ * delta_{s.}(s) = 0. */
 bc_status bc_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_t out_mode,
                           double *out, int32_t *dist_out, double *sigma_mant,
-                          int32_t *sigma_exp);
+                          int32_t *sigma_exp, const int32_t *targets, int32_t T);
 
 /* Bader's adaptive source sampling as restated in Section 4, for T targets
  * sharing one sample stream (target i's results equal a T = 1 call with the
@@ -210,9 +244,14 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
  * does not depend on its batch mates, so a query's result is bit-identical
  * to running it alone, and to bc_adaptive_source / bc_adaptive_pair with T = 1
  * on the same graph, seed and schedule.
- * Admission by HBM budget: bc_server_add_graph fails with BC_E_NOMEM when the
- * graph's CSR would exceed the budget; each graph's batch width is the widest
- * (<= max_batch) whose engine workspace fits what the resident graphs leave.
+ * Admission by HBM budget: resident bytes (every graph's CSR and lane-order
+ * key) plus the shared workspace never exceed the budget. The workspace is
+ * sized per buffer for the widest need of any admitted graph; a new graph
+ * takes the widest batch width (<= max_batch, and within the 32-bit index
+ * range of its engine) that keeps that sum within the budget, and
+ * bc_server_add_graph fails with BC_E_NOMEM when even width 64 does not fit.
+ * A round whose level record would outgrow the budgeted workspace runs its
+ * samples in two halves instead (results are unchanged).
  * Scheduling: shortest job first at graph granularity (the graph whose
  * cheapest unfinished query has the smallest bound (k_max - k) * nnz runs the
  * next round), with every eighth round given to the graph of the oldest
@@ -245,8 +284,11 @@ typedef struct {
     double done_s;
 } bc_result;
 
-bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, void *hip_stream,
-                           bc_server **out);
+/* hbm_budget_bytes bounds the device memory the server holds: the resident
+ * graphs (CSR, lane-order keys) plus the shared engine workspace. alloc as in
+ * bc_graph_create (NULL = hipMalloc). */
+bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch,
+                           const bc_allocator *alloc, void *hip_stream, bc_server **out);
 void bc_server_destroy(bc_server *s);
 bc_status bc_server_add_graph(bc_server *s, const bc_csr *csr, int32_t *graph_id);
 bc_status bc_server_submit(bc_server *s, const bc_query *q, int64_t *id);
@@ -263,10 +305,16 @@ typedef struct {
     int64_t rounds;
     int64_t samples_executed; /* slots run, including those past a query's stop */
     int64_t samples_used;     /* samples counted by the stopping rules */
-    int64_t resident_bytes;   /* graphs' device CSR */
-    int64_t workspace_bytes;  /* shared engine workspace */
+    int64_t resident_bytes;   /* graphs' device CSR and lane-order keys */
+    int64_t workspace_bytes;  /* shared engine workspace held now */
+    int64_t budget_bytes;     /* the budget: resident + workspace never exceed it */
+    int64_t split_rounds;     /* rounds run in halves to stay within the budget */
 } bc_server_stats;
 bc_status bc_server_stats_get(const bc_server *s, bc_server_stats *out);
+/* Batch width and engine (BC_SCHED_BATCHED or BC_SCHED_THREADED) chosen for a
+ * graph at admission. */
+bc_status bc_server_graph_width(const bc_server *s, int32_t graph, int32_t *width,
+                                int32_t *schedule);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *bc_last_error(void);

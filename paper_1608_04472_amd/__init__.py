@@ -7,7 +7,10 @@ if the library is missing; there is no fallback path.
 
 Names follow the C ABI: bc_graph_create, bc_exact, bc_dependencies,
 bc_pair_dependencies, bc_adaptive_source, bc_adaptive_pair, bc_draw_sources,
-bc_draw_pairs. Array arguments are CUDA (HIP) tensors on the graph's device.
+bc_draw_pairs. Array arguments are CUDA (HIP) tensors on the graph's device
+(or, for a graph set to BC_IO_HOST, contiguous CPU tensors or numpy arrays).
+By default the library's device memory comes from torch's caching allocator,
+passed in as the ABI's bc_allocator.
 """
 from __future__ import annotations
 
@@ -28,17 +31,20 @@ HIPCC_FLAGS = [
 
 BC_OK, BC_E_INVALID, BC_E_NOMEM, BC_E_DEVICE, BC_E_UNSUPPORTED = 0, 1, 2, 3, 4
 BC_DONE, BC_CAPPED = 0, 1
-BC_OUT_FULL, BC_OUT_SUM = 0, 1
+BC_OUT_FULL, BC_OUT_SUM, BC_OUT_TARGETS = 0, 1, 2
+BC_IO_DEVICE, BC_IO_HOST = 0, 1
 BC_PAIR_ALG1, BC_PAIR_EPS = 0, 1
 BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED = 0, 1, 2, 3
 
 EXPORTS = [
-    "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_configure",
+    "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_set_io",
+    "bc_graph_configure",
     "bc_graph_info", "bc_exact", "bc_dependencies", "bc_pair_dependencies",
     "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
     "bc_last_stats", "bc_last_error", "bc_profile_enable", "bc_profile_read",
     "bc_server_create", "bc_server_destroy", "bc_server_add_graph", "bc_server_submit",
     "bc_server_step", "bc_server_poll", "bc_server_now", "bc_server_stats_get",
+    "bc_server_graph_width",
 ]
 BC_QUERY_SOURCE, BC_QUERY_PAIR = 0, 1
 
@@ -100,7 +106,57 @@ class _Result(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("queued", "active", "finished", "rounds",
                                                "samples_executed", "samples_used",
-                                               "resident_bytes", "workspace_bytes")]
+                                               "resident_bytes", "workspace_bytes",
+                                               "budget_bytes", "split_rounds")]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def _torch_alloc(size, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(size), torch.cuda.current_device(),
+                                                  torch.cuda.current_stream())
+    except Exception:       # out of memory: the library reports BC_E_NOMEM
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+# torch's caching allocator as a bc_allocator (kept alive for the process)
+TORCH_ALLOCATOR = _Allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+
+
+def _allocator(which):
+    """'torch' -> torch's caching allocator, 'hip' -> the library's hipMalloc."""
+    if which == "torch":
+        return ctypes.byref(TORCH_ALLOCATOR)
+    if which == "hip":
+        return None
+    raise ValueError("allocator must be 'torch' or 'hip'")
+
+
+def _csr_arrays(row, col):
+    """Host CSR arrays: int64 or int32 row offsets (kept as given), int32 columns."""
+    import numpy as np
+    row = np.asarray(row)
+    row = np.ascontiguousarray(row, dtype=np.int32 if row.dtype == np.int32 else np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    csr = _Csr(row.shape[0] - 1, col.shape[0], row.ctypes.data, 1 if row.dtype == np.int64 else 0,
+               col.ctypes.data if col.shape[0] else None)
+    return csr, (row, col)
 
 
 _lib = None
@@ -127,12 +183,13 @@ def load_library(path: str | None = None):
     lib.bc_server_destroy.restype = None
     lib.bc_server_destroy.argtypes = [V]
     sigs = {
-        "bc_graph_create": [c.POINTER(_Csr), V, c.POINTER(V)],
+        "bc_graph_create": [c.POINTER(_Csr), V, V, c.POINTER(V)],
         "bc_graph_set_stream": [V, V],
+        "bc_graph_set_io": [V, c.c_int32],
         "bc_graph_configure": [V, c.POINTER(_Config)],
         "bc_graph_info": [V, c.POINTER(c.c_int64), c.POINTER(c.c_int64)],
         "bc_exact": [V, V],
-        "bc_dependencies": [V, V, c.c_int64, c.c_int32, V, V, V, V],
+        "bc_dependencies": [V, V, c.c_int64, c.c_int32, V, V, V, V, V, c.c_int32],
         "bc_pair_dependencies": [V, V, V, c.c_int64, V],
         "bc_adaptive_source": [V, V, c.c_int32, c.c_double, c.c_uint64, c.c_int64, V, V, V, V],
         "bc_adaptive_pair": [V, V, c.c_int32, c.c_int32, c.c_double, c.c_double, c.c_uint64,
@@ -141,7 +198,8 @@ def load_library(path: str | None = None):
         "bc_draw_pairs": [V, c.c_uint64, c.c_int64, c.c_int64, V, V],
         "bc_last_stats": [V, c.POINTER(_Stats)],
         "bc_profile_enable": [V, c.c_int32],
-        "bc_server_create": [c.c_size_t, c.c_int32, V, c.POINTER(V)],
+        "bc_server_create": [c.c_size_t, c.c_int32, V, V, c.POINTER(V)],
+        "bc_server_graph_width": [V, c.c_int32, c.POINTER(c.c_int32), c.POINTER(c.c_int32)],
         "bc_server_add_graph": [V, c.POINTER(_Csr), c.POINTER(c.c_int32)],
         "bc_server_submit": [V, c.POINTER(_Query), c.POINTER(c.c_int64)],
         "bc_server_step": [V, c.POINTER(c.c_int32)],
@@ -164,12 +222,19 @@ def _check(rc):
         raise BcError(rc, _lib.bc_last_error().decode())
 
 
-def _ptr(t, dtype=None, numel=None, name="tensor"):
-    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+def _ptr(t, dtype=None, numel=None, name="tensor", host=False):
+    """Pointer of a contiguous tensor (None -> NULL): a device tensor, or with
+    host=True a CPU tensor or numpy array (graphs set to BC_IO_HOST)."""
     if t is None:
         return None
+    import numpy as np
     import torch
-    if not t.is_cuda:
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(t)
+    if host:
+        if t.is_cuda:
+            raise ValueError("%s must be a host array (the graph is set to BC_IO_HOST)" % name)
+    elif not t.is_cuda:
         raise ValueError("%s must be a device tensor" % name)
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
@@ -186,22 +251,26 @@ def _stream():
 
 
 class Graph:
-    """Handle to a device-resident CSR graph (bc_graph)."""
+    """Handle to a device-resident CSR graph (bc_graph). row may be int64 or
+    int32 offsets; allocator 'torch' (default) or 'hip'."""
 
-    def __init__(self, row, col):
-        import numpy as np
+    def __init__(self, row, col, allocator="torch"):
         lib = load_library()
-        row = np.ascontiguousarray(row, dtype=np.int64)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        self._keep = (row, col)
-        csr = _Csr(row.shape[0] - 1, col.shape[0], row.ctypes.data, 1,
-                   col.ctypes.data if col.shape[0] else None)
+        csr, keep = _csr_arrays(row, col)
         h = ctypes.c_void_p()
-        _check(lib.bc_graph_create(ctypes.byref(csr), _stream(), ctypes.byref(h)))
+        self._h = None
+        _check(lib.bc_graph_create(ctypes.byref(csr), _allocator(allocator), _stream(),
+                                   ctypes.byref(h)))
         self._h = h
         self.n = int(csr.n)
         self.nnz = int(csr.nnz)
-        self._keep = None
+        self.host_io = False
+        del keep
+
+    def set_io(self, host: bool):
+        """BC_IO_HOST: later compute calls take host arrays."""
+        _check(_lib.bc_graph_set_io(self.handle, BC_IO_HOST if host else BC_IO_DEVICE))
+        self.host_io = bool(host)
 
     @property
     def handle(self):
@@ -245,22 +314,26 @@ class Graph:
 class Server:
     """Query server with continuous batching over device-resident graphs."""
 
-    def __init__(self, hbm_budget_bytes, max_batch=256):
+    def __init__(self, hbm_budget_bytes, max_batch=256, allocator="torch"):
         lib = load_library()
         h = ctypes.c_void_p()
-        _check(lib.bc_server_create(int(hbm_budget_bytes), int(max_batch), _stream(),
-                                    ctypes.byref(h)))
+        self._h = None
+        _check(lib.bc_server_create(int(hbm_budget_bytes), int(max_batch), _allocator(allocator),
+                                    _stream(), ctypes.byref(h)))
         self._h = h
 
     def add_graph(self, row, col) -> int:
-        import numpy as np
-        row = np.ascontiguousarray(row, dtype=np.int64)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        csr = _Csr(row.shape[0] - 1, col.shape[0], row.ctypes.data, 1,
-                   col.ctypes.data if col.shape[0] else None)
+        csr, keep = _csr_arrays(row, col)
         gid = ctypes.c_int32()
         _check(_lib.bc_server_add_graph(self._h, ctypes.byref(csr), ctypes.byref(gid)))
+        del keep
         return gid.value
+
+    def graph_width(self, graph):
+        w = ctypes.c_int32()
+        sch = ctypes.c_int32()
+        _check(_lib.bc_server_graph_width(self._h, int(graph), ctypes.byref(w), ctypes.byref(sch)))
+        return w.value, sch.value
 
     def submit(self, graph, target, kind, seed, k_max, c=1.0, eps=0.1, rule=BC_PAIR_EPS,
                arrival_s=-1.0) -> int:
@@ -307,65 +380,79 @@ def bc_graph_create(row, col) -> Graph:
     return Graph(row, col)
 
 
+def _numel(t):
+    return int(t.numel()) if hasattr(t, "numel") else int(t.size)
+
+
 def bc_exact(g: Graph, out):
     import torch
-    _check(_lib.bc_exact(g.handle, _ptr(out, torch.float64, g.n, "out")))
+    _check(_lib.bc_exact(g.handle, _ptr(out, torch.float64, g.n, "out", g.host_io)))
 
 
 def bc_dependencies(g: Graph, sources, out_mode, out, dist_out=None, sigma_mant=None,
-                    sigma_exp=None):
+                    sigma_exp=None, targets=None):
     import torch
-    k = sources.numel()
-    need = k * g.n if out_mode == BC_OUT_FULL else g.n
+    h = g.host_io
+    k = _numel(sources)
+    T = _numel(targets) if targets is not None else 0
+    need = {BC_OUT_FULL: k * g.n, BC_OUT_SUM: g.n, BC_OUT_TARGETS: k * T}[int(out_mode)]
     _check(_lib.bc_dependencies(
-        g.handle, _ptr(sources, torch.int32, k, "sources"), k, int(out_mode),
-        _ptr(out, torch.float64, need, "out"), _ptr(dist_out, torch.int32, k * g.n, "dist_out"),
-        _ptr(sigma_mant, torch.float64, k * g.n, "sigma_mant"),
-        _ptr(sigma_exp, torch.int32, k * g.n, "sigma_exp")))
+        g.handle, _ptr(sources, torch.int32, k, "sources", h), k, int(out_mode),
+        _ptr(out, torch.float64, need, "out", h),
+        _ptr(dist_out, torch.int32, k * g.n, "dist_out", h),
+        _ptr(sigma_mant, torch.float64, k * g.n, "sigma_mant", h),
+        _ptr(sigma_exp, torch.int32, k * g.n, "sigma_exp", h),
+        _ptr(targets, torch.int32, T, "targets", h), T))
 
 
 def bc_pair_dependencies(g: Graph, us, vs, out):
     import torch
-    k = us.numel()
-    if vs.numel() != k:
+    h = g.host_io
+    k = _numel(us)
+    if _numel(vs) != k:
         raise ValueError("us and vs differ in length")
-    _check(_lib.bc_pair_dependencies(g.handle, _ptr(us, torch.int32, k, "us"),
-                                     _ptr(vs, torch.int32, k, "vs"), k,
-                                     _ptr(out, torch.float64, k * g.n, "out")))
+    _check(_lib.bc_pair_dependencies(g.handle, _ptr(us, torch.int32, k, "us", h),
+                                     _ptr(vs, torch.int32, k, "vs", h), k,
+                                     _ptr(out, torch.float64, k * g.n, "out", h)))
 
 
 def bc_adaptive_source(g: Graph, targets, c, seed, k_max, out_est, out_samples, out_S,
                        out_status):
     import torch
-    T = targets.numel()
+    h = g.host_io
+    T = _numel(targets)
     _check(_lib.bc_adaptive_source(
-        g.handle, _ptr(targets, torch.int32, T, "targets"), T, float(c), int(seed), int(k_max),
-        _ptr(out_est, torch.float64, T, "out_est"), _ptr(out_samples, torch.int64, T, "out_samples"),
-        _ptr(out_S, torch.float64, T, "out_S"), _ptr(out_status, torch.uint8, T, "out_status")))
+        g.handle, _ptr(targets, torch.int32, T, "targets", h), T, float(c), int(seed), int(k_max),
+        _ptr(out_est, torch.float64, T, "out_est", h),
+        _ptr(out_samples, torch.int64, T, "out_samples", h),
+        _ptr(out_S, torch.float64, T, "out_S", h), _ptr(out_status, torch.uint8, T, "out_status", h)))
 
 
 def bc_adaptive_pair(g: Graph, targets, rule, eps, c, seed, k_max, out_est, out_samples, out_S,
                      out_status):
     import torch
-    T = targets.numel()
+    h = g.host_io
+    T = _numel(targets)
     _check(_lib.bc_adaptive_pair(
-        g.handle, _ptr(targets, torch.int32, T, "targets"), T, int(rule), float(eps), float(c),
-        int(seed), int(k_max), _ptr(out_est, torch.float64, T, "out_est"),
-        _ptr(out_samples, torch.int64, T, "out_samples"), _ptr(out_S, torch.float64, T, "out_S"),
-        _ptr(out_status, torch.uint8, T, "out_status")))
+        g.handle, _ptr(targets, torch.int32, T, "targets", h), T, int(rule), float(eps), float(c),
+        int(seed), int(k_max), _ptr(out_est, torch.float64, T, "out_est", h),
+        _ptr(out_samples, torch.int64, T, "out_samples", h),
+        _ptr(out_S, torch.float64, T, "out_S", h),
+        _ptr(out_status, torch.uint8, T, "out_status", h)))
 
 
 def bc_draw_sources(g: Graph, seed, j0, count, out_u):
     import torch
     _check(_lib.bc_draw_sources(g.handle, int(seed), int(j0), int(count),
-                                _ptr(out_u, torch.int32, count, "out_u")))
+                                _ptr(out_u, torch.int32, count, "out_u", g.host_io)))
 
 
 def bc_draw_pairs(g: Graph, seed, j0, count, out_u, out_v):
     import torch
+    h = g.host_io
     _check(_lib.bc_draw_pairs(g.handle, int(seed), int(j0), int(count),
-                              _ptr(out_u, torch.int32, count, "out_u"),
-                              _ptr(out_v, torch.int32, count, "out_v")))
+                              _ptr(out_u, torch.int32, count, "out_u", h),
+                              _ptr(out_v, torch.int32, count, "out_v", h)))
 
 
 # ---------------------------------------------------- allocating conveniences
@@ -394,6 +481,15 @@ def dependencies(g: Graph, sources, mode=BC_OUT_FULL, dist=False, sigma=False):
         out = out.view(k, g.n)
     return out, (d.view(k, g.n) if dist else None), \
         ((sm.view(k, g.n), se.view(k, g.n)) if sigma else None)
+
+
+def target_dependencies(g: Graph, sources, targets):
+    """delta_{sources[i].}(targets[t]) as a k x T tensor (BC_OUT_TARGETS)."""
+    import torch
+    k, T = sources.numel(), targets.numel()
+    out = torch.empty(k * T, dtype=torch.float64, device=_dev())
+    bc_dependencies(g, sources, BC_OUT_TARGETS, out, targets=targets)
+    return out.view(k, T)
 
 
 def pair_dependencies(g: Graph, us, vs):

@@ -13,7 +13,7 @@
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
-#include <hipcub/device/device_radix_sort.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -46,23 +46,81 @@ void hip_check(hipError_t e, const char *what)
 }
 #define HIPX(expr) hip_check((expr), #expr)
 
+// Device memory provider of a handle: the caller's bc_allocator, or hipMalloc.
+// `forbid` marks the allocation-free entry point, where any attempt to
+// allocate is an error.
+struct Alloc {
+    bc_allocator a{nullptr, nullptr, nullptr};
+    bool forbid = false;
+    void *get(size_t bytes) const
+    {
+        if (forbid) fail(BC_E_UNSUPPORTED, "the scratch array is too small for this request");
+        void *p = nullptr;
+        if (a.alloc) {
+            p = a.alloc(bytes, a.ctx);
+            if (!p) fail(BC_E_NOMEM, "the caller's allocator returned no memory");
+        } else {
+            HIPX(hipMalloc(&p, bytes));
+        }
+        return p;
+    }
+    void put(void *p) const
+    {
+        if (!p) return;
+        if (a.free) a.free(p, a.ctx);
+        else (void)hipFree(p);
+    }
+};
+
+// The allocator of the handle the current ABI call works on (one per host
+// thread; null = hipMalloc).
+thread_local const Alloc *tl_alloc = nullptr;
+
+struct UseAlloc {
+    const Alloc *prev;
+    explicit UseAlloc(const Alloc *a) : prev(tl_alloc) { tl_alloc = a; }
+    ~UseAlloc() { tl_alloc = prev; }
+};
+
+// A lazily grown device array. It remembers the allocator it came from, so it
+// is released through that one. A view (set by `view`) borrows memory it does
+// not own: it never grows and is never freed.
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t cap = 0;
+    const Alloc *from = nullptr;
+    bool borrowed = false;
     void ensure(size_t count)
     {
         if (count <= cap) return;
+        if (borrowed) fail(BC_E_UNSUPPORTED, "the scratch array is too small for this request");
         release();
-        HIPX(hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T)));
+        static const Alloc plain;
+        const Alloc *al = tl_alloc ? tl_alloc : &plain;
+        p = (T *)al->get(std::max<size_t>(count, 1) * sizeof(T));
+        from = al == &plain ? nullptr : al;
         cap = count;
+    }
+    void view(T *mem, size_t count)
+    {
+        release();
+        p = mem;
+        cap = count;
+        borrowed = true;
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) {
+            if (from) from->put(p);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         cap = 0;
+        from = nullptr;
+        borrowed = false;
     }
+    size_t bytes() const { return cap * sizeof(T); }
 };
 
 int grid_for(int64_t threads)
@@ -130,6 +188,10 @@ struct Work {
     DBuf<int32_t> draw_src, draw_dst;   // a round's draws in draw order
     DBuf<uint8_t> sort_tmp;
     unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
+    // largest level record (entries) a batch may grow to; 0 = no limit. A
+    // server sets it from its budget; a batch that would need more raises
+    // RecordLimit.
+    int64_t cap_limit = 0;
 
     void init()
     {
@@ -158,6 +220,8 @@ struct bc_graph {
     int64_t n = 0, nnz = 0;
     int device = 0;
     hipStream_t stream = nullptr;
+    Alloc alloc;                 // device memory of this handle
+    int32_t io = BC_IO_DEVICE;   // where compute calls' arrays live
     DBuf<int64_t> row;
     DBuf<int32_t> col;
     bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0};
@@ -229,6 +293,69 @@ void need(bool ok, const char *msg)
 }
 
 void use_device(bc_graph *g) { HIPX(hipSetDevice(g->device)); }
+
+// Host arrays of a compute call in BC_IO_HOST mode, staged through device
+// memory from the handle's allocator: inputs are copied in when staged,
+// outputs copied back by finish(). In BC_IO_DEVICE mode pointers pass through.
+class Staging {
+public:
+    Staging(bc_graph *g) : g_(g), host_(g->io == BC_IO_HOST) {}
+    ~Staging()
+    {
+        if (!bufs_.empty()) (void)hipStreamSynchronize(g_->stream);
+        for (auto &b : bufs_) b.release();
+    }
+    template <class T>
+    const T *in(const T *h, int64_t count)
+    {
+        if (!host_ || !h || count <= 0) return h;
+        T *d = take<T>(count);
+        HIPX(hipMemcpyAsync(d, h, (size_t)count * sizeof(T), hipMemcpyHostToDevice, g_->stream));
+        return d;
+    }
+    template <class T>
+    T *out(T *h, int64_t count)
+    {
+        if (!host_ || !h || count <= 0) return h;
+        T *d = take<T>(count);
+        outs_.push_back({(void *)h, (const void *)d, (size_t)count * sizeof(T)});
+        return d;
+    }
+    void finish()
+    {
+        for (auto &o : outs_)
+            HIPX(hipMemcpyAsync(o.host, o.dev, o.bytes, hipMemcpyDeviceToHost, g_->stream));
+        HIPX(hipStreamSynchronize(g_->stream));
+    }
+    // a host array read on the host (u != v checks): copied when on the device
+    template <class T>
+    std::vector<T> to_host(const T *p, int64_t count)
+    {
+        std::vector<T> v((size_t)std::max<int64_t>(count, 0));
+        if (count <= 0) return v;
+        if (host_) std::memcpy(v.data(), p, (size_t)count * sizeof(T));
+        else HIPX(hipMemcpy(v.data(), p, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
+        return v;
+    }
+
+private:
+    template <class T>
+    T *take(int64_t count)
+    {
+        bufs_.emplace_back();
+        bufs_.back().ensure((size_t)count * sizeof(T));
+        return (T *)bufs_.back().p;
+    }
+    struct Out {
+        void *host;
+        const void *dev;
+        size_t bytes;
+    };
+    bc_graph *g_;
+    bool host_;
+    std::deque<DBuf<uint8_t>> bufs_;
+    std::vector<Out> outs_;
+};
 
 // ------------------------------------------------------------------ profiler
 
@@ -426,10 +553,17 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     return a;
 }
 
-struct Retry {
-    bool overflow_record;
-    bool overflow_sigma;
-};
+// Raised by run_batch when the level record would outgrow Work::cap_limit.
+struct RecordLimit {};
+
+// The record capacity after an overflow: `want`, clamped to the work's limit.
+int64_t grow_cap(const bc_graph *g, int64_t cap, int64_t want)
+{
+    const int64_t limit = g->w->cap_limit;
+    if (limit <= 0) return want;
+    if (cap >= limit) throw RecordLimit{};
+    return std::min(want, limit);
+}
 
 // Hook between the forward and backward passes (per-source path counts).
 struct SigmaOut {
@@ -456,6 +590,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
     const int64_t n = g->n, W = 1ll << p.logW;
     bool ext = g->ext_sticky;
     int64_t cap = std::max<int64_t>(g->cap_hint, std::max<int64_t>(4 * n * W, 1 << 16));
+    if (g->w->cap_limit > 0) cap = std::min(cap, g->w->cap_limit);
     const double bu_frac = bottom_up_fraction(g);
     for (;;) {
         ensure_batch(g, p, ext, cap, kind);
@@ -470,7 +605,10 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         launch(s, grid_for(p.B), k_init_sources, a, g->w->F0.p);
         read_ctl(g);
         std::vector<int64_t> off{0, (int64_t)g->w->h_ctl[CTL_TAIL]};
-        if (g->w->h_ctl[CTL_REC_OVERFLOW]) { cap *= 2; continue; }
+        if (g->w->h_ctl[CTL_REC_OVERFLOW]) {
+            cap = grow_cap(g, cap, cap * 2);
+            continue;
+        }
         launch(s, grid_for(off[1]), k_init_level0, a, (int64_t)0, off[1],
                (const uint64_t *)g->w->F0.p, g->w->SG0.p);
 
@@ -490,7 +628,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
             if (g->prof_on) g->prof_host_units[2 * PROF_LEVEL + 1] += e2 - e1;
             if (g->w->h_ctl[CTL_REC_OVERFLOW]) {
-                cap = std::max<int64_t>(cap * 2, e2 + (e2 >> 2));
+                cap = grow_cap(g, cap, std::max<int64_t>(cap * 2, e2 + (e2 >> 2)));
                 redo = true;
                 break;
             }
@@ -816,6 +954,16 @@ void ensure_source_keys(bc_graph *g)
     g->skey_ready = true;
 }
 
+// Temporary bytes of the lane-order sort of k keys (no device work).
+size_t sort_temp_bytes(int64_t k)
+{
+    size_t bytes = 0;
+    HIPX(rocprim::radix_sort_pairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                   (const int32_t *)nullptr, (int32_t *)nullptr, (size_t)k, 0u,
+                                   8u * (unsigned)sizeof(uint64_t), (hipStream_t)0));
+    return bytes;
+}
+
 // g->w->operm[0..k) = the sample indices in ascending (key of source, index)
 // order (a stable radix sort: deterministic for a given graph and input).
 void order_samples(bc_graph *g, const int32_t *sources, int64_t k)
@@ -829,13 +977,10 @@ void order_samples(bc_graph *g, const int32_t *sources, int64_t k)
     w.operm.ensure((size_t)k);
     launch(s, grid_for(k), k_key_gather, (const uint64_t *)g->skey.p, sources, k, w.okey_in.p,
            w.oidx_in.p);
-    size_t bytes = 0;
-    HIPX(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, w.okey_in.p, w.okey_out.p, w.oidx_in.p,
-                                            w.operm.p, (int)k, 0, 8 * (int)sizeof(uint64_t), s));
+    size_t bytes = sort_temp_bytes(k);
     w.sort_tmp.ensure(std::max<size_t>(bytes, 1));
-    HIPX(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp.p, bytes, w.okey_in.p, w.okey_out.p,
-                                            w.oidx_in.p, w.operm.p, (int)k, 0,
-                                            8 * (int)sizeof(uint64_t), s));
+    HIPX(rocprim::radix_sort_pairs(w.sort_tmp.p, bytes, w.okey_in.p, w.okey_out.p, w.oidx_in.p,
+                                   w.operm.p, (size_t)k, 0u, 8u * (unsigned)sizeof(uint64_t), s));
 }
 
 // Lane order inside a sampler or server round: the nb samples drawn into
@@ -865,7 +1010,7 @@ const int32_t *order_round(bc_graph *g, int nb, bool pair, int B)
 
 void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode, double *out,
                        int32_t *dist_out, double *sig_m, int32_t *sig_e, bool pair,
-                       const int32_t *dests)
+                       const int32_t *dests, const int32_t *targets = nullptr, int32_t T = 0)
 {
     const int64_t n = g->n;
     hipStream_t s = g->stream;
@@ -886,6 +1031,9 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
             if (mode == BC_OUT_SUM)
                 launch(s, grid_for(off.back() - 1), k_ss_out_sum, (const double *)g->w->ss_dlt.p,
                        (const int32_t *)g->w->ss_q.p, (int64_t)1, off.back(), out);
+            else if (mode == BC_OUT_TARGETS)
+                launch(s, grid_for(T), k_ss_out_targets, (const int32_t *)g->w->ss_d.p,
+                       (const double *)g->w->ss_dlt.p, targets, T, out + i * T);
             else
                 launch(s, grid_for(n), k_ss_out_full, (const int32_t *)g->w->ss_d.p,
                        (const double *)g->w->ss_dlt.p, n, out + i * n);
@@ -922,6 +1070,9 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
             run_pairs(g, B, count, pair, &ext, &so);
             PairArgs a = make_pair_args(g, B, ext, count, pair);
             if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_p_out_sum, a, out);
+            else if (mode == BC_OUT_TARGETS)
+                launch(s, grid_for((int64_t)count * T), k_p_out_targets, a, targets, T,
+                       (int32_t)count, b0, out);
             else launch(s, grid_for(n * count), k_p_out_full, a, (int32_t)count, b0, out);
             if (dist_out)
                 HIPX(hipMemcpyAsync(dist_out + b0 * n, g->w->lv.p, (size_t)count * n * 4,
@@ -968,6 +1119,9 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->w->ridx.cap, kind);
         a.lane_row = lane_row;
         if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_vsum, a, out);
+        else if (mode == BC_OUT_TARGETS)
+            launch(s, grid_for((int64_t)count * T), k_out_targets, a, targets, T, (int32_t)count,
+                   b0, out);
         else launch(s, grid_for(n * count), k_out_full, a, (int32_t)count, b0, out);
         if (dist_out)
             for (size_t l = 0; l + 1 < off.size(); ++l)
@@ -1085,23 +1239,28 @@ extern "C" {
 
 const char *bc_last_error(void) { return tl_error.c_str(); }
 
-bc_status bc_graph_create(const bc_csr *csr, void *hip_stream, bc_graph **out)
+bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream,
+                          bc_graph **out)
 {
     return guarded([&] {
         need(csr && out, "null argument");
         need(csr->n >= 1 && csr->n < 0x7fffffffll, "n must be in [1, 2^31 - 1)");
         need(csr->nnz >= 0 && csr->row && (csr->col || csr->nnz == 0), "bad CSR arrays");
+        need(!alloc || (alloc->alloc && alloc->free), "allocator needs both alloc and free");
         std::vector<int64_t> row((size_t)csr->n + 1);
         if (csr->row_is_i64) {
             const int64_t *r = (const int64_t *)csr->row;
             validate_csr(csr, r);
             std::copy(r, r + csr->n + 1, row.begin());
         } else {
+            need(csr->nnz < 0x7fffffffll, "int32 row offsets need nnz < 2^31");
             const int32_t *r = (const int32_t *)csr->row;
             validate_csr(csr, r);
             std::copy(r, r + csr->n + 1, row.begin());
         }
         bc_graph *g = new bc_graph();
+        if (alloc) g->alloc.a = *alloc;
+        UseAlloc ua(&g->alloc);
         try {
             HIPX(hipGetDevice(&g->device));
             g->n = csr->n;
@@ -1158,6 +1317,15 @@ bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream)
     });
 }
 
+bc_status bc_graph_set_io(bc_graph *g, int32_t io)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(io == BC_IO_DEVICE || io == BC_IO_HOST, "unknown io mode");
+        g->io = io;
+    });
+}
+
 bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg)
 {
     return guarded([&] {
@@ -1194,6 +1362,7 @@ bc_status bc_profile_enable(bc_graph *g, int32_t enable)
     return guarded([&] {
         need(g, "null graph");
         use_device(g);
+        UseAlloc ua(&g->alloc);
         prof_flush(g);
         g->prof_dev.ensure(2 * PROF_KERNELS * kProfSlots);
         HIPX(hipMemsetAsync(g->prof_dev.p, 0, 2 * PROF_KERNELS * kProfSlots * 8, g->stream));
@@ -1249,12 +1418,16 @@ bc_status bc_exact(bc_graph *g, double *out)
     return guarded([&] {
         need(g && out, "null argument");
         use_device(g);
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        double *d_out = io.out(out, g->n);
         DBuf<int32_t> all;
         all.ensure((size_t)g->n);
         try {
             launch(g->stream, grid_for(g->n), k_iota, all.p, (int64_t)0, g->n);
-            dependencies_impl(g, all.p, g->n, BC_OUT_SUM, out, nullptr, nullptr, nullptr, false,
+            dependencies_impl(g, all.p, g->n, BC_OUT_SUM, d_out, nullptr, nullptr, nullptr, false,
                               nullptr);
+            io.finish();
         } catch (...) {
             (void)hipStreamSynchronize(g->stream);
             all.release();
@@ -1265,21 +1438,42 @@ bc_status bc_exact(bc_graph *g, double *out)
 }
 
 bc_status bc_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_t out_mode,
-                          double *out, int32_t *dist_out, double *sigma_mant, int32_t *sigma_exp)
+                          double *out, int32_t *dist_out, double *sigma_mant, int32_t *sigma_exp,
+                          const int32_t *targets, int32_t T)
 {
     return guarded([&] {
         need(g, "null graph");
         need(k >= 0, "k must be >= 0");
-        need(k == 0 || (sources && out), "null argument");
-        need(out_mode == BC_OUT_FULL || out_mode == BC_OUT_SUM, "unknown out_mode");
+        need(out_mode == BC_OUT_FULL || out_mode == BC_OUT_SUM || out_mode == BC_OUT_TARGETS,
+             "unknown out_mode");
         need(out_mode == BC_OUT_FULL || (!dist_out && !sigma_mant && !sigma_exp),
              "per-source outputs need BC_OUT_FULL");
+        need(out_mode != BC_OUT_TARGETS || (T >= 0 && (T == 0 || targets)),
+             "BC_OUT_TARGETS needs T >= 0 targets");
+        const int64_t want = out_mode == BC_OUT_SUM ? g->n
+                             : out_mode == BC_OUT_FULL ? k * g->n : k * (int64_t)T;
+        need(want == 0 || out, "null argument");
+        need(k == 0 || sources, "null argument");
         use_device(g);
-        check_indices(g, sources, k, "source");
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        const int32_t *d_src = io.in(sources, k);
+        const int32_t *d_tg = out_mode == BC_OUT_TARGETS ? io.in(targets, T) : nullptr;
+        check_indices(g, d_src, k, "source");
+        if (out_mode == BC_OUT_TARGETS) check_indices(g, d_tg, T, "target");
         if (per_source_schedule(g) && (sigma_mant || sigma_exp))
             fail(BC_E_UNSUPPORTED, "path-count output is served by the batched schedule");
-        dependencies_impl(g, sources, k, out_mode, out, dist_out, sigma_mant, sigma_exp, false,
-                          nullptr);
+        double *d_out = io.out(out, want);
+        int32_t *d_dist = io.out(dist_out, k * g->n);
+        double *d_sm = io.out(sigma_mant, k * g->n);
+        int32_t *d_se = io.out(sigma_exp, k * g->n);
+        if (out_mode == BC_OUT_TARGETS && (k == 0 || T == 0)) {
+            io.finish();
+            return;
+        }
+        dependencies_impl(g, d_src, k, out_mode, d_out, d_dist, d_sm, d_se, false, nullptr, d_tg,
+                          T);
+        io.finish();
     });
 }
 
@@ -1292,16 +1486,20 @@ bc_status bc_pair_dependencies(bc_graph *g, const int32_t *us, const int32_t *vs
         need(k == 0 || (us && vs && out), "null argument");
         need(g->n >= 2, "pairs need n >= 2");
         use_device(g);
-        check_indices(g, us, k, "pair start");
-        check_indices(g, vs, k, "pair end");
-        // u != v is checked on the host copy (k is small in practice)
-        if (k > 0) {
-            std::vector<int32_t> hu((size_t)k), hv((size_t)k);
-            HIPX(hipMemcpy(hu.data(), us, (size_t)k * 4, hipMemcpyDeviceToHost));
-            HIPX(hipMemcpy(hv.data(), vs, (size_t)k * 4, hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < k; ++i) need(hu[i] != hv[i], "pair with u == v");
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        const int32_t *d_us = io.in(us, k);
+        const int32_t *d_vs = io.in(vs, k);
+        check_indices(g, d_us, k, "pair start");
+        check_indices(g, d_vs, k, "pair end");
+        // u != v is checked on the host (k is small in practice)
+        {
+            const std::vector<int32_t> hu = io.to_host(us, k), hv = io.to_host(vs, k);
+            for (int64_t i = 0; i < k; ++i) need(hu[(size_t)i] != hv[(size_t)i], "pair with u == v");
         }
-        dependencies_impl(g, us, k, BC_OUT_FULL, out, nullptr, nullptr, nullptr, true, vs);
+        double *d_out = io.out(out, k * g->n);
+        dependencies_impl(g, d_us, k, BC_OUT_FULL, d_out, nullptr, nullptr, nullptr, true, d_vs);
+        io.finish();
     });
 }
 
@@ -1317,11 +1515,17 @@ bc_status bc_adaptive_source(bc_graph *g, const int32_t *targets, int32_t T, dou
         need(c >= 1.0, "c must be >= 1 (and not NaN)");
         need(k_max >= 1, "k_max must be >= 1");
         use_device(g);
-        check_indices(g, targets, T, "target");
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        const int32_t *d_tg = io.in(targets, T);
+        check_indices(g, d_tg, T, "target");
         if (per_source_schedule(g))
             fail(BC_E_UNSUPPORTED, "samplers run on the batched schedule");
-        sampler_impl(g, targets, T, false, RULE_SOURCE, c, 0.0, seed, k_max, out_est,
-                     out_samples, out_S, out_status);
+        double *d_est = io.out(out_est, T), *d_S = io.out(out_S, T);
+        int64_t *d_k = io.out(out_samples, T);
+        uint8_t *d_st = io.out(out_status, T);
+        sampler_impl(g, d_tg, T, false, RULE_SOURCE, c, 0.0, seed, k_max, d_est, d_k, d_S, d_st);
+        io.finish();
     });
 }
 
@@ -1340,11 +1544,18 @@ bc_status bc_adaptive_pair(bc_graph *g, const int32_t *targets, int32_t T, int32
         need(k_max >= 1, "k_max must be >= 1");
         need(g->n >= 2, "pairs need n >= 2");
         use_device(g);
-        check_indices(g, targets, T, "target");
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        const int32_t *d_tg = io.in(targets, T);
+        check_indices(g, d_tg, T, "target");
         if (per_source_schedule(g))
             fail(BC_E_UNSUPPORTED, "samplers run on the batched schedule");
-        sampler_impl(g, targets, T, true, rule == BC_PAIR_EPS ? RULE_PAIR_EPS : RULE_PAIR_ALG1,
-                     c, eps, seed, k_max, out_est, out_samples, out_S, out_status);
+        double *d_est = io.out(out_est, T), *d_S = io.out(out_S, T);
+        int64_t *d_k = io.out(out_samples, T);
+        uint8_t *d_st = io.out(out_status, T);
+        sampler_impl(g, d_tg, T, true, rule == BC_PAIR_EPS ? RULE_PAIR_EPS : RULE_PAIR_ALG1, c, eps,
+                     seed, k_max, d_est, d_k, d_S, d_st);
+        io.finish();
     });
 }
 
@@ -1356,8 +1567,11 @@ bc_status bc_draw_sources(bc_graph *g, uint64_t seed, int64_t j0, int64_t count,
         need(count == 0 || out_u, "null argument");
         use_device(g);
         if (count == 0) return;
-        launch(g->stream, grid_for(count), k_draw_sources, seed, j0, count, g->n, out_u);
-        HIPX(hipStreamSynchronize(g->stream));
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        int32_t *d_u = io.out(out_u, count);
+        launch(g->stream, grid_for(count), k_draw_sources, seed, j0, count, g->n, d_u);
+        io.finish();
     });
 }
 
@@ -1371,8 +1585,11 @@ bc_status bc_draw_pairs(bc_graph *g, uint64_t seed, int64_t j0, int64_t count, i
         need(g->n >= 2, "pairs need n >= 2");
         use_device(g);
         if (count == 0) return;
-        launch(g->stream, grid_for(count), k_draw_pairs, seed, j0, count, g->n, out_u, out_v);
-        HIPX(hipStreamSynchronize(g->stream));
+        UseAlloc ua(&g->alloc);
+        Staging io(g);
+        int32_t *d_u = io.out(out_u, count), *d_v = io.out(out_v, count);
+        launch(g->stream, grid_for(count), k_draw_pairs, seed, j0, count, g->n, d_u, d_v);
+        io.finish();
     });
 }
 
@@ -1390,21 +1607,109 @@ struct ServerQuery {
     double arrival = 0.0;
 };
 
+// Device buffers a server holds, per kind, so that the shared workspace can
+// be budgeted buffer by buffer: the workspace keeps, for each buffer, the
+// largest size any admitted graph needs.
+enum WsBuf {
+    WB_SIG, WB_DLT, WB_SIGE, WB_VIS, WB_F0, WB_F1, WB_SG0, WB_SG1, WB_ACTIVE, WB_VALID,
+    WB_RIDX, WB_RMASK, WB_RSEG, WB_BCNT, WB_BPOP, WB_SRCS, WB_DEST, WB_LV, WB_PACTIVE,
+    WB_SS_D, WB_SS_Q, WB_SS_SIG, WB_SS_DLT, WB_PROBE, WB_OKEY_IN, WB_OKEY_OUT, WB_OIDX,
+    WB_OPERM, WB_LANE_ROW, WB_DRAW_SRC, WB_DRAW_DST, WB_SORT_TMP, WB_KEY_TMP, WB_QD,
+    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_COUNT
+};
+
+struct WsNeed {
+    size_t b[WB_COUNT] = {};
+    size_t total() const
+    {
+        size_t t = 0;
+        for (size_t x : b) t += x;
+        return t;
+    }
+    WsNeed max_with(const WsNeed &o) const
+    {
+        WsNeed r;
+        for (int i = 0; i < WB_COUNT; ++i) r.b[i] = std::max(b[i], o.b[i]);
+        return r;
+    }
+};
+
+// Record entries a server batch of W words on n vertices starts with, and
+// the most it may grow to (the budgeted size).
+int64_t server_record_entries(int64_t n, int64_t W)
+{
+    return std::max<int64_t>(4 * n * W, 1 << 16);
+}
+
+// Upper bound of the device bytes a server round on a graph of n vertices at
+// width B allocates, per buffer (engine slabs and bitmaps, level record,
+// lane-order sort, the one-off depth probe and key bitmaps, round arrays).
+WsNeed need_for(Engine e, int64_t n, int B)
+{
+    WsNeed r;
+    const size_t N = (size_t)n, Bs = (size_t)B, W = (size_t)std::max(1, B / 64);
+    r.b[WB_SIG] = N * Bs * 8;
+    r.b[WB_DLT] = N * Bs * 8;
+    r.b[WB_SIGE] = N * Bs * 4;
+    r.b[WB_SRCS] = Bs * 4;
+    r.b[WB_DEST] = Bs * 4;
+    if (e == ENG_PAIR) {
+        r.b[WB_LV] = N * Bs * 4;
+        r.b[WB_RIDX] = N * Bs * 4;
+        r.b[WB_PACTIVE] = Bs;
+    } else {
+        const size_t cap = (size_t)server_record_entries(n, (int64_t)W);
+        r.b[WB_VIS] = r.b[WB_F0] = r.b[WB_F1] = r.b[WB_SG0] = r.b[WB_SG1] = N * W * 8;
+        r.b[WB_ACTIVE] = r.b[WB_VALID] = W * 8;
+        r.b[WB_RIDX] = cap * 4;
+        r.b[WB_RMASK] = r.b[WB_RSEG] = cap * 8;
+        r.b[WB_BCNT] = r.b[WB_BPOP] = (((N * W) >> kLevelShift) + 2) * 8;
+        r.b[WB_OKEY_IN] = r.b[WB_OKEY_OUT] = Bs * 8;
+        r.b[WB_OIDX] = r.b[WB_OPERM] = r.b[WB_LANE_ROW] = Bs * 4;
+        r.b[WB_DRAW_SRC] = r.b[WB_DRAW_DST] = Bs * 4;
+        r.b[WB_SORT_TMP] = std::max<size_t>(sort_temp_bytes(B), 1);
+        r.b[WB_KEY_TMP] = 3 * N + kLandmarks * 4 + 8;
+    }
+    r.b[WB_SS_D] = r.b[WB_SS_Q] = N * 4;
+    r.b[WB_SS_SIG] = r.b[WB_SS_DLT] = N * 8;
+    r.b[WB_PROBE] = 4;
+    r.b[WB_QD] = Bs * sizeof(QueryDesc);
+    r.b[WB_SLOTQ] = r.b[WB_TGT] = Bs * 4;
+    r.b[WB_X] = Bs * 8;
+    r.b[WB_CTL] = 8 * sizeof(unsigned long long);
+    return r;
+}
+
+// Widest width <= max_batch within the 32-bit index range of engine e:
+// pair indices b*n + v (pair engine), (vertex, word) indices n*W (wave).
+int widest_width(Engine e, int64_t n, int max_batch)
+{
+    int B = max_batch;
+    if (e == ENG_PAIR)
+        while (B > 64 && (int64_t)B * n >= (1ll << 32)) B /= 2;
+    else
+        while (B > 64 && n * (int64_t)(B / 64) >= (1ll << 32)) B /= 2;
+    return B;
+}
+
 }  // namespace
 
 struct bc_server {
     int device = 0;
     hipStream_t stream = nullptr;
+    Alloc alloc;
     size_t budget = 0;
-    size_t resident = 0;
+    size_t resident = 0;               // graphs' CSR and lane-order keys
     int max_batch = 256;
     Work work;
+    WsNeed ws;                         // budgeted workspace, per buffer
     std::vector<bc_graph *> graphs;
     std::vector<int> width;            // batch width per graph
     std::deque<ServerQuery> queued;    // arrival order
     std::vector<std::vector<ServerQuery>> active;
     std::deque<bc_result> done;
     int64_t next_id = 0, finished = 0, rounds = 0, samples_exec = 0, samples_used = 0;
+    int64_t split_rounds = 0;
     DBuf<QueryDesc> qd;
     DBuf<int32_t> slotq, tgt;
     DBuf<double> X;
@@ -1414,13 +1719,20 @@ struct bc_server {
     {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+    // device bytes the shared workspace holds now
     size_t workspace_bytes() const
     {
         const Work &w = work;
-        return w.sig.cap * 8 + w.dlt.cap * 8 + w.sige.cap * 4 + w.vis.cap * 8 + w.F0.cap * 8 +
-               w.F1.cap * 8 + w.SG0.cap * 8 + w.SG1.cap * 8 + w.vsum.cap * 8 + w.ridx.cap * 4 +
-               w.rmask.cap * 8 + w.rseg.cap * 8 + w.lv.cap * 4 +
-               qd.cap * sizeof(QueryDesc) + slotq.cap * 4 + tgt.cap * 4 + X.cap * 8;
+        return w.sig.bytes() + w.dlt.bytes() + w.sige.bytes() + w.vis.bytes() + w.F0.bytes() +
+               w.F1.bytes() + w.SG0.bytes() + w.SG1.bytes() + w.active.bytes() +
+               w.valid.bytes() + w.vsum.bytes() + w.ridx.bytes() + w.rmask.bytes() +
+               w.rseg.bytes() + w.bcnt.bytes() + w.bpop.bytes() + w.ctl.bytes() +
+               w.srcs.bytes() + w.dest.bytes() + w.X.bytes() + w.S.bytes() + w.K.bytes() +
+               w.st.bytes() + w.lv.bytes() + w.pactive.bytes() + w.ss_d.bytes() +
+               w.ss_q.bytes() + w.ss_sig.bytes() + w.ss_dlt.bytes() + w.probe_src.bytes() +
+               w.okey_in.bytes() + w.okey_out.bytes() + w.oidx_in.bytes() + w.operm.bytes() +
+               w.lane_row.bytes() + w.draw_src.bytes() + w.draw_dst.bytes() +
+               w.sort_tmp.bytes() + qd.bytes() + slotq.bytes() + tgt.bytes() + X.bytes();
     }
     void release()
     {
@@ -1436,14 +1748,54 @@ struct bc_server {
 
 namespace {
 
-// Device bytes an engine needs for a batch of width B on n vertices.
-size_t engine_bytes(Engine e, int64_t n, int B)
+// Slots [lo, hi) of the round's batch on graph g: draw their samples, run
+// them as one batch and gather each slot's value at its query's target into
+// X[lo..hi). A batch whose level record would outgrow the budgeted workspace
+// runs as two halves (each sample's arithmetic does not depend on its batch
+// mates, so the values are the same).
+void run_slots(bc_server *sv, bc_graph *g, Engine e, int B, int lo, int hi)
 {
-    const size_t W = (size_t)std::max(1, B / 64);
-    if (e == ENG_PAIR) return (size_t)n * B * 28;
-    // slabs (count, dependency, exponent), bitmaps and sums, a record of ~4 entries
-    // per (vertex, word)
-    return (size_t)n * B * 20 + (size_t)n * W * 8 * 7 + (size_t)n * W * 4 * 20;
+    const int cnt = hi - lo;
+    const int64_t n = g->n;
+    hipStream_t st = sv->stream;
+    try {
+        bool ext = false;
+        if (e == ENG_PAIR) {
+            ensure_pairs(g, B, false);
+            launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)sv->qd.p,
+                   (const int32_t *)sv->slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
+                   g->w->dest.p, sv->tgt.p);
+            run_pairs(g, B, cnt, true, &ext, nullptr);
+            PairArgs a = make_pair_args(g, B, ext, cnt, true);
+            launch(st, grid_for(cnt), k_p_gather_slots, a, (const int32_t *)sv->tgt.p,
+                   (int32_t)lo, sv->X.p);
+        } else {
+            Plan p;
+            p.B = B;
+            while ((64 << p.logW) < B) ++p.logW;
+            ensure_batch(g, p, false, std::max<int64_t>(std::min(g->cap_hint, g->w->cap_limit),
+                                                        1 << 16),
+                         OUT_DELTA);
+            launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)sv->qd.p,
+                   (const int32_t *)sv->slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
+                   g->w->dest.p, sv->tgt.p);
+            const int32_t *lane_row = order_round(g, cnt, true, B);
+            run_batch(g, p, cnt, true, &ext, nullptr, OUT_DELTA);
+            BatchArgs a = make_args(g, p, ext, cnt, true, (int64_t)g->w->ridx.cap, OUT_DELTA);
+            a.lane_row = lane_row;
+            launch(st, grid_for(cnt), k_gather_slots, a, (const int32_t *)sv->tgt.p, (int32_t)lo,
+                   sv->X.p);
+        }
+    } catch (const RecordLimit &) {
+        // a single sample reaches at most n (vertex, word) entries, within the
+        // 4 n W entries budgeted for any width, so halving always ends
+        if (cnt <= 1) fail(BC_E_NOMEM, "level record exceeds the server's budget");
+        (void)hipStreamSynchronize(st);
+        sv->split_rounds += 1;
+        const int mid = lo + cnt / 2;
+        run_slots(sv, g, e, B, lo, mid);
+        run_slots(sv, g, e, B, mid, hi);
+    }
 }
 
 void server_round(bc_server *sv, int gi, int32_t *completed)
@@ -1490,37 +1842,14 @@ void server_round(bc_server *sv, int gi, int32_t *completed)
     const int nb = (int)hslot.size();
     hipStream_t st = sv->stream;
     g->stream = st;
-    sv->qd.ensure((size_t)A);
+    sv->qd.ensure((size_t)B);
     sv->slotq.ensure((size_t)B);
     sv->tgt.ensure((size_t)B);
     sv->X.ensure((size_t)B);
     HIPX(hipMemcpyAsync(sv->qd.p, hd.data(), hd.size() * sizeof(QueryDesc),
                         hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(sv->slotq.p, hslot.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st));
-    const Engine e = engine_for(g);
-    bool ext = false;
-    if (e == ENG_PAIR) {
-        ensure_pairs(g, B, false);
-        launch(st, grid_for(nb), k_serve_draw, (const QueryDesc *)sv->qd.p,
-               (const int32_t *)sv->slotq.p, (int32_t)nb, n, g->w->srcs.p, g->w->dest.p,
-               sv->tgt.p);
-        run_pairs(g, B, nb, true, &ext, nullptr);
-        PairArgs a = make_pair_args(g, B, ext, nb, true);
-        launch(st, grid_for(nb), k_p_gather_slots, a, (const int32_t *)sv->tgt.p, sv->X.p);
-    } else {
-        Plan p;
-        p.B = B;
-        while ((64 << p.logW) < B) ++p.logW;
-        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
-        launch(st, grid_for(nb), k_serve_draw, (const QueryDesc *)sv->qd.p,
-               (const int32_t *)sv->slotq.p, (int32_t)nb, n, g->w->srcs.p, g->w->dest.p,
-               sv->tgt.p);
-        const int32_t *lane_row = order_round(g, nb, true, B);
-        run_batch(g, p, nb, true, &ext, nullptr, OUT_DELTA);
-        BatchArgs a = make_args(g, p, ext, nb, true, (int64_t)g->w->ridx.cap, OUT_DELTA);
-        a.lane_row = lane_row;
-        launch(st, grid_for(nb), k_gather_slots, a, (const int32_t *)sv->tgt.p, sv->X.p);
-    }
+    run_slots(sv, g, engine_for(g), B, 0, nb);
     launch(st, grid_for(A), k_stop_queries, sv->qd.p, (int32_t)A, (const double *)sv->X.p);
     HIPX(hipMemcpyAsync(hd.data(), sv->qd.p, hd.size() * sizeof(QueryDesc),
                         hipMemcpyDeviceToHost, st));
@@ -1562,21 +1891,26 @@ void server_round(bc_server *sv, int gi, int32_t *completed)
 
 extern "C" {
 
-bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, void *hip_stream,
-                           bc_server **out)
+bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, const bc_allocator *alloc,
+                           void *hip_stream, bc_server **out)
 {
     return guarded([&] {
         need(out != nullptr, "null argument");
         need(max_batch >= 64 && max_batch <= 4096 && (max_batch & (max_batch - 1)) == 0,
              "max_batch must be a power of two in [64, 4096]");
         need(hbm_budget_bytes > 0, "budget must be positive");
+        need(!alloc || (alloc->alloc && alloc->free), "allocator needs both alloc and free");
         bc_server *sv = new bc_server();
+        if (alloc) sv->alloc.a = *alloc;
+        UseAlloc ua(&sv->alloc);
         try {
             HIPX(hipGetDevice(&sv->device));
             sv->stream = (hipStream_t)hip_stream;
             sv->budget = hbm_budget_bytes;
             sv->max_batch = max_batch;
+            need(hbm_budget_bytes >= 8 * sizeof(unsigned long long), "budget below 64 bytes");
             sv->work.init();
+            sv->ws.b[WB_CTL] = sv->work.ctl.bytes();
         } catch (...) {
             sv->release();
             delete sv;
@@ -1591,6 +1925,7 @@ void bc_server_destroy(bc_server *sv)
     if (!sv) return;
     (void)hipSetDevice(sv->device);
     if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    UseAlloc ua(&sv->alloc);
     sv->release();
     delete sv;
 }
@@ -1600,24 +1935,41 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
     return guarded([&] {
         need(sv && csr && graph_id, "null argument");
         HIPX(hipSetDevice(sv->device));
-        const size_t csr_bytes = (size_t)(csr->n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4;
-        if (sv->resident + csr_bytes > sv->budget)
+        UseAlloc ua(&sv->alloc);
+        need(csr->n >= 1 && csr->n < 0x7fffffffll, "n must be in [1, 2^31 - 1)");
+        const int64_t n = csr->n;
+        // resident: the CSR (int64 rows, int32 columns) and the lane-order key
+        // and the handle's own control block
+        const size_t res_bytes = (size_t)(n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4 +
+                                 (size_t)n * 8 + 8 * sizeof(unsigned long long);
+        auto fits = [&](const WsNeed &w) {
+            return sv->resident + res_bytes + w.total() <= sv->budget;
+        };
+        // the engine choice runs a depth probe in the shared workspace: it must fit first
+        WsNeed probe;
+        probe.b[WB_SS_D] = probe.b[WB_SS_Q] = (size_t)n * 4;
+        probe.b[WB_SS_SIG] = probe.b[WB_SS_DLT] = (size_t)n * 8;
+        probe.b[WB_PROBE] = 4;
+        if (!fits(sv->ws.max_with(probe)))
             fail(BC_E_NOMEM, "graph does not fit the server's HBM budget");
         bc_graph *g = nullptr;
-        const bc_status rc = bc_graph_create(csr, (void *)sv->stream, &g);
+        bc_allocator *al = sv->alloc.a.alloc ? &sv->alloc.a : nullptr;
+        const bc_status rc = bc_graph_create(csr, al, (void *)sv->stream, &g);
         if (rc != BC_OK) fail(rc, tl_error);
         g->w = &sv->work;
         try {
             const Engine e = engine_for(g);
-            const size_t room = sv->budget - sv->resident - csr_bytes;
-            int B = sv->max_batch;
-            while (B > 64 && engine_bytes(e, g->n, B) > room) B /= 2;
-            if (engine_bytes(e, g->n, B) > room)
+            int B = widest_width(e, n, sv->max_batch);
+            while (B > 64 && !fits(sv->ws.max_with(need_for(e, n, B)))) B /= 2;
+            const WsNeed ws = sv->ws.max_with(need_for(e, n, B));
+            if (!fits(ws))
                 fail(BC_E_NOMEM, "no batch width fits the server's HBM budget for this graph");
+            sv->ws = ws;
+            sv->work.cap_limit = (int64_t)(ws.b[WB_RIDX] / 4);
             sv->graphs.push_back(g);
             sv->width.push_back(B);
             sv->active.emplace_back();
-            sv->resident += csr_bytes;
+            sv->resident += res_bytes;
         } catch (...) {
             g->w = &g->own;
             bc_graph_destroy(g);
@@ -1658,6 +2010,7 @@ bc_status bc_server_step(bc_server *sv, int32_t *completed)
     return guarded([&] {
         need(sv && completed, "null argument");
         HIPX(hipSetDevice(sv->device));
+        UseAlloc ua(&sv->alloc);
         *completed = 0;
         // Shortest job first at graph granularity: the graph whose cheapest
         // unfinished query has the least remaining work bound ((k_max - k)
@@ -1729,6 +2082,21 @@ bc_status bc_server_stats_get(const bc_server *sv, bc_server_stats *out)
         out->samples_used = sv->samples_used;
         out->resident_bytes = (int64_t)sv->resident;
         out->workspace_bytes = (int64_t)sv->workspace_bytes();
+        out->budget_bytes = (int64_t)sv->budget;
+        out->split_rounds = sv->split_rounds;
+    });
+}
+
+bc_status bc_server_graph_width(const bc_server *sv, int32_t graph, int32_t *width,
+                                int32_t *schedule)
+{
+    return guarded([&] {
+        need(sv && (width || schedule), "null argument");
+        need(graph >= 0 && graph < (int32_t)sv->graphs.size(), "unknown graph id");
+        if (width) *width = sv->width[(size_t)graph];
+        if (schedule)
+            *schedule = sv->graphs[(size_t)graph]->engine == ENG_PAIR ? BC_SCHED_THREADED
+                                                                     : BC_SCHED_BATCHED;
     });
 }
 

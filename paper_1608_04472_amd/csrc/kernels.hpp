@@ -1116,6 +1116,20 @@ __global__ void k_out_full(BatchArgs a, int32_t count, int64_t b0, double *out)
     }
 }
 
+// out[row(b) * T + t] = delta_{s_b}(targets[t]) for b < count (0 where unreached)
+__global__ void k_out_targets(BatchArgs a, const int32_t *targets, int32_t T, int32_t count,
+                              int64_t b0, double *out)
+{
+    const int64_t total = (int64_t)count * T;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / T);
+        const int t = (int)(i - (int64_t)b * T);
+        const int64_t v = targets[t];
+        out[out_row(a, b0, b) * T + t] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
+    }
+}
+
 // out[v] += sum over j ascending of vsum[v][j]
 __global__ void k_out_vsum(BatchArgs a, double *out)
 {
@@ -1531,6 +1545,19 @@ __global__ void k_p_out_full(PairArgs a, int32_t count, int64_t b0, double *out)
     }
 }
 
+__global__ void k_p_out_targets(PairArgs a, const int32_t *targets, int32_t T, int32_t count,
+                                int64_t b0, double *out)
+{
+    const int64_t total = (int64_t)count * T;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / T);
+        const int t = (int)(i - (int64_t)b * T);
+        const uint32_t o = (uint32_t)b * a.n + (uint32_t)targets[t];
+        out[(b0 + b) * T + t] = a.lv[o] >= 1 ? a.dlt[o] : 0.0;
+    }
+}
+
 __global__ void k_p_out_sigma(PairArgs a, int32_t count, int64_t b0, double *mant, int32_t *ex)
 {
     const int64_t total = (int64_t)a.n * count;
@@ -1588,13 +1615,16 @@ struct QueryDesc {
     int32_t pad;
 };
 
-__global__ void k_serve_draw(const QueryDesc *q, const int32_t *slot_query, int32_t nb,
-                             int64_t n, int32_t *srcs, int32_t *dest, int32_t *tgt)
+// Draws of slots [b0, b0 + nb) into lanes 0..nb-1 (a round may run its slots
+// in parts).
+__global__ void k_serve_draw(const QueryDesc *q, const int32_t *slot_query, int32_t b0,
+                             int32_t nb, int64_t n, int32_t *srcs, int32_t *dest, int32_t *tgt)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
-    const QueryDesc &d = q[slot_query[b]];
-    const int64_t j = d.j0 + (b - d.slot0);
+    const int slot = b0 + b;
+    const QueryDesc &d = q[slot_query[slot]];
+    const int64_t j = d.j0 + (slot - d.slot0);
     if (d.rule == RULE_SOURCE) {
         const Block4 r = philox4x64_10((uint64_t)j, 0, 0, 0, d.seed, 0);
         srcs[b] = (int32_t)scale_to_range(r.w[0], (uint64_t)n);
@@ -1610,21 +1640,22 @@ __global__ void k_serve_draw(const QueryDesc *q, const int32_t *slot_query, int3
     tgt[b] = d.target;
 }
 
-__global__ void k_gather_slots(BatchArgs a, const int32_t *tgt, double *X)
+// X[b0 + slot] for the lanes of a part that starts at slot b0
+__global__ void k_gather_slots(BatchArgs a, const int32_t *tgt, int32_t b0, double *X)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.nvalid) return;
-    const int r = a.lane_row ? a.lane_row[b] : b;   // the lane's slot
+    const int r = a.lane_row ? a.lane_row[b] : b;   // the lane's slot within the part
     const int64_t v = tgt[r];
-    X[r] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
+    X[b0 + r] = reached(a, v, b) ? a.dlt[v * a.B + b] : 0.0;
 }
 
-__global__ void k_p_gather_slots(PairArgs a, const int32_t *tgt, double *X)
+__global__ void k_p_gather_slots(PairArgs a, const int32_t *tgt, int32_t b0, double *X)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.nvalid) return;
     const uint32_t o = (uint32_t)b * a.n + (uint32_t)tgt[b];
-    X[b] = a.lv[o] >= 1 ? a.dlt[o] : 0.0;
+    X[b0 + b] = a.lv[o] >= 1 ? a.dlt[o] : 0.0;
 }
 
 __global__ void k_stop_queries(QueryDesc *q, int32_t nq, const double *X)
@@ -1712,6 +1743,16 @@ __global__ void k_ss_out_sum(const double *dlt, const int32_t *queue, int64_t q0
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = queue[i];
         out[v] += dlt[v];
+    }
+}
+
+__global__ void k_ss_out_targets(const int32_t *d, const double *dlt, const int32_t *targets,
+                                 int32_t T, double *out_row)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = targets[t];
+        out_row[t] = d[v] > 0 ? dlt[v] : 0.0;
     }
 }
 

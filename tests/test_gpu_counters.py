@@ -1,0 +1,97 @@
+"""The profiler's work-unit counters against the oracle's work counts.
+
+The roofline figure's numerator is (bytes per unit) x (units the kernels
+count). These cases check the units themselves: over a source list, the
+kernels must count exactly the (vertex, source) pairs and shortest-path DAG
+edges that the oracle's plain BFS counts (oracle_source_work):
+  discovery (top-down + bottom-up) units_a = sum over sources of (reached - 1)
+  sigma_pull units_a = sum of (reached - 1);  units_b = sum of DAG edges
+  backward (both forms) units_a = sum of (reached - 1);
+                        units_b = sum of (DAG edges - deg(s)), the source's own
+                        edges being the only DAG edges the sweep from level 1
+                        up does not read.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1608_04472_amd as bc  # noqa: E402
+
+O = oracle.load()
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def expected(g, src):
+    deg = g.degree()
+    reach = dag = own = 0
+    for s in src:
+        r, _, d = O.source_work(g, int(s))
+        reach += r - 1
+        dag += d
+        own += int(deg[s])
+    return reach, dag, dag - own
+
+
+def counted(G, src, dev, mode):
+    G.profile(True)
+    bc.dependencies(G, torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev), mode)
+    prof = {k["name"]: k for k in G.profile_read()}
+    G.profile(False)
+    disc = prof["discover_topdown"]["units_a"] + prof["discover_bottomup"]["units_a"]
+    bwd_a = prof["backward"]["units_a"] + prof["backward_split"]["units_a"]
+    bwd_b = prof["backward"]["units_b"] + prof["backward_split"]["units_b"]
+    return disc, prof["sigma_pull"]["units_a"], prof["sigma_pull"]["units_b"], bwd_a, bwd_b
+
+
+CASES = [
+    ("er2000 wave", lambda: gg.config_graph("er2000"), bc.BC_SCHED_BATCHED, 128, 0.0, 300),
+    ("er2000 wave bottom-up", lambda: gg.config_graph("er2000"), bc.BC_SCHED_BATCHED, 256, 1e-9,
+     300),
+    ("rmat12 wave", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9), bc.BC_SCHED_BATCHED, 512,
+     0.0, 700),
+    ("rmat12 pair engine", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9),
+     bc.BC_SCHED_THREADED, 128, 0.0, 300),
+    ("grid60 pair engine", lambda: gg.grid(60, 60), bc.BC_SCHED_THREADED, 64, 0.0, 100),
+]
+
+
+@pytest.mark.parametrize("name,make,sched,batch,bu,k", CASES, ids=[c[0] for c in CASES])
+def test_work_units_equal_the_oracle_counts(dev, name, make, sched, batch, bu, k):
+    g = make()
+    src = gg.philox_sources(5, k, g.n)
+    src[:3] = gg.top_degree(g, 3)            # hubs, and a repeat of one
+    src[7] = src[0]
+    iso = np.flatnonzero(g.degree() == 0)
+    if iso.size:
+        src[9] = iso[0]                      # an isolated source reaches only itself
+    reach, dag, bwd_dag = expected(g, src)
+    G = bc.Graph(g.row, g.col)
+    G.configure(sched, batch, bu)
+    for mode in (bc.BC_OUT_SUM, bc.BC_OUT_FULL):
+        say(name, "mode", mode)
+        disc, sa, sb, ba, bb = counted(G, src, dev, mode)
+        assert G.stats()["schedule"] == sched
+        assert disc == reach, (name, disc, reach)
+        assert sa == reach, (name, sa, reach)
+        assert sb == dag, (name, sb, dag)
+        assert ba == reach, (name, ba, reach)
+        assert bb == bwd_dag, (name, bb, bwd_dag)
+    G.close()

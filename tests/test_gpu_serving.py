@@ -57,6 +57,7 @@ def make_queries(graphs):
 
 
 def new_server(graphs, budget=8 * GIB, max_batch=128):
+    """A server holding `graphs` (ids 0, 1, ...)."""
     S = bc.Server(budget, max_batch)
     ids = [S.add_graph(g.row, g.col) for g in graphs]
     assert ids == list(range(len(graphs)))
@@ -174,3 +175,107 @@ def test_budget_admission(dev):
         S.submit(gid, 0, bc.BC_QUERY_PAIR, 1, 10, eps=0.7, rule=bc.BC_PAIR_EPS)
     assert S.step() == 0                   # nothing queued: no device work
     S.close()
+
+
+def test_widest_batch_mixed_alone_oracle(dev):
+    """max_batch 4096: the shallow graph runs 64-word wave batches, the deep
+    one 4096-lane pair-engine batches. Mixed = alone = oracle."""
+    graphs = [gg.rmat(10, 8, 0.57, 0.19, 0.19, seed=2), gg.grid(40, 40)]
+    qs = []
+    for gi, g in enumerate(graphs):
+        for j, t in enumerate(gg.top_degree(g, 2)):
+            qs.append((gi, int(t), bc.BC_QUERY_SOURCE, 0, 2.0, 0.1, 31 + 7 * j + gi, 1024))
+            qs.append((gi, int(t), bc.BC_QUERY_PAIR, bc.BC_PAIR_EPS, 1.0, 0.1, 61 + 5 * j + gi,
+                       4096))
+    say("serving max_batch 4096 mixed", len(qs))
+    S = new_server(graphs, budget=32 * GIB, max_batch=4096)
+    assert S.graph_width(0) == (4096, bc.BC_SCHED_BATCHED)
+    assert S.graph_width(1) == (4096, bc.BC_SCHED_THREADED)
+    mixed = run(S, qs)
+    st = S.stats()
+    assert st["resident_bytes"] + st["workspace_bytes"] <= st["budget_bytes"]
+    S.close()
+    for i, q in enumerate(qs):
+        say("serving max_batch 4096 alone", i)
+        A = new_server(graphs, budget=32 * GIB, max_batch=4096)
+        alone = run(A, [q])[0]
+        A.close()
+        assert key(alone) == key(mixed[i]), (i, q)
+        gi, t, kind, rule, c, eps, seed, kmax = q
+        g = graphs[gi]
+        if kind == bc.BC_QUERY_SOURCE:
+            oe, ok, oS, ost = O.adaptive_source(g, [t], c, seed, kmax)
+        else:
+            oe, ok, oS, ost = O.adaptive_pair(g, [t], oracle.RULE_EPS, eps, c, seed, kmax)
+        assert mixed[i]["samples"] == ok[0] and mixed[i]["status"] == ost[0], (i, q)
+        assert abs(mixed[i]["est"] - oe[0]) <= 1e-9 * abs(oe[0]), (i, q)
+
+
+def test_budget_is_an_invariant(dev):
+    """Graph after graph, and round after round, resident bytes plus the shared
+    workspace stay within the budget; a tight budget narrows the widths."""
+    graphs = [gg.rmat(s, 8, 0.57, 0.19, 0.19, seed=40 + s) for s in (11, 13, 12)] + \
+             [gg.grid(70, 70)]
+    budget = 96 << 20
+    say("serving budget invariant")
+    S = bc.Server(budget, 4096)
+    for g in graphs:
+        S.add_graph(g.row, g.col)
+        st = S.stats()
+        assert st["resident_bytes"] + st["workspace_bytes"] <= budget
+    widths = [S.graph_width(i)[0] for i in range(len(graphs))]
+    assert min(widths) < 4096, widths
+    qs = []
+    for gi, g in enumerate(graphs):
+        t = int(gg.top_degree(g, 1)[0])
+        qs.append((gi, t, bc.BC_QUERY_SOURCE, 0, 2.0, 0.1, 5 + gi, 600))
+        qs.append((gi, t, bc.BC_QUERY_PAIR, bc.BC_PAIR_EPS, 1.0, 0.2, 9 + gi, 2000))
+    for gi, t, kind, rule, c, eps, seed, kmax in qs:
+        S.submit(gi, t, kind, seed, kmax, c=c, eps=eps, rule=rule)
+    done = 0
+    while done < len(qs):
+        S.step()
+        done += len(S.poll())
+        st = S.stats()
+        assert st["resident_bytes"] + st["workspace_bytes"] <= budget, st
+    S.close()
+    # a budget that holds the graphs but not the widest width gets narrower
+    # widths, never a larger footprint
+    S = bc.Server(32 << 20, 4096)
+    S.add_graph(graphs[1].row, graphs[1].col)
+    assert S.graph_width(0)[0] < widths[1] or widths[1] == 64
+    st = S.stats()
+    assert st["resident_bytes"] + st["workspace_bytes"] <= 32 << 20
+    S.close()
+
+
+def test_rounds_split_when_the_record_outgrows_the_budget(dev):
+    """A hub with 1100 paths of 15 vertices: shallow from the hub (wave
+    engine), but a word of random sources meets each vertex at ~15 levels, far
+    beyond the 4 record entries per (vertex, word) a server budgets. Rounds
+    then run their samples in halves; results match the oracle."""
+    paths, length = 1100, 15
+    n = 1 + paths * length
+    src, dst = [], []
+    for p in range(paths):
+        first = 1 + p * length
+        src.append(0)
+        dst.append(first)
+        for i in range(length - 1):
+            src.append(first + i)
+            dst.append(first + i + 1)
+    g = gg.from_edges(n, src, dst, "broom")
+    qs = [(0, 0, bc.BC_QUERY_SOURCE, 0, 2.0, 0.1, 3, 64),
+          (0, 1 + 3 * length + 4, bc.BC_QUERY_SOURCE, 0, 1.5, 0.1, 4, 64)]
+    say("serving split rounds")
+    S = new_server([g], budget=GIB, max_batch=64)
+    assert S.graph_width(0) == (64, bc.BC_SCHED_BATCHED)
+    res = run(S, qs)
+    st = S.stats()
+    assert st["split_rounds"] > 0, st
+    assert st["resident_bytes"] + st["workspace_bytes"] <= GIB
+    S.close()
+    for i, (gi, t, kind, rule, c, eps, seed, kmax) in enumerate(qs):
+        oe, ok, oS, ost = O.adaptive_source(g, [t], c, seed, kmax)
+        assert res[i]["samples"] == ok[0] and res[i]["status"] == ost[0]
+        assert abs(res[i]["est"] - oe[0]) <= 1e-9 * abs(oe[0])
