@@ -180,6 +180,26 @@ bc_status bc_adaptive_pair(bc_graph *g, const int32_t *targets, int32_t T, int32
                            double *out_est, int64_t *out_samples, double *out_S,
                            uint8_t *out_status);
 
+/* ---------------------------------------------------- allocation-free call
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Computes
+ * what bc_dependencies computes in BC_OUT_FULL or BC_OUT_SUM mode without any
+ * hipMalloc, hipFree or allocator call: the engine's buffers come from one
+ * fixed device array of BC_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends (the graph handle, created
+ * beforehand, supplies the CSR). Sources run in batches of 64, in the
+ * caller's order. Results equal bc_dependencies' up to FP64 summation order.
+ * Limits: about 1.2 KB per vertex in BC_OUT_FULL and 0.7 KB in BC_OUT_SUM must
+ * fit the array (extended path counts need 256 B more); a larger graph, a
+ * level record beyond what is left, or BC_IO_HOST returns BC_E_UNSUPPORTED.
+ * Arrays are device pointers. All calls on one device share its array and
+ * it keeps the last call's contents: each call clears what it reads, and
+ * calls that overlap on one device (other host threads or streams) race, so
+ * the caller must not overlap them. */
+#define BC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k,
+                                  int32_t out_mode, double *out);
+
 /* Pair dependencies of k given pairs: out[i*n + t] = sigma_{u_i v_i}(t) /
  * sigma_{u_i v_i} (0 for t in {u_i, v_i} or when v_i is unreachable).
  * us, vs: k int32 each, u_i != v_i. out: k*n doubles (device). */

@@ -39,7 +39,8 @@ BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED = 0, 1, 
 EXPORTS = [
     "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_set_io",
     "bc_graph_configure",
-    "bc_graph_info", "bc_exact", "bc_dependencies", "bc_pair_dependencies",
+    "bc_graph_info", "bc_exact", "bc_dependencies", "bc_dependencies_noalloc",
+    "bc_pair_dependencies",
     "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
     "bc_last_stats", "bc_last_error", "bc_profile_enable", "bc_profile_read",
     "bc_server_create", "bc_server_destroy", "bc_server_add_graph", "bc_server_submit",
@@ -191,6 +192,7 @@ def load_library(path: str | None = None):
         "bc_exact": [V, V],
         "bc_dependencies": [V, V, c.c_int64, c.c_int32, V, V, V, V, V, c.c_int32],
         "bc_pair_dependencies": [V, V, V, c.c_int64, V],
+        "bc_dependencies_noalloc": [V, V, c.c_int64, c.c_int32, V],
         "bc_adaptive_source": [V, V, c.c_int32, c.c_double, c.c_uint64, c.c_int64, V, V, V, V],
         "bc_adaptive_pair": [V, V, c.c_int32, c.c_int32, c.c_double, c.c_double, c.c_uint64,
                              c.c_int64, V, V, V, V],
@@ -403,6 +405,16 @@ def bc_dependencies(g: Graph, sources, out_mode, out, dist_out=None, sigma_mant=
         _ptr(sigma_mant, torch.float64, k * g.n, "sigma_mant", h),
         _ptr(sigma_exp, torch.int32, k * g.n, "sigma_exp", h),
         _ptr(targets, torch.int32, T, "targets", h), T))
+
+
+def bc_dependencies_noalloc(g: Graph, sources, out_mode, out):
+    """bc_dependencies (BC_OUT_FULL / BC_OUT_SUM) with no device allocation:
+    the library's fixed scratch array holds the engine's buffers."""
+    import torch
+    k = _numel(sources)
+    need = k * g.n if int(out_mode) == BC_OUT_FULL else g.n
+    _check(_lib.bc_dependencies_noalloc(g.handle, _ptr(sources, torch.int32, k, "sources"), k,
+                                        int(out_mode), _ptr(out, torch.float64, need, "out")))
 
 
 def bc_pair_dependencies(g: Graph, us, vs, out):

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1008,9 +1009,20 @@ const int32_t *order_round(bc_graph *g, int nb, bool pair, int B)
 
 // ------------------------------------------------------------ dependencies
 
+// The record capacity a batch starts from: what earlier batches on the graph
+// needed, within the work's limit.
+int64_t start_cap(const bc_graph *g)
+{
+    const int64_t c = std::max<int64_t>(g->cap_hint, 1 << 16);
+    return g->w->cap_limit > 0 ? std::min(c, g->w->cap_limit) : c;
+}
+
+// `fixed`: run the wave engine at that plan, in the caller's sample order (no
+// depth probe, no lane-order sort): the allocation-free entry point's form.
 void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode, double *out,
                        int32_t *dist_out, double *sig_m, int32_t *sig_e, bool pair,
-                       const int32_t *dests, const int32_t *targets = nullptr, int32_t T = 0)
+                       const int32_t *dests, const int32_t *targets = nullptr, int32_t T = 0,
+                       const Plan *fixed = nullptr)
 {
     const int64_t n = g->n;
     hipStream_t s = g->stream;
@@ -1025,7 +1037,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     if (sig_m) launch(s, grid_for(k * n), k_fill_f64, sig_m, 0.0, k * n);
     if (sig_e) launch(s, grid_for(k * n), k_fill_i32, sig_e, (int32_t)0, k * n);
 
-    if (per_source_schedule(g) && !pair) {
+    if (!fixed && per_source_schedule(g) && !pair) {
         for (int64_t i = 0; i < k; ++i) {
             std::vector<int64_t> off = run_single(g, sources + i);
             if (mode == BC_OUT_SUM)
@@ -1049,7 +1061,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         return;
     }
 
-    if (engine_for(g) == ENG_PAIR) {
+    if (!fixed && engine_for(g) == ENG_PAIR) {
         const int B = plan_pairs(g, k, 512);
         g->stats.batch_width = B;
         g->stats.schedule = BC_SCHED_THREADED;
@@ -1085,16 +1097,16 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         return;
     }
 
-    const Plan p = plan_batch(g, k, 2048);
+    const Plan p = fixed ? *fixed : plan_batch(g, k, 2048);
     g->stats.batch_width = p.B;
     g->stats.schedule = BC_SCHED_BATCHED;
     // samples sorted by the clustering key, cut into batches, rows mapped back
-    const bool ordered = k >= kOrderMin && !g->landmarks.empty();
+    const bool ordered = !fixed && k >= kOrderMin && !g->landmarks.empty();
     if (ordered) order_samples(g, sources, k);
     for (int64_t b0 = 0; b0 < k; b0 += p.B) {
         const int count = (int)std::min<int64_t>(p.B, k - b0);
         const OutKind kind = mode == BC_OUT_SUM ? OUT_VSUM : OUT_DELTA;
-        ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), kind);
+        ensure_batch(g, p, false, start_cap(g), kind);
         if (ordered) {
             g->w->lane_row.ensure((size_t)p.B);
             launch(s, grid_for(count), k_take_batch, (const int32_t *)g->w->operm.p, b0, count,
@@ -1170,7 +1182,7 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     for (;;) {
         const int nb = (int)std::min<int64_t>(p.B, k_max - j0);
         if (use_pairs) ensure_pairs(g, p.B, false);
-        else ensure_batch(g, p, false, std::max<int64_t>(g->cap_hint, 1 << 16), OUT_DELTA);
+        else ensure_batch(g, p, false, start_cap(g), OUT_DELTA);
         if (pair)
             launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->w->srcs.p, g->w->dest.p);
         else
@@ -1230,6 +1242,58 @@ void validate_csr(const bc_csr *c, const R *row)
         }
     }
 }
+
+}  // namespace
+
+// ------------------------------------------------ allocation-free variant
+
+// Scratch of bc_dependencies_noalloc: a file-scope device array, one copy on
+// each device, held until the process ends. Host code reaches it only through
+// the address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) unsigned char scratch[BC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned char *scratch_dev[kMaxDevices] = {};
+
+// The scratch array's device address on device `dev`, which must be current
+// (looked up once per device).
+unsigned char *scratch_on(int dev)
+{
+    need(dev >= 0 && dev < kMaxDevices, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPX(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        need(p != nullptr, "no address for the scratch array");
+        scratch_dev[dev] = (unsigned char *)p;
+    }
+    return scratch_dev[dev];
+}
+
+// Consecutive 256-byte-aligned pieces of the scratch array, as buffer views.
+struct Carve {
+    unsigned char *base;
+    size_t cap;
+    size_t used = 0;
+    size_t left() const
+    {
+        const size_t at = (used + 255) & ~(size_t)255;
+        return at >= cap ? 0 : cap - at;
+    }
+    template <class T>
+    bool take(DBuf<T> &b, size_t count)
+    {
+        const size_t at = (used + 255) & ~(size_t)255;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (at > cap || bytes > cap - at) return false;
+        b.view((T *)(base + at), count);
+        used = at + bytes;
+        return true;
+    }
+};
 
 }  // namespace
 
@@ -1474,6 +1538,79 @@ bc_status bc_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_
         dependencies_impl(g, d_src, k, out_mode, d_out, d_dist, d_sm, d_se, false, nullptr, d_tg,
                           T);
         io.finish();
+    });
+}
+
+bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k,
+                                  int32_t out_mode, double *out)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        need(k >= 0, "k must be >= 0");
+        need(out_mode == BC_OUT_FULL || out_mode == BC_OUT_SUM,
+             "out_mode must be BC_OUT_FULL or BC_OUT_SUM");
+        need(k == 0 || sources, "null argument");
+        need(out || (out_mode == BC_OUT_FULL && k == 0), "null argument");
+        if (g->io == BC_IO_HOST)
+            fail(BC_E_UNSUPPORTED, "the allocation-free call takes device arrays only");
+        use_device(g);
+        // any attempt to allocate in this call is an error
+        Alloc none;
+        none.forbid = true;
+        UseAlloc ua(&none);
+        const int64_t n = g->n;
+        Plan p;
+        p.B = 64;
+        p.logW = 0;
+        // the wave engine's buffers at one word per vertex, carved from the array
+        Work nw;
+        Carve c{scratch_on(g->device), (size_t)BC_NOALLOC_SCRATCH_BYTES};
+        const size_t N = (size_t)n, blocks = (N >> kLevelShift) + 2;
+        const size_t min_rec = (size_t)std::max<int64_t>(4 * n, 1 << 16);
+        bool ok = c.take(nw.sig, N * 64) &&
+                  (out_mode == BC_OUT_FULL ? c.take(nw.dlt, N * 64) : c.take(nw.vsum, N)) &&
+                  c.take(nw.vis, N) && c.take(nw.F0, N) && c.take(nw.F1, N) && c.take(nw.SG0, N) &&
+                  c.take(nw.SG1, N) && c.take(nw.active, 1) && c.take(nw.valid, 1) &&
+                  c.take(nw.srcs, 64) && c.take(nw.dest, 64) && c.take(nw.bcnt, blocks) &&
+                  c.take(nw.bpop, blocks);
+        // the level record (4 + 8 + 8 bytes per entry) takes what is left; it
+        // needs at least 4 entries per vertex
+        const size_t rec_bytes = 20, pad = 3 * 256;
+        ok = ok && c.left() >= min_rec * rec_bytes + pad;
+        if (!ok)
+            fail(BC_E_UNSUPPORTED, "graph too large for the allocation-free call (" +
+                                       std::to_string(n) + " vertices need more than the " +
+                                       std::to_string((size_t)BC_NOALLOC_SCRATCH_BYTES) +
+                                       "-byte scratch array)");
+        // extended path-count exponents when room remains beside that record
+        if (c.left() >= N * 64 * 4 + 256 + min_rec * rec_bytes + pad) (void)c.take(nw.sige, N * 64);
+        const size_t rec = (c.left() - pad) / rec_bytes;
+        (void)(c.take(nw.ridx, rec) && c.take(nw.rmask, rec) && c.take(nw.rseg, rec));
+        nw.cap_limit = (int64_t)rec;
+        nw.ctl.view(g->own.ctl.p, g->own.ctl.cap);   // the handle's control block
+        nw.h_ctl = g->own.h_ctl;
+        Work *saved = g->w;
+        const bool prof = g->prof_on;
+        g->w = &nw;
+        g->prof_on = false;
+        auto restore = [&] {
+            g->w = saved;
+            g->prof_on = prof;
+        };
+        try {
+            check_indices(g, sources, k, "source");
+            dependencies_impl(g, sources, k, out_mode, out, nullptr, nullptr, nullptr, false,
+                              nullptr, nullptr, 0, &p);
+        } catch (const RecordLimit &) {
+            restore();
+            (void)hipStreamSynchronize(g->stream);
+            fail(BC_E_UNSUPPORTED, "the level record outgrows the allocation-free scratch array");
+        } catch (...) {
+            restore();
+            (void)hipStreamSynchronize(g->stream);
+            throw;
+        }
+        restore();
     });
 }
 
@@ -1773,9 +1910,7 @@ void run_slots(bc_server *sv, bc_graph *g, Engine e, int B, int lo, int hi)
             Plan p;
             p.B = B;
             while ((64 << p.logW) < B) ++p.logW;
-            ensure_batch(g, p, false, std::max<int64_t>(std::min(g->cap_hint, g->w->cap_limit),
-                                                        1 << 16),
-                         OUT_DELTA);
+            ensure_batch(g, p, false, start_cap(g), OUT_DELTA);
             launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)sv->qd.p,
                    (const int32_t *)sv->slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
                    g->w->dest.p, sv->tgt.p);
