@@ -183,6 +183,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--schedule", default="auto", choices=["auto", "wave", "pair"])
     ap.add_argument("--bottom-up", type=float, default=0.0)
+    ap.add_argument("--level-loop", type=int, default=0,
+                    help="pair engine: 1 persistent level loops, -1 one launch per level "
+                         "phase, 0 auto")
     ap.add_argument("--per-source", type=int, default=16, help="sources for the per-source leg")
     ap.add_argument("--pair-targets", type=int, default=32)
     ap.add_argument("--pair-eps", type=float, default=0.05)
@@ -228,7 +231,7 @@ def main():
     G = bc.Graph(g.row, g.col)
     sched = {"auto": bc.BC_SCHED_AUTO, "wave": bc.BC_SCHED_BATCHED,
              "pair": bc.BC_SCHED_THREADED}[args.schedule]
-    G.configure(sched, args.batch, args.bottom_up)
+    G.configure(sched, args.batch, args.bottom_up, 0, args.level_loop)
 
     K = args.sources
     srcs = torch.empty(K, dtype=torch.int32, device=dev)

@@ -105,6 +105,13 @@ typedef struct {
                               entries than this sums its rows longer than 256 with a
                               whole workgroup; 0 = auto (2^20), < 0 = never. Values
                               are identical either way. */
+    int32_t level_loop;    /* pair-per-thread engine: > 0 runs all levels of a pass in
+                              one persistent cooperative launch (grid barriers between
+                              phases, each wait bounded in time: BC_E_DEVICE if one
+                              gives up); <= 0 launches each level's phases
+                              separately (the default). Values are identical
+                              either way. */
+    int32_t reserved;
 } bc_config;
 
 /* Host CSR. row has n+1 entries, int64 if row_is_i64 else int32. */
@@ -239,6 +246,10 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *   backward_split: the backward of levels with fewer than 2^20 record
  *                entries, whose rows longer than 256 are summed by a whole
  *                workgroup (same units and bytes as backward)
+ *   pair_forward : the pair engine's persistent forward loop (discovery and
+ *                path counts of every level): 12 per units_a (level and
+ *                count write) + 8 per units_b (count read)
+ *   pair_backward: its persistent backward loop, bytes as backward
  *   level_record: 8 per (vertex, word) read + 36 per record entry written
  * Enabling resets the accumulators. Profiling adds one event pair per launch
  * and one counter update per wavefront. */

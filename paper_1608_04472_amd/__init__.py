@@ -75,7 +75,8 @@ class _Csr(ctypes.Structure):
 
 class _Config(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("bottom_up", ctypes.c_double), ("split_entries", ctypes.c_int64)]
+                ("bottom_up", ctypes.c_double), ("split_entries", ctypes.c_int64),
+                ("level_loop", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -281,8 +282,10 @@ class Graph:
         _check(_lib.bc_graph_set_stream(self._h, _stream()))
         return self._h
 
-    def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0, split_entries=0):
-        cfg = _Config(int(schedule), int(batch), float(bottom_up), int(split_entries))
+    def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0, split_entries=0,
+                  level_loop=0):
+        cfg = _Config(int(schedule), int(batch), float(bottom_up), int(split_entries),
+                      int(level_loop), 0)
         _check(_lib.bc_graph_configure(self.handle, ctypes.byref(cfg)))
 
     def stats(self):

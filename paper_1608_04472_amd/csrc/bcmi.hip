@@ -179,6 +179,7 @@ struct Work {
     // pair-per-thread engine (shares sig/dlt/sige/ridx with the wave engine)
     DBuf<int32_t> lv;
     DBuf<uint8_t> pactive;
+    DBuf<unsigned long long> loff;   // level offsets written by the persistent loops
     // per-source plain form
     DBuf<int32_t> ss_d, ss_q;
     DBuf<double> ss_sig, ss_dlt;
@@ -196,8 +197,8 @@ struct Work {
 
     void init()
     {
-        ctl.ensure(8);
-        if (!h_ctl) HIPX(hipHostMalloc((void **)&h_ctl, 8 * sizeof(unsigned long long), 0));
+        ctl.ensure(CTL_WORDS);
+        if (!h_ctl) HIPX(hipHostMalloc((void **)&h_ctl, CTL_WORDS * sizeof(unsigned long long), 0));
     }
     void release()
     {
@@ -208,7 +209,7 @@ struct Work {
         bcnt.release(); bpop.release();
         srcs.release();
         dest.release(); X.release(); S.release(); K.release(); st.release();
-        lv.release(); pactive.release();
+        lv.release(); pactive.release(); loff.release();
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release(); probe_src.release();
         okey_in.release(); okey_out.release(); oidx_in.release(); operm.release();
         lane_row.release(); sort_tmp.release(); draw_src.release(); draw_dst.release();
@@ -225,7 +226,7 @@ struct bc_graph {
     int32_t io = BC_IO_DEVICE;   // where compute calls' arrays live
     DBuf<int64_t> row;
     DBuf<int32_t> col;
-    bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0};
+    bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0};
     Work own;
     Work *w = &own;
     int64_t cap_hint = 0;
@@ -433,14 +434,14 @@ void build_level(bc_graph *g, const BatchArgs &a, const uint64_t *nxt, int64_t c
 
 void read_ctl(bc_graph *g)
 {
-    HIPX(hipMemcpyAsync(g->w->h_ctl, g->w->ctl.p, 8 * sizeof(unsigned long long),
+    HIPX(hipMemcpyAsync(g->w->h_ctl, g->w->ctl.p, CTL_WORDS * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, g->stream));
     HIPX(hipStreamSynchronize(g->stream));
 }
 
 void zero_ctl(bc_graph *g)
 {
-    HIPX(hipMemsetAsync(g->w->ctl.p, 0, 8 * sizeof(unsigned long long), g->stream));
+    HIPX(hipMemsetAsync(g->w->ctl.p, 0, CTL_WORDS * sizeof(unsigned long long), g->stream));
 }
 
 // Device-side range check of an index array (sources, targets, pair ends).
@@ -843,43 +844,147 @@ struct PairSigmaOut {
     int64_t b0 = 0;
 };
 
+// Persistent level loops of the pair engine: when to use them, on what grid.
+// The loops are opt-in: on the 2048^2 grid (thousands of levels of ~0.5 M
+// pairs) they measured 2.3x slower than one launch per phase, the halved
+// resident grid hiding less latency and every block's barrier fence writing
+// back and invalidating its L2.
+bool use_level_loop(const bc_graph *g)
+{
+    if (g->cfg.level_loop <= 0) return false;
+    int coop = 0;
+    HIPX(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device));
+    if (!coop && g->cfg.level_loop > 0)
+        fail(BC_E_UNSUPPORTED, "the device has no cooperative launch for the level loop");
+    return coop != 0;
+}
+
+// A grid that is resident as a whole. The occupancy query's blocks per CU is
+// the theoretical figure; at a kernel's register-file limit fewer blocks are
+// resident in practice (a grid of the full figure left blocks waiting for
+// others to exit), so the loops take half of it on every CU.
+template <class K>
+int resident_grid(const bc_graph *g, K kernel)
+{
+    int per_cu = 0, cus = 0;
+    HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
+    HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+    if (per_cu < 1 || cus < 1) fail(BC_E_UNSUPPORTED, "the level loop kernel cannot be resident");
+    return std::max(1, per_cu / 2) * cus;
+}
+
+// A grid barrier wait longer than this is taken as a failure (no level of
+// any graph here takes a fraction of it).
+constexpr double kBarrierSeconds = 5.0;
+
+uint64_t barrier_ticks(const bc_graph *g)
+{
+    int khz = 0;
+    HIPX(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
+    return (uint64_t)(kBarrierSeconds * 1e3 * (double)std::max(khz, 1));
+}
+
+// One cooperative launch of a persistent loop (profiled like a hot kernel).
+template <class K, class... A>
+void launch_loop(bc_graph *g, int kernel, K fn, int grid, A... args)
+{
+    void *params[] = {(void *)&args...};
+    bc_graph::Pending p{kernel, nullptr, nullptr};
+    if (g->prof_on) {
+        p.start = take_event(g);
+        p.stop = take_event(g);
+        HIPX(hipEventRecord(p.start, g->stream));
+    }
+    HIPX(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(kBlock),
+                                    params, 0, g->stream));
+    if (g->prof_on) {
+        HIPX(hipEventRecord(p.stop, g->stream));
+        g->pending.push_back(p);
+        if (g->pending.size() >= 256) prof_flush(g);
+    }
+}
+
+// After a persistent loop: a barrier that timed out is an error; the message
+// names the loop, the barriers completed and the blocks that had arrived at
+// the one that failed.
+void check_barrier(bc_graph *g, const char *loop, int grid)
+{
+    const unsigned long long *h = g->w->h_ctl;
+    if (h[CTL_BAR + 2])
+        fail(BC_E_DEVICE, std::string("a grid barrier of the ") + loop +
+                              " level loop timed out after " + std::to_string(h[CTL_BAR + 1]) +
+                              " completed barriers, with " + std::to_string(h[CTL_BAR]) + " of " +
+                              std::to_string(grid) + " blocks arrived at the next one");
+}
+
 std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *ext_used,
                                const PairSigmaOut *sigout)
 {
     const int64_t n = g->n;
     hipStream_t s = g->stream;
     bool ext = g->ext_sticky;
+    const bool loop = use_level_loop(g);
     for (;;) {
         ensure_pairs(g, B, ext);
         PairArgs a = make_pair_args(g, B, ext, nvalid, pair);
         HIPX(hipMemsetAsync(g->w->lv.p, 0xff, (size_t)B * n * 4, s));
         zero_ctl(g);
         launch(s, grid_for(B), k_p_init, a);
-        read_ctl(g);
-        std::vector<int64_t> off{0, (int64_t)g->w->h_ctl[CTL_TAIL]};
+        std::vector<int64_t> off;
         bool redo = false;
-        for (int level = 0;; ++level) {
-            const int64_t e0 = off[level], e1 = off[level + 1];
-            launch_hot(g, PROF_TOPDOWN, grid_for(e1 - e0), k_p_topdown, a, e0, e1, (int32_t)level);
+        PairLoop L{};
+        int grid_b = 0;
+        if (loop) {
+            // every level of the forward pass in one launch
+            g->w->loff.ensure((size_t)n + 2);
+            L.a = a;
+            L.loff = g->w->loff.p;
+            L.max_levels = (int64_t)g->w->loff.cap;
+            const int grid_f = ext ? resident_grid(g, k_p_forward_loop<true>)
+                                   : resident_grid(g, k_p_forward_loop<false>);
+            grid_b = ext ? resident_grid(g, k_p_backward_loop<true>)
+                         : resident_grid(g, k_p_backward_loop<false>);
+            L.gs.bar = g->w->ctl.p + CTL_BAR;
+            L.gs.nblocks = (unsigned long long)grid_f;
+            L.gs.limit = barrier_ticks(g);
+            if (ext) launch_loop(g, PROF_PAIR_FWD, k_p_forward_loop<true>, grid_f, L);
+            else launch_loop(g, PROF_PAIR_FWD, k_p_forward_loop<false>, grid_f, L);
             read_ctl(g);
-            const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
+            check_barrier(g, "forward", grid_f);
             if (g->w->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_DEVICE, "pair record overflow");
             if (!ext && g->w->h_ctl[CTL_SIG_OVERFLOW]) {
                 redo = true;
-                break;
+            } else {
+                off.resize((size_t)g->w->h_ctl[CTL_LEVELS] + 1);
+                HIPX(hipMemcpy(off.data(), g->w->loff.p, off.size() * 8, hipMemcpyDeviceToHost));
             }
-            if (e2 == e1) break;
-            if (ext)
-                launch_hot(g, PROF_SIGMA, grid_for(e2 - e1), k_p_sigma<true>, a, e1, e2,
-                           (int32_t)level);
-            else
-                launch_hot(g, PROF_SIGMA, grid_for(e2 - e1), k_p_sigma<false>, a, e1, e2,
-                           (int32_t)level);
-            off.push_back(e2);
-        }
-        if (!redo && !ext) {
+        } else {
             read_ctl(g);
-            redo = g->w->h_ctl[CTL_SIG_OVERFLOW] != 0;
+            off = {0, (int64_t)g->w->h_ctl[CTL_TAIL]};
+            for (int level = 0;; ++level) {
+                const int64_t e0 = off[level], e1 = off[level + 1];
+                launch_hot(g, PROF_TOPDOWN, grid_for(e1 - e0), k_p_topdown, a, e0, e1,
+                           (int32_t)level);
+                read_ctl(g);
+                const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
+                if (g->w->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_DEVICE, "pair record overflow");
+                if (!ext && g->w->h_ctl[CTL_SIG_OVERFLOW]) {
+                    redo = true;
+                    break;
+                }
+                if (e2 == e1) break;
+                if (ext)
+                    launch_hot(g, PROF_SIGMA, grid_for(e2 - e1), k_p_sigma<true>, a, e1, e2,
+                               (int32_t)level);
+                else
+                    launch_hot(g, PROF_SIGMA, grid_for(e2 - e1), k_p_sigma<false>, a, e1, e2,
+                               (int32_t)level);
+                off.push_back(e2);
+            }
+            if (!redo && !ext) {
+                read_ctl(g);
+                redo = g->w->h_ctl[CTL_SIG_OVERFLOW] != 0;
+            }
         }
         if (redo) {
             ext = true;
@@ -889,17 +994,31 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
         if (sigout && (sigout->mant || sigout->ex))
             launch(s, grid_for(n * sigout->count), k_p_out_sigma, a, sigout->count, sigout->b0,
                    sigout->mant, sigout->ex);
-        const int L = (int)off.size() - 1;
-        for (int level = L - 1; level >= 1; --level) {
-            if (ext)
-                launch_hot(g, PROF_BACKWARD, grid_for(off[level + 1] - off[level]),
-                           k_p_backward<true>, a, off[level], off[level + 1], (int32_t)level);
-            else
-                launch_hot(g, PROF_BACKWARD, grid_for(off[level + 1] - off[level]),
-                           k_p_backward<false>, a, off[level], off[level + 1], (int32_t)level);
+        const int nlev = (int)off.size() - 1;
+        if (loop) {
+            if (nlev >= 2) {
+                L.gs.nblocks = (unsigned long long)grid_b;
+                zero_ctl(g);
+                if (ext)
+                    launch_loop(g, PROF_PAIR_BWD, k_p_backward_loop<true>, grid_b, L, (int32_t)nlev);
+                else
+                    launch_loop(g, PROF_PAIR_BWD, k_p_backward_loop<false>, grid_b, L,
+                                (int32_t)nlev);
+                read_ctl(g);
+                check_barrier(g, "backward", grid_b);
+            }
+        } else {
+            for (int level = nlev - 1; level >= 1; --level) {
+                if (ext)
+                    launch_hot(g, PROF_BACKWARD, grid_for(off[level + 1] - off[level]),
+                               k_p_backward<true>, a, off[level], off[level + 1], (int32_t)level);
+                else
+                    launch_hot(g, PROF_BACKWARD, grid_for(off[level + 1] - off[level]),
+                               k_p_backward<false>, a, off[level], off[level + 1], (int32_t)level);
+            }
         }
         *ext_used = ext;
-        g->stats.levels += L;
+        g->stats.levels += nlev;
         g->stats.extended |= ext ? 1 : 0;
         return off;
     }
@@ -1457,11 +1576,12 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         for (int k = 0; k < 2 * PROF_KERNELS; ++k) units[k] += (unsigned long long)g->prof_host_units[k];
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
                                                   "sigma_pull", "backward", "level_record",
-                                                  "backward_split"};
+                                                  "backward_split", "pair_forward",
+                                                  "pair_backward"};
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
-        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0};
-        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0};
+        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0};
+        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];
@@ -1752,7 +1872,7 @@ enum WsBuf {
     WB_RIDX, WB_RMASK, WB_RSEG, WB_BCNT, WB_BPOP, WB_SRCS, WB_DEST, WB_LV, WB_PACTIVE,
     WB_SS_D, WB_SS_Q, WB_SS_SIG, WB_SS_DLT, WB_PROBE, WB_OKEY_IN, WB_OKEY_OUT, WB_OIDX,
     WB_OPERM, WB_LANE_ROW, WB_DRAW_SRC, WB_DRAW_DST, WB_SORT_TMP, WB_KEY_TMP, WB_QD,
-    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_COUNT
+    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_LOFF, WB_COUNT
 };
 
 struct WsNeed {
@@ -1813,7 +1933,8 @@ WsNeed need_for(Engine e, int64_t n, int B)
     r.b[WB_QD] = Bs * sizeof(QueryDesc);
     r.b[WB_SLOTQ] = r.b[WB_TGT] = Bs * 4;
     r.b[WB_X] = Bs * 8;
-    r.b[WB_CTL] = 8 * sizeof(unsigned long long);
+    r.b[WB_CTL] = CTL_WORDS * sizeof(unsigned long long);
+    if (e == ENG_PAIR) r.b[WB_LOFF] = (N + 2) * 8;
     return r;
 }
 
@@ -1865,7 +1986,7 @@ struct bc_server {
                w.valid.bytes() + w.vsum.bytes() + w.ridx.bytes() + w.rmask.bytes() +
                w.rseg.bytes() + w.bcnt.bytes() + w.bpop.bytes() + w.ctl.bytes() +
                w.srcs.bytes() + w.dest.bytes() + w.X.bytes() + w.S.bytes() + w.K.bytes() +
-               w.st.bytes() + w.lv.bytes() + w.pactive.bytes() + w.ss_d.bytes() +
+               w.st.bytes() + w.lv.bytes() + w.pactive.bytes() + w.loff.bytes() + w.ss_d.bytes() +
                w.ss_q.bytes() + w.ss_sig.bytes() + w.ss_dlt.bytes() + w.probe_src.bytes() +
                w.okey_in.bytes() + w.okey_out.bytes() + w.oidx_in.bytes() + w.operm.bytes() +
                w.lane_row.bytes() + w.draw_src.bytes() + w.draw_dst.bytes() +
@@ -2043,7 +2164,7 @@ bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, const bc_
             sv->stream = (hipStream_t)hip_stream;
             sv->budget = hbm_budget_bytes;
             sv->max_batch = max_batch;
-            need(hbm_budget_bytes >= 8 * sizeof(unsigned long long), "budget below 64 bytes");
+            need(hbm_budget_bytes >= CTL_WORDS * sizeof(unsigned long long), "budget below 128 bytes");
             sv->work.init();
             sv->ws.b[WB_CTL] = sv->work.ctl.bytes();
         } catch (...) {
@@ -2076,7 +2197,7 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
         // resident: the CSR (int64 rows, int32 columns) and the lane-order key
         // and the handle's own control block
         const size_t res_bytes = (size_t)(n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4 +
-                                 (size_t)n * 8 + 8 * sizeof(unsigned long long);
+                                 (size_t)n * 8 + CTL_WORDS * sizeof(unsigned long long);
         auto fits = [&](const WsNeed &w) {
             return sv->resident + res_bytes + w.total() <= sv->budget;
         };

@@ -38,7 +38,11 @@ enum : int {
     CTL_REC_OVERFLOW = 1,
     CTL_SIG_OVERFLOW = 2, // some path count reached 2^1000 in plain FP64
     CTL_RUNNING = 3,      // targets still sampling
-    CTL_POOL = 4          // value-pool tail
+    CTL_POOL = 4,         // value-pool tail
+    CTL_LEVELS = 5,       // levels of a pass run by a persistent loop
+    CTL_BAR = 8,          // grid barrier of the persistent loops: arrivals,
+                          // generation, failure flag (CTL_BAR .. CTL_BAR + 2)
+    CTL_WORDS = 16
 };
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -137,7 +141,9 @@ enum : int {
     PROF_BACKWARD = 3,
     PROF_LEVEL = 4,   // record layout of a level (k_level_*), counted on the host
     PROF_BACKWARD_SPLIT = 5,
-    PROF_KERNELS = 6
+    PROF_PAIR_FWD = 6,   // pair engine's persistent forward loop (discovery + path counts)
+    PROF_PAIR_BWD = 7,   // pair engine's persistent backward loop
+    PROF_KERNELS = 8
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
@@ -1357,8 +1363,10 @@ __global__ void k_p_init(PairArgs a)
 // Top-down discovery: each pair (v, b) of the level claims its unreached
 // neighbours for source b (compare-and-swap on the level word). A lane looks
 // at four neighbours per step and the wavefront appends all its claims of
-// that step with one atomic.
-__global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+// that step with one atomic. Grid-stride over [e0, e1); returns this lane's
+// claim count. Every lane of the wavefront must call it.
+__device__ __forceinline__ unsigned long long p_topdown(const PairArgs &a, int64_t e0, int64_t e1,
+                                                        int32_t level)
 {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1414,18 +1422,16 @@ __global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
             }
         }
     }
-    if (a.prof) {
-        const unsigned long long t = wave_sum_u64(found);
-        if (lane == 0 && t) atomicAdd(prof_slot(a.prof, PROF_TOPDOWN, 0), t);
-    }
+    return found;
 }
 
-// sigma for the pairs discovered at level+1: sum over neighbours one level up
-// (ascending CSR order), four neighbour loads in flight.
+// sigma for the pairs discovered at level+1, in [e0, e1): sum over
+// neighbours one level up (ascending CSR order), four neighbour loads in
+// flight. Adds this lane's pair and DAG-edge counts to ua, ub.
 template <bool kExt>
-__global__ void k_p_sigma(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+__device__ __forceinline__ void p_sigma(const PairArgs &a, int64_t e0, int64_t e1, int32_t level,
+                                        unsigned long long &ua, unsigned long long &ub)
 {
-    unsigned long long ua = 0, ub = 0;
     for (int64_t i = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < e1;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t o = a.rec[i];
@@ -1462,17 +1468,14 @@ __global__ void k_p_sigma(PairArgs a, int64_t e0, int64_t e1, int32_t level)
         }
         if (a.dest && a.dest[b] == (int32_t)x) a.active[b] = 0;
     }
-    if (a.prof) {
-        const unsigned long long ta = wave_sum_u64(ua), tb = wave_sum_u64(ub);
-        prof_add_raw(a.prof, PROF_SIGMA, ta, tb);
-    }
 }
 
-// Theorem 1 (rho form) for the pairs of one level.
+// Theorem 1 (rho form) for the pairs of one level, in [e0, e1).
 template <bool kExt>
-__global__ void k_p_backward(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+__device__ __forceinline__ void p_backward(const PairArgs &a, int64_t e0, int64_t e1,
+                                           int32_t level, unsigned long long &ua,
+                                           unsigned long long &ub)
 {
-    unsigned long long ua = 0, ub = 0;
     for (int64_t i = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < e1;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t o = a.rec[i];
@@ -1516,10 +1519,153 @@ __global__ void k_p_backward(PairArgs a, int64_t e0, int64_t e1, int32_t level)
         }
         a.dlt[o] = d;
     }
+}
+
+__global__ void k_p_topdown(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+{
+    const unsigned long long found = p_topdown(a, e0, e1, level);
     if (a.prof) {
-        const unsigned long long ta = wave_sum_u64(ua), tb = wave_sum_u64(ub);
-        prof_add_raw(a.prof, PROF_BACKWARD, ta, tb);
+        const unsigned long long t = wave_sum_u64(found);
+        if (lane_id() == 0 && t) atomicAdd(prof_slot(a.prof, PROF_TOPDOWN, 0), t);
     }
+}
+
+template <bool kExt>
+__global__ void k_p_sigma(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+{
+    unsigned long long ua = 0, ub = 0;
+    p_sigma<kExt>(a, e0, e1, level, ua, ub);
+    if (a.prof) prof_add_raw(a.prof, PROF_SIGMA, wave_sum_u64(ua), wave_sum_u64(ub));
+}
+
+template <bool kExt>
+__global__ void k_p_backward(PairArgs a, int64_t e0, int64_t e1, int32_t level)
+{
+    unsigned long long ua = 0, ub = 0;
+    p_backward<kExt>(a, e0, e1, level, ua, ub);
+    if (a.prof) prof_add_raw(a.prof, PROF_BACKWARD, wave_sum_u64(ua), wave_sum_u64(ub));
+}
+
+// ------------------------------------------ pair engine: persistent level loops
+//
+// A deep graph has thousands of levels, each with little work: one launch
+// per level phase spends most of its time starting and draining the grid.
+// The loops below run every level of a pass in one launch on a grid that is
+// resident as a whole (cooperative launch, sized by occupancy), with a grid
+// barrier between phases. The barrier's wait is bounded by wall-clock time:
+// a block that waits too long raises the failure flag and leaves, every other
+// block then fails its next wait too, and the host reports the error, so
+// every wait ends.
+
+// bar[0]: arrivals, bar[1]: generation, bar[2]: failure flag
+struct GridSync {
+    unsigned long long *bar;
+    unsigned long long nblocks;
+    uint64_t limit;       // wall-clock ticks a block may wait at one barrier
+};
+
+__device__ __forceinline__ unsigned long long ld_acquire(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns false once the failure flag is set (by this block or another).
+__device__ bool grid_sync(const GridSync &g)
+{
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = 1;
+        __threadfence();
+        const unsigned long long gen = ld_acquire(&g.bar[1]);
+        const unsigned long long arrived = atomicAdd(&g.bar[0], 1ull);
+        if (arrived == g.nblocks - 1) {
+            __hip_atomic_store(&g.bar[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&g.bar[1], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (ld_acquire(&g.bar[1]) == gen) {
+                if (ld_acquire(&g.bar[2]) != 0ull || wall_clock64() - t0 > g.limit) {
+                    atomicOr(&g.bar[2], 1ull);
+                    good = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        if (ld_acquire(&g.bar[2]) != 0ull) good = 0;
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// loff[l] = first record entry of level l; ctl[CTL_TAIL] = record tail;
+// ctl[CTL_LEVELS] receives the number of levels when the pass ends.
+struct PairLoop {
+    PairArgs a;
+    unsigned long long *loff;
+    int64_t max_levels;
+    GridSync gs;
+};
+
+// Forward pass from the level-0 record [0, nvalid): discovery, then
+// the path counts of the new level, level after level until a level comes
+// out empty (or, in plain FP64, a count reaches 2^1000: the host then redoes
+// the batch with extended counts).
+template <bool kExt>
+__global__ __launch_bounds__(kBlock) void k_p_forward_loop(PairLoop L)
+{
+    const PairArgs &a = L.a;
+    // level 0 holds one entry per valid lane (k_p_init). It must not be read
+    // from the record tail: blocks start at different times, and the first
+    // ones are already appending level 1 while later ones start.
+    int64_t e0 = 0;
+    int64_t e1 = a.nvalid;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        L.loff[0] = 0;
+        L.loff[1] = (unsigned long long)e1;
+    }
+    unsigned long long found = 0, ua = 0, ub = 0;
+    int32_t level = 0;
+    for (;; ++level) {
+        found += p_topdown(a, e0, e1, level);
+        if (!grid_sync(L.gs)) break;
+        const int64_t e2 = (int64_t)__hip_atomic_load(&a.ctl[CTL_TAIL], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        if (level + 2 >= L.max_levels && blockIdx.x == 0 && threadIdx.x == 0)
+            a.ctl[CTL_REC_OVERFLOW] = 1ull;   // no room for the next level's offset
+        const bool stop = e2 == e1 || level + 2 >= L.max_levels ||
+                          __hip_atomic_load(&a.ctl[CTL_REC_OVERFLOW], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                          (!kExt && __hip_atomic_load(&a.ctl[CTL_SIG_OVERFLOW], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT) != 0);
+        if (stop) break;
+        if (blockIdx.x == 0 && threadIdx.x == 0) L.loff[level + 2] = (unsigned long long)e2;
+        p_sigma<kExt>(a, e1, e2, level, ua, ub);
+        if (!grid_sync(L.gs)) break;
+        e0 = e1;
+        e1 = e2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[CTL_LEVELS] = (unsigned long long)(level + 1);
+    // every discovered pair gets its path count once: found and ua agree
+    (void)found;
+    if (a.prof) prof_add_raw(a.prof, PROF_PAIR_FWD, wave_sum_u64(ua), wave_sum_u64(ub));
+}
+
+// Backward pass over levels nlev-1 .. 1 of the record laid out by the forward
+// loop.
+template <bool kExt>
+__global__ __launch_bounds__(kBlock) void k_p_backward_loop(PairLoop L, int32_t nlev)
+{
+    const PairArgs &a = L.a;
+    unsigned long long ua = 0, ub = 0;
+    for (int32_t level = nlev - 1; level >= 1; --level) {
+        p_backward<kExt>(a, (int64_t)L.loff[level], (int64_t)L.loff[level + 1], level, ua, ub);
+        if (level > 1 && !grid_sync(L.gs)) break;
+    }
+    if (a.prof) prof_add_raw(a.prof, PROF_PAIR_BWD, wave_sum_u64(ua), wave_sum_u64(ub));
 }
 
 // out[v] += sum over b ascending of the reached pairs' dependencies

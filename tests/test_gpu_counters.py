@@ -55,21 +55,30 @@ def counted(G, src, dev, mode):
     bc.dependencies(G, torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev), mode)
     prof = {k["name"]: k for k in G.profile_read()}
     G.profile(False)
-    disc = prof["discover_topdown"]["units_a"] + prof["discover_bottomup"]["units_a"]
-    bwd_a = prof["backward"]["units_a"] + prof["backward_split"]["units_a"]
-    bwd_b = prof["backward"]["units_b"] + prof["backward_split"]["units_b"]
-    return disc, prof["sigma_pull"]["units_a"], prof["sigma_pull"]["units_b"], bwd_a, bwd_b
+    # the pair engine's persistent loops count discovery and path counts
+    # together (pair_forward) and the sweep as pair_backward
+    fwd = prof["pair_forward"]
+    disc = prof["discover_topdown"]["units_a"] + prof["discover_bottomup"]["units_a"] + \
+        fwd["units_a"]
+    sa = prof["sigma_pull"]["units_a"] + fwd["units_a"]
+    sb = prof["sigma_pull"]["units_b"] + fwd["units_b"]
+    bwd_a = sum(prof[k]["units_a"] for k in ("backward", "backward_split", "pair_backward"))
+    bwd_b = sum(prof[k]["units_b"] for k in ("backward", "backward_split", "pair_backward"))
+    return disc, sa, sb, bwd_a, bwd_b
 
 
 CASES = [
     ("er2000 wave", lambda: gg.config_graph("er2000"), bc.BC_SCHED_BATCHED, 128, 0.0, 300),
+    ("rmat12 pair engine per level", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9),
+     -bc.BC_SCHED_THREADED, 128, 0.0, 300),
     ("er2000 wave bottom-up", lambda: gg.config_graph("er2000"), bc.BC_SCHED_BATCHED, 256, 1e-9,
      300),
     ("rmat12 wave", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9), bc.BC_SCHED_BATCHED, 512,
      0.0, 700),
-    ("rmat12 pair engine", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9),
+    ("rmat12 pair engine level loop", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9),
      bc.BC_SCHED_THREADED, 128, 0.0, 300),
-    ("grid60 pair engine", lambda: gg.grid(60, 60), bc.BC_SCHED_THREADED, 64, 0.0, 100),
+    ("grid60 pair engine level loop", lambda: gg.grid(60, 60), bc.BC_SCHED_THREADED, 64, 0.0,
+     100),
 ]
 
 
@@ -84,7 +93,10 @@ def test_work_units_equal_the_oracle_counts(dev, name, make, sched, batch, bu, k
         src[9] = iso[0]                      # an isolated source reaches only itself
     reach, dag, bwd_dag = expected(g, src)
     G = bc.Graph(g.row, g.col)
-    G.configure(sched, batch, bu)
+    # a negative schedule id: that engine with one launch per level phase;
+    # else the pair engine runs its persistent level loops
+    G.configure(abs(sched), batch, bu, 0, -1 if sched < 0 else 1)
+    sched = abs(sched)
     for mode in (bc.BC_OUT_SUM, bc.BC_OUT_FULL):
         say(name, "mode", mode)
         disc, sa, sb, ba, bb = counted(G, src, dev, mode)

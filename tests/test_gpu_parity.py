@@ -524,3 +524,63 @@ def test_backward_forms_bit_identical(dev):
         G.close()
     assert np.array_equal(outs[-1], outs[0])
     assert np.array_equal(outs[-1], outs[1 << 40])
+
+
+@pytest.mark.parametrize("what", ["grid600 extended", "rmat12 pairs", "grid90 sampler"])
+def test_pair_engine_level_loop_equals_per_level(dev, what):
+    """The pair engine's persistent level loops (one launch per pass, grid
+    barriers between phases) and its one-launch-per-phase form do the same
+    additions in the same order: identical bits, and the oracle's values."""
+    outs = []
+    for loop in (1, -1):
+        if what == "grid600 extended":
+            g = gg.grid(600, 600)
+            G = bc.Graph(g.row, g.col)
+            G.configure(bc.BC_SCHED_THREADED, 64, 0.0, 0, loop)
+            src = np.array([0, 359999, 180300, 7], dtype=np.int32)
+            say("level loop", loop, what)
+            full, dist, sig = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL, dist=True,
+                                              sigma=True)
+            assert G.stats()["extended"] == 1
+            outs.append([full.cpu().numpy(), dist.cpu().numpy(), sig[0].cpu().numpy(),
+                         sig[1].cpu().numpy()])
+            if loop == 1:
+                for i in (0, 2):
+                    d, (om, oe), de = O.brandes(g, int(src[i]))
+                    assert np.array_equal(outs[-1][1][i], d)
+                    assert_sigma(outs[-1][2][i], outs[-1][3][i], om, oe, "loop sigma")
+                    assert_close(outs[-1][0][i], de, what="loop delta")
+        elif what == "rmat12 pairs":
+            g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
+            G = bc.Graph(g.row, g.col)
+            G.configure(bc.BC_SCHED_THREADED, 128, 0.0, 0, loop)
+            us = torch.empty(300, dtype=torch.int32, device=dev)
+            vs = torch.empty(300, dtype=torch.int32, device=dev)
+            bc.bc_draw_pairs(G, 4, 0, 300, us, vs)
+            say("level loop", loop, what)
+            p = bc.pair_dependencies(G, us, vs).cpu().numpy()
+            src = gg.philox_sources(9, 300, g.n)
+            tot, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+            outs.append([p, tot.cpu().numpy()])
+            if loop == 1:
+                for i in (0, 299):
+                    assert_close(p[i], O.pair_dependency(g, int(us[i]), int(vs[i])),
+                                 what="loop pair %d" % i)
+                _, want = O.dependencies(g, src, full=False, total=True)
+                assert_close(outs[-1][1], want, what="loop sum")
+        else:
+            g = gg.grid(90, 90)
+            G = bc.Graph(g.row, g.col)
+            G.configure(bc.BC_SCHED_THREADED, 0, 0.0, 0, loop)
+            tg = np.array([4095, 4050, 45], dtype=np.int32)
+            say("level loop", loop, what)
+            a = bc.adaptive_source(G, T(tg, dev), 2.0, 3, 500)
+            b = bc.adaptive_pair(G, T(tg, dev), bc.BC_PAIR_EPS, 0.2, 1.0, 3, 3000)
+            outs.append([x.cpu().numpy() for x in a + b])
+            if loop == 1:
+                check_sampler(a, O.adaptive_source(g, tg, 2.0, 3, 500), "loop source")
+                check_sampler(b, O.adaptive_pair(g, tg, oracle.RULE_EPS, 0.2, 1.0, 3, 3000),
+                              "loop pair")
+        G.close()
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y), what
