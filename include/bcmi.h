@@ -92,8 +92,10 @@ typedef enum {
                               (vertex, 64-source word), lanes = sources */
     BC_SCHED_PER_SOURCE = 2, /* one source per launch sequence, one thread per
                               frontier vertex: the plain form, for comparison */
-    BC_SCHED_THREADED = 3  /* many sources per launch, one thread per (vertex,
+    BC_SCHED_THREADED = 3, /* many sources per launch, one thread per (vertex,
                               source) pair: for graphs of large diameter */
+    BC_SCHED_TUNED = 4     /* the first compute call times candidate plans and
+                              keeps the fastest (bc_graph_tune) */
 } bc_schedule;
 
 typedef struct {
@@ -146,6 +148,22 @@ bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hi
                           bc_graph **out);
 void bc_graph_destroy(bc_graph *g);
 bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
+/* Autotuner: times candidate plans on one seeded batch of sources each and
+ * installs the fastest per source, by coordinate descent: the engine
+ * (BC_SCHED_BATCHED or BC_SCHED_THREADED) at its default width, then the
+ * batch width (256 .. 4096, within 32-bit indices and free memory), then the
+ * wave engine's bottom_up (0.04, 0.01, 0.15, never) and split_entries (2^18,
+ * 2^20, 2^22), or the pair engine's level_loop. A candidate slower than 1.5x
+ * the best so far is abandoned early. Winners are cached per process by graph
+ * signature (n, nnz, log2-degree histogram, BFS depth from a highest-degree
+ * vertex). The width applies to bc_dependencies and bc_exact; the samplers keep
+ * their round widths. Plans change scheduling only: values equal any other
+ * plan's (sums up to FP64 summation order). *plan (optional) receives it. */
+bc_status bc_graph_tune(bc_graph *g, bc_config *plan);
+/* The plan compute calls on g use now, with the schedule resolved to the
+ * engine that runs (BC_SCHED_BATCHED, BC_SCHED_THREADED or PER_SOURCE) and
+ * batch the tuned width (0 = automatic). */
+bc_status bc_graph_plan(bc_graph *g, bc_config *out);
 /* bc_io: where the array arguments of later compute calls on g live. */
 bc_status bc_graph_set_io(bc_graph *g, int32_t io);
 bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg);

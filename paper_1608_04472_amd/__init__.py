@@ -34,11 +34,12 @@ BC_DONE, BC_CAPPED = 0, 1
 BC_OUT_FULL, BC_OUT_SUM, BC_OUT_TARGETS = 0, 1, 2
 BC_IO_DEVICE, BC_IO_HOST = 0, 1
 BC_PAIR_ALG1, BC_PAIR_EPS = 0, 1
-BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED = 0, 1, 2, 3
+BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED, BC_SCHED_TUNED = \
+    0, 1, 2, 3, 4
 
 EXPORTS = [
     "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_set_io",
-    "bc_graph_configure",
+    "bc_graph_configure", "bc_graph_tune", "bc_graph_plan",
     "bc_graph_info", "bc_exact", "bc_dependencies", "bc_dependencies_noalloc",
     "bc_pair_dependencies",
     "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
@@ -189,6 +190,8 @@ def load_library(path: str | None = None):
         "bc_graph_set_stream": [V, V],
         "bc_graph_set_io": [V, c.c_int32],
         "bc_graph_configure": [V, c.POINTER(_Config)],
+        "bc_graph_tune": [V, c.POINTER(_Config)],
+        "bc_graph_plan": [V, c.POINTER(_Config)],
         "bc_graph_info": [V, c.POINTER(c.c_int64), c.POINTER(c.c_int64)],
         "bc_exact": [V, V],
         "bc_dependencies": [V, V, c.c_int64, c.c_int32, V, V, V, V, V, c.c_int32],
@@ -287,6 +290,18 @@ class Graph:
         cfg = _Config(int(schedule), int(batch), float(bottom_up), int(split_entries),
                       int(level_loop), 0)
         _check(_lib.bc_graph_configure(self.handle, ctypes.byref(cfg)))
+
+    def tune(self):
+        """Time candidate plans, install the fastest and return it (a dict)."""
+        cfg = _Config()
+        _check(_lib.bc_graph_tune(self.handle, ctypes.byref(cfg)))
+        return {f: getattr(cfg, f) for f, _ in _Config._fields_ if f != "reserved"}
+
+    def plan(self):
+        """The plan compute calls use now (a dict)."""
+        cfg = _Config()
+        _check(_lib.bc_graph_plan(self.handle, ctypes.byref(cfg)))
+        return {f: getattr(cfg, f) for f, _ in _Config._fields_ if f != "reserved"}
 
     def stats(self):
         st = _Stats()

@@ -16,7 +16,10 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -234,6 +237,12 @@ struct bc_graph {
     int32_t hub = 0;          // a highest-degree vertex (depth probe)
     int64_t hub_degree = 0;
     int32_t engine = -1;      // cached automatic engine choice
+    int32_t depth = -1;       // BFS depth from the hub (probe), -1 until probed
+    bool tuned = false;       // cfg holds a plan chosen by the autotuner
+    int32_t tuned_batch = 0;  // batch width of the tuned plan (bc_dependencies, bc_exact)
+    std::array<int64_t, 33> deg_hist{};   // vertices per floor(log2(degree + 1))
+    bool timed = false;       // a tuning candidate is running against `deadline`
+    std::chrono::steady_clock::time_point deadline{};
     bool ext_sticky = false;  // an earlier batch on this graph needed extended counts
     // lane-order key: distances to up to kLandmarks highest-degree vertices
     std::vector<int32_t> landmarks;
@@ -295,6 +304,16 @@ void need(bool ok, const char *msg)
 }
 
 void use_device(bc_graph *g) { HIPX(hipSetDevice(g->device)); }
+
+// A tuning candidate that runs past its deadline is abandoned at the next
+// level boundary.
+struct TuneTimeout {};
+
+void check_deadline(const bc_graph *g)
+{
+    if (g->timed && std::chrono::steady_clock::now() > g->deadline) throw TuneTimeout{};
+}
+
 
 // Host arrays of a compute call in BC_IO_HOST mode, staged through device
 // memory from the handle's allocator: inputs are copied in when staged,
@@ -627,6 +646,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
                 launch_hot(g, PROF_TOPDOWN, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
             build_level(g, a, nxt, cap);
             read_ctl(g);
+            check_deadline(g);
             const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
             if (g->prof_on) g->prof_host_units[2 * PROF_LEVEL + 1] += e2 - e1;
             if (g->w->h_ctl[CTL_REC_OVERFLOW]) {
@@ -765,23 +785,30 @@ constexpr int kDeepGraphLevels = 32;
 // across a batch's sources (small-world graphs); for deep graphs each
 // (vertex, source) is on its own, so pairs get one thread each. The automatic
 // choice probes the BFS depth from a highest-degree vertex once per graph.
+// BFS depth from a highest-degree vertex (once per graph). A path count is at
+// most maxdeg^distance and distances are at most twice that depth: counts
+// start extended when that bound reaches 2^1000 (they agree bit for bit with
+// plain FP64 in range).
+int probe_depth(bc_graph *g)
+{
+    if (g->depth < 0) {
+        g->w->probe_src.ensure(1);
+        HIPX(hipMemcpy(g->w->probe_src.p, &g->hub, 4, hipMemcpyHostToDevice));
+        std::vector<int64_t> off = run_single(g, g->w->probe_src.p, true);
+        g->depth = (int)off.size() - 2;
+        g->stats.levels = 0;
+        const double bound =
+            2.0 * g->depth * std::log2(std::max<double>(2.0, (double)g->hub_degree));
+        if (bound >= 1000.0) g->ext_sticky = true;
+    }
+    return g->depth;
+}
+
 Engine engine_for(bc_graph *g)
 {
     if (g->cfg.schedule == BC_SCHED_BATCHED) return ENG_WAVE;
     if (g->cfg.schedule == BC_SCHED_THREADED) return ENG_PAIR;
-    if (g->engine < 0) {
-        g->w->probe_src.ensure(1);
-        HIPX(hipMemcpy(g->w->probe_src.p, &g->hub, 4, hipMemcpyHostToDevice));
-        std::vector<int64_t> off = run_single(g, g->w->probe_src.p, true);
-        const int depth = (int)off.size() - 2;
-        g->engine = depth > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
-        g->stats.levels = 0;
-        // A path count is at most maxdeg^distance and distances are at most
-        // twice the probe depth: start in extended counts when that bound
-        // reaches 2^1000 (they agree bit for bit with plain FP64 in range).
-        const double bound = 2.0 * depth * std::log2(std::max<double>(2.0, (double)g->hub_degree));
-        if (bound >= 1000.0) g->ext_sticky = true;
-    }
+    if (g->engine < 0) g->engine = probe_depth(g) > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
     return (Engine)g->engine;
 }
 
@@ -966,6 +993,7 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
                 launch_hot(g, PROF_TOPDOWN, grid_for(e1 - e0), k_p_topdown, a, e0, e1,
                            (int32_t)level);
                 read_ctl(g);
+                check_deadline(g);
                 const int64_t e2 = (int64_t)g->w->h_ctl[CTL_TAIL];
                 if (g->w->h_ctl[CTL_REC_OVERFLOW]) fail(BC_E_DEVICE, "pair record overflow");
                 if (!ext && g->w->h_ctl[CTL_SIG_OVERFLOW]) {
@@ -1181,7 +1209,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     }
 
     if (!fixed && engine_for(g) == ENG_PAIR) {
-        const int B = plan_pairs(g, k, 512);
+        const int B = plan_pairs(g, k, g->tuned_batch ? g->tuned_batch : 512);
         g->stats.batch_width = B;
         g->stats.schedule = BC_SCHED_THREADED;
         for (int64_t b0 = 0; b0 < k; b0 += B) {
@@ -1216,7 +1244,7 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         return;
     }
 
-    const Plan p = fixed ? *fixed : plan_batch(g, k, 2048);
+    const Plan p = fixed ? *fixed : plan_batch(g, k, g->tuned_batch ? g->tuned_batch : 2048);
     g->stats.batch_width = p.B;
     g->stats.schedule = BC_SCHED_BATCHED;
     // samples sorted by the clustering key, cut into batches, rows mapped back
@@ -1263,6 +1291,194 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     }
     HIPX(hipStreamSynchronize(s));
     prof_flush(g);
+}
+
+// -------------------------------------------------------------- autotuner
+//
+// Times candidate plans on one seeded batch of sources each and keeps the
+// fastest per source, by coordinate descent: the engine (wave per word or
+// thread per pair) at its default width, then the batch width, then, for the
+// wave engine, the bottom-up threshold and the split size of the backward,
+// or, for the pair engine, the persistent level loop. A candidate that runs
+// past 1.5x the best time for its batch is abandoned at a level boundary.
+// Winners are cached per process by graph signature (size, log2-degree
+// histogram, BFS depth from the hub). Every plan only changes how sources
+// are scheduled: results are those of any other plan (sums up to FP64
+// summation order).
+
+struct TuneKey {
+    int64_t n, nnz;
+    int32_t depth;
+    std::array<int64_t, 33> hist;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(n, nnz, depth, hist) < std::tie(o.n, o.nnz, o.depth, o.hist);
+    }
+};
+
+std::mutex tune_mu;
+std::map<TuneKey, bc_config> tune_cache;
+
+constexpr int kTuneWidths[] = {4096, 2048, 1024, 512, 256};
+constexpr double kTuneBottomUp[] = {0.04, 0.01, 0.15, -1.0};
+constexpr int64_t kTuneSplit[] = {1ll << 20, 1ll << 18, 1ll << 22};
+constexpr uint64_t kTuneSeed = 0x74756e65ull;   // the sample sources' Philox key
+
+// Widest width <= want that an engine serves on this graph (32-bit indices,
+// 70 % of free device memory).
+int fit_width(bc_graph *g, Engine e, int want)
+{
+    bc_config keep = g->cfg;
+    g->cfg.batch = want;
+    const int B = e == ENG_PAIR ? plan_pairs(g, want, want) : plan_batch(g, want, want).B;
+    g->cfg = keep;
+    return B;
+}
+
+bc_config tune_plan(bc_graph *g)
+{
+    const TuneKey key{g->n, g->nnz, probe_depth(g), g->deg_hist};
+    {
+        std::lock_guard<std::mutex> lock(tune_mu);
+        auto it = tune_cache.find(key);
+        if (it != tune_cache.end()) return it->second;
+    }
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    DBuf<int32_t> sample;
+    DBuf<double> out;
+    sample.ensure(4096);
+    out.ensure((size_t)n);
+    launch(s, grid_for(4096), k_draw_sources, kTuneSeed, (int64_t)0, (int64_t)4096, n, sample.p);
+    const bc_config user = g->cfg;
+    const int32_t user_batch = g->tuned_batch;
+    double best_per = 0.0;
+    bc_config best{};
+    bool have = false;
+    // seconds per source of k sources (default: one batch of width c.batch)
+    // under plan c, or < 0 when abandoned
+    auto trial = [&](bc_config c, int64_t k) -> double {
+        if (k <= 0) k = std::min<int64_t>(n, c.batch);
+        g->cfg = c;
+        g->tuned_batch = 0;
+        double per = -1.0;
+        try {
+            // size the plan's buffers first, so that allocation is not timed
+            if (c.schedule == BC_SCHED_THREADED) {
+                ensure_pairs(g, c.batch, g->ext_sticky);
+            } else {
+                const Plan p = plan_batch(g, k, c.batch);
+                ensure_batch(g, p, g->ext_sticky, start_cap(g), OUT_VSUM);
+            }
+            HIPX(hipStreamSynchronize(s));
+            g->timed = have;
+            g->deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double>(std::max(0.05, 1.5 * best_per * k)));
+            const auto t0 = std::chrono::steady_clock::now();
+            dependencies_impl(g, sample.p, k, BC_OUT_SUM, out.p, nullptr, nullptr, nullptr, false,
+                              nullptr);
+            per = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() /
+                  (double)k;
+        } catch (const TuneTimeout &) {
+            (void)hipStreamSynchronize(s);
+        } catch (...) {
+            g->timed = false;
+            g->cfg = user;
+            g->tuned_batch = user_batch;
+            throw;
+        }
+        g->timed = false;
+        if (per > 0.0 && (!have || per < best_per)) {
+            best_per = per;
+            best = c;
+            have = true;
+        }
+        return per;
+    };
+    auto make = [&](Engine e, int B) {
+        bc_config c{};
+        c.schedule = e == ENG_PAIR ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
+        c.batch = fit_width(g, e, B);
+        return c;
+    };
+    try {
+        // 1. engine, the heuristic one first, on the same 256 sources
+        const Engine first = probe_depth(g) > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
+        const Engine second = first == ENG_PAIR ? ENG_WAVE : ENG_PAIR;
+        const int64_t k_eng = std::min<int64_t>(n, 256);
+        trial(make(first, first == ENG_PAIR ? 512 : 2048), k_eng);
+        trial(make(second, second == ENG_PAIR ? 512 : 2048), k_eng);
+        // 2. batch width, widest first (buffers grow once), up to the first
+        // width that holds all n sources; each timed on a batch of its width
+        const Engine e = best.schedule == BC_SCHED_THREADED ? ENG_PAIR : ENG_WAVE;
+        have = false;
+        int prev = 0;
+        for (int W : kTuneWidths) {
+            if (W > 2 * n && W > 256) continue;
+            bc_config c = make(e, W);
+            if (c.batch == prev) continue;
+            prev = c.batch;
+            trial(c, 0);
+        }
+        // 3. the engine's own knobs at the best width
+        const bc_config width = best;
+        const double width_per = best_per;
+        if (e == ENG_WAVE) {
+            for (double bu : kTuneBottomUp) {
+                if (bu == 0.04) continue;
+                bc_config c = width;
+                c.bottom_up = bu;
+                trial(c, 0);
+            }
+            const bc_config dir = best;
+            for (int64_t sp : kTuneSplit) {
+                if (sp == (1ll << 20)) continue;
+                bc_config c = dir;
+                c.split_entries = sp;
+                trial(c, 0);
+            }
+        } else {
+            // a persistent loop cannot be abandoned mid-launch: it is tried
+            // where a batch takes under 50 ms (many short levels)
+            int coop = 0;
+            HIPX(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device));
+            if (coop && width_per * std::min<int64_t>(n, width.batch) < 0.05) {
+                bc_config c = width;
+                c.level_loop = 1;
+                trial(c, 0);
+            }
+        }
+    } catch (...) {
+        sample.release();
+        out.release();
+        throw;
+    }
+    sample.release();
+    out.release();
+    g->cfg = user;
+    g->tuned_batch = user_batch;
+    if (!have) fail(BC_E_DEVICE, "no tuning candidate finished");
+    {
+        std::lock_guard<std::mutex> lock(tune_mu);
+        tune_cache[key] = best;
+    }
+    return best;
+}
+
+// Install a tuned plan: engine and knobs in cfg, width for bc_dependencies and
+// bc_exact only (the samplers keep their own round widths).
+void apply_plan(bc_graph *g, const bc_config &plan)
+{
+    g->cfg = plan;
+    g->tuned_batch = plan.batch;
+    g->cfg.batch = 0;
+    g->tuned = true;
+}
+
+void ensure_tuned(bc_graph *g)
+{
+    if (g->cfg.schedule == BC_SCHED_TUNED && !g->tuned) apply_plan(g, tune_plan(g));
 }
 
 // --------------------------------------------------------------- samplers
@@ -1455,6 +1671,15 @@ bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hi
                     g->hub = (int32_t)v;
                 }
             g->hub_degree = best;
+            for (int64_t v = 0; v < csr->n; ++v) {
+                int64_t d = row[v + 1] - row[v] + 1;
+                int b = 0;
+                while (d > 1) {
+                    d >>= 1;
+                    ++b;
+                }
+                g->deg_hist[(size_t)std::min(b, 32)] += 1;
+            }
             {
                 // landmarks: the kLandmarks highest degrees (ties by vertex id)
                 std::vector<int32_t> ids((size_t)csr->n);
@@ -1513,13 +1738,42 @@ bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg)
 {
     return guarded([&] {
         need(g && cfg, "null argument");
-        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_THREADED,
+        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_TUNED,
              "unknown schedule");
         const int b = cfg->batch;
         need(b == 0 || (b >= 64 && b <= 4096 && (b & (b - 1)) == 0),
              "batch must be 0 or a power of two in [64, 4096]");
         need(cfg->bottom_up == cfg->bottom_up, "bottom_up is NaN");
         g->cfg = *cfg;
+        g->tuned = false;
+        g->tuned_batch = 0;
+    });
+}
+
+bc_status bc_graph_tune(bc_graph *g, bc_config *plan)
+{
+    return guarded([&] {
+        need(g, "null graph");
+        use_device(g);
+        UseAlloc ua(&g->alloc);
+        const bc_config best = tune_plan(g);
+        apply_plan(g, best);
+        if (plan) *plan = best;
+    });
+}
+
+bc_status bc_graph_plan(bc_graph *g, bc_config *out)
+{
+    return guarded([&] {
+        need(g && out, "null argument");
+        use_device(g);
+        UseAlloc ua(&g->alloc);
+        ensure_tuned(g);
+        bc_config c = g->cfg;
+        if (c.schedule == BC_SCHED_AUTO)
+            c.schedule = engine_for(g) == ENG_PAIR ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
+        if (c.batch == 0) c.batch = g->tuned_batch;
+        *out = c;
     });
 }
 
@@ -1603,6 +1857,7 @@ bc_status bc_exact(bc_graph *g, double *out)
         need(g && out, "null argument");
         use_device(g);
         UseAlloc ua(&g->alloc);
+        ensure_tuned(g);
         Staging io(g);
         double *d_out = io.out(out, g->n);
         DBuf<int32_t> all;
@@ -1640,6 +1895,7 @@ bc_status bc_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_
         need(k == 0 || sources, "null argument");
         use_device(g);
         UseAlloc ua(&g->alloc);
+        ensure_tuned(g);
         Staging io(g);
         const int32_t *d_src = io.in(sources, k);
         const int32_t *d_tg = out_mode == BC_OUT_TARGETS ? io.in(targets, T) : nullptr;
@@ -1744,6 +2000,7 @@ bc_status bc_pair_dependencies(bc_graph *g, const int32_t *us, const int32_t *vs
         need(g->n >= 2, "pairs need n >= 2");
         use_device(g);
         UseAlloc ua(&g->alloc);
+        ensure_tuned(g);
         Staging io(g);
         const int32_t *d_us = io.in(us, k);
         const int32_t *d_vs = io.in(vs, k);
@@ -1773,6 +2030,7 @@ bc_status bc_adaptive_source(bc_graph *g, const int32_t *targets, int32_t T, dou
         need(k_max >= 1, "k_max must be >= 1");
         use_device(g);
         UseAlloc ua(&g->alloc);
+        ensure_tuned(g);
         Staging io(g);
         const int32_t *d_tg = io.in(targets, T);
         check_indices(g, d_tg, T, "target");
@@ -1802,6 +2060,7 @@ bc_status bc_adaptive_pair(bc_graph *g, const int32_t *targets, int32_t T, int32
         need(g->n >= 2, "pairs need n >= 2");
         use_device(g);
         UseAlloc ua(&g->alloc);
+        ensure_tuned(g);
         Staging io(g);
         const int32_t *d_tg = io.in(targets, T);
         check_indices(g, d_tg, T, "target");
