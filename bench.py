@@ -12,9 +12,16 @@ component, divided by the step time (Graph500 convention, fwd+bwd counted once).
 
 Printed on one JSON line, beside the headline value:
   per_source  the same pass in the one-source-per-launch form on a subset
-  pair_leg    adaptive pair sampling (eps = 0.05, 32 top-degree targets)
+  pair_leg    adaptive pair sampling (eps = 0.05, 32 top-degree targets), with
+              pair-search GTEPS and its dominant kernel's roofline
   roofline    the dominant kernel against the 8 TB/s HBM peak
   cpu_baseline the CPU oracle on a bounded sample of the same sources
+  legs        the other workloads: C1 (ER n = 2000: exact BC and the three
+              samplers), C2 (R-MAT scale 16: 64 degree-percentile targets,
+              c = 5, 256 per round), C4 (2048^2 grid, 5 % of edges removed, 1024
+              sources) and C5 (serving a prefix of the 20,000-query stream)
+The graph's plan comes from the autotuner (bc_graph_tune) unless --schedule
+names one; it is part of the printed config.
 """
 from __future__ import annotations
 
@@ -102,6 +109,41 @@ def component_edges(g):
     return per_comp[lab]
 
 
+def pair_search_edges(dist, v, ea, eb):
+    """Undirected edges with an endpoint at distance < d(u, v) from u, the
+    edges a search from u that stops after v's level has looked at (all of u's
+    component when v is unreachable). dist: distances from u (-1 unreached);
+    ea, eb: the CSR's directed entries."""
+    import numpy as np
+    lim = dist[v] if dist[v] >= 0 else np.iinfo(np.int64).max
+    da = dist[ea].astype(np.int64)
+    db = dist[eb].astype(np.int64)
+    keep = ea < eb
+    lo = np.minimum(da[keep], db[keep])
+    return int(((da[keep] >= 0) & (lo < lim)).sum())
+
+
+def cpu_info():
+    """Model name, logical CPUs of the host and CPUs this process may use."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "usable": len(os.sched_getaffinity(0))}
+
+
+def sampler_gteps(bc, G, gg, comp_edges, seed, executed, pairs):
+    """Undirected edges searched by a sampler's executed samples: for sources,
+    each source's component (Graph500 convention); pairs are not counted here."""
+    import numpy as np
+    src = gg.philox_sources(seed, int(executed), G.n)
+    return float(np.asarray(comp_edges)[src].sum())
+
+
 def serving_leg(args, bc, gg):
     """200 resident R-MAT graphs (scales 10-18, edge factors 8-32), a Poisson
     stream of queries (graph uniform, target degree-weighted, half source
@@ -156,6 +198,9 @@ def serving_leg(args, bc, gg):
         "samples_executed": st["samples_executed"], "samples_used": st["samples_used"],
         "batch_fill": st["samples_executed"] / max(1, args.serve_batch * st["rounds"]),
         "capped": int(sum(r["status"] == bc.BC_CAPPED for r in res)),
+        "capped_fraction": float(np.mean([r["status"] == bc.BC_CAPPED for r in res])),
+        "offered_qps": N / max(1e-9, max(q["arrival"] for q in qs)),
+        "split_rounds": st["split_rounds"], "budget_bytes": st["budget_bytes"],
         "used_sample_gteps_full_search_equiv": edges / makespan / 1e9,
         "resident_bytes": st["resident_bytes"], "workspace_bytes": st["workspace_bytes"],
     }
@@ -172,6 +217,168 @@ def serving_leg(args, bc, gg):
     return out
 
 
+def c1_leg(args, bc, gg, dev):
+    """ER n = 2000 (graph seed 1): exact BC; source sampling c = 5, pair sampling
+    eps = 0.1 and Algorithm 1 as printed (c = 1) for the 16 highest-degree
+    vertices, seed 1."""
+    import torch
+    g = gg.config_graph("er2000")
+    ce = component_edges(g)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_TUNED)
+    out = {"workload": "ER n=2000 p=8/1999 (seed 1), %d undirected edges" % g.m_undirected}
+    bc.exact(G)                                     # tunes, warms
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bc.exact(G)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out["exact"] = {"ms": 1e3 * dt, "gteps": float(ce.sum()) / dt / 1e9}
+    tg = torch.from_numpy(gg.top_degree(g, 16)).to(dev)
+    for name, call in (("source_c5", lambda: bc.adaptive_source(G, tg, 5.0, 1, g.n)),
+                       ("pair_eps0.1", lambda: bc.adaptive_pair(G, tg, bc.BC_PAIR_EPS, 0.1, 1.0,
+                                                                1, 1 << 20)),
+                       ("pair_alg1_c1", lambda: bc.adaptive_pair(G, tg, bc.BC_PAIR_ALG1, 0.1, 1.0,
+                                                                 1, 1 << 20))):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        est, k, S, st = call()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        ex = G.stats()["samples_executed"]
+        kk = k.cpu().numpy()
+        rec = {"ms": 1e3 * dt, "samples_executed": int(ex), "samples_used": int(kk.max()),
+               "capped": int((st.cpu().numpy() == bc.BC_CAPPED).sum()),
+               "samples_per_s": ex / dt}
+        if name.startswith("source"):
+            rec["gteps"] = sampler_gteps(bc, G, gg, ce, 1, ex, False) / dt / 1e9
+        out[name] = rec
+    out["plan"] = G.plan()
+    G.close()
+    log("C1: exact %.1f ms; source %.1f ms; pair eps %.1f ms; alg1 %.1f ms (%d pairs)" % (
+        out["exact"]["ms"], out["source_c5"]["ms"], out["pair_eps0.1"]["ms"],
+        out["pair_alg1_c1"]["ms"], out["pair_alg1_c1"]["samples_executed"]))
+    return out
+
+
+def c2_leg(args, bc, gg, dev):
+    """R-MAT scale 16 (graph seed 2): adaptive source sampling for 64 targets at
+    degree percentiles among degree >= 2 vertices, c = 5, 256 samples per round,
+    seed 2, k_max = n."""
+    import torch
+    g = gg.config_graph("rmat16")
+    ce = component_edges(g)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_TUNED, 256)
+    tg = torch.from_numpy(gg.degree_percentile_targets(g, 64)).to(dev)
+    bc.adaptive_source(G, tg[:2].contiguous(), 5.0, 2, 300)          # tunes, warms
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    est, k, S, st = bc.adaptive_source(G, tg, 5.0, 2, g.n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ex = G.stats()["samples_executed"]
+    kk = k.cpu().numpy()
+    stt = st.cpu().numpy()
+    out = {"workload": "R-MAT scale 16 ef 16 (seed 2), %d undirected edges; 64 degree-percentile "
+                       "targets, c=5, 256 per round, k_max=n" % g.m_undirected,
+           "ms": 1e3 * dt, "samples_executed": int(ex), "samples_used_sum": int(kk.sum()),
+           "samples_used_max": int(kk.max()), "rounds": int(G.stats()["batches"]),
+           "capped": int((stt == bc.BC_CAPPED).sum()), "done": int((stt == bc.BC_DONE).sum()),
+           "gteps": sampler_gteps(bc, G, gg, ce, 2, ex, False) / dt / 1e9, "plan": G.plan()}
+    G.close()
+    log("C2: %.1f ms, %d sources executed, %d capped, %.2f GTEPS" % (
+        out["ms"], ex, out["capped"], out["gteps"]))
+    return out
+
+
+def c4_leg(args, bc, gg, dev):
+    """2048^2 grid, 5 % of edges removed (seed 3), largest component: 1024
+    sources (seed 3), fwd+bwd, per-vertex sum; one step after a warm-up."""
+    import torch
+    t0 = time.time()
+    g = gg.config_graph("grid2048")
+    ce = component_edges(g)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_AUTO, args.c4_batch)
+    K = 1024
+    srcs = torch.from_numpy(gg.philox_sources(3, K, g.n)).to(dev)
+    out_t = torch.empty(g.n, dtype=torch.float64, device=dev)
+    bc.bc_dependencies(G, srcs[:64].contiguous(), bc.BC_OUT_SUM, out_t)   # warm
+    torch.cuda.synchronize()
+    G.profile(True)
+    t = time.perf_counter()
+    bc.bc_dependencies(G, srcs, bc.BC_OUT_SUM, out_t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    kern = G.profile_read()
+    G.profile(False)
+    st = G.stats()
+    edges = float(ce[srcs.cpu().numpy()].sum())
+    out = {"workload": "2048^2 grid, 5%% of edges removed (seed 3), n=%d, %d undirected edges; "
+                       "1024 sources (seed 3), fwd+bwd, sum" % (g.n, g.m_undirected),
+           "ms_per_step": 1e3 * dt, "gteps": edges / dt / 1e9, "levels": int(st["levels"]),
+           "batch": int(st["batch_width"]), "extended": int(st["extended"]),
+           "launches": int(sum(k["launches"] for k in kern)), "plan": G.plan(),
+           "setup_s": time.time() - t0 - dt}
+    G.close()
+    log("C4: %.0f ms/step, %.2f GTEPS, %d levels, batch %d, %d hot launches" % (
+        out["ms_per_step"], out["gteps"], out["levels"], out["batch"], out["launches"]))
+    return out
+
+
+def pair_leg(args, bc, gg, G, g, dev):
+    """Adaptive pair sampling (eps, the top-degree targets, seed 7): time,
+    samples, pair-search GTEPS (edges with an endpoint below d(u,v), measured on
+    an evenly spaced sample of the executed pairs and scaled to all of them) and
+    the dominant kernel's roofline."""
+    import numpy as np
+    import torch
+    targets = torch.from_numpy(gg.top_degree(g, args.pair_targets)).to(dev)
+    torch.cuda.synchronize()
+    G.profile(True)
+    t = time.perf_counter()
+    est, k, S, stt = bc.adaptive_pair(G, targets, bc.BC_PAIR_EPS, args.pair_eps, 1.0,
+                                      args.seed, 1 << 20)
+    torch.cuda.synchronize()
+    pt = time.perf_counter() - t
+    kern = G.profile_read()
+    G.profile(False)
+    pst = G.stats()
+    ex = int(pst["samples_executed"])
+    kk = k.cpu().numpy()
+    # pair-search edges on a sample of the executed pairs: distances from u by
+    # the library (pinned to the oracle), edges counted on the host
+    m = min(args.pair_work_sample, ex)
+    js = np.unique(np.linspace(0, ex - 1, m).astype(np.int64))
+    us = torch.empty(ex, dtype=torch.int32, device=dev)
+    vs = torch.empty(ex, dtype=torch.int32, device=dev)
+    bc.bc_draw_pairs(G, args.seed, 0, ex, us, vs)
+    su = us[torch.from_numpy(js).to(dev)].contiguous()
+    sv = vs[torch.from_numpy(js).to(dev)].cpu().numpy()
+    _, dist, _ = bc.dependencies(G, su, bc.BC_OUT_FULL, dist=True)
+    dist = dist.cpu().numpy()
+    ea = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row))
+    eb = g.col.astype(np.int64)
+    work = [pair_search_edges(dist[i], int(sv[i]), ea, eb) for i in range(len(js))]
+    mean_work = float(np.mean(work))
+    dom = max(kern, key=lambda x: x["ms"])
+    ach = dom["algo_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    out = {"targets": args.pair_targets, "eps": args.pair_eps, "ms": 1e3 * pt,
+           "samples_executed": ex, "samples_used_max": int(kk.max()),
+           "samples_used_min": int(kk.min()), "pairs_per_s": ex / pt,
+           "rounds": int(pst["batches"]), "capped": int((stt.cpu().numpy() == bc.BC_CAPPED).sum()),
+           "pair_search_edges_mean": mean_work,
+           "pair_work_sample": "%d of the %d executed pairs, evenly spaced in draw order" % (
+               len(js), ex),
+           "gteps": mean_work * ex / pt / 1e9,
+           "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}}
+    log("pair leg: %.1f ms, %d pairs executed (%.0f pairs/s), %.2f GTEPS (pair-search edges)" % (
+        out["ms"], ex, out["pairs_per_s"], out["gteps"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,22 +388,26 @@ def main():
     ap.add_argument("--sources", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--batch", type=int, default=0)
-    ap.add_argument("--schedule", default="auto", choices=["auto", "wave", "pair"])
+    ap.add_argument("--schedule", default="tuned", choices=["tuned", "auto", "wave", "pair"])
     ap.add_argument("--bottom-up", type=float, default=0.0)
     ap.add_argument("--level-loop", type=int, default=0,
-                    help="pair engine: 1 persistent level loops, -1 one launch per level "
-                         "phase, 0 auto")
+                    help="pair engine: 1 persistent level loops, else one launch per level phase")
     ap.add_argument("--per-source", type=int, default=16, help="sources for the per-source leg")
     ap.add_argument("--pair-targets", type=int, default=32)
     ap.add_argument("--pair-eps", type=float, default=0.05)
+    ap.add_argument("--pair-work-sample", type=int, default=64,
+                    help="executed pairs whose search edges are counted for the pair GTEPS")
     ap.add_argument("--no-pair", action="store_true")
+    ap.add_argument("--legs", default="c1,c2,c4,c5",
+                    help="other workloads to measure (comma list of c1, c2, c4, c5; '' = none)")
+    ap.add_argument("--c4-batch", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-threads", type=int, default=16,
                     help="threads for the all-cores oracle run (capped by the CPUs this "
                          "process may use)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-graphs", type=int, default=200)
-    ap.add_argument("--serve-queries", type=int, default=200,
+    ap.add_argument("--serve-queries", type=int, default=2000,
                     help="prefix of the 20,000-query stream to serve (the whole stream "
                          "exceeds one GPU's capacity)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
@@ -229,9 +440,14 @@ def main():
     log("graph %s n=%d nnz=%d built in %.1fs" % (args.graph, g.n, g.nnz, time.time() - t0))
     comp_edges = component_edges(g)
     G = bc.Graph(g.row, g.col)
-    sched = {"auto": bc.BC_SCHED_AUTO, "wave": bc.BC_SCHED_BATCHED,
+    sched = {"tuned": bc.BC_SCHED_TUNED, "auto": bc.BC_SCHED_AUTO, "wave": bc.BC_SCHED_BATCHED,
              "pair": bc.BC_SCHED_THREADED}[args.schedule]
     G.configure(sched, args.batch, args.bottom_up, 0, args.level_loop)
+    if sched == bc.BC_SCHED_TUNED:
+        t = time.time()
+        plan = G.tune()
+        log("tuned in %.1fs: %s" % (time.time() - t, plan))
+    plan = G.plan()
 
     K = args.sources
     srcs = torch.empty(K, dtype=torch.int32, device=dev)
@@ -285,15 +501,15 @@ def main():
                 "avg_launch_us": 1e3 * dom["ms"] / dom["launches"],
                 "algo_bytes_per_launch": dom["algo_bytes"] / dom["launches"]}
     sig = next(k for k in kern if k["name"] == "sigma_pull")
+    fwd = next(k for k in kern if k["name"] == "pair_forward")
     csr_bytes = 8 * (g.n + 1) + 4 * g.nnz
     batches = -(-K // st["batch_width"])
-    reach = sig["units_a"] + K * args.steps          # level-0 pairs are the sources
-    step_bytes = (2 * csr_bytes * batches * args.steps + 32 * reach + 16 * sig["units_b"]) \
-        / args.steps
+    reach = sig["units_a"] + fwd["units_a"] + K * args.steps   # level-0 pairs are the sources
+    dag = sig["units_b"] + fwd["units_b"]
+    step_bytes = (2 * csr_bytes * batches * args.steps + 32 * reach + 16 * dag) / args.steps
     step_model = {"algo_bytes": step_bytes, "GBs": step_bytes / (ms * 1e-3) / 1e9,
                   "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                  "reached_pairs": reach / args.steps,
-                  "dag_edge_pairs": sig["units_b"] / args.steps}
+                  "reached_pairs": reach / args.steps, "dag_edge_pairs": dag / args.steps}
     log("dominant %s: %.1f GB/s (%.1f%% of HBM); whole step %.1f GB/s (%.1f%%)" % (
         dom["name"], achieved, 100 * achieved / HBM_PEAK_GBS, step_model["GBs"],
         100 * step_model["frac"]))
@@ -322,26 +538,17 @@ def main():
     # ----------------------------------------------------------- pair leg
     pair = None
     if not args.no_pair and args.pair_targets > 0:
-        targets = torch.from_numpy(gg.top_degree(g, args.pair_targets)).to(dev)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        est, k, S, stt = bc.adaptive_pair(G, targets, bc.BC_PAIR_EPS, args.pair_eps, 1.0,
-                                          args.seed, 1 << 20)
-        torch.cuda.synchronize()
-        pt = time.perf_counter() - t
-        pst = G.stats()
-        kk = k.cpu().numpy()
-        pair = {"targets": args.pair_targets, "eps": args.pair_eps, "ms": 1e3 * pt,
-                "samples_executed": int(pst["samples_executed"]),
-                "samples_used_max": int(kk.max()), "samples_used_min": int(kk.min()),
-                "pairs_per_s": pst["samples_executed"] / pt,
-                "capped": int((stt.cpu().numpy() == bc.BC_CAPPED).sum())}
-        log("pair leg: %.1f ms, %d pairs executed (%.0f pairs/s)" % (
-            pair["ms"], pair["samples_executed"], pair["pairs_per_s"]))
+        pair = pair_leg(args, bc, gg, G, g, dev)
+    G.close()
 
-    # ------------------------------------------------------------ serving
+    # ------------------------------------------------------ other workloads
+    legs = {}
+    want = [x for x in args.legs.split(",") if x]
+    for name, fn in (("c1", c1_leg), ("c2", c2_leg), ("c4", c4_leg)):
+        if name in want:
+            legs[name] = fn(args, bc, gg, dev)
     serving = None
-    if not args.no_serve and args.serve_queries > 0:
+    if "c5" in want and not args.no_serve and args.serve_queries > 0:
         serving = serving_leg(args, bc, gg)
 
     # ------------------------------------------------------- cpu baseline
@@ -351,13 +558,16 @@ def main():
         O = oracle.load()
         d1, e1, t1 = oracle_rate(O, g, host_src, comp_edges, args.cpu_seconds, 1)
         log("cpu oracle, 1 thread: %d sources in %.1f s -> %.4f GTEPS" % (d1, t1, e1 / t1 / 1e9))
-        nt = max(1, min(args.cpu_threads, len(os.sched_getaffinity(0))))
+        info = cpu_info()
+        nt = max(1, min(args.cpu_threads, info["usable"]))
         dn, en, tn = oracle_rate(O, g, host_src, comp_edges, args.cpu_seconds, nt)
         log("cpu oracle, %d threads: %d sources in %.1f s -> %.4f GTEPS" % (
             nt, dn, tn, en / tn / 1e9))
         cpu = {"value": en / tn / 1e9, "unit": "GTEPS", "cores": nt, "kind": "oracle",
                "sample": "first %d of the step's %d sources, fwd+bwd, summed, one source per "
                          "call on %d threads, %.1f s" % (dn, K, nt, tn),
+               "cpu_model": info["model"], "nproc": info["nproc"],
+               "usable_cpus": info["usable"],
                "single_thread": {"value": e1 / t1 / 1e9, "cores": 1,
                                  "sample": "first %d sources, %.1f s" % (d1, t1)}}
 
@@ -370,16 +580,15 @@ def main():
                                "(seed %d), fwd+bwd, per-vertex dependency sum" % (
                                    g.m_undirected, K, args.seed),
                    "graph": args.graph, "n": g.n, "nnz": g.nnz, "sources": K,
-                   "batch": st["batch_width"], "parallelism": "single GPU"},
+                   "batch": st["batch_width"], "plan": plan, "parallelism": "single GPU"},
         "per_source": per_source, "pair_leg": pair, "roofline": roofline, "cpu_baseline": cpu,
-        "step_model": step_model, "serving": serving,
+        "step_model": step_model, "legs": legs, "serving": serving,
         "p99_query_ms": serving["p99_ms"] if serving else None,
         "kernels": [{"name": k["name"], "launches": k["launches"], "ms": k["ms"] / args.steps,
                      "algo_GBs": k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] else 0.0}
                     for k in kern],
     }
     print(json.dumps(res), flush=True)
-    G.close()
 
 
 if __name__ == "__main__":

@@ -50,3 +50,25 @@ def test_traffic_lookup_needs_a_matching_record():
     b = load_bench()
     assert b.measured_traffic("no_such_kernel", "ba1m-4096-b2048") is None
     assert b.measured_traffic("backward", "no_such_workload") is None
+
+
+def test_pair_search_edges_equals_the_oracle_count():
+    """bench.py's pair GTEPS counts edges with an endpoint below d(u,v) from
+    distances; on random graphs (with isolated vertices) it must equal
+    oracle_pair_work for every sampled pair, reachable or not."""
+    b = load_bench()
+    O = oracle.load()
+    for g in (gg.rmat(9, 6, 0.57, 0.19, 0.19, seed=8), gg.er(400, 0.006, seed=2)):
+        ea = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row))
+        eb = g.col.astype(np.int64)
+        r = np.random.default_rng(3)
+        for _ in range(40):
+            u, v = (int(x) for x in r.choice(g.n, 2, replace=False))
+            dist = O.brandes(g, u)[0]
+            assert b.pair_search_edges(dist, v, ea, eb) == O.pair_work(g, u, v), (u, v)
+
+
+def test_cpu_info_fields():
+    b = load_bench()
+    info = b.cpu_info()
+    assert info["nproc"] >= 1 and 1 <= info["usable"] <= info["nproc"]
