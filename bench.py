@@ -335,6 +335,8 @@ def pair_leg(args, bc, gg, G, g, dev):
     import numpy as np
     import torch
     targets = torch.from_numpy(gg.top_degree(g, args.pair_targets)).to(dev)
+    if args.pair_sampler_batch:
+        G.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, args.pair_sampler_batch)
     torch.cuda.synchronize()
     G.profile(True)
     t = time.perf_counter()
@@ -397,6 +399,8 @@ def main():
     ap.add_argument("--pair-eps", type=float, default=0.05)
     ap.add_argument("--pair-work-sample", type=int, default=64,
                     help="executed pairs whose search edges are counted for the pair GTEPS")
+    ap.add_argument("--pair-sampler-batch", type=int, default=0,
+                    help="samples per pair-sampler round (0 = the library's default)")
     ap.add_argument("--no-pair", action="store_true")
     ap.add_argument("--legs", default="c1,c2,c4,c5",
                     help="other workloads to measure (comma list of c1, c2, c4, c5; '' = none)")

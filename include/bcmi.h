@@ -113,7 +113,11 @@ typedef struct {
                               gives up); <= 0 launches each level's phases
                               separately (the default). Values are identical
                               either way. */
-    int32_t reserved;
+    int32_t sampler_batch; /* samples per round of bc_adaptive_source / _pair, a
+                              power of two in [64, 4096]; 0 = auto (256 sources,
+                              2048 pairs). A round
+                              runs ahead of the stop rule by at most its width:
+                              results do not depend on it. */
 } bc_config;
 
 /* Host CSR. row has n+1 entries, int64 if row_is_i64 else int32. */

@@ -77,7 +77,7 @@ class _Csr(ctypes.Structure):
 class _Config(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("bottom_up", ctypes.c_double), ("split_entries", ctypes.c_int64),
-                ("level_loop", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("level_loop", ctypes.c_int32), ("sampler_batch", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -286,22 +286,22 @@ class Graph:
         return self._h
 
     def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0, split_entries=0,
-                  level_loop=0):
+                  level_loop=0, sampler_batch=0):
         cfg = _Config(int(schedule), int(batch), float(bottom_up), int(split_entries),
-                      int(level_loop), 0)
+                      int(level_loop), int(sampler_batch))
         _check(_lib.bc_graph_configure(self.handle, ctypes.byref(cfg)))
 
     def tune(self):
         """Time candidate plans, install the fastest and return it (a dict)."""
         cfg = _Config()
         _check(_lib.bc_graph_tune(self.handle, ctypes.byref(cfg)))
-        return {f: getattr(cfg, f) for f, _ in _Config._fields_ if f != "reserved"}
+        return {f: getattr(cfg, f) for f, _ in _Config._fields_}
 
     def plan(self):
         """The plan compute calls use now (a dict)."""
         cfg = _Config()
         _check(_lib.bc_graph_plan(self.handle, ctypes.byref(cfg)))
-        return {f: getattr(cfg, f) for f, _ in _Config._fields_ if f != "reserved"}
+        return {f: getattr(cfg, f) for f, _ in _Config._fields_}
 
     def stats(self):
         st = _Stats()
