@@ -66,6 +66,7 @@ class CSR:
     row: np.ndarray  # int64[n+1]
     col: np.ndarray  # int32[nnz]
     name: str = ""
+    directed: bool = False   # row v lists v's out-neighbours (arcs v -> w)
 
     @property
     def nnz(self) -> int:
@@ -100,6 +101,57 @@ def from_edges(n: int, src, dst, name: str = "") -> CSR:
     if nnz < 0:
         raise ValueError("edge list has an endpoint outside [0, n)")
     return CSR(n, row, col[:nnz].copy(), name)
+
+
+def from_arcs(n: int, src, dst, name: str = "") -> CSR:
+    """Directed CSR of out-neighbours from an arc list: rows sorted ascending,
+    self-loops and repeated arcs dropped."""
+    src = np.asarray(src, dtype=np.int64).ravel()
+    dst = np.asarray(dst, dtype=np.int64).ravel()
+    assert src.shape == dst.shape
+    if n <= 0:
+        raise ValueError("n must be positive")
+    if src.size and (src.min() < 0 or dst.min() < 0 or src.max() >= n or dst.max() >= n):
+        raise ValueError("arc list has an endpoint outside [0, n)")
+    keep = src != dst
+    key = np.unique(src[keep] * n + dst[keep])
+    a, b = key // n, key % n
+    row = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row, a + 1, 1)
+    row = np.cumsum(row)
+    return CSR(n, row, b.astype(np.int32), name, directed=True)
+
+
+def directed_path(n: int) -> CSR:
+    return from_arcs(n, np.arange(n - 1), np.arange(1, n), "dpath%d" % n)
+
+
+def directed_cycle(n: int) -> CSR:
+    return from_arcs(n, np.arange(n), (np.arange(n) + 1) % n, "dcycle%d" % n)
+
+
+def out_star(n: int) -> CSR:
+    """Vertex 0 with an arc to every other vertex."""
+    return from_arcs(n, np.zeros(n - 1, np.int64), np.arange(1, n), "ostar%d" % n)
+
+
+def bidirected(g: CSR) -> CSR:
+    """An undirected CSR read as a directed one (every edge an arc both ways)."""
+    return CSR(g.n, g.row, g.col, g.name + "_bidir", directed=True)
+
+
+def rmat_directed(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) -> CSR:
+    """The R-MAT draws of rmat() kept as arcs (not symmetrised)."""
+    n = 1 << scale
+    ne = edge_factor * n
+    src = np.zeros(ne, dtype=np.int32)
+    dst = np.zeros(ne, dtype=np.int32)
+    key = (int(seed) * 0x100000001B3 + STREAM_GRAPH) & ((1 << 64) - 1)
+    got = _native().graphgen_rmat(scale, edge_factor, a, b, c, key, src.ctypes.data,
+                                  dst.ctypes.data)
+    if got != ne:
+        raise RuntimeError("graphgen_rmat failed")
+    return from_arcs(n, src, dst, "drmat%d_%d" % (scale, edge_factor))
 
 
 def relabel_subgraph(g: CSR, keep: np.ndarray, name: str = "") -> CSR:

@@ -22,6 +22,11 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
                       counts, planted mistakes
   pair_work           closed forms (paths, stars, adjacent and unreachable
                       pairs), scipy BFS distances, planted mistakes
+  *_directed          the same functions on directed graphs (out-neighbour
+                      CSR): brute-force path enumeration on small digraphs,
+                      closed forms (directed paths, cycles, stars, DAG
+                      layers), networkx's directed betweenness, bidirected
+                      graphs equal to their undirected form, planted mistakes
 """
 from __future__ import annotations
 
@@ -83,9 +88,15 @@ def _declare(lib):
     lib.oracle_pair_work.argtypes = [c.c_int64, c.c_void_p, c.c_void_p, c.c_int32,
                                      c.c_int32, c.c_void_p]
     for name in ("oracle_brandes", "oracle_bc_exact", "oracle_dependencies",
+                 "oracle_pair_dependency", "oracle_adaptive_source", "oracle_adaptive_pair"):
+        d = getattr(lib, name + "_directed")
+        d.argtypes = getattr(lib, name).argtypes
+    for name in ("oracle_brandes", "oracle_bc_exact", "oracle_dependencies",
                  "oracle_pair_dependency", "oracle_adaptive_source", "oracle_adaptive_pair",
                  "oracle_source_work", "oracle_pair_work"):
         getattr(lib, name).restype = c.c_int
+        if hasattr(lib, name + "_directed"):
+            getattr(lib, name + "_directed").restype = c.c_int
     return lib
 
 
@@ -117,8 +128,14 @@ def _ok(rc, what):
 
 
 class Oracle:
+    """Calls take an undirected CSR, or with directed=True a CSR of
+    out-neighbours (edges followed in their direction)."""
+
     def __init__(self, lib):
         self.lib = lib
+
+    def _f(self, name, directed):
+        return getattr(self.lib, name + ("_directed" if directed else ""))
 
     def philox(self, ctr, key):
         c = np.asarray(ctr, dtype=np.uint64)
@@ -136,41 +153,41 @@ class Oracle:
         self.lib.oracle_draw_pair(seed, j, n, ctypes.byref(u), ctypes.byref(v))
         return u.value, v.value
 
-    def brandes(self, g, s):
+    def brandes(self, g, s, directed=False):
         """-> dist int32[n], sigma (mant f64[n], exp int32[n]), delta f64[n]"""
         n, row, col = _csr(g)
         dist = np.zeros(n, np.int32)
         sm = np.zeros(n, np.float64)
         se = np.zeros(n, np.int32)
         de = np.zeros(n, np.float64)
-        _ok(self.lib.oracle_brandes(n, _p(row), _p(col), int(s), _p(dist), _p(sm), _p(se),
-                                    _p(de)), "oracle_brandes")
+        _ok(self._f("oracle_brandes", directed)(n, _p(row), _p(col), int(s), _p(dist), _p(sm),
+                                                _p(se), _p(de)), "oracle_brandes")
         return dist, (sm, se), de
 
-    def bc_exact(self, g):
+    def bc_exact(self, g, directed=False):
         n, row, col = _csr(g)
         bc = np.zeros(n, np.float64)
-        _ok(self.lib.oracle_bc_exact(n, _p(row), _p(col), _p(bc)), "oracle_bc_exact")
+        _ok(self._f("oracle_bc_exact", directed)(n, _p(row), _p(col), _p(bc)), "oracle_bc_exact")
         return bc
 
-    def dependencies(self, g, sources, full=True, total=True):
+    def dependencies(self, g, sources, full=True, total=True, directed=False):
         n, row, col = _csr(g)
         src = np.ascontiguousarray(sources, dtype=np.int32)
         k = src.shape[0]
         f = np.zeros((k, n), np.float64) if full else None
         s = np.zeros(n, np.float64) if total else None
-        _ok(self.lib.oracle_dependencies(n, _p(row), _p(col), _p(src), k, _p(f), _p(s)),
-            "oracle_dependencies")
+        _ok(self._f("oracle_dependencies", directed)(n, _p(row), _p(col), _p(src), k, _p(f),
+                                                     _p(s)), "oracle_dependencies")
         return f, s
 
-    def pair_dependency(self, g, u, v):
+    def pair_dependency(self, g, u, v, directed=False):
         n, row, col = _csr(g)
         y = np.zeros(n, np.float64)
-        _ok(self.lib.oracle_pair_dependency(n, _p(row), _p(col), int(u), int(v), _p(y)),
-            "oracle_pair_dependency")
+        _ok(self._f("oracle_pair_dependency", directed)(n, _p(row), _p(col), int(u), int(v),
+                                                        _p(y)), "oracle_pair_dependency")
         return y
 
-    def adaptive_source(self, g, targets, c, seed, k_max):
+    def adaptive_source(self, g, targets, c, seed, k_max, directed=False):
         n, row, col = _csr(g)
         t = np.ascontiguousarray(targets, dtype=np.int32)
         T = t.shape[0]
@@ -178,12 +195,12 @@ class Oracle:
         k = np.zeros(T, np.int64)
         S = np.zeros(T, np.float64)
         st = np.zeros(T, np.uint8)
-        _ok(self.lib.oracle_adaptive_source(n, _p(row), _p(col), _p(t), T, float(c), int(seed),
-                                            int(k_max), _p(est), _p(k), _p(S), _p(st)),
-            "oracle_adaptive_source")
+        _ok(self._f("oracle_adaptive_source", directed)(n, _p(row), _p(col), _p(t), T, float(c),
+                                                        int(seed), int(k_max), _p(est), _p(k),
+                                                        _p(S), _p(st)), "oracle_adaptive_source")
         return est, k, S, st
 
-    def adaptive_pair(self, g, targets, rule, eps, c, seed, k_max):
+    def adaptive_pair(self, g, targets, rule, eps, c, seed, k_max, directed=False):
         n, row, col = _csr(g)
         t = np.ascontiguousarray(targets, dtype=np.int32)
         T = t.shape[0]
@@ -191,9 +208,10 @@ class Oracle:
         k = np.zeros(T, np.int64)
         S = np.zeros(T, np.float64)
         st = np.zeros(T, np.uint8)
-        _ok(self.lib.oracle_adaptive_pair(n, _p(row), _p(col), _p(t), T, int(rule), float(eps),
-                                          float(c), int(seed), int(k_max), _p(est), _p(k),
-                                          _p(S), _p(st)), "oracle_adaptive_pair")
+        _ok(self._f("oracle_adaptive_pair", directed)(n, _p(row), _p(col), _p(t), T, int(rule),
+                                                      float(eps), float(c), int(seed), int(k_max),
+                                                      _p(est), _p(k), _p(S), _p(st)),
+            "oracle_adaptive_pair")
         return est, k, S, st
 
     def source_work(self, g, s):

@@ -112,6 +112,52 @@ static double xnum_div(xnum a, xnum b)
 
 /* ------------------------------------------------------------ Brandes pass */
 
+/* A graph as a pass reads it: out-neighbour rows (the search and the
+ * dependency sums follow edges forward) and in-neighbour rows (path counts
+ * sum over predecessors, Definition 3). An undirected graph is its own
+ * reverse: both pairs of arrays are the same. */
+typedef struct {
+    int64_t n;
+    const int64_t *row;     /* out-neighbours */
+    const int32_t *col;
+    const int64_t *rrow;    /* in-neighbours */
+    const int32_t *rcol;
+} graph_t;
+
+static graph_t undirected(int64_t n, const int64_t *row, const int32_t *col)
+{
+    graph_t g = {n, row, col, row, col};
+    return g;
+}
+
+/* the same graph with every edge reversed */
+static graph_t reversed(const graph_t *g)
+{
+    graph_t r = {g->n, g->rrow, g->rcol, g->row, g->col};
+    return r;
+}
+
+/* In-neighbour rows of a directed CSR (rows sorted ascending, as the out
+ * rows are). Returns 0, or -2 when out of memory. */
+static int transpose(int64_t n, const int64_t *row, const int32_t *col, int64_t **trow,
+                     int32_t **tcol)
+{
+    const int64_t nnz = row[n];
+    int64_t *tr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *tc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!tr || !tc || !fill) { free(tr); free(tc); free(fill); return -2; }
+    for (int64_t e = 0; e < nnz; ++e) tr[col[e] + 1] += 1;
+    for (int64_t v = 0; v < n; ++v) tr[v + 1] += tr[v];
+    for (int64_t v = 0; v < n; ++v) fill[v] = tr[v];
+    for (int64_t u = 0; u < n; ++u)          /* sources ascending: rows come out sorted */
+        for (int64_t e = row[u]; e < row[u + 1]; ++e) tc[fill[col[e]]++] = (int32_t)u;
+    free(fill);
+    *trow = tr;
+    *tcol = tc;
+    return 0;
+}
+
 typedef struct {
     int32_t *dist;
     xnum *sig;
@@ -141,10 +187,12 @@ static int check_graph(int64_t n, const int64_t *row, const int32_t *col)
 }
 
 /* Brandes' first step for an unweighted graph: breadth-first search from s
- * giving d(s, .) and the visiting order. */
-static void bfs(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pass_t *p)
+ * along out-edges, giving d(s, .) and the visiting order. */
+static void bfs(const graph_t *g, int32_t s, pass_t *p)
 {
-    for (int64_t v = 0; v < n; ++v) p->dist[v] = -1;
+    const int64_t *row = g->row;
+    const int32_t *col = g->col;
+    for (int64_t v = 0; v < g->n; ++v) p->dist[v] = -1;
     int64_t head = 0, tail = 0;
     p->dist[s] = 0;
     p->order[tail++] = s;
@@ -162,11 +210,13 @@ static void bfs(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pa
 }
 
 /* sigma_sw = sum of sigma_su over the predecessors u of w (Definition 3:
- * neighbours with d(s,u) = d(s,w) - 1), in BFS order so that every
+ * in-neighbours with d(s,u) = d(s,w) - 1), in BFS order so that every
  * predecessor is final before it is read. */
-static void path_counts(const int64_t *row, const int32_t *col, int64_t n, pass_t *p)
+static void path_counts(const graph_t *g, pass_t *p)
 {
-    for (int64_t v = 0; v < n; ++v) { p->sig[v].m = 0.0; p->sig[v].e = 0; }
+    const int64_t *row = g->rrow;
+    const int32_t *col = g->rcol;
+    for (int64_t v = 0; v < g->n; ++v) { p->sig[v].m = 0.0; p->sig[v].e = 0; }
     int32_t s = p->order[0];
     p->sig[s] = xnum_make(1.0, 0);
     for (int64_t i = 1; i < p->reached; ++i) {
@@ -180,13 +230,16 @@ static void path_counts(const int64_t *row, const int32_t *col, int64_t n, pass_
     }
 }
 
-/* Theorem 1: delta_s(v) = sum over t with v in P_s(t) of
- * (sigma_sv / sigma_st) * (1 + delta_s(t)), evaluated in non-increasing
- * distance (Brandes' second step) so every successor t is final. The source
- * itself is excluded from its own dependency (s != t != v), so delta_s(s) = 0. */
-static void dependencies(const int64_t *row, const int32_t *col, int64_t n, pass_t *p)
+/* Theorem 1: delta_s(v) = sum over t with v in P_s(t) (out-neighbours of v
+ * one level further) of (sigma_sv / sigma_st) * (1 + delta_s(t)), evaluated
+ * in non-increasing distance (Brandes' second step) so every successor t is
+ * final. The source itself is excluded from its own dependency (s != t != v),
+ * so delta_s(s) = 0. */
+static void dependencies(const graph_t *g, pass_t *p)
 {
-    for (int64_t v = 0; v < n; ++v) p->delta[v] = 0.0;
+    const int64_t *row = g->row;
+    const int32_t *col = g->col;
+    for (int64_t v = 0; v < g->n; ++v) p->delta[v] = 0.0;
     for (int64_t i = p->reached - 1; i >= 1; --i) {
         int32_t v = p->order[i];
         double acc = 0.0;
@@ -202,21 +255,21 @@ static void dependencies(const int64_t *row, const int32_t *col, int64_t n, pass
     }
 }
 
-static void brandes_pass(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pass_t *p)
+static void brandes_pass(const graph_t *g, int32_t s, pass_t *p)
 {
-    bfs(n, row, col, s, p);
-    path_counts(row, col, n, p);
-    dependencies(row, col, n, p);
+    bfs(g, s, p);
+    path_counts(g, p);
+    dependencies(g, p);
 }
 
-int oracle_brandes(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
-                   int32_t *dist, double *sig_m, int32_t *sig_e, double *delta)
+static int brandes_g(const graph_t *g, int32_t s, int32_t *dist, double *sig_m, int32_t *sig_e,
+                     double *delta)
 {
-    if (check_graph(n, row, col) || s < 0 || s >= n) return -1;
+    if (s < 0 || s >= g->n) return -1;
     pass_t p;
-    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
-    brandes_pass(n, row, col, s, &p);
-    for (int64_t v = 0; v < n; ++v) {
+    if (pass_alloc(&p, g->n)) { pass_free(&p); return -2; }
+    brandes_pass(g, s, &p);
+    for (int64_t v = 0; v < g->n; ++v) {
         if (dist) dist[v] = p.dist[v];
         if (sig_m) sig_m[v] = p.sig[v].m;
         if (sig_e) sig_e[v] = p.sig[v].e;
@@ -227,31 +280,32 @@ int oracle_brandes(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
 }
 
 /* Exact BC as the sum of source dependencies (Section 3). */
-int oracle_bc_exact(int64_t n, const int64_t *row, const int32_t *col, double *bc)
+static int bc_exact_g(const graph_t *g, double *bc)
 {
-    if (check_graph(n, row, col) || !bc) return -1;
+    if (!bc) return -1;
     pass_t p;
-    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
-    for (int64_t v = 0; v < n; ++v) bc[v] = 0.0;
-    for (int64_t s = 0; s < n; ++s) {
-        brandes_pass(n, row, col, (int32_t)s, &p);
-        for (int64_t v = 0; v < n; ++v) bc[v] += p.delta[v];
+    if (pass_alloc(&p, g->n)) { pass_free(&p); return -2; }
+    for (int64_t v = 0; v < g->n; ++v) bc[v] = 0.0;
+    for (int64_t s = 0; s < g->n; ++s) {
+        brandes_pass(g, (int32_t)s, &p);
+        for (int64_t v = 0; v < g->n; ++v) bc[v] += p.delta[v];
     }
     pass_free(&p);
     return 0;
 }
 
-int oracle_dependencies(int64_t n, const int64_t *row, const int32_t *col,
-                        const int32_t *sources, int64_t k, double *full, double *sum)
+static int dependencies_g(const graph_t *g, const int32_t *sources, int64_t k, double *full,
+                          double *sum)
 {
-    if (check_graph(n, row, col) || k < 0 || (k > 0 && !sources)) return -1;
+    const int64_t n = g->n;
+    if (k < 0 || (k > 0 && !sources)) return -1;
     for (int64_t i = 0; i < k; ++i)
         if (sources[i] < 0 || sources[i] >= n) return -1;
     pass_t p;
     if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
     if (sum) for (int64_t v = 0; v < n; ++v) sum[v] = 0.0;
     for (int64_t i = 0; i < k; ++i) {
-        brandes_pass(n, row, col, sources[i], &p);
+        brandes_pass(g, sources[i], &p);
         for (int64_t v = 0; v < n; ++v) {
             if (full) full[i * n + v] = p.delta[v];
             if (sum) sum[v] += p.delta[v];
@@ -263,6 +317,8 @@ int oracle_dependencies(int64_t n, const int64_t *row, const int32_t *col,
 
 /* -------------------------------------------------------- pair dependency */
 
+/* pu: search from u; pv: search from v over reversed edges, so pv->dist[t] =
+ * d(t, v) and pv->sig[t] = sigma_tv. */
 static void pair_from_passes(int64_t n, int32_t u, int32_t v, const pass_t *pu,
                              const pass_t *pv, double *y)
 {
@@ -278,22 +334,22 @@ static void pair_from_passes(int64_t n, int32_t u, int32_t v, const pass_t *pu,
     }
 }
 
-static void sssp_counts(int64_t n, const int64_t *row, const int32_t *col, int32_t s, pass_t *p)
+static void sssp_counts(const graph_t *g, int32_t s, pass_t *p)
 {
-    bfs(n, row, col, s, p);
-    path_counts(row, col, n, p);
+    bfs(g, s, p);
+    path_counts(g, p);
 }
 
-int oracle_pair_dependency(int64_t n, const int64_t *row, const int32_t *col,
-                           int32_t u, int32_t v, double *y)
+static int pair_dependency_g(const graph_t *g, int32_t u, int32_t v, double *y)
 {
-    if (check_graph(n, row, col) || !y || u < 0 || v < 0 || u >= n || v >= n || u == v)
-        return -1;
+    const int64_t n = g->n;
+    if (!y || u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
+    const graph_t r = reversed(g);
     pass_t pu, pv;
     int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n);
     if (bad) { pass_free(&pu); pass_free(&pv); return -2; }
-    sssp_counts(n, row, col, u, &pu);
-    sssp_counts(n, row, col, v, &pv);
+    sssp_counts(g, u, &pu);
+    sssp_counts(&r, v, &pv);
     pair_from_passes(n, u, v, &pu, &pv, y);
     pass_free(&pu); pass_free(&pv);
     return 0;
@@ -308,13 +364,13 @@ enum { ST_RUNNING = 255, ST_DONE = 0, ST_CAPPED = 1 };
  * dependency on the target; the loop repeats while S <= c*n; the estimate
  * is n*S/k. Targets share the sample stream, so one pass per draw serves all
  * targets that are still running. */
-int oracle_adaptive_source(int64_t n, const int64_t *row, const int32_t *col,
-                           const int32_t *targets, int32_t T, double c, uint64_t seed,
-                           int64_t k_max, double *est, int64_t *samples, double *S,
-                           uint8_t *status)
+static int adaptive_source_g(const graph_t *g, const int32_t *targets, int32_t T, double c,
+                             uint64_t seed, int64_t k_max, double *est, int64_t *samples,
+                             double *S, uint8_t *status)
 {
-    if (check_graph(n, row, col) || T < 0 || (T > 0 && !targets) || !(c >= 1.0) ||
-        k_max < 1 || !est || !samples || !S || !status)
+    const int64_t n = g->n;
+    if (T < 0 || (T > 0 && !targets) || !(c >= 1.0) || k_max < 1 || !est || !samples || !S ||
+        !status)
         return -1;
     for (int32_t i = 0; i < T; ++i)
         if (targets[i] < 0 || targets[i] >= n) return -1;
@@ -325,7 +381,7 @@ int oracle_adaptive_source(int64_t n, const int64_t *row, const int32_t *col,
     int32_t running = T;
     for (int64_t j = 0; running > 0; ++j) {
         int32_t s = oracle_draw_source(seed, j, n);
-        brandes_pass(n, row, col, s, &p);
+        brandes_pass(g, s, &p);
         for (int32_t i = 0; i < T; ++i) {
             if (status[i] != ST_RUNNING) continue;
             S[i] += p.delta[targets[i]];
@@ -345,19 +401,19 @@ int oracle_adaptive_source(int64_t n, const int64_t *row, const int32_t *col,
  * stops once k reaches Lemma 5's sample count eps*(n^2(n-1)/A)^(2/3) with A
  * read as the running estimate n(n-1)S/k, which rearranges to
  * k*S^2 >= eps^3*n^2. */
-int oracle_adaptive_pair(int64_t n, const int64_t *row, const int32_t *col,
-                         const int32_t *targets, int32_t T, int rule, double eps, double c,
-                         uint64_t seed, int64_t k_max, double *est, int64_t *samples,
-                         double *S, uint8_t *status)
+static int adaptive_pair_g(const graph_t *g, const int32_t *targets, int32_t T, int rule,
+                           double eps, double c, uint64_t seed, int64_t k_max, double *est,
+                           int64_t *samples, double *S, uint8_t *status)
 {
-    if (check_graph(n, row, col) || n < 2 || T < 0 || (T > 0 && !targets) || k_max < 1 ||
-        !est || !samples || !S || !status)
+    const int64_t n = g->n;
+    if (n < 2 || T < 0 || (T > 0 && !targets) || k_max < 1 || !est || !samples || !S || !status)
         return -1;
     if (rule == 0 && !(c >= 1.0)) return -1;
     if (rule == 1 && !(eps > 0.0 && eps < 0.5)) return -1;
     if (rule != 0 && rule != 1) return -1;
     for (int32_t i = 0; i < T; ++i)
         if (targets[i] < 0 || targets[i] >= n) return -1;
+    const graph_t r = reversed(g);
     pass_t pu, pv;
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
     int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n);
@@ -369,8 +425,8 @@ int oracle_adaptive_pair(int64_t n, const int64_t *row, const int32_t *col,
     for (int64_t j = 0; running > 0; ++j) {
         int32_t u, v;
         oracle_draw_pair(seed, j, n, &u, &v);
-        sssp_counts(n, row, col, u, &pu);
-        sssp_counts(n, row, col, v, &pv);
+        sssp_counts(g, u, &pu);
+        sssp_counts(&r, v, &pv);
         pair_from_passes(n, u, v, &pu, &pv, y);
         for (int32_t i = 0; i < T; ++i) {
             if (status[i] != ST_RUNNING) continue;
@@ -389,6 +445,116 @@ int oracle_adaptive_pair(int64_t n, const int64_t *row, const int32_t *col,
     return 0;
 }
 
+/* ------------------------------------------------- undirected entry points */
+
+int oracle_brandes(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
+                   int32_t *dist, double *sig_m, int32_t *sig_e, double *delta)
+{
+    if (check_graph(n, row, col)) return -1;
+    const graph_t g = undirected(n, row, col);
+    return brandes_g(&g, s, dist, sig_m, sig_e, delta);
+}
+
+int oracle_bc_exact(int64_t n, const int64_t *row, const int32_t *col, double *bc)
+{
+    if (check_graph(n, row, col)) return -1;
+    const graph_t g = undirected(n, row, col);
+    return bc_exact_g(&g, bc);
+}
+
+int oracle_dependencies(int64_t n, const int64_t *row, const int32_t *col,
+                        const int32_t *sources, int64_t k, double *full, double *sum)
+{
+    if (check_graph(n, row, col)) return -1;
+    const graph_t g = undirected(n, row, col);
+    return dependencies_g(&g, sources, k, full, sum);
+}
+
+int oracle_pair_dependency(int64_t n, const int64_t *row, const int32_t *col,
+                           int32_t u, int32_t v, double *y)
+{
+    if (check_graph(n, row, col)) return -1;
+    const graph_t g = undirected(n, row, col);
+    return pair_dependency_g(&g, u, v, y);
+}
+
+int oracle_adaptive_source(int64_t n, const int64_t *row, const int32_t *col,
+                           const int32_t *targets, int32_t T, double c, uint64_t seed,
+                           int64_t k_max, double *est, int64_t *samples, double *S,
+                           uint8_t *status)
+{
+    if (check_graph(n, row, col)) return -1;
+    const graph_t g = undirected(n, row, col);
+    return adaptive_source_g(&g, targets, T, c, seed, k_max, est, samples, S, status);
+}
+
+int oracle_adaptive_pair(int64_t n, const int64_t *row, const int32_t *col,
+                         const int32_t *targets, int32_t T, int rule, double eps, double c,
+                         uint64_t seed, int64_t k_max, double *est, int64_t *samples,
+                         double *S, uint8_t *status)
+{
+    if (check_graph(n, row, col)) return -1;
+    const graph_t g = undirected(n, row, col);
+    return adaptive_pair_g(&g, targets, T, rule, eps, c, seed, k_max, est, samples, S, status);
+}
+
+/* --------------------------------------------------- directed entry points
+ * row/col hold out-neighbours; the in-neighbour rows are built here. */
+
+#define WITH_DIRECTED(n, row, col, CALL)                                           \
+    do {                                                                           \
+        if (check_graph(n, row, col)) return -1;                                   \
+        int64_t *trow_ = NULL;                                                     \
+        int32_t *tcol_ = NULL;                                                     \
+        if (transpose(n, row, col, &trow_, &tcol_)) return -2;                     \
+        const graph_t g = {n, row, col, trow_, tcol_};                             \
+        const int rc_ = (CALL);                                                    \
+        free(trow_);                                                               \
+        free(tcol_);                                                               \
+        return rc_;                                                                \
+    } while (0)
+
+int oracle_brandes_directed(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
+                            int32_t *dist, double *sig_m, int32_t *sig_e, double *delta)
+{
+    WITH_DIRECTED(n, row, col, brandes_g(&g, s, dist, sig_m, sig_e, delta));
+}
+
+int oracle_bc_exact_directed(int64_t n, const int64_t *row, const int32_t *col, double *bc)
+{
+    WITH_DIRECTED(n, row, col, bc_exact_g(&g, bc));
+}
+
+int oracle_dependencies_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                 const int32_t *sources, int64_t k, double *full, double *sum)
+{
+    WITH_DIRECTED(n, row, col, dependencies_g(&g, sources, k, full, sum));
+}
+
+int oracle_pair_dependency_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                    int32_t u, int32_t v, double *y)
+{
+    WITH_DIRECTED(n, row, col, pair_dependency_g(&g, u, v, y));
+}
+
+int oracle_adaptive_source_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                    const int32_t *targets, int32_t T, double c, uint64_t seed,
+                                    int64_t k_max, double *est, int64_t *samples, double *S,
+                                    uint8_t *status)
+{
+    WITH_DIRECTED(n, row, col,
+                  adaptive_source_g(&g, targets, T, c, seed, k_max, est, samples, S, status));
+}
+
+int oracle_adaptive_pair_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                  const int32_t *targets, int32_t T, int rule, double eps,
+                                  double c, uint64_t seed, int64_t k_max, double *est,
+                                  int64_t *samples, double *S, uint8_t *status)
+{
+    WITH_DIRECTED(n, row, col, adaptive_pair_g(&g, targets, T, rule, eps, c, seed, k_max, est,
+                                               samples, S, status));
+}
+
 /* ------------------------------------------------------------ work counts */
 
 int oracle_source_work(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
@@ -397,7 +563,8 @@ int oracle_source_work(int64_t n, const int64_t *row, const int32_t *col, int32_
     if (check_graph(n, row, col) || s < 0 || s >= n) return -1;
     pass_t p;
     if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
-    bfs(n, row, col, s, &p);
+    const graph_t g = undirected(n, row, col);
+    bfs(&g, s, &p);
     int64_t deg = 0, dag = 0;
     for (int64_t i = 0; i < p.reached; ++i) {
         int32_t u = p.order[i];
@@ -418,7 +585,8 @@ int oracle_pair_work(int64_t n, const int64_t *row, const int32_t *col, int32_t 
     if (check_graph(n, row, col) || u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
     pass_t p;
     if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
-    bfs(n, row, col, u, &p);
+    const graph_t g = undirected(n, row, col);
+    bfs(&g, u, &p);
     int32_t limit = p.dist[v] < 0 ? 0x7fffffff : p.dist[v];
     int64_t cnt = 0;
     for (int64_t i = 0; i < p.reached; ++i) {

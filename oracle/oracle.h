@@ -82,6 +82,29 @@ int oracle_adaptive_pair(int64_t n, const int64_t *row, const int32_t *col,
                          uint64_t seed, int64_t k_max, double *est, int64_t *samples,
                          double *S, uint8_t *status);
 
+/* Directed graphs (Definition 1 over ordered pairs, shortest paths following
+ * edge directions): row/col hold each vertex's out-neighbours (rows sorted,
+ * no self-loops or duplicates); the in-neighbour rows are built inside. The
+ * search and Theorem 1's successor sums follow out-edges, the path counts of
+ * Definition 3 sum over in-neighbours, and a pair's sigma_tv comes from a
+ * search from v over reversed edges. Arguments and results as in the
+ * undirected functions above. */
+int oracle_brandes_directed(int64_t n, const int64_t *row, const int32_t *col, int32_t s,
+                            int32_t *dist, double *sig_m, int32_t *sig_e, double *delta);
+int oracle_bc_exact_directed(int64_t n, const int64_t *row, const int32_t *col, double *bc);
+int oracle_dependencies_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                 const int32_t *sources, int64_t k, double *full, double *sum);
+int oracle_pair_dependency_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                    int32_t u, int32_t v, double *y);
+int oracle_adaptive_source_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                    const int32_t *targets, int32_t T, double c, uint64_t seed,
+                                    int64_t k_max, double *est, int64_t *samples, double *S,
+                                    uint8_t *status);
+int oracle_adaptive_pair_directed(int64_t n, const int64_t *row, const int32_t *col,
+                                  const int32_t *targets, int32_t T, int rule, double eps,
+                                  double c, uint64_t seed, int64_t k_max, double *est,
+                                  int64_t *samples, double *S, uint8_t *status);
+
 /* Work counters for the throughput metric: for source s, the number of
  * vertices reached and the undirected edges of s's component; for a pair
  * (u, v), the undirected edges with an endpoint at distance < d(u,v)
