@@ -150,6 +150,15 @@ typedef struct {
  * row_is_i64 = 0 takes int32 row offsets (nnz < 2^31). */
 bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream,
                           bc_graph **out);
+/* A directed graph (Definition 1 over ordered pairs, paths following arc
+ * directions): csr->row / csr->col list each vertex's out-neighbours (rows
+ * sorted ascending, no self-loops or repeated arcs, 0 <= col < n; no symmetry
+ * required). The library builds the in-neighbour rows: the search and
+ * Theorem 1's successor sums follow out-arcs, the path counts of Definition 3
+ * sum over in-neighbours. Every compute call serves the handle; the query
+ * server takes undirected graphs. */
+bc_status bc_graph_create_directed(const bc_csr *csr, const bc_allocator *alloc,
+                                   void *hip_stream, bc_graph **out);
 void bc_graph_destroy(bc_graph *g);
 bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
 /* Autotuner: times candidate plans on one seeded batch of sources each and

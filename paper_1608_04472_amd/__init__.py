@@ -38,7 +38,8 @@ BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED, BC_SCHE
     0, 1, 2, 3, 4
 
 EXPORTS = [
-    "bc_graph_create", "bc_graph_destroy", "bc_graph_set_stream", "bc_graph_set_io",
+    "bc_graph_create", "bc_graph_create_directed", "bc_graph_destroy", "bc_graph_set_stream",
+    "bc_graph_set_io",
     "bc_graph_configure", "bc_graph_tune", "bc_graph_plan",
     "bc_graph_info", "bc_exact", "bc_dependencies", "bc_dependencies_noalloc",
     "bc_pair_dependencies",
@@ -187,6 +188,7 @@ def load_library(path: str | None = None):
     lib.bc_server_destroy.argtypes = [V]
     sigs = {
         "bc_graph_create": [c.POINTER(_Csr), V, V, c.POINTER(V)],
+        "bc_graph_create_directed": [c.POINTER(_Csr), V, V, c.POINTER(V)],
         "bc_graph_set_stream": [V, V],
         "bc_graph_set_io": [V, c.c_int32],
         "bc_graph_configure": [V, c.POINTER(_Config)],
@@ -258,15 +260,17 @@ def _stream():
 
 class Graph:
     """Handle to a device-resident CSR graph (bc_graph). row may be int64 or
-    int32 offsets; allocator 'torch' (default) or 'hip'."""
+    int32 offsets; allocator 'torch' (default) or 'hip'; directed=True reads
+    row/col as out-neighbour lists (bc_graph_create_directed)."""
 
-    def __init__(self, row, col, allocator="torch"):
+    def __init__(self, row, col, allocator="torch", directed=False):
         lib = load_library()
         csr, keep = _csr_arrays(row, col)
         h = ctypes.c_void_p()
         self._h = None
-        _check(lib.bc_graph_create(ctypes.byref(csr), _allocator(allocator), _stream(),
-                                   ctypes.byref(h)))
+        create = lib.bc_graph_create_directed if directed else lib.bc_graph_create
+        _check(create(ctypes.byref(csr), _allocator(allocator), _stream(), ctypes.byref(h)))
+        self.directed = bool(directed)
         self._h = h
         self.n = int(csr.n)
         self.nnz = int(csr.nnz)

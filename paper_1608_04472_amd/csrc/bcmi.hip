@@ -229,6 +229,11 @@ struct bc_graph {
     int32_t io = BC_IO_DEVICE;   // where compute calls' arrays live
     DBuf<int64_t> row;
     DBuf<int32_t> col;
+    bool directed = false;    // row/col hold out-neighbours; rrow/rcol in-neighbours
+    DBuf<int64_t> rrow_buf;
+    DBuf<int32_t> rcol_buf;
+    const int64_t *rrow() const { return directed ? rrow_buf.p : row.p; }
+    const int32_t *rcol() const { return directed ? rcol_buf.p : col.p; }
     bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0};   // sampler_batch last
     Work own;
     Work *w = &own;
@@ -264,6 +269,7 @@ struct bc_graph {
     void release_all()
     {
         row.release(); col.release();
+        rrow_buf.release(); rcol_buf.release();
         skey.release();
         own.release();
         prof_dev.release();
@@ -551,6 +557,8 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     BatchArgs a;
     a.row = g->row.p;
     a.col = g->col.p;
+    a.rrow = g->rrow();
+    a.rcol = g->rcol();
     a.n = g->n;
     a.logW = p.logW;
     a.B = p.B;
@@ -754,8 +762,8 @@ std::vector<int64_t> run_single(bc_graph *g, const int32_t *src_dev, bool forwar
         read_ctl(g);
         const int64_t q2 = (int64_t)g->w->h_ctl[CTL_TAIL];
         if (q2 == q1) break;
-        launch(s, grid_for(q2 - q1), k_ss_sigma, (const int64_t *)g->row.p,
-               (const int32_t *)g->col.p, (const int32_t *)g->w->ss_d.p, g->w->ss_sig.p,
+        launch(s, grid_for(q2 - q1), k_ss_sigma, g->rrow(), g->rcol(),
+               (const int32_t *)g->w->ss_d.p, g->w->ss_sig.p,
                (const int32_t *)g->w->ss_q.p, q1, q2, (int32_t)level, g->w->ctl.p);
         off.push_back(q2);
     }
@@ -834,6 +842,8 @@ PairArgs make_pair_args(bc_graph *g, int B, bool ext, int nvalid, bool pair)
     PairArgs a;
     a.row = g->row.p;
     a.col = g->col.p;
+    a.rrow = g->rrow();
+    a.rcol = g->rcol();
     a.n = (uint32_t)g->n;
     a.B = B;
     a.lv = g->w->lv.p;
@@ -1080,8 +1090,9 @@ void ensure_source_keys(bc_graph *g)
         int32_t depth = 0;
         for (int32_t level = 1;; ++level) {
             HIPX(hipMemsetAsync(grew.p, 0, 8, s));
-            launch(s, grid_for(n), k_key_level, (const int64_t *)g->row.p, (const int32_t *)g->col.p,
-                   n, all, level, (const uint8_t *)f, fn, seen.p, g->skey.p, grew.p);
+            // a vertex joins a landmark's next level from an in-neighbour
+            launch(s, grid_for(n), k_key_level, g->rrow(), g->rcol(), n, all, level,
+                   (const uint8_t *)f, fn, seen.p, g->skey.p, grew.p);
             unsigned long long h = 0;
             HIPX(hipMemcpyAsync(&h, grew.p, 8, hipMemcpyDeviceToHost, s));
             HIPX(hipStreamSynchronize(s));
@@ -1564,7 +1575,7 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
 // ---------------------------------------------------------- CSR validation
 
 template <class R>
-void validate_csr(const bc_csr *c, const R *row)
+void validate_csr(const bc_csr *c, const R *row, bool symmetric)
 {
     const int64_t n = c->n, nnz = c->nnz;
     need(row[0] == 0, "row[0] must be 0");
@@ -1579,6 +1590,7 @@ void validate_csr(const bc_csr *c, const R *row)
             need(i == b || c->col[i - 1] < w, "rows must be sorted ascending without duplicates");
         }
     }
+    if (!symmetric) return;
     // symmetry: every (v, w) needs (w, v)
     for (int64_t v = 0; v < n; ++v) {
         for (int64_t i = (int64_t)row[v]; i < (int64_t)row[v + 1]; ++i) {
@@ -1649,10 +1661,16 @@ extern "C" {
 
 const char *bc_last_error(void) { return tl_error.c_str(); }
 
-bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream,
-                          bc_graph **out)
+}  // extern "C"
+
+namespace {
+
+// Validate a host CSR (symmetric unless directed) and build the handle: the
+// device copy of the rows and, for a directed graph, of its in-neighbour rows.
+void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream, bc_graph **out,
+                  bool directed)
 {
-    return guarded([&] {
+    {
         need(csr && out, "null argument");
         need(csr->n >= 1 && csr->n < 0x7fffffffll, "n must be in [1, 2^31 - 1)");
         need(csr->nnz >= 0 && csr->row && (csr->col || csr->nnz == 0), "bad CSR arrays");
@@ -1660,12 +1678,12 @@ bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hi
         std::vector<int64_t> row((size_t)csr->n + 1);
         if (csr->row_is_i64) {
             const int64_t *r = (const int64_t *)csr->row;
-            validate_csr(csr, r);
+            validate_csr(csr, r, !directed);
             std::copy(r, r + csr->n + 1, row.begin());
         } else {
             need(csr->nnz < 0x7fffffffll, "int32 row offsets need nnz < 2^31");
             const int32_t *r = (const int32_t *)csr->row;
-            validate_csr(csr, r);
+            validate_csr(csr, r, !directed);
             std::copy(r, r + csr->n + 1, row.begin());
         }
         bc_graph *g = new bc_graph();
@@ -1710,13 +1728,48 @@ bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hi
             HIPX(hipMemcpy(g->row.p, row.data(), row.size() * 8, hipMemcpyHostToDevice));
             if (csr->nnz)
                 HIPX(hipMemcpy(g->col.p, csr->col, (size_t)csr->nnz * 4, hipMemcpyHostToDevice));
+            if (directed) {
+                // in-neighbour rows, sorted ascending (sources visited in order)
+                const int64_t n = csr->n;
+                std::vector<int64_t> trow((size_t)n + 1, 0), fill((size_t)n);
+                std::vector<int32_t> tcol((size_t)std::max<int64_t>(csr->nnz, 1));
+                for (int64_t e = 0; e < csr->nnz; ++e) trow[(size_t)csr->col[e] + 1] += 1;
+                for (int64_t v = 0; v < n; ++v) trow[(size_t)v + 1] += trow[(size_t)v];
+                for (int64_t v = 0; v < n; ++v) fill[(size_t)v] = trow[(size_t)v];
+                for (int64_t u = 0; u < n; ++u)
+                    for (int64_t e = row[(size_t)u]; e < row[(size_t)u + 1]; ++e)
+                        tcol[(size_t)fill[(size_t)csr->col[e]]++] = (int32_t)u;
+                g->directed = true;
+                g->rrow_buf.ensure(trow.size());
+                g->rcol_buf.ensure((size_t)csr->nnz);
+                HIPX(hipMemcpy(g->rrow_buf.p, trow.data(), trow.size() * 8, hipMemcpyHostToDevice));
+                if (csr->nnz)
+                    HIPX(hipMemcpy(g->rcol_buf.p, tcol.data(), (size_t)csr->nnz * 4,
+                                   hipMemcpyHostToDevice));
+            }
         } catch (...) {
             g->release_all();
             delete g;
             throw;
         }
         *out = g;
-    });
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream,
+                          bc_graph **out)
+{
+    return guarded([&] { create_graph(csr, alloc, hip_stream, out, false); });
+}
+
+bc_status bc_graph_create_directed(const bc_csr *csr, const bc_allocator *alloc,
+                                   void *hip_stream, bc_graph **out)
+{
+    return guarded([&] { create_graph(csr, alloc, hip_stream, out, true); });
 }
 
 void bc_graph_destroy(bc_graph *g)

@@ -103,8 +103,10 @@ __device__ __forceinline__ int64_t wave_append(bool want, unsigned long long *ta
 }
 
 struct BatchArgs {
-    const int64_t *row;
+    const int64_t *row;   // out-neighbours (the search, Theorem 1's successors)
     const int32_t *col;
+    const int64_t *rrow;  // in-neighbours (Definition 3's predecessors); the same
+    const int32_t *rcol;  // arrays as row/col for an undirected graph
     int64_t n;
     int32_t logW;        // words per batch = 1 << logW
     int32_t B;           // sources per batch = 64 << logW
@@ -304,8 +306,12 @@ __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t
 // neighbours and stops early once all its unvisited sources are found
 // (membership only: the path counts are pulled afterwards from all parents;
 // the level's record is built from the words by k_level_*).
-__global__ void k_discover_bottomup(BatchArgs a, const uint64_t *cur, uint64_t *nxt)
+__global__ void k_discover_bottomup(BatchArgs a_in, const uint64_t *cur, uint64_t *nxt)
 {
+    // a vertex looks for frontier predecessors: its in-neighbours
+    BatchArgs a = a_in;
+    a.row = a_in.rrow;
+    a.col = a_in.rcol;
     const int64_t total = a.n << a.logW;
     const uint32_t wmask = (1u << a.logW) - 1u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -515,8 +521,8 @@ constexpr int kHub = 256;
 // segment are this lane's fm and sx) in ascending order. fk[q] receives the
 // q-th neighbour's overlap with the wave-uniform `want` (0 for an unused
 // slot). Every lane loads, so the loads are straight-line code and all of a
-// batch is in flight together: lanes outside the overlap read the segment's
-// first slot (always valid) and add_batch discards it.
+// batch is in flight together: lanes outside the overlap read the first
+// overlapping lane's slot (always valid) and add_batch discards it.
 template <bool kExt, int kIF = kInFlight>
 __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uint64_t sx,
                                             uint64_t want, uint64_t &bal, double (&vm)[kIF],
@@ -535,7 +541,12 @@ __device__ __forceinline__ void issue_batch(const BatchArgs &a, uint64_t fm, uin
             const uint64_t sk = lane_read_u64(sx, k);
             fk[q] = mk & want;
             units += __popcll(fk[q]);
-            const uint64_t o = sk + (lane_in(fk[q]) ? slot_rank(mk) : 0u);
+            // lanes outside the overlap read the first overlapping lane's slot,
+            // a line the overlap needs anyway (the segment's first slot may sit
+            // in a line no overlapping lane uses)
+            const uint64_t low = fk[q] & (~fk[q] + 1ull);
+            const uint32_t first = (uint32_t)__popcll(mk & (low - 1ull));
+            const uint64_t o = sk + (lane_in(fk[q]) ? slot_rank(mk) : first);
             vm[q] = a.sig[o];
             if (kExt) ve[q] = a.sige[o];
         }
@@ -968,7 +979,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
                                                        const uint64_t *cur, const uint64_t *sgcur,
                                                        uint64_t *sgnxt)
 {
-    pull_tiles<kExt, false, false>(a, e0, e1, cur, sgcur, nullptr, sgnxt);
+    // predecessors are in-neighbours
+    BatchArgs b = a;
+    b.row = a.rrow;
+    b.col = a.rcol;
+    pull_tiles<kExt, false, false>(b, e0, e1, cur, sgcur, nullptr, sgnxt);
 }
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
@@ -1315,8 +1330,10 @@ __global__ void k_stop_finish(StopArgs s, double scale, double *est, int64_t *sa
 // indices o = b*n + v (32-bit), level by level.
 
 struct PairArgs {
-    const int64_t *row;
+    const int64_t *row;   // out-neighbours
     const int32_t *col;
+    const int64_t *rrow;  // in-neighbours (the same arrays when undirected)
+    const int32_t *rcol;
     uint32_t n;
     int32_t B;
     int32_t *lv;         // [B][n] level, -1 = unreached
@@ -1429,9 +1446,14 @@ __device__ __forceinline__ unsigned long long p_topdown(const PairArgs &a, int64
 // neighbours one level up (ascending CSR order), four neighbour loads in
 // flight. Adds this lane's pair and DAG-edge counts to ua, ub.
 template <bool kExt>
-__device__ __forceinline__ void p_sigma(const PairArgs &a, int64_t e0, int64_t e1, int32_t level,
-                                        unsigned long long &ua, unsigned long long &ub)
+__device__ __forceinline__ void p_sigma(const PairArgs &a_in, int64_t e0, int64_t e1,
+                                        int32_t level, unsigned long long &ua,
+                                        unsigned long long &ub)
 {
+    // predecessors are in-neighbours
+    PairArgs a = a_in;
+    a.row = a_in.rrow;
+    a.col = a_in.rcol;
     for (int64_t i = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < e1;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t o = a.rec[i];
