@@ -213,12 +213,17 @@ __device__ __forceinline__ XNum xnorm(double m, int32_t e)
     return r;
 }
 
+// Fields are selected one by one: a select of the whole struct (or a return
+// of one of several structs) is lowered through a stack slot.
 __device__ __forceinline__ XNum xadd(XNum a, XNum b)
 {
-    if (a.m == 0.0) return b;
-    if (b.m == 0.0) return a;
     const int32_t e = a.e > b.e ? a.e : b.e;
-    return xnorm(ldexp(a.m, a.e - e) + ldexp(b.m, b.e - e), e);
+    const XNum s = xnorm(ldexp(a.m, a.e - e) + ldexp(b.m, b.e - e), e);
+    const bool az = a.m == 0.0, bz = b.m == 0.0;
+    XNum r;
+    r.m = az ? b.m : (bz ? a.m : s.m);
+    r.e = az ? b.e : (bz ? a.e : s.e);
+    return r;
 }
 
 // ------------------------------------------------------------------ level 0
@@ -567,7 +572,8 @@ __device__ __forceinline__ void add_batch(const double (&vm)[kIF], const int32_t
         if (kExt) {
             if (fk[q]) {
                 const XNum y = xadd(accx, XNum{vm[q], ve[q]});
-                accx = on ? y : accx;
+                accx.m = on ? y.m : accx.m;
+                accx.e = on ? y.e : accx.e;
             }
         } else {
             accp += on ? vm[q] : 0.0;
