@@ -335,20 +335,34 @@ def pair_leg(args, bc, gg, G, g, dev):
     import numpy as np
     import torch
     targets = torch.from_numpy(gg.top_degree(g, args.pair_targets)).to(dev)
-    if args.pair_sampler_batch:
-        G.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, args.pair_sampler_batch)
-    torch.cuda.synchronize()
-    G.profile(True)
-    t = time.perf_counter()
-    est, k, S, stt = bc.adaptive_pair(G, targets, bc.BC_PAIR_EPS, args.pair_eps, 1.0,
-                                      args.seed, 1 << 20)
-    torch.cuda.synchronize()
-    pt = time.perf_counter() - t
-    kern = G.profile_read()
-    G.profile(False)
-    pst = G.stats()
+    search = {"auto": bc.BC_PAIR_SEARCH_AUTO, "one": bc.BC_PAIR_SEARCH_ONE_SIDED,
+              "bidir": bc.BC_PAIR_SEARCH_BIDIRECTIONAL}
+
+    def run(mode):
+        G.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, args.pair_sampler_batch, search[mode])
+        G.plan()                      # the tuned plan from the cache, outside the timing
+        torch.cuda.synchronize()
+        G.profile(True)
+        t = time.perf_counter()
+        res = bc.adaptive_pair(G, targets, bc.BC_PAIR_EPS, args.pair_eps, 1.0, args.seed, 1 << 20)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        kern = G.profile_read()
+        G.profile(False)
+        return res, el, kern, G.stats()
+
+    one = None
+    if args.pair_search == "auto":
+        # the one-sided search on the same stream, for comparison
+        (_, k1, _, _), t1, _, st1 = run("one")
+        one = {"ms": 1e3 * t1, "pairs_per_s": int(st1["samples_executed"]) / t1,
+               "samples_executed": int(st1["samples_executed"])}
+    (est, k, S, stt), pt, kern, pst = run(args.pair_search)
+    G.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, 0, 0)
     ex = int(pst["samples_executed"])
     kk = k.cpu().numpy()
+    if one is not None:
+        assert np.array_equal(kk, k1.cpu().numpy()), "pair searches disagree on samples used"
     # pair-search edges on a sample of the executed pairs: distances from u by
     # the library (pinned to the oracle), edges counted on the host
     m = min(args.pair_work_sample, ex)
@@ -366,7 +380,12 @@ def pair_leg(args, bc, gg, G, g, dev):
     mean_work = float(np.mean(work))
     dom = max(kern, key=lambda x: x["ms"])
     ach = dom["algo_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    bi = next(x for x in kern if x["name"] == "bidir_pair")
     out = {"targets": args.pair_targets, "eps": args.pair_eps, "ms": 1e3 * pt,
+           "pair_search": {1: "one-sided", 2: "bidirectional"}.get(int(pst["pair_search"]), "?"),
+           "one_sided": one,
+           "bidir_arcs_walked_per_pair": bi["units_b"] / ex if bi["launches"] else None,
+           "bidir_vertices_found_per_pair": bi["units_a"] / ex if bi["launches"] else None,
            "samples_executed": ex, "samples_used_max": int(kk.max()),
            "samples_used_min": int(kk.min()), "pairs_per_s": ex / pt,
            "rounds": int(pst["batches"]), "capped": int((stt.cpu().numpy() == bc.BC_CAPPED).sum()),
@@ -376,8 +395,18 @@ def pair_leg(args, bc, gg, G, g, dev):
            "gteps": mean_work * ex / pt / 1e9,
            "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}}
-    log("pair leg: %.1f ms, %d pairs executed (%.0f pairs/s), %.2f GTEPS (pair-search edges)" % (
-        out["ms"], ex, out["pairs_per_s"], out["gteps"]))
+    log("pair leg (%s): %.1f ms, %d pairs executed (%.0f pairs/s), %.2f GTEPS (one-sided "
+        "pair-search edges)" % (out["pair_search"], out["ms"], ex, out["pairs_per_s"],
+                                out["gteps"]))
+    if bi["launches"]:
+        log("  bidir_pair: %d launches %.1f ms, %.0f arcs walked and %.0f vertices found per pair"
+            " (one-sided search: %.0f edges), %.1f GB/s algorithmic" % (
+                bi["launches"], bi["ms"], out["bidir_arcs_walked_per_pair"],
+                out["bidir_vertices_found_per_pair"], mean_work,
+                bi["algo_bytes"] / (bi["ms"] * 1e-3) / 1e9 if bi["ms"] > 0 else 0.0))
+    if one is not None:
+        log("  one-sided on the same stream: %.1f ms (%.0f pairs/s)" % (one["ms"],
+                                                                      one["pairs_per_s"]))
     return out
 
 
@@ -401,6 +430,8 @@ def main():
                     help="executed pairs whose search edges are counted for the pair GTEPS")
     ap.add_argument("--pair-sampler-batch", type=int, default=0,
                     help="samples per pair-sampler round (0 = the library's default)")
+    ap.add_argument("--pair-search", default="auto", choices=["auto", "one", "bidir"],
+                    help="pair samples' search; auto also times the one-sided one")
     ap.add_argument("--no-pair", action="store_true")
     ap.add_argument("--legs", default="c1,c2,c4,c5",
                     help="other workloads to measure (comma list of c1, c2, c4, c5; '' = none)")

@@ -118,7 +118,22 @@ typedef struct {
                               2048 pairs). A round
                               runs ahead of the stop rule by at most its width:
                               results do not depend on it. */
+    int32_t pair_search;   /* bc_pair_search: how pair samples (bc_adaptive_pair,
+                              bc_pair_dependencies) find their shortest paths */
 } bc_config;
+
+/* Pair samples: the search from u that stops once v's level is complete
+ * (Section 6.2), run by the engine the schedule picks, or a balanced search
+ * from both ends, one workgroup per pair (the side with fewer frontier arcs
+ * grows until the two sides meet; the counts on the shortest paths are then
+ * completed by one sweep per side). AUTO takes the bidirectional search; a
+ * batch whose path counts reach 2^1000 in it is run one-sided. Values are
+ * identical either way up to FP64 summation order. */
+typedef enum {
+    BC_PAIR_SEARCH_AUTO = 0,
+    BC_PAIR_SEARCH_ONE_SIDED = 1,
+    BC_PAIR_SEARCH_BIDIRECTIONAL = 2
+} bc_pair_search;
 
 /* Host CSR. row has n+1 entries, int64 if row_is_i64 else int32. */
 typedef struct {
@@ -210,7 +225,9 @@ bc_status bc_adaptive_source(bc_graph *g, const int32_t *targets, int32_t T, dou
 /* Adaptive pair sampling (Algorithm 1) for T targets sharing one stream.
  * Per target: S = 0, k = 0; repeat { draw ordered pair (u, v), u != v;
  * S += sigma_uv(t)/sigma_uv; k += 1 } until the rule stops or k = k_max;
- * est = n(n-1)*S/k. The pair's search stops once v's level is complete.
+ * est = n(n-1)*S/k. The pair's search stops once v's level is complete
+ * (one-sided), or once the searches from u and from v meet (bidirectional;
+ * bc_config.pair_search).
  * rule BC_PAIR_ALG1 needs c >= 1; BC_PAIR_EPS needs 0 < eps < 1/2. Outputs as
  * in bc_adaptive_source. */
 bc_status bc_adaptive_pair(bc_graph *g, const int32_t *targets, int32_t T, int32_t rule,
@@ -239,7 +256,8 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
                                   int32_t out_mode, double *out);
 
 /* Pair dependencies of k given pairs: out[i*n + t] = sigma_{u_i v_i}(t) /
- * sigma_{u_i v_i} (0 for t in {u_i, v_i} or when v_i is unreachable).
+ * sigma_{u_i v_i} (0 for t in {u_i, v_i} or when v_i is unreachable), by the
+ * search bc_config.pair_search selects.
  * us, vs: k int32 each, u_i != v_i. out: k*n doubles (device). */
 bc_status bc_pair_dependencies(bc_graph *g, const int32_t *us, const int32_t *vs, int64_t k,
                                double *out);
@@ -260,7 +278,9 @@ typedef struct {
     int32_t extended;
     int32_t batch_width;
     int32_t schedule;      /* bc_schedule that ran (never BC_SCHED_AUTO) */
-    int32_t reserved;
+    int32_t pair_search;   /* pair samples: BC_PAIR_SEARCH_BIDIRECTIONAL when every
+                              batch took the two-sided search, ONE_SIDED when any
+                              ran one-sided, 0 for source samples */
 } bc_stats;
 bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
 
@@ -282,6 +302,11 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *                count write) + 8 per units_b (count read)
  *   pair_backward: its persistent backward loop, bytes as backward
  *   level_record: 8 per (vertex, word) read + 36 per record entry written
+ *   bidir_pair : the two-sided pair search (one launch per batch of pairs):
+ *                units_a = vertices found by either side, 36 each (row
+ *                bounds, stamp, list entry, path count); units_b = arcs
+ *                walked by its expansions, count sums and sweeps, 12 each
+ *                (head, head's stamp)
  * Enabling resets the accumulators. Profiling adds one event pair per launch
  * and one counter update per wavefront. */
 typedef struct {

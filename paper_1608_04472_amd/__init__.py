@@ -36,6 +36,7 @@ BC_IO_DEVICE, BC_IO_HOST = 0, 1
 BC_PAIR_ALG1, BC_PAIR_EPS = 0, 1
 BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED, BC_SCHED_TUNED = \
     0, 1, 2, 3, 4
+BC_PAIR_SEARCH_AUTO, BC_PAIR_SEARCH_ONE_SIDED, BC_PAIR_SEARCH_BIDIRECTIONAL = 0, 1, 2
 
 EXPORTS = [
     "bc_graph_create", "bc_graph_create_directed", "bc_graph_destroy", "bc_graph_set_stream",
@@ -78,14 +79,15 @@ class _Csr(ctypes.Structure):
 class _Config(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("bottom_up", ctypes.c_double), ("split_entries", ctypes.c_int64),
-                ("level_loop", ctypes.c_int32), ("sampler_batch", ctypes.c_int32)]
+                ("level_loop", ctypes.c_int32), ("sampler_batch", ctypes.c_int32),
+                ("pair_search", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("samples_executed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("levels", ctypes.c_int64), ("extended", ctypes.c_int32),
                 ("batch_width", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("pair_search", ctypes.c_int32)]
 
 
 class _KProf(ctypes.Structure):
@@ -290,9 +292,9 @@ class Graph:
         return self._h
 
     def configure(self, schedule=BC_SCHED_AUTO, batch=0, bottom_up=0.0, split_entries=0,
-                  level_loop=0, sampler_batch=0):
+                  level_loop=0, sampler_batch=0, pair_search=0):
         cfg = _Config(int(schedule), int(batch), float(bottom_up), int(split_entries),
-                      int(level_loop), int(sampler_batch))
+                      int(level_loop), int(sampler_batch), int(pair_search))
         _check(_lib.bc_graph_configure(self.handle, ctypes.byref(cfg)))
 
     def tune(self):

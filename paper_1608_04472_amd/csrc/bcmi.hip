@@ -11,6 +11,7 @@
 // The host reads one 64-byte control block per level (queue tail, flags).
 #include "../../include/bcmi.h"
 #include "kernels.hpp"
+#include "bidir.hpp"
 
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
@@ -192,6 +193,14 @@ struct Work {
     DBuf<int32_t> oidx_in, operm, lane_row;
     DBuf<int32_t> draw_src, draw_dst;   // a round's draws in draw order
     DBuf<uint8_t> sort_tmp;
+    // two-sided pair search: per-slot stamps, counts, lists and level starts
+    // of both sides ([2][slots][n], level starts [2][slots][n + 2])
+    DBuf<uint64_t> bst;
+    DBuf<double> bval;
+    DBuf<int32_t> bq, blo;
+    int32_t bslots = 0;
+    int64_t bn = 0;
+    uint32_t bepoch = 0;   // epochs up to this one are used in every slot
     unsigned long long *h_ctl = nullptr;  // pinned mirror of ctl
     // largest level record (entries) a batch may grow to; 0 = no limit. A
     // server sets it from its budget; a batch that would need more raises
@@ -216,6 +225,10 @@ struct Work {
         ss_d.release(); ss_q.release(); ss_sig.release(); ss_dlt.release(); probe_src.release();
         okey_in.release(); okey_out.release(); oidx_in.release(); operm.release();
         lane_row.release(); sort_tmp.release(); draw_src.release(); draw_dst.release();
+        bst.release(); bval.release(); bq.release(); blo.release();
+        bslots = 0;
+        bn = 0;
+        bepoch = 0;
         if (h_ctl) (void)hipHostFree(h_ctl);
         h_ctl = nullptr;
     }
@@ -234,7 +247,7 @@ struct bc_graph {
     DBuf<int32_t> rcol_buf;
     const int64_t *rrow() const { return directed ? rrow_buf.p : row.p; }
     const int32_t *rcol() const { return directed ? rcol_buf.p : col.p; }
-    bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0};   // sampler_batch last
+    bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0, BC_PAIR_SEARCH_AUTO};
     Work own;
     Work *w = &own;
     int64_t cap_hint = 0;
@@ -249,6 +262,7 @@ struct bc_graph {
     bool timed = false;       // a tuning candidate is running against `deadline`
     std::chrono::steady_clock::time_point deadline{};
     bool ext_sticky = false;  // an earlier batch on this graph needed extended counts
+    bool bidir_off = false;   // a two-sided pair search here reached 2^1000
     // lane-order key: distances to up to kLandmarks highest-degree vertices
     std::vector<int32_t> landmarks;
     DBuf<uint64_t> skey;
@@ -1062,6 +1076,104 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
     }
 }
 
+// ------------------------------------------------------ two-sided pair search
+
+// Pairs in flight at once: one workgroup and one slot of per-vertex state each.
+constexpr int kBiSlotsMax = 2048;
+// pairs per launch of bc_pair_dependencies' two-sided search
+constexpr int64_t kBiChunk = 1 << 16;
+
+size_t bidir_slot_bytes(int64_t n)
+{
+    return (size_t)n * 2 * (8 + 8 + 4) + (size_t)(n + 2) * 2 * 4;
+}
+
+// Pair samples take the two-sided search unless the caller asked for the
+// one-sided one or its path counts once reached 2^1000 on this graph.
+bool use_bidir(const bc_graph *g)
+{
+    return g->cfg.pair_search != BC_PAIR_SEARCH_ONE_SIDED && !g->bidir_off;
+}
+
+// Slots for `want` pairs: at most kBiSlotsMax, within a quarter of the free device
+// memory (what the slots hold already counts as free).
+int plan_bidir(bc_graph *g, int64_t want)
+{
+    const Work &w = *g->w;
+    const size_t held = w.bst.bytes() + w.bval.bytes() + w.bq.bytes() + w.blo.bytes();
+    const size_t budget = (free_device_bytes() + held) / 4;
+    const size_t per = bidir_slot_bytes(g->n);
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(want, kBiSlotsMax));
+    while (S > 1 && (size_t)S * per > budget) S /= 2;
+    return S;
+}
+
+// The two-sided search of `count` pairs (device arrays us, vs): target values
+// into X[t * stride + i] when X is given, rows into full[i * n + w] (zeroed by
+// the caller) when full is given. Returns false when a path count reached
+// 2^1000 (plain FP64 only): the caller runs those pairs one-sided.
+bool run_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, int count,
+               const int32_t *targets, int32_t T, int32_t stride, double *X, double *full)
+{
+    if (count <= 0) return true;
+    Work &w = *g->w;
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    const int want = plan_bidir(g, count);
+    if (want > w.bslots || w.bn != n) {
+        w.bst.release(); w.bval.release(); w.bq.release(); w.blo.release();
+        w.bslots = 0;
+        const size_t cells = (size_t)2 * want * n;
+        w.bst.ensure(cells);
+        w.bval.ensure(cells);
+        w.bq.ensure(cells);
+        w.blo.ensure((size_t)2 * want * (n + 2));
+        HIPX(hipMemsetAsync(w.bst.p, 0, cells * sizeof(uint64_t), s));
+        w.bslots = want;
+        w.bn = n;
+        w.bepoch = 0;
+    }
+    const int grid = std::min(w.bslots, count);
+    const uint32_t per_slot = (uint32_t)((count + grid - 1) / grid);
+    if ((uint64_t)w.bepoch + per_slot + 1 >= 0xffffffffull) {
+        HIPX(hipMemsetAsync(w.bst.p, 0, w.bst.bytes(), s));
+        w.bepoch = 0;
+    }
+    const size_t half = (size_t)w.bslots * n, half_lo = (size_t)w.bslots * (n + 2);
+    BiArgs a;
+    a.row[0] = g->row.p;
+    a.col[0] = g->col.p;
+    a.row[1] = g->rrow();
+    a.col[1] = g->rcol();
+    a.n = n;
+    a.us = us;
+    a.vs = vs;
+    a.count = count;
+    a.st[0] = w.bst.p;
+    a.st[1] = w.bst.p + half;
+    a.val[0] = w.bval.p;
+    a.val[1] = w.bval.p + half;
+    a.q[0] = w.bq.p;
+    a.q[1] = w.bq.p + half;
+    a.lo[0] = w.blo.p;
+    a.lo[1] = w.blo.p + half_lo;
+    a.epoch0 = w.bepoch;
+    a.ctl = w.ctl.p;
+    a.prof = g->prof_on ? g->prof_dev.p : nullptr;
+    a.targets = targets;
+    a.T = T;
+    a.stride = stride;
+    a.X = X;
+    a.full = full;
+    zero_ctl(g);
+    launch_hot(g, PROF_BIDIR, grid, k_bidir, a);
+    w.bepoch += per_slot;
+    read_ctl(g);
+    if (w.h_ctl[CTL_SIG_OVERFLOW] == 0) return true;
+    g->bidir_off = true;
+    return false;
+}
+
 // ------------------------------------------------------------ lane order
 
 // key[v]: the BFS distances from the landmarks interleaved in Morton order,
@@ -1304,6 +1416,40 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     prof_flush(g);
 }
 
+// bc_pair_dependencies by the two-sided search, in launches of kBiChunk pairs;
+// a launch whose counts reached 2^1000 is run again one-sided.
+void pair_dependencies_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, int64_t k,
+                             double *out)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    if (k > 0) launch(s, grid_for(k * n), k_fill_f64, out, 0.0, k * n);
+    bc_stats st{};
+    st.pair_search = BC_PAIR_SEARCH_BIDIRECTIONAL;
+    for (int64_t b0 = 0; b0 < k; b0 += kBiChunk) {
+        const int count = (int)std::min<int64_t>(kBiChunk, k - b0);
+        if (use_bidir(g) && run_bidir(g, us + b0, vs + b0, count, nullptr, 0, 0, nullptr,
+                                      out + b0 * n)) {
+            st.batches += 1;
+            st.samples_executed += count;
+            st.batch_width = std::max(st.batch_width, std::min(g->w->bslots, count));
+            continue;
+        }
+        dependencies_impl(g, us + b0, count, BC_OUT_FULL, out + b0 * n, nullptr, nullptr,
+                          nullptr, true, vs + b0);
+        st.batches += g->stats.batches;
+        st.samples_executed += g->stats.samples_executed;
+        st.levels += g->stats.levels;
+        st.extended |= g->stats.extended;
+        st.batch_width = std::max(st.batch_width, g->stats.batch_width);
+        st.pair_search = BC_PAIR_SEARCH_ONE_SIDED;
+    }
+    st.schedule = engine_for(g) == ENG_PAIR ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
+    HIPX(hipStreamSynchronize(s));
+    prof_flush(g);
+    g->stats = st;
+}
+
 // -------------------------------------------------------------- autotuner
 //
 // Times candidate plans on one seeded batch of sources each and keeps the
@@ -1481,11 +1627,13 @@ bc_config tune_plan(bc_graph *g)
 // bc_exact only (the samplers keep their own round widths).
 void apply_plan(bc_graph *g, const bc_config &plan)
 {
-    const int32_t sampler_batch = g->cfg.sampler_batch;   // the caller's, not tuned
+    // the caller's sampler width and pair search, not tuned
+    const int32_t sampler_batch = g->cfg.sampler_batch, pair_search = g->cfg.pair_search;
     g->cfg = plan;
     g->tuned_batch = plan.batch;
     g->cfg.batch = 0;
     g->cfg.sampler_batch = sampler_batch;
+    g->cfg.pair_search = pair_search;
     g->tuned = true;
 }
 
@@ -1536,16 +1684,36 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     sa.status = g->w->st.p;
     launch(s, grid_for(T), k_stop_init, sa);
     int64_t j0 = 0;
+    bool one_sided = pair && !use_bidir(g);
     for (;;) {
         const int nb = (int)std::min<int64_t>(p.B, k_max - j0);
-        if (use_pairs) ensure_pairs(g, p.B, false);
-        else ensure_batch(g, p, false, start_cap(g), OUT_DELTA);
+        const bool bidir = pair && use_bidir(g);
+        if (bidir) {
+            g->w->srcs.ensure((size_t)p.B);
+            g->w->dest.ensure((size_t)p.B);
+        } else if (use_pairs) {
+            ensure_pairs(g, p.B, false);
+        } else {
+            ensure_batch(g, p, false, start_cap(g), OUT_DELTA);
+        }
         if (pair)
             launch(s, grid_for(nb), k_draw_pairs, seed, j0, (int64_t)nb, n, g->w->srcs.p, g->w->dest.p);
         else
             launch(s, grid_for(nb), k_draw_sources, seed, j0, (int64_t)nb, n, g->w->srcs.p);
         bool ext = false;
-        if (use_pairs) {
+        bool done = false;
+        if (bidir) {
+            done = run_bidir(g, g->w->srcs.p, g->w->dest.p, nb, targets, T, p.B, g->w->X.p,
+                             nullptr);
+            if (!done) {
+                // counts reached 2^1000: this round (its draws are in place) one-sided
+                one_sided = true;
+                if (use_pairs) ensure_pairs(g, p.B, false);
+                else ensure_batch(g, p, false, start_cap(g), OUT_DELTA);
+            }
+        }
+        if (done) {
+        } else if (use_pairs) {
             run_pairs(g, p.B, nb, pair, &ext, nullptr);
             PairArgs a = make_pair_args(g, p.B, ext, nb, pair);
             launch(s, grid_for((int64_t)T * p.B), k_p_gather_targets, a, targets, T,
@@ -1566,6 +1734,7 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
         if (j0 >= k_max) fail(BC_E_DEVICE, "stop rule left targets running at k_max");
     }
     g->stats.samples_executed = j0;
+    if (pair) g->stats.pair_search = one_sided ? BC_PAIR_SEARCH_ONE_SIDED : BC_PAIR_SEARCH_BIDIRECTIONAL;
     const double scale = pair ? (double)n * (double)(n - 1) : (double)n;
     launch(s, grid_for(T), k_stop_finish, sa, scale, out_est, out_samples, out_S, out_status);
     HIPX(hipStreamSynchronize(s));
@@ -1811,6 +1980,9 @@ bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg)
         need(sb == 0 || (sb >= 64 && sb <= 4096 && (sb & (sb - 1)) == 0),
              "sampler_batch must be 0 or a power of two in [64, 4096]");
         need(cfg->bottom_up == cfg->bottom_up, "bottom_up is NaN");
+        need(cfg->pair_search >= BC_PAIR_SEARCH_AUTO &&
+                 cfg->pair_search <= BC_PAIR_SEARCH_BIDIRECTIONAL,
+             "unknown pair_search");
         g->cfg = *cfg;
         g->tuned = false;
         g->tuned_batch = 0;
@@ -1898,11 +2070,13 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
                                                   "sigma_pull", "backward", "level_record",
                                                   "backward_split", "pair_forward",
-                                                  "pair_backward"};
+                                                  "pair_backward", "bidir_pair"};
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
-        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0};
-        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0};
+        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0,
+                                                   36.0};
+        static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0,
+                                                   12.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];
@@ -2079,7 +2253,11 @@ bc_status bc_pair_dependencies(bc_graph *g, const int32_t *us, const int32_t *vs
             for (int64_t i = 0; i < k; ++i) need(hu[(size_t)i] != hv[(size_t)i], "pair with u == v");
         }
         double *d_out = io.out(out, k * g->n);
-        dependencies_impl(g, d_us, k, BC_OUT_FULL, d_out, nullptr, nullptr, nullptr, true, d_vs);
+        if (use_bidir(g)) pair_dependencies_bidir(g, d_us, d_vs, k, d_out);
+        else {
+            dependencies_impl(g, d_us, k, BC_OUT_FULL, d_out, nullptr, nullptr, nullptr, true, d_vs);
+            g->stats.pair_search = BC_PAIR_SEARCH_ONE_SIDED;
+        }
         io.finish();
     });
 }

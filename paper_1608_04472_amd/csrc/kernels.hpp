@@ -145,7 +145,8 @@ enum : int {
     PROF_BACKWARD_SPLIT = 5,
     PROF_PAIR_FWD = 6,   // pair engine's persistent forward loop (discovery + path counts)
     PROF_PAIR_BWD = 7,   // pair engine's persistent backward loop
-    PROF_KERNELS = 8
+    PROF_BIDIR = 8,      // two-sided pair search
+    PROF_KERNELS = 9
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)

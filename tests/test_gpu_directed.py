@@ -15,7 +15,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1608_04472_amd as bc  # noqa: E402
-from test_gpu_parity import assert_close, assert_sigma, check_sampler  # noqa: E402
+from test_gpu_parity import (PAIR_IDS, PAIR_SEARCHES, assert_close, assert_sigma,  # noqa: E402
+                             check_sampler)
 
 O = oracle.load()
 SCHEDS = [bc.BC_SCHED_BATCHED, bc.BC_SCHED_THREADED]
@@ -95,11 +96,11 @@ def test_rmat_directed_batches(dev, batch, bottom_up):
     G.close()
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
-def test_directed_pairs_and_samplers(dev, sched):
+@pytest.mark.parametrize("sched,search", PAIR_SEARCHES, ids=PAIR_IDS)
+def test_directed_pairs_and_samplers(dev, sched, search):
     g = gg.rmat_directed(11, 8, 0.57, 0.19, 0.19, seed=4)
     G = bc.Graph(g.row, g.col, directed=True)
-    G.configure(sched, 0, 0.0)
+    G.configure(sched, 0, 0.0, pair_search=search)
     us = torch.empty(200, dtype=torch.int32, device=dev)
     vs = torch.empty(200, dtype=torch.int32, device=dev)
     bc.bc_draw_pairs(G, 3, 0, 200, us, vs)

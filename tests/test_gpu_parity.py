@@ -129,6 +129,11 @@ SMALL = [
 
 
 SCHEDS = [bc.BC_SCHED_BATCHED, bc.BC_SCHED_THREADED]
+# pair samples: the one-sided search on either engine, and the two-sided search
+ONE, BIDIR = bc.BC_PAIR_SEARCH_ONE_SIDED, bc.BC_PAIR_SEARCH_BIDIRECTIONAL
+PAIR_SEARCHES = [(bc.BC_SCHED_BATCHED, ONE), (bc.BC_SCHED_THREADED, ONE),
+                 (bc.BC_SCHED_AUTO, BIDIR)]
+PAIR_IDS = ["wave", "pair", "bidir"]
 
 
 @pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
@@ -365,11 +370,11 @@ def test_invalid_arguments(dev):
 
 # --------------------------------------------------------- pair dependencies
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
-def test_pair_dependencies(dev, sched):
+@pytest.mark.parametrize("sched,search", PAIR_SEARCHES, ids=PAIR_IDS)
+def test_pair_dependencies(dev, sched, search):
     g = gg.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)
     G = bc.Graph(g.row, g.col)
-    G.configure(sched, 0, 0.0)
+    G.configure(sched, 0, 0.0, pair_search=search)
     r = np.random.default_rng(0)
     us = r.integers(0, g.n, 150).astype(np.int32)
     vs = r.integers(0, g.n - 1, 150).astype(np.int32)
@@ -380,25 +385,69 @@ def test_pair_dependencies(dev, sched):
     iso = np.flatnonzero(g.degree() == 0)
     if iso.shape[0]:
         vs[1] = iso[0] if iso[0] != us[1] else iso[-1]  # unreachable destination
-    say("pair deps")
+    say("pair deps", search)
     got = bc.pair_dependencies(G, T(us, dev), T(vs.astype(np.int32), dev)).cpu().numpy()
+    assert G.stats()["pair_search"] == search
     for i in range(us.shape[0]):
         assert_close(got[i], O.pair_dependency(g, int(us[i]), int(vs[i])), what="pair %d" % i)
     G.close()
 
 
+@pytest.mark.parametrize("search", [ONE, BIDIR], ids=["one", "bidir"])
 @pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
-def test_pair_dependencies_grid_extended(dev, sched):
+def test_pair_dependencies_grid_extended(dev, sched, search):
+    # corner to corner of the 600 x 600 grid: counts beyond 2^1000, so the
+    # two-sided search hands the pairs to the one-sided engine
     g = gg.grid(600, 600)
     G = bc.Graph(g.row, g.col)
-    G.configure(sched, 0, 0.0)
+    G.configure(sched, 0, 0.0, pair_search=search)
     us = np.array([0, 1000, 5], dtype=np.int32)
     vs = np.array([359999, 300000, 359000], dtype=np.int32)
-    say("pair deps grid600")
+    say("pair deps grid600", search)
     got = bc.pair_dependencies(G, T(us, dev), T(vs, dev)).cpu().numpy()
+    assert G.stats()["pair_search"] == ONE
     for i in range(3):
         assert_close(got[i], O.pair_dependency(g, int(us[i]), int(vs[i])), what="gpair %d" % i)
     G.close()
+
+
+def test_bidir_pairs_below_the_fp64_range(dev):
+    # the 60 x 60 grid's corner-to-corner counts (C(118, 59) < 2^1000) stay
+    # in the two-sided search; hubs, leaves, adjacent and unreachable pairs
+    g = gg.grid(60, 60)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_AUTO, 0, 0.0, pair_search=BIDIR)
+    us = np.array([0, 59, 1830, 0, 3599, 7], dtype=np.int32)
+    vs = np.array([3599, 3540, 1769, 1, 0, 3000], dtype=np.int32)
+    say("bidir grid60")
+    got = bc.pair_dependencies(G, T(us, dev), T(vs, dev)).cpu().numpy()
+    assert G.stats()["pair_search"] == BIDIR
+    for i in range(us.shape[0]):
+        assert_close(got[i], O.pair_dependency(g, int(us[i]), int(vs[i])), what="g60 %d" % i)
+    h = gg.config_graph("er2000")
+    H = bc.Graph(h.row, h.col)
+    H.configure(bc.BC_SCHED_AUTO, 0, 0.0, pair_search=BIDIR)
+    iso = np.flatnonzero(h.degree() == 0)
+    hub = gg.top_degree(h, 2)
+    us = np.array([hub[0], hub[1], iso[0] if iso.size else 3, 17], dtype=np.int32)
+    vs = np.array([hub[1], 5, 9, iso[-1] if iso.size else 4], dtype=np.int32)
+    vs = np.where(us == vs, (vs + 1) % h.n, vs).astype(np.int32)
+    # more pairs than slots: each workgroup serves several in a row
+    r = np.random.default_rng(8)
+    ru = r.integers(0, h.n, 5000).astype(np.int32)
+    rv = r.integers(0, h.n - 1, 5000).astype(np.int32)
+    rv = rv + (rv >= ru)
+    us, vs = np.concatenate([us, ru]), np.concatenate([vs, rv]).astype(np.int32)
+    say("bidir er2000 5004 pairs")
+    got = bc.pair_dependencies(H, T(us, dev), T(vs, dev)).cpu().numpy()
+    assert H.stats()["pair_search"] == BIDIR
+    for i in list(range(4)) + list(range(4, us.shape[0], 97)):
+        assert_close(got[i], O.pair_dependency(h, int(us[i]), int(vs[i])), what="er %d" % i)
+    # the same pairs again: slots reuse their state under new epochs
+    again = bc.pair_dependencies(H, T(us, dev), T(vs, dev)).cpu().numpy()
+    assert np.array_equal(got, again)
+    G.close()
+    H.close()
 
 
 # --------------------------------------------------------------- samplers
@@ -451,26 +500,27 @@ def test_adaptive_source_threshold_tie(dev):
     G.close()
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
-def test_adaptive_pair_eps_er2000(dev, sched):
+@pytest.mark.parametrize("sched,search", PAIR_SEARCHES, ids=PAIR_IDS)
+def test_adaptive_pair_eps_er2000(dev, sched, search):
     g = gg.config_graph("er2000")
     G = bc.Graph(g.row, g.col)
-    G.configure(sched, 0, 0.0)
+    G.configure(sched, 0, 0.0, pair_search=search)
     targets = gg.top_degree(g, 16)
-    say("adaptive pair eps er2000")
+    say("adaptive pair eps er2000", search)
     got = bc.adaptive_pair(G, T(targets, dev), bc.BC_PAIR_EPS, 0.1, 1.0, 1, 1 << 20)
     check_sampler(got, O.adaptive_pair(g, targets, oracle.RULE_EPS, 0.1, 1.0, 1, 1 << 20),
                   "pair eps er2000")
+    assert G.stats()["pair_search"] == search
     G.close()
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
-def test_adaptive_pair_alg1_small(dev, sched):
+@pytest.mark.parametrize("sched,search", PAIR_SEARCHES, ids=PAIR_IDS)
+def test_adaptive_pair_alg1_small(dev, sched, search):
     g = gg.er(150, 0.04, seed=2)
     G = bc.Graph(g.row, g.col)
-    G.configure(sched, 0, 0.0)
+    G.configure(sched, 0, 0.0, pair_search=search)
     targets = gg.top_degree(g, 3)
-    say("adaptive pair alg1")
+    say("adaptive pair alg1", search)
     got = bc.adaptive_pair(G, T(targets, dev), bc.BC_PAIR_ALG1, 0.1, 1.0, 5, 1 << 20)
     check_sampler(got, O.adaptive_pair(g, targets, oracle.RULE_ALG1, 0.1, 1.0, 5, 1 << 20),
                   "pair alg1")
