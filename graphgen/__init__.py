@@ -67,6 +67,7 @@ class CSR:
     col: np.ndarray  # int32[nnz]
     name: str = ""
     directed: bool = False   # row v lists v's out-neighbours (arcs v -> w)
+    w: np.ndarray | None = None   # int32[nnz] arc weights (col order), or None
 
     @property
     def nnz(self) -> int:
@@ -152,6 +153,25 @@ def rmat_directed(scale: int, edge_factor: int, a: float, b: float, c: float, se
     if got != ne:
         raise RuntimeError("graphgen_rmat failed")
     return from_arcs(n, src, dst, "drmat%d_%d" % (scale, edge_factor))
+
+
+def with_weights(g: CSR, wmax: int, seed: int, stream: int = 7) -> CSR:
+    """g with positive integer arc weights drawn uniformly from [1, wmax]
+    (Philox key (seed, stream)). Undirected graphs draw one weight per edge,
+    so both arcs of an edge carry it; directed graphs one per arc."""
+    r = rng(seed, stream)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row))
+    dst = g.col.astype(np.int64)
+    if g.directed:
+        w = r.integers(1, wmax + 1, g.nnz)
+    else:
+        # weight of edge {a, b}: a draw indexed by the edge's rank among the
+        # arcs a -> b with a < b (the same rank from either end)
+        lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+        key = lo * g.n + hi
+        uniq, inv = np.unique(key, return_inverse=True)
+        w = r.integers(1, wmax + 1, uniq.shape[0])[inv]
+    return CSR(g.n, g.row, g.col, g.name + "-w%d" % wmax, g.directed, w.astype(np.int32))
 
 
 def relabel_subgraph(g: CSR, keep: np.ndarray, name: str = "") -> CSR:

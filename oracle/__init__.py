@@ -22,6 +22,13 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
                       counts, planted mistakes
   pair_work           closed forms (paths, stars, adjacent and unreachable
                       pairs), scipy BFS distances, planted mistakes
+  *_weighted          the same functions on graphs with positive integer arc
+                      weights (Dijkstra's algorithm): brute-force enumeration
+                      of weighted shortest paths, networkx's weighted
+                      betweenness, unit weights equal the unweighted oracle,
+                      scaled weights leave every result unchanged, a weight
+                      that lengthens an edge past a detour removes it from
+                      every shortest path, planted mistakes
   *_directed          the same functions on directed graphs (out-neighbour
                       CSR): brute-force path enumeration on small digraphs,
                       closed forms (directed paths, cycles, stars, DAG
@@ -91,6 +98,10 @@ def _declare(lib):
                  "oracle_pair_dependency", "oracle_adaptive_source", "oracle_adaptive_pair"):
         d = getattr(lib, name + "_directed")
         d.argtypes = getattr(lib, name).argtypes
+        w = getattr(lib, name + "_weighted")
+        a = getattr(lib, name).argtypes
+        w.argtypes = a[:3] + [c.c_void_p, c.c_int] + a[3:]
+        w.restype = c.c_int
     for name in ("oracle_brandes", "oracle_bc_exact", "oracle_dependencies",
                  "oracle_pair_dependency", "oracle_adaptive_source", "oracle_adaptive_pair",
                  "oracle_source_work", "oracle_pair_work"):
@@ -137,6 +148,17 @@ class Oracle:
     def _f(self, name, directed):
         return getattr(self.lib, name + ("_directed" if directed else ""))
 
+    def _call(self, name, g, directed, *rest):
+        """name's entry point for g: weighted when g carries arc weights
+        (g.w, int32 in col order), else the plain or directed form."""
+        n, row, col = _csr(g)
+        w = getattr(g, "w", None)
+        if w is None:
+            return self._f(name, directed)(n, _p(row), _p(col), *rest)
+        wt = np.ascontiguousarray(w, dtype=np.int32)
+        return getattr(self.lib, name + "_weighted")(n, _p(row), _p(col), _p(wt),
+                                                     1 if directed else 0, *rest)
+
     def philox(self, ctr, key):
         c = np.asarray(ctr, dtype=np.uint64)
         k = np.asarray(key, dtype=np.uint64)
@@ -160,14 +182,14 @@ class Oracle:
         sm = np.zeros(n, np.float64)
         se = np.zeros(n, np.int32)
         de = np.zeros(n, np.float64)
-        _ok(self._f("oracle_brandes", directed)(n, _p(row), _p(col), int(s), _p(dist), _p(sm),
-                                                _p(se), _p(de)), "oracle_brandes")
+        _ok(self._call("oracle_brandes", g, directed, int(s), _p(dist), _p(sm), _p(se), _p(de)),
+            "oracle_brandes")
         return dist, (sm, se), de
 
     def bc_exact(self, g, directed=False):
         n, row, col = _csr(g)
         bc = np.zeros(n, np.float64)
-        _ok(self._f("oracle_bc_exact", directed)(n, _p(row), _p(col), _p(bc)), "oracle_bc_exact")
+        _ok(self._call("oracle_bc_exact", g, directed, _p(bc)), "oracle_bc_exact")
         return bc
 
     def dependencies(self, g, sources, full=True, total=True, directed=False):
@@ -176,15 +198,15 @@ class Oracle:
         k = src.shape[0]
         f = np.zeros((k, n), np.float64) if full else None
         s = np.zeros(n, np.float64) if total else None
-        _ok(self._f("oracle_dependencies", directed)(n, _p(row), _p(col), _p(src), k, _p(f),
-                                                     _p(s)), "oracle_dependencies")
+        _ok(self._call("oracle_dependencies", g, directed, _p(src), k, _p(f), _p(s)),
+            "oracle_dependencies")
         return f, s
 
     def pair_dependency(self, g, u, v, directed=False):
         n, row, col = _csr(g)
         y = np.zeros(n, np.float64)
-        _ok(self._f("oracle_pair_dependency", directed)(n, _p(row), _p(col), int(u), int(v),
-                                                        _p(y)), "oracle_pair_dependency")
+        _ok(self._call("oracle_pair_dependency", g, directed, int(u), int(v), _p(y)),
+            "oracle_pair_dependency")
         return y
 
     def adaptive_source(self, g, targets, c, seed, k_max, directed=False):
@@ -195,9 +217,8 @@ class Oracle:
         k = np.zeros(T, np.int64)
         S = np.zeros(T, np.float64)
         st = np.zeros(T, np.uint8)
-        _ok(self._f("oracle_adaptive_source", directed)(n, _p(row), _p(col), _p(t), T, float(c),
-                                                        int(seed), int(k_max), _p(est), _p(k),
-                                                        _p(S), _p(st)), "oracle_adaptive_source")
+        _ok(self._call("oracle_adaptive_source", g, directed, _p(t), T, float(c), int(seed),
+                       int(k_max), _p(est), _p(k), _p(S), _p(st)), "oracle_adaptive_source")
         return est, k, S, st
 
     def adaptive_pair(self, g, targets, rule, eps, c, seed, k_max, directed=False):
@@ -208,9 +229,8 @@ class Oracle:
         k = np.zeros(T, np.int64)
         S = np.zeros(T, np.float64)
         st = np.zeros(T, np.uint8)
-        _ok(self._f("oracle_adaptive_pair", directed)(n, _p(row), _p(col), _p(t), T, int(rule),
-                                                      float(eps), float(c), int(seed), int(k_max),
-                                                      _p(est), _p(k), _p(S), _p(st)),
+        _ok(self._call("oracle_adaptive_pair", g, directed, _p(t), T, int(rule), float(eps),
+                       float(c), int(seed), int(k_max), _p(est), _p(k), _p(S), _p(st)),
             "oracle_adaptive_pair")
         return est, k, S, st
 

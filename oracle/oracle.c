@@ -8,8 +8,11 @@
  * Paper: S. Ji and Z. Yan, "Refining Approximating Betweenness Centrality
  * Based on Samplings" (arXiv 1608.04472). Each function cites the passage it
  * follows. Readings of silent or ambiguous points:
- *   - graphs are undirected and unweighted, so the single-source shortest
- *     paths of Brandes' first step are a breadth-first search;
+ *   - unweighted graphs: the single-source shortest paths of Brandes' first
+ *     step are a breadth-first search; weighted graphs (the *_weighted
+ *     entry points): Dijkstra's algorithm, weights positive integers with
+ *     max weight * (n - 1) < 2^30, so distances, their sums and ties are
+ *     exact;
  *   - BC sums over ordered pairs (s, t), s, t, v pairwise distinct;
  *   - the predecessor condition of Definition 3 is read as "if and only if";
  *   - sampling is uniform with replacement over all n vertices (sources) or
@@ -122,6 +125,8 @@ typedef struct {
     const int32_t *col;
     const int64_t *rrow;    /* in-neighbours */
     const int32_t *rcol;
+    const int32_t *wt;      /* weights of the out-arcs (row/col order), or NULL */
+    const int32_t *rwt;     /* weights of the in-arcs (rrow/rcol order), or NULL */
 } graph_t;
 
 static graph_t undirected(int64_t n, const int64_t *row, const int32_t *col)
@@ -134,6 +139,8 @@ static graph_t undirected(int64_t n, const int64_t *row, const int32_t *col)
 static graph_t reversed(const graph_t *g)
 {
     graph_t r = {g->n, g->rrow, g->rcol, g->row, g->col};
+    r.wt = g->rwt;
+    r.rwt = g->wt;
     return r;
 }
 
@@ -164,6 +171,12 @@ typedef struct {
     double *delta;
     int32_t *order;     /* vertices in BFS order: non-decreasing distance */
     int64_t reached;
+    /* weighted graphs: Dijkstra's heap of (distance, vertex) entries with
+     * lazy deletion (one entry per improving relaxation: at most nnz + 1),
+     * and the tentative distances */
+    int64_t *hkey;
+    int32_t *hval;
+    int32_t *tent;
 } pass_t;
 
 static int pass_alloc(pass_t *p, int64_t n)
@@ -173,12 +186,27 @@ static int pass_alloc(pass_t *p, int64_t n)
     p->delta = (double *)malloc(sizeof(double) * (size_t)n);
     p->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     p->reached = 0;
+    p->hkey = NULL;
+    p->hval = NULL;
+    p->tent = NULL;
     return (p->dist && p->sig && p->delta && p->order) ? 0 : -1;
+}
+
+/* the heap and tentative distances of a weighted graph's passes */
+static int pass_alloc_heap(pass_t *p, const graph_t *g)
+{
+    if (!g->wt) return 0;
+    const size_t cap = (size_t)g->row[g->n] + 1;
+    p->hkey = (int64_t *)malloc(sizeof(int64_t) * cap);
+    p->hval = (int32_t *)malloc(sizeof(int32_t) * cap);
+    p->tent = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->n);
+    return (p->hkey && p->hval && p->tent) ? 0 : -1;
 }
 
 static void pass_free(pass_t *p)
 {
     free(p->dist); free(p->sig); free(p->delta); free(p->order);
+    free(p->hkey); free(p->hval); free(p->tent);
 }
 
 static int check_graph(int64_t n, const int64_t *row, const int32_t *col)
@@ -255,8 +283,119 @@ static void dependencies(const graph_t *g, pass_t *p)
     }
 }
 
+/* ------------------------------------------------------- weighted graphs */
+
+/* binary min-heap on (key, vertex) in hkey/hval, `size` entries */
+static void heap_push(pass_t *p, int64_t *size, int64_t key, int32_t v)
+{
+    int64_t i = (*size)++;
+    while (i > 0) {
+        const int64_t up = (i - 1) / 2;
+        if (p->hkey[up] <= key) break;
+        p->hkey[i] = p->hkey[up];
+        p->hval[i] = p->hval[up];
+        i = up;
+    }
+    p->hkey[i] = key;
+    p->hval[i] = v;
+}
+
+static void heap_pop(pass_t *p, int64_t *size, int64_t *key, int32_t *v)
+{
+    *key = p->hkey[0];
+    *v = p->hval[0];
+    const int64_t last = --(*size);
+    const int64_t k = p->hkey[last];
+    const int32_t x = p->hval[last];
+    int64_t i = 0;
+    for (;;) {
+        int64_t c = 2 * i + 1;
+        if (c >= last) break;
+        if (c + 1 < last && p->hkey[c + 1] < p->hkey[c]) c += 1;
+        if (p->hkey[c] >= k) break;
+        p->hkey[i] = p->hkey[c];
+        p->hval[i] = p->hval[c];
+        i = c;
+    }
+    if (last > 0) {
+        p->hkey[i] = k;
+        p->hval[i] = x;
+    }
+}
+
+/* Brandes' first step on a weighted graph (Section 3 names Dijkstra's
+ * algorithm): vertices are settled in non-decreasing distance; a stale heap
+ * entry (its vertex settled, or its key above the tentative distance) is
+ * skipped. p->order lists the settled vertices in that order. */
+static void dijkstra(const graph_t *g, int32_t s, pass_t *p)
+{
+    for (int64_t v = 0; v < g->n; ++v) { p->dist[v] = -1; p->tent[v] = -1; }
+    int64_t size = 0;
+    p->reached = 0;
+    p->tent[s] = 0;
+    heap_push(p, &size, 0, s);
+    while (size > 0) {
+        int64_t key;
+        int32_t u;
+        heap_pop(p, &size, &key, &u);
+        if (p->dist[u] >= 0 || key != p->tent[u]) continue;
+        p->dist[u] = (int32_t)key;
+        p->order[p->reached++] = u;
+        for (int64_t e = g->row[u]; e < g->row[u + 1]; ++e) {
+            const int32_t w = g->col[e];
+            const int32_t through = p->dist[u] + g->wt[e];
+            if (p->dist[w] < 0 && (p->tent[w] < 0 || through < p->tent[w])) {
+                p->tent[w] = through;
+                heap_push(p, &size, through, w);
+            }
+        }
+    }
+}
+
+/* Definition 3 with weights: u precedes w when the arc u->w lies on a
+ * shortest path, d(s,u) + w(u,w) = d(s,w). Settled order puts every
+ * predecessor (strictly closer: weights are positive) first. */
+static void weighted_counts(const graph_t *g, pass_t *p)
+{
+    for (int64_t v = 0; v < g->n; ++v) { p->sig[v].m = 0.0; p->sig[v].e = 0; }
+    p->sig[p->order[0]] = xnum_make(1.0, 0);
+    for (int64_t i = 1; i < p->reached; ++i) {
+        const int32_t w = p->order[i];
+        xnum sum = {0.0, 0};
+        for (int64_t e = g->rrow[w]; e < g->rrow[w + 1]; ++e) {
+            const int32_t u = g->rcol[e];
+            if (p->dist[u] >= 0 && p->dist[u] + g->rwt[e] == p->dist[w])
+                sum = xnum_add(sum, p->sig[u]);
+        }
+        p->sig[w] = sum;
+    }
+}
+
+/* Theorem 1 with weights: the successors of v are the heads t of arcs
+ * v->t with d(s,v) + w(v,t) = d(s,t); reverse settled order; delta_s(s) = 0. */
+static void weighted_dependencies(const graph_t *g, pass_t *p)
+{
+    for (int64_t v = 0; v < g->n; ++v) p->delta[v] = 0.0;
+    for (int64_t i = p->reached - 1; i > 0; --i) {
+        const int32_t v = p->order[i];
+        double sum = 0.0;
+        for (int64_t e = g->row[v]; e < g->row[v + 1]; ++e) {
+            const int32_t t = g->col[e];
+            if (p->dist[v] + g->wt[e] == p->dist[t])
+                sum += xnum_div(p->sig[v], p->sig[t]) * (1.0 + p->delta[t]);
+        }
+        p->delta[v] = sum;
+    }
+}
+
 static void brandes_pass(const graph_t *g, int32_t s, pass_t *p)
 {
+    if (g->wt) {
+        dijkstra(g, s, p);
+        weighted_counts(g, p);
+        weighted_dependencies(g, p);
+        return;
+    }
     bfs(g, s, p);
     path_counts(g, p);
     dependencies(g, p);
@@ -267,7 +406,7 @@ static int brandes_g(const graph_t *g, int32_t s, int32_t *dist, double *sig_m, 
 {
     if (s < 0 || s >= g->n) return -1;
     pass_t p;
-    if (pass_alloc(&p, g->n)) { pass_free(&p); return -2; }
+    if (pass_alloc(&p, g->n) | pass_alloc_heap(&p, g)) { pass_free(&p); return -2; }
     brandes_pass(g, s, &p);
     for (int64_t v = 0; v < g->n; ++v) {
         if (dist) dist[v] = p.dist[v];
@@ -284,7 +423,7 @@ static int bc_exact_g(const graph_t *g, double *bc)
 {
     if (!bc) return -1;
     pass_t p;
-    if (pass_alloc(&p, g->n)) { pass_free(&p); return -2; }
+    if (pass_alloc(&p, g->n) | pass_alloc_heap(&p, g)) { pass_free(&p); return -2; }
     for (int64_t v = 0; v < g->n; ++v) bc[v] = 0.0;
     for (int64_t s = 0; s < g->n; ++s) {
         brandes_pass(g, (int32_t)s, &p);
@@ -302,7 +441,7 @@ static int dependencies_g(const graph_t *g, const int32_t *sources, int64_t k, d
     for (int64_t i = 0; i < k; ++i)
         if (sources[i] < 0 || sources[i] >= n) return -1;
     pass_t p;
-    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    if (pass_alloc(&p, n) | pass_alloc_heap(&p, g)) { pass_free(&p); return -2; }
     if (sum) for (int64_t v = 0; v < n; ++v) sum[v] = 0.0;
     for (int64_t i = 0; i < k; ++i) {
         brandes_pass(g, sources[i], &p);
@@ -336,6 +475,11 @@ static void pair_from_passes(int64_t n, int32_t u, int32_t v, const pass_t *pu,
 
 static void sssp_counts(const graph_t *g, int32_t s, pass_t *p)
 {
+    if (g->wt) {
+        dijkstra(g, s, p);
+        weighted_counts(g, p);
+        return;
+    }
     bfs(g, s, p);
     path_counts(g, p);
 }
@@ -346,7 +490,8 @@ static int pair_dependency_g(const graph_t *g, int32_t u, int32_t v, double *y)
     if (!y || u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
     const graph_t r = reversed(g);
     pass_t pu, pv;
-    int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n);
+    int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n) | pass_alloc_heap(&pu, g) |
+              pass_alloc_heap(&pv, &r);
     if (bad) { pass_free(&pu); pass_free(&pv); return -2; }
     sssp_counts(g, u, &pu);
     sssp_counts(&r, v, &pv);
@@ -375,7 +520,7 @@ static int adaptive_source_g(const graph_t *g, const int32_t *targets, int32_t T
     for (int32_t i = 0; i < T; ++i)
         if (targets[i] < 0 || targets[i] >= n) return -1;
     pass_t p;
-    if (pass_alloc(&p, n)) { pass_free(&p); return -2; }
+    if (pass_alloc(&p, n) | pass_alloc_heap(&p, g)) { pass_free(&p); return -2; }
     const double threshold = c * (double)n;
     for (int32_t i = 0; i < T; ++i) { S[i] = 0.0; samples[i] = 0; status[i] = ST_RUNNING; }
     int32_t running = T;
@@ -416,7 +561,8 @@ static int adaptive_pair_g(const graph_t *g, const int32_t *targets, int32_t T, 
     const graph_t r = reversed(g);
     pass_t pu, pv;
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
-    int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n);
+    int bad = pass_alloc(&pu, n) | pass_alloc(&pv, n) | pass_alloc_heap(&pu, g) |
+              pass_alloc_heap(&pv, &r);
     if (bad || !y) { pass_free(&pu); pass_free(&pv); free(y); return -2; }
     const double threshold = c * (double)n;
     const double eps_rhs = ((eps * eps) * eps) * ((double)n * (double)n);
@@ -553,6 +699,121 @@ int oracle_adaptive_pair_directed(int64_t n, const int64_t *row, const int32_t *
 {
     WITH_DIRECTED(n, row, col, adaptive_pair_g(&g, targets, T, rule, eps, c, seed, k_max, est,
                                                samples, S, status));
+}
+
+/* --------------------------------------------------- weighted entry points
+ * wt[e]: the weight of arc e of row/col, a positive integer with
+ * max weight * (n - 1) < 2^30. directed = 0: an undirected CSR whose two
+ * arcs of an edge carry equal weights; directed != 0: out-neighbour rows,
+ * the in-neighbour rows and their weights built here. */
+
+static int check_weights(int64_t n, const int64_t *row, const int32_t *col, const int32_t *wt,
+                         int directed)
+{
+    if (!wt && row[n] > 0) return -1;
+    int32_t most = 0;
+    for (int64_t e = 0; e < row[n]; ++e) {
+        if (wt[e] <= 0) return -1;
+        if (wt[e] > most) most = wt[e];
+    }
+    if ((int64_t)most * (n - 1) >= (1ll << 30)) return -1;
+    if (directed) return 0;
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = row[u]; e < row[u + 1]; ++e) {
+            const int32_t v = col[e];
+            int64_t f = row[v];
+            while (f < row[v + 1] && col[f] != u) ++f;
+            if (f == row[v + 1] || wt[f] != wt[e]) return -1;
+        }
+    return 0;
+}
+
+/* weights of the in-neighbour rows that transpose() builds, in its order */
+static int transpose_weights(int64_t n, const int64_t *row, const int32_t *col,
+                             const int32_t *wt, const int64_t *trow, int32_t **twt)
+{
+    const int64_t nnz = row[n];
+    int32_t *tw = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!tw || !next) { free(tw); free(next); return -2; }
+    for (int64_t v = 0; v < n; ++v) next[v] = trow[v];
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = row[u]; e < row[u + 1]; ++e) tw[next[col[e]]++] = wt[e];
+    free(next);
+    *twt = tw;
+    return 0;
+}
+
+#define WITH_WEIGHTS(n, row, col, wt, directed, CALL)                              \
+    do {                                                                           \
+        if (check_graph(n, row, col) || check_weights(n, row, col, wt, directed))  \
+            return -1;                                                             \
+        int64_t *trow_ = NULL;                                                     \
+        int32_t *tcol_ = NULL, *twt_ = NULL;                                       \
+        graph_t g = {n, row, col, row, col, wt, wt};                               \
+        if (directed) {                                                            \
+            if (transpose(n, row, col, &trow_, &tcol_)) return -2;                 \
+            if (transpose_weights(n, row, col, wt, trow_, &twt_)) {                \
+                free(trow_);                                                       \
+                free(tcol_);                                                       \
+                return -2;                                                         \
+            }                                                                      \
+            g.rrow = trow_;                                                        \
+            g.rcol = tcol_;                                                        \
+            g.rwt = twt_;                                                          \
+        }                                                                          \
+        const int rc_ = (CALL);                                                    \
+        free(trow_);                                                               \
+        free(tcol_);                                                               \
+        free(twt_);                                                                \
+        return rc_;                                                                \
+    } while (0)
+
+int oracle_brandes_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                            const int32_t *wt, int directed, int32_t s, int32_t *dist,
+                            double *sig_m, int32_t *sig_e, double *delta)
+{
+    WITH_WEIGHTS(n, row, col, wt, directed, brandes_g(&g, s, dist, sig_m, sig_e, delta));
+}
+
+int oracle_bc_exact_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                             const int32_t *wt, int directed, double *bc)
+{
+    WITH_WEIGHTS(n, row, col, wt, directed, bc_exact_g(&g, bc));
+}
+
+int oracle_dependencies_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                 const int32_t *wt, int directed, const int32_t *sources,
+                                 int64_t k, double *full, double *sum)
+{
+    WITH_WEIGHTS(n, row, col, wt, directed, dependencies_g(&g, sources, k, full, sum));
+}
+
+int oracle_pair_dependency_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                    const int32_t *wt, int directed, int32_t u, int32_t v,
+                                    double *y)
+{
+    WITH_WEIGHTS(n, row, col, wt, directed, pair_dependency_g(&g, u, v, y));
+}
+
+int oracle_adaptive_source_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                    const int32_t *wt, int directed, const int32_t *targets,
+                                    int32_t T, double c, uint64_t seed, int64_t k_max,
+                                    double *est, int64_t *samples, double *S, uint8_t *status)
+{
+    WITH_WEIGHTS(n, row, col, wt, directed,
+                 adaptive_source_g(&g, targets, T, c, seed, k_max, est, samples, S, status));
+}
+
+int oracle_adaptive_pair_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                  const int32_t *wt, int directed, const int32_t *targets,
+                                  int32_t T, int rule, double eps, double c, uint64_t seed,
+                                  int64_t k_max, double *est, int64_t *samples, double *S,
+                                  uint8_t *status)
+{
+    WITH_WEIGHTS(n, row, col, wt, directed,
+                 adaptive_pair_g(&g, targets, T, rule, eps, c, seed, k_max, est, samples, S,
+                                 status));
 }
 
 /* ------------------------------------------------------------ work counts */

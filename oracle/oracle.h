@@ -105,6 +105,32 @@ int oracle_adaptive_pair_directed(int64_t n, const int64_t *row, const int32_t *
                                   double c, uint64_t seed, int64_t k_max, double *est,
                                   int64_t *samples, double *S, uint8_t *status);
 
+/* Weighted graphs (Brandes' first step by Dijkstra's algorithm, Section 3):
+ * wt[e] is the weight of arc e (row/col order), a positive integer with
+ * max weight * (n - 1) < 2^30. directed = 0 takes an undirected CSR whose two
+ * arcs of an edge carry the same weight; directed != 0 a CSR of out-arcs.
+ * dist holds weighted distances. Results as the unweighted calls. */
+int oracle_brandes_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                            const int32_t *wt, int directed, int32_t s, int32_t *dist,
+                            double *sig_m, int32_t *sig_e, double *delta);
+int oracle_bc_exact_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                             const int32_t *wt, int directed, double *bc);
+int oracle_dependencies_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                 const int32_t *wt, int directed, const int32_t *sources,
+                                 int64_t k, double *full, double *sum);
+int oracle_pair_dependency_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                    const int32_t *wt, int directed, int32_t u, int32_t v,
+                                    double *y);
+int oracle_adaptive_source_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                    const int32_t *wt, int directed, const int32_t *targets,
+                                    int32_t T, double c, uint64_t seed, int64_t k_max,
+                                    double *est, int64_t *samples, double *S, uint8_t *status);
+int oracle_adaptive_pair_weighted(int64_t n, const int64_t *row, const int32_t *col,
+                                  const int32_t *wt, int directed, const int32_t *targets,
+                                  int32_t T, int rule, double eps, double c, uint64_t seed,
+                                  int64_t k_max, double *est, int64_t *samples, double *S,
+                                  uint8_t *status);
+
 /* Work counters for the throughput metric: for source s, the number of
  * vertices reached and the undirected edges of s's component; for a pair
  * (u, v), the undirected edges with an endpoint at distance < d(u,v)
