@@ -174,6 +174,20 @@ bc_status bc_graph_create(const bc_csr *csr, const bc_allocator *alloc, void *hi
  * server takes undirected graphs. */
 bc_status bc_graph_create_directed(const bc_csr *csr, const bc_allocator *alloc,
                                    void *hip_stream, bc_graph **out);
+/* A weighted graph (Section 3: Brandes' first step by Dijkstra's algorithm;
+ * shortest paths minimise the total arc weight). weights[e] is the weight of
+ * arc e of csr->col: positive, with max weight * (n - 1) < 2^30 so distances
+ * and their sums are exact in int32; undirected graphs (directed = 0) need
+ * equal weights on the two arcs of an edge, directed ones (directed != 0) take
+ * a CSR of out-arcs as bc_graph_create_directed. Every compute call serves
+ * the handle with one engine (a label-correcting search of the batch's
+ * sources, then path counts and Theorem 1 over the shortest-path DAG in
+ * topological rounds); dist_out holds weighted distances; path counts must
+ * stay below 2^1000 (BC_E_UNSUPPORTED otherwise); pair samples search from
+ * u to the end of the search (no early stop, no two-sided search). Not
+ * served: the query server, bc_dependencies_noalloc. */
+bc_status bc_graph_create_weighted(const bc_csr *csr, const int32_t *weights, int32_t directed,
+                                   const bc_allocator *alloc, void *hip_stream, bc_graph **out);
 void bc_graph_destroy(bc_graph *g);
 bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
 /* Autotuner: times candidate plans on one seeded batch of sources each and
@@ -302,6 +316,14 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *                count write) + 8 per units_b (count read)
  *   pair_backward: its persistent backward loop, bytes as backward
  *   level_record: 8 per (vertex, word) read + 36 per record entry written
+ *   w_search   : weighted graphs' search rounds: 12 per units_a (arc
+ *                relaxed: head, weight, head's distance)
+ *   w_counts   : their path-count rounds: 16 per units_a (entry done: count,
+ *                order entry, pending counter) + 20 per units_b (in-arc read:
+ *                tail, weight, distance, count)
+ *   w_backward : their dependency rounds: 24 per units_a (entry: order entry,
+ *                distance, count, dependency write) + 28 per units_b (out-arc:
+ *                head, weight, distance, count, dependency)
  *   bidir_pair : the two-sided pair search (one launch per batch of pairs):
  *                units_a = vertices found by either side, 36 each (row
  *                bounds, stamp, list entry, path count); units_b = arcs

@@ -39,7 +39,8 @@ BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED, BC_SCHE
 BC_PAIR_SEARCH_AUTO, BC_PAIR_SEARCH_ONE_SIDED, BC_PAIR_SEARCH_BIDIRECTIONAL = 0, 1, 2
 
 EXPORTS = [
-    "bc_graph_create", "bc_graph_create_directed", "bc_graph_destroy", "bc_graph_set_stream",
+    "bc_graph_create", "bc_graph_create_directed", "bc_graph_create_weighted",
+    "bc_graph_destroy", "bc_graph_set_stream",
     "bc_graph_set_io",
     "bc_graph_configure", "bc_graph_tune", "bc_graph_plan",
     "bc_graph_info", "bc_exact", "bc_dependencies", "bc_dependencies_noalloc",
@@ -191,6 +192,7 @@ def load_library(path: str | None = None):
     sigs = {
         "bc_graph_create": [c.POINTER(_Csr), V, V, c.POINTER(V)],
         "bc_graph_create_directed": [c.POINTER(_Csr), V, V, c.POINTER(V)],
+        "bc_graph_create_weighted": [c.POINTER(_Csr), V, c.c_int32, V, V, c.POINTER(V)],
         "bc_graph_set_stream": [V, V],
         "bc_graph_set_io": [V, c.c_int32],
         "bc_graph_configure": [V, c.POINTER(_Config)],
@@ -263,15 +265,26 @@ def _stream():
 class Graph:
     """Handle to a device-resident CSR graph (bc_graph). row may be int64 or
     int32 offsets; allocator 'torch' (default) or 'hip'; directed=True reads
-    row/col as out-neighbour lists (bc_graph_create_directed)."""
+    row/col as out-neighbour lists (bc_graph_create_directed); weights (int32
+    per arc of col, positive) make it a weighted graph (bc_graph_create_weighted)."""
 
-    def __init__(self, row, col, allocator="torch", directed=False):
+    def __init__(self, row, col, allocator="torch", directed=False, weights=None):
         lib = load_library()
         csr, keep = _csr_arrays(row, col)
         h = ctypes.c_void_p()
         self._h = None
-        create = lib.bc_graph_create_directed if directed else lib.bc_graph_create
-        _check(create(ctypes.byref(csr), _allocator(allocator), _stream(), ctypes.byref(h)))
+        if weights is not None:
+            import numpy as np
+            wt = np.ascontiguousarray(np.asarray(weights), dtype=np.int32)
+            if wt.shape != (int(csr.nnz),):
+                raise ValueError("weights need one entry per arc")
+            _check(lib.bc_graph_create_weighted(ctypes.byref(csr), wt.ctypes.data,
+                                                1 if directed else 0, _allocator(allocator),
+                                                _stream(), ctypes.byref(h)))
+        else:
+            create = lib.bc_graph_create_directed if directed else lib.bc_graph_create
+            _check(create(ctypes.byref(csr), _allocator(allocator), _stream(), ctypes.byref(h)))
+        self.weighted = weights is not None
         self.directed = bool(directed)
         self._h = h
         self.n = int(csr.n)

@@ -12,6 +12,7 @@
 #include "../../include/bcmi.h"
 #include "kernels.hpp"
 #include "bidir.hpp"
+#include "weighted.hpp"
 
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
@@ -198,6 +199,10 @@ struct Work {
     DBuf<uint64_t> bst;
     DBuf<double> bval;
     DBuf<int32_t> bq, blo;
+    // weighted graphs: predecessors pending, queue stamps, search frontiers
+    // ([B][n] each; distances, counts, dependencies and the order of the
+    // counts' rounds use lv, sig, dlt and ridx)
+    DBuf<uint32_t> wpend, wflag, wfa, wfb;
     int32_t bslots = 0;
     int64_t bn = 0;
     uint32_t bepoch = 0;   // epochs up to this one are used in every slot
@@ -226,6 +231,7 @@ struct Work {
         okey_in.release(); okey_out.release(); oidx_in.release(); operm.release();
         lane_row.release(); sort_tmp.release(); draw_src.release(); draw_dst.release();
         bst.release(); bval.release(); bq.release(); blo.release();
+        wpend.release(); wflag.release(); wfa.release(); wfb.release();
         bslots = 0;
         bn = 0;
         bepoch = 0;
@@ -247,6 +253,9 @@ struct bc_graph {
     DBuf<int32_t> rcol_buf;
     const int64_t *rrow() const { return directed ? rrow_buf.p : row.p; }
     const int32_t *rcol() const { return directed ? rcol_buf.p : col.p; }
+    bool weighted = false;    // wt_buf: out-arc weights; rwt_buf: in-arc weights (directed)
+    DBuf<int32_t> wt_buf, rwt_buf;
+    const int32_t *rwt() const { return directed ? rwt_buf.p : wt_buf.p; }
     bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0, BC_PAIR_SEARCH_AUTO};
     Work own;
     Work *w = &own;
@@ -284,6 +293,7 @@ struct bc_graph {
     {
         row.release(); col.release();
         rrow_buf.release(); rcol_buf.release();
+        wt_buf.release(); rwt_buf.release();
         skey.release();
         own.release();
         prof_dev.release();
@@ -828,6 +838,7 @@ int probe_depth(bc_graph *g)
 
 Engine engine_for(bc_graph *g)
 {
+    if (g->weighted) return ENG_PAIR;   // the layout of the weighted engine
     if (g->cfg.schedule == BC_SCHED_BATCHED) return ENG_WAVE;
     if (g->cfg.schedule == BC_SCHED_THREADED) return ENG_PAIR;
     if (g->engine < 0) g->engine = probe_depth(g) > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
@@ -1076,6 +1087,160 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
     }
 }
 
+// ------------------------------------------------------------ weighted graphs
+
+// Width of a weighted batch: as the pair-per-thread engine (32-bit entry
+// indices), 48 bytes per entry.
+int plan_weighted(bc_graph *g, int64_t want, int default_cap)
+{
+    int B = g->cfg.batch;
+    if (B == 0) {
+        B = 64;
+        while (B < want && B < default_cap) B *= 2;
+    }
+    while (B > 1 && (int64_t)B * g->n >= (1ll << 32)) B /= 2;
+    const Work &w = *g->w;
+    const size_t held = w.sig.bytes() + w.dlt.bytes() + w.lv.bytes() + w.ridx.bytes() +
+                        w.wpend.bytes() + w.wflag.bytes() + w.wfa.bytes() + w.wfb.bytes();
+    const size_t budget = (free_device_bytes() + held) / 10 * 7;
+    while (B > 1 && (size_t)g->n * B * 48 > budget) B /= 2;
+    return B;
+}
+
+void ensure_weighted(bc_graph *g, int B)
+{
+    const size_t np = (size_t)B * g->n;
+    Work &w = *g->w;
+    w.lv.ensure(np);
+    w.sig.ensure(np);
+    w.dlt.ensure(np);
+    w.ridx.ensure(np);
+    w.wpend.ensure(np);
+    w.wflag.ensure(np);
+    w.wfa.ensure(np);
+    w.wfb.ensure(np);
+    w.srcs.ensure((size_t)B);
+    w.dest.ensure((size_t)B);
+}
+
+WArgs make_weighted_args(bc_graph *g, int B, int nvalid, bool pair)
+{
+    WArgs a;
+    a.row = g->row.p;
+    a.col = g->col.p;
+    a.wt = g->wt_buf.p;
+    a.rrow = g->rrow();
+    a.rcol = g->rcol();
+    a.rwt = g->rwt();
+    a.n = (uint32_t)g->n;
+    a.B = B;
+    a.dist = g->w->lv.p;
+    a.sig = g->w->sig.p;
+    a.dlt = g->w->dlt.p;
+    a.pend = g->w->wpend.p;
+    a.flag = g->w->wflag.p;
+    a.order = g->w->ridx.p;
+    a.ctl = g->w->ctl.p;
+    a.srcs = g->w->srcs.p;
+    a.dest = pair ? g->w->dest.p : nullptr;
+    a.nvalid = nvalid;
+    a.prof = g->prof_on ? g->prof_dev.p : nullptr;
+    return a;
+}
+
+// The weighted engine's arrays as the pair-per-thread engine's output and
+// gather kernels read them (lv: distance, -1 unreached; plain counts).
+PairArgs weighted_pair_args(bc_graph *g, int B, int nvalid, bool pair)
+{
+    PairArgs a = make_pair_args(g, B, false, nvalid, pair);
+    a.sige = nullptr;
+    return a;
+}
+
+// Brandes' pass (pair mode: toward each lane's destination) for the nvalid
+// sources in g->w->srcs (and destinations in g->w->dest). Returns the rounds
+// of the path counts.
+int64_t run_weighted(bc_graph *g, int B, int nvalid, bool pair)
+{
+    hipStream_t s = g->stream;
+    Work &w = *g->w;
+    const int64_t np = (int64_t)nvalid * g->n;
+    WArgs a = make_weighted_args(g, B, nvalid, pair);
+    launch(s, grid_for(np), k_fill_i32, w.lv.p, kWUnreached, np);
+    launch(s, grid_for(np), k_fill_i32, (int32_t *)w.wflag.p, (int32_t)0, np);
+    launch(s, grid_for(nvalid), k_w_init, a, w.wfa.p);
+    // the search: rounds until no distance falls
+    uint32_t *cur = w.wfa.p, *nxt = w.wfb.p;
+    int64_t count = nvalid;
+    for (uint32_t round = 1; count > 0; ++round) {
+        zero_ctl(g);
+        launch_hot(g, PROF_W_SEARCH, grid_for(count), k_w_relax, a, (const uint32_t *)cur, count,
+                   nxt, round);
+        read_ctl(g);
+        count = (int64_t)w.h_ctl[CTL_TAIL];
+        std::swap(cur, nxt);
+        if (g->timed) check_deadline(g);
+    }
+    // path counts in rounds; the order list grows behind each round (its
+    // tail starts after the sources, set by k_w_count)
+    zero_ctl(g);
+    launch(s, grid_for(np), k_w_count, a);
+    std::vector<int64_t> off{0, nvalid};
+    for (;;) {
+        const int64_t s0 = off[off.size() - 2], s1 = off.back();
+        launch_hot(g, PROF_W_COUNTS, grid_for(s1 - s0), k_w_sigma, a, s0, s1);
+        read_ctl(g);
+        const int64_t t = (int64_t)w.h_ctl[CTL_TAIL];
+        if (t == s1) break;
+        off.push_back(t);
+    }
+    if (w.h_ctl[CTL_SIG_OVERFLOW])
+        fail(BC_E_UNSUPPORTED, "path counts reach 2^1000 on a weighted graph");
+    for (size_t r = off.size() - 1; r >= 2; --r)
+        launch_hot(g, PROF_W_BACKWARD, grid_for(off[r] - off[r - 1]), k_w_backward, a,
+                   off[r - 1], off[r]);
+    const int64_t rounds = (int64_t)off.size() - 1;
+    g->stats.levels += rounds;
+    return rounds;
+}
+
+// dependencies_impl for weighted graphs (every schedule: one engine)
+void weighted_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode,
+                           double *out, int32_t *dist_out, double *sig_m, int32_t *sig_e,
+                           bool pair, const int32_t *dests, const int32_t *targets, int32_t T)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    const int B = plan_weighted(g, k, g->tuned_batch ? g->tuned_batch : 512);
+    g->stats.batch_width = B;
+    g->stats.schedule = BC_SCHED_THREADED;
+    for (int64_t b0 = 0; b0 < k; b0 += B) {
+        const int count = (int)std::min<int64_t>(B, k - b0);
+        ensure_weighted(g, B);
+        HIPX(hipMemcpyAsync(g->w->srcs.p, sources + b0, (size_t)count * 4,
+                            hipMemcpyDeviceToDevice, s));
+        if (pair)
+            HIPX(hipMemcpyAsync(g->w->dest.p, dests + b0, (size_t)count * 4,
+                                hipMemcpyDeviceToDevice, s));
+        run_weighted(g, B, count, pair);
+        PairArgs a = weighted_pair_args(g, B, count, pair);
+        if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_p_out_sum, a, out);
+        else if (mode == BC_OUT_TARGETS)
+            launch(s, grid_for((int64_t)count * T), k_p_out_targets, a, targets, T,
+                   (int32_t)count, b0, out);
+        else launch(s, grid_for(n * count), k_p_out_full, a, (int32_t)count, b0, out);
+        if (dist_out)
+            HIPX(hipMemcpyAsync(dist_out + b0 * n, g->w->lv.p, (size_t)count * n * 4,
+                                hipMemcpyDeviceToDevice, s));
+        if (sig_m || sig_e)
+            launch(s, grid_for(n * count), k_p_out_sigma, a, (int32_t)count, b0, sig_m, sig_e);
+        g->stats.batches += 1;
+        g->stats.samples_executed += count;
+    }
+    HIPX(hipStreamSynchronize(s));
+    prof_flush(g);
+}
+
 // ------------------------------------------------------ two-sided pair search
 
 // Pairs in flight at once: one workgroup and one slot of per-vertex state each.
@@ -1092,7 +1257,7 @@ size_t bidir_slot_bytes(int64_t n)
 // one-sided one or its path counts once reached 2^1000 on this graph.
 bool use_bidir(const bc_graph *g)
 {
-    return g->cfg.pair_search != BC_PAIR_SEARCH_ONE_SIDED && !g->bidir_off;
+    return g->cfg.pair_search != BC_PAIR_SEARCH_ONE_SIDED && !g->bidir_off && !g->weighted;
 }
 
 // Slots for `want` pairs: at most kBiSlotsMax, within a quarter of the free device
@@ -1306,6 +1471,11 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
     if (dist_out) launch(s, grid_for(k * n), k_fill_i32, dist_out, (int32_t)-1, k * n);
     if (sig_m) launch(s, grid_for(k * n), k_fill_f64, sig_m, 0.0, k * n);
     if (sig_e) launch(s, grid_for(k * n), k_fill_i32, sig_e, (int32_t)0, k * n);
+    if (g->weighted) {
+        weighted_dependencies(g, sources, k, mode, out, dist_out, sig_m, sig_e, pair, dests,
+                              targets, T);
+        return;
+    }
 
     if (!fixed && per_source_schedule(g) && !pair) {
         for (int64_t i = 0; i < k; ++i) {
@@ -1494,6 +1664,13 @@ int fit_width(bc_graph *g, Engine e, int want)
 
 bc_config tune_plan(bc_graph *g)
 {
+    if (g->weighted) {
+        // one engine serves weighted graphs: nothing to choose but the width
+        bc_config c = g->cfg;
+        c.schedule = BC_SCHED_THREADED;
+        c.batch = 0;
+        return c;
+    }
     const TuneKey key{g->n, g->nnz, probe_depth(g), g->deg_hist};
     {
         std::lock_guard<std::mutex> lock(tune_mu);
@@ -1662,7 +1839,9 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     if (g->cfg.sampler_batch > 0) g->cfg.batch = g->cfg.sampler_batch;
     const int round = pair ? 2048 : 256;
     Plan p = plan_batch(g, k_max, round);
-    if (use_pairs) {
+    if (g->weighted) {
+        p.B = plan_weighted(g, k_max, round);
+    } else if (use_pairs) {
         // the pair engine takes any power-of-two width; keep the sampler's stride
         p.B = plan_pairs(g, k_max, round);
     }
@@ -1688,7 +1867,9 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     for (;;) {
         const int nb = (int)std::min<int64_t>(p.B, k_max - j0);
         const bool bidir = pair && use_bidir(g);
-        if (bidir) {
+        if (g->weighted) {
+            ensure_weighted(g, p.B);
+        } else if (bidir) {
             g->w->srcs.ensure((size_t)p.B);
             g->w->dest.ensure((size_t)p.B);
         } else if (use_pairs) {
@@ -1713,6 +1894,11 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
             }
         }
         if (done) {
+        } else if (g->weighted) {
+            run_weighted(g, p.B, nb, pair);
+            PairArgs a = weighted_pair_args(g, p.B, nb, pair);
+            launch(s, grid_for((int64_t)T * p.B), k_p_gather_targets, a, targets, T,
+                   (int32_t)p.B, g->w->X.p);
         } else if (use_pairs) {
             run_pairs(g, p.B, nb, pair, &ext, nullptr);
             PairArgs a = make_pair_args(g, p.B, ext, nb, pair);
@@ -1836,8 +2022,30 @@ namespace {
 
 // Validate a host CSR (symmetric unless directed) and build the handle: the
 // device copy of the rows and, for a directed graph, of its in-neighbour rows.
+// Arc weights: positive, max weight * (n - 1) < 2^30 (distances and their
+// sums stay exact in int32), and on an undirected graph equal on both arcs of
+// an edge.
+void validate_weights(const bc_csr *c, const std::vector<int64_t> &row, const int32_t *wt,
+                      bool directed)
+{
+    int32_t most = 0;
+    for (int64_t e = 0; e < c->nnz; ++e) {
+        need(wt[e] > 0, "arc weights must be positive");
+        most = std::max(most, wt[e]);
+    }
+    need((int64_t)most * (c->n - 1) < (1ll << 30), "max weight * (n - 1) must be below 2^30");
+    if (directed) return;
+    for (int64_t v = 0; v < c->n; ++v)
+        for (int64_t e = row[(size_t)v]; e < row[(size_t)v + 1]; ++e) {
+            const int32_t w = c->col[e];
+            const int32_t *lo = c->col + row[(size_t)w], *hi = c->col + row[(size_t)w + 1];
+            const int32_t *f = std::lower_bound(lo, hi, (int32_t)v);
+            need(wt[f - c->col] == wt[e], "the two arcs of an edge carry different weights");
+        }
+}
+
 void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream, bc_graph **out,
-                  bool directed)
+                  bool directed, const int32_t *weights = nullptr)
 {
     {
         need(csr && out, "null argument");
@@ -1855,6 +2063,7 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
             validate_csr(csr, r, !directed);
             std::copy(r, r + csr->n + 1, row.begin());
         }
+        if (weights) validate_weights(csr, row, weights, directed);
         bc_graph *g = new bc_graph();
         if (alloc) g->alloc.a = *alloc;
         UseAlloc ua(&g->alloc);
@@ -1897,6 +2106,13 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
             HIPX(hipMemcpy(g->row.p, row.data(), row.size() * 8, hipMemcpyHostToDevice));
             if (csr->nnz)
                 HIPX(hipMemcpy(g->col.p, csr->col, (size_t)csr->nnz * 4, hipMemcpyHostToDevice));
+            if (weights) {
+                g->weighted = true;
+                g->wt_buf.ensure((size_t)std::max<int64_t>(csr->nnz, 1));
+                if (csr->nnz)
+                    HIPX(hipMemcpy(g->wt_buf.p, weights, (size_t)csr->nnz * 4,
+                                   hipMemcpyHostToDevice));
+            }
             if (directed) {
                 // in-neighbour rows, sorted ascending (sources visited in order)
                 const int64_t n = csr->n;
@@ -1905,9 +2121,18 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
                 for (int64_t e = 0; e < csr->nnz; ++e) trow[(size_t)csr->col[e] + 1] += 1;
                 for (int64_t v = 0; v < n; ++v) trow[(size_t)v + 1] += trow[(size_t)v];
                 for (int64_t v = 0; v < n; ++v) fill[(size_t)v] = trow[(size_t)v];
+                std::vector<int32_t> twt(weights ? tcol.size() : 0);
                 for (int64_t u = 0; u < n; ++u)
-                    for (int64_t e = row[(size_t)u]; e < row[(size_t)u + 1]; ++e)
-                        tcol[(size_t)fill[(size_t)csr->col[e]]++] = (int32_t)u;
+                    for (int64_t e = row[(size_t)u]; e < row[(size_t)u + 1]; ++e) {
+                        const int64_t at = fill[(size_t)csr->col[e]]++;
+                        tcol[(size_t)at] = (int32_t)u;
+                        if (weights) twt[(size_t)at] = weights[e];
+                    }
+                if (weights) {
+                    g->rwt_buf.ensure(twt.size());
+                    HIPX(hipMemcpy(g->rwt_buf.p, twt.data(), twt.size() * 4,
+                                   hipMemcpyHostToDevice));
+                }
                 g->directed = true;
                 g->rrow_buf.ensure(trow.size());
                 g->rcol_buf.ensure((size_t)csr->nnz);
@@ -1939,6 +2164,16 @@ bc_status bc_graph_create_directed(const bc_csr *csr, const bc_allocator *alloc,
                                    void *hip_stream, bc_graph **out)
 {
     return guarded([&] { create_graph(csr, alloc, hip_stream, out, true); });
+}
+
+bc_status bc_graph_create_weighted(const bc_csr *csr, const int32_t *weights, int32_t directed,
+                                   const bc_allocator *alloc, void *hip_stream, bc_graph **out)
+{
+    return guarded([&] {
+        need(csr && (weights || csr->nnz == 0), "null argument");
+        static const int32_t none = 1;
+        create_graph(csr, alloc, hip_stream, out, directed != 0, weights ? weights : &none);
+    });
 }
 
 void bc_graph_destroy(bc_graph *g)
@@ -2070,13 +2305,14 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
                                                   "sigma_pull", "backward", "level_record",
                                                   "backward_split", "pair_forward",
-                                                  "pair_backward", "bidir_pair"};
+                                                  "pair_backward", "bidir_pair", "w_search",
+                                                  "w_counts", "w_backward"};
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
         static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0,
-                                                   36.0};
+                                                   36.0, 12.0, 16.0, 24.0};
         static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0,
-                                                   12.0};
+                                                   12.0, 0.0, 20.0, 28.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];
@@ -2170,6 +2406,7 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
         need(out || (out_mode == BC_OUT_FULL && k == 0), "null argument");
         if (g->io == BC_IO_HOST)
             fail(BC_E_UNSUPPORTED, "the allocation-free call takes device arrays only");
+        if (g->weighted) fail(BC_E_UNSUPPORTED, "the allocation-free call takes unweighted graphs");
         use_device(g);
         // any attempt to allocate in this call is an error
         Alloc none;

@@ -146,7 +146,10 @@ enum : int {
     PROF_PAIR_FWD = 6,   // pair engine's persistent forward loop (discovery + path counts)
     PROF_PAIR_BWD = 7,   // pair engine's persistent backward loop
     PROF_BIDIR = 8,      // two-sided pair search
-    PROF_KERNELS = 9
+    PROF_W_SEARCH = 9,   // weighted graphs: search rounds
+    PROF_W_COUNTS = 10,  //   path-count rounds
+    PROF_W_BACKWARD = 11,  // dependency rounds
+    PROF_KERNELS = 12
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)

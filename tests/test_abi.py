@@ -120,3 +120,29 @@ def test_server_arguments_checked_before_device_work():
     assert lib.bc_server_create(0, 64, None, None, ctypes.byref(s)) == bc.BC_E_INVALID
     assert lib.bc_server_graph_width(None, 0, None, None) == bc.BC_E_INVALID
     assert lib.bc_graph_set_io(None, 1) == bc.BC_E_INVALID
+
+
+def test_weights_validated_on_the_host():
+    import numpy as np
+    import graphgen as gg
+    lib = bc.load_library()
+    g = gg.with_weights(gg.path(5), 3, seed=1)
+    csr, keep = bc._csr_arrays(g.row, g.col)
+    h = ctypes.c_void_p()
+
+    def create(w, directed=0):
+        w = np.ascontiguousarray(w, dtype=np.int32)
+        return lib.bc_graph_create_weighted(ctypes.byref(csr), w.ctypes.data, directed, None,
+                                            None, ctypes.byref(h))
+
+    zero = g.w.copy()
+    zero[3] = 0
+    assert create(zero) == bc.BC_E_INVALID
+    assert b"positive" in lib.bc_last_error()
+    asym = g.w.copy()
+    asym[0] += 1
+    assert create(asym) == bc.BC_E_INVALID
+    assert b"different weights" in lib.bc_last_error()
+    assert create(np.full(g.nnz, 1 << 28)) == bc.BC_E_INVALID
+    assert lib.bc_graph_create_weighted(ctypes.byref(csr), None, 0, None, None,
+                                        ctypes.byref(h)) == bc.BC_E_INVALID
