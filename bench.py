@@ -19,6 +19,7 @@ Printed on one JSON line, beside the headline value:
   legs        the other workloads: C1 (ER n = 2000: exact BC and the three
               samplers), C2 (R-MAT scale 16: 64 degree-percentile targets,
               c = 5, 256 per round), C4 (2048^2 grid, 5 % of edges removed, 1024
+              sources), w (the C3 graph with arc weights in [1, 100], 1024
               sources) and C5 (serving a prefix of the 20,000-query stream)
 The graph's plan comes from the autotuner (bc_graph_tune) unless --schedule
 names one; it is part of the printed config.
@@ -35,7 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1608_04472_amd/csrc/kernels.hpp", "paper_1608_04472_amd/csrc/bcmi.hip"]
+KERNEL_SOURCES = ["paper_1608_04472_amd/csrc/kernels.hpp", "paper_1608_04472_amd/csrc/bcmi.hip",
+                  "paper_1608_04472_amd/csrc/bidir.hpp", "paper_1608_04472_amd/csrc/weighted.hpp"]
 
 
 def kernel_source_hash():
@@ -292,15 +294,26 @@ def c2_leg(args, bc, gg, dev):
     return out
 
 
+def schedule_id(bc, name):
+    return {"tuned": bc.BC_SCHED_TUNED, "auto": bc.BC_SCHED_AUTO, "wave": bc.BC_SCHED_BATCHED,
+            "pair": bc.BC_SCHED_THREADED, "wg": bc.BC_SCHED_WORKGROUP}[name]
+
+
 def c4_leg(args, bc, gg, dev):
     """2048^2 grid, 5 % of edges removed (seed 3), largest component: 1024
-    sources (seed 3), fwd+bwd, per-vertex sum; one step after a warm-up."""
+    sources (seed 3), fwd+bwd, per-vertex sum; one step after a warm-up, under
+    the tuned plan unless --c4-schedule names one."""
     import torch
     t0 = time.time()
     g = gg.config_graph("grid2048")
     ce = component_edges(g)
     G = bc.Graph(g.row, g.col)
-    G.configure(bc.BC_SCHED_AUTO, args.c4_batch)
+    G.configure(schedule_id(bc, args.c4_schedule), args.c4_batch)
+    tune_s = 0.0
+    if args.c4_schedule == "tuned":
+        t = time.time()
+        G.tune()
+        tune_s = time.time() - t
     K = 1024
     srcs = torch.from_numpy(gg.philox_sources(3, K, g.n)).to(dev)
     out_t = torch.empty(g.n, dtype=torch.float64, device=dev)
@@ -320,10 +333,61 @@ def c4_leg(args, bc, gg, dev):
            "ms_per_step": 1e3 * dt, "gteps": edges / dt / 1e9, "levels": int(st["levels"]),
            "batch": int(st["batch_width"]), "extended": int(st["extended"]),
            "launches": int(sum(k["launches"] for k in kern)), "plan": G.plan(),
+           "kernels": {k["name"]: {"ms": k["ms"], "launches": k["launches"]}
+                       for k in kern if k["launches"]},
+           "tune_s": tune_s, "setup_s": time.time() - t0 - dt}
+    G.close()
+    log("C4: %.0f ms/step, %.2f GTEPS, %d levels, batch %d, %d hot launches, plan %s" % (
+        out["ms_per_step"], out["gteps"], out["levels"], out["batch"], out["launches"],
+        out["plan"]))
+    return out
+
+
+def weighted_leg(args, bc, gg, dev):
+    """The C3 graph (BA, n = 2^20, m = 5, seed 7) with integer arc weights
+    drawn uniformly from [1, 100] (seed 7, one per edge): 1024 sources (seed 7),
+    fwd+bwd, per-vertex sum; one step after a warm-up. GTEPS counts each
+    source's component edges once, as the unweighted legs do."""
+    import torch
+    t0 = time.time()
+    g = gg.with_weights(gg.config_graph("ba1m"), 100, seed=7)
+    ce = component_edges(g)
+    G = bc.Graph(g.row, g.col, weights=g.w)
+    K = 1024
+    srcs = torch.from_numpy(gg.philox_sources(7, K, g.n)).to(dev)
+    out_t = torch.empty(g.n, dtype=torch.float64, device=dev)
+    bc.bc_dependencies(G, srcs[:64].contiguous(), bc.BC_OUT_SUM, out_t)   # warm
+    torch.cuda.synchronize()
+    G.profile(True)
+    t = time.perf_counter()
+    bc.bc_dependencies(G, srcs, bc.BC_OUT_SUM, out_t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    kern = G.profile_read()
+    G.profile(False)
+    st = G.stats()
+    edges = float(ce[srcs.cpu().numpy()].sum())
+    by = {k["name"]: k for k in kern}
+    dom = max(kern, key=lambda x: x["ms"])
+    ach = dom["algo_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    relax = by["w_search"]["units_a"]
+    out = {"workload": "BA n=2^20, m=5 (seed 7), arc weights uniform in [1, 100] (seed 7); "
+                       "1024 sources (seed 7), fwd+bwd, sum",
+           "ms_per_step": 1e3 * dt, "gteps": edges / dt / 1e9,
+           "rounds_counts": int(st["levels"]), "batch": int(st["batch_width"]),
+           "search_launches": int(by["w_search"]["launches"]),
+           "relaxations_per_arc": relax / (2.0 * edges) if edges else None,
+           "launches": int(sum(k["launches"] for k in kern)),
+           "kernels": {k["name"]: {"ms": k["ms"], "launches": k["launches"]}
+                       for k in kern if k["launches"]},
+           "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS},
            "setup_s": time.time() - t0 - dt}
     G.close()
-    log("C4: %.0f ms/step, %.2f GTEPS, %d levels, batch %d, %d hot launches" % (
-        out["ms_per_step"], out["gteps"], out["levels"], out["batch"], out["launches"]))
+    log("weighted: %.0f ms/step, %.2f GTEPS, batch %d, %d search rounds, %.2f relaxations "
+        "per arc, dominant %s %.1f GB/s" % (out["ms_per_step"], out["gteps"], out["batch"],
+                                             out["search_launches"], out["relaxations_per_arc"]
+                                             or 0.0, dom["name"], ach))
     return out
 
 
@@ -419,7 +483,7 @@ def main():
     ap.add_argument("--sources", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--batch", type=int, default=0)
-    ap.add_argument("--schedule", default="tuned", choices=["tuned", "auto", "wave", "pair"])
+    ap.add_argument("--schedule", default="tuned", choices=["tuned", "auto", "wave", "pair", "wg"])
     ap.add_argument("--bottom-up", type=float, default=0.0)
     ap.add_argument("--level-loop", type=int, default=0,
                     help="pair engine: 1 persistent level loops, else one launch per level phase")
@@ -433,9 +497,12 @@ def main():
     ap.add_argument("--pair-search", default="auto", choices=["auto", "one", "bidir"],
                     help="pair samples' search; auto also times the one-sided one")
     ap.add_argument("--no-pair", action="store_true")
-    ap.add_argument("--legs", default="c1,c2,c4,c5",
+    ap.add_argument("--legs", default="c1,c2,c4,w,c5",
                     help="other workloads to measure (comma list of c1, c2, c4, c5; '' = none)")
-    ap.add_argument("--c4-batch", type=int, default=1024)
+    ap.add_argument("--c4-batch", type=int, default=0,
+                    help="C4 batch width (0: the schedule's own)")
+    ap.add_argument("--c4-schedule", default="tuned",
+                    choices=["tuned", "auto", "wave", "pair", "wg"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-threads", type=int, default=16,
                     help="threads for the all-cores oracle run (capped by the CPUs this "
@@ -475,8 +542,7 @@ def main():
     log("graph %s n=%d nnz=%d built in %.1fs" % (args.graph, g.n, g.nnz, time.time() - t0))
     comp_edges = component_edges(g)
     G = bc.Graph(g.row, g.col)
-    sched = {"tuned": bc.BC_SCHED_TUNED, "auto": bc.BC_SCHED_AUTO, "wave": bc.BC_SCHED_BATCHED,
-             "pair": bc.BC_SCHED_THREADED}[args.schedule]
+    sched = schedule_id(bc, args.schedule)
     G.configure(sched, args.batch, args.bottom_up, 0, args.level_loop)
     if sched == bc.BC_SCHED_TUNED:
         t = time.time()
@@ -579,8 +645,11 @@ def main():
     # ------------------------------------------------------ other workloads
     legs = {}
     want = [x for x in args.legs.split(",") if x]
-    for name, fn in (("c1", c1_leg), ("c2", c2_leg), ("c4", c4_leg)):
+    for name, fn in (("c1", c1_leg), ("c2", c2_leg), ("c4", c4_leg), ("w", weighted_leg)):
         if name in want:
+            # the library sizes its buffers from the device's free memory:
+            # hand back what torch's allocator cached for the previous leg
+            torch.cuda.empty_cache()
             legs[name] = fn(args, bc, gg, dev)
     serving = None
     if "c5" in want and not args.no_serve and args.serve_queries > 0:

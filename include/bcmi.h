@@ -94,8 +94,15 @@ typedef enum {
                               frontier vertex: the plain form, for comparison */
     BC_SCHED_THREADED = 3, /* many sources per launch, one thread per (vertex,
                               source) pair: for graphs of large diameter */
-    BC_SCHED_TUNED = 4     /* the first compute call times candidate plans and
+    BC_SCHED_TUNED = 4,    /* the first compute call times candidate plans and
                               keeps the fastest (bc_graph_tune) */
+    BC_SCHED_WORKGROUP = 5 /* one workgroup per source, whole passes with
+                              workgroup barriers only (no device-wide step per
+                              level): for graphs of large diameter; batch =
+                              sources in flight (0 = auto, up to 1024 within
+                              70 % of free memory, 40 bytes per vertex each).
+                              bc_dependencies, bc_exact, bc_pair_dependencies
+                              (one-sided); the samplers run the THREADED engine */
 } bc_schedule;
 
 typedef struct {
@@ -192,8 +199,9 @@ void bc_graph_destroy(bc_graph *g);
 bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
 /* Autotuner: times candidate plans on one seeded batch of sources each and
  * installs the fastest per source, by coordinate descent: the engine
- * (BC_SCHED_BATCHED or BC_SCHED_THREADED) at its default width, then the
- * batch width (256 .. 4096, within 32-bit indices and free memory), then the
+ * (BC_SCHED_BATCHED, BC_SCHED_THREADED or BC_SCHED_WORKGROUP) at its default
+ * width, then the batch width (256 .. 4096, within 32-bit indices and free
+ * memory; for BC_SCHED_WORKGROUP the sources in flight, 64 .. 1024), then the
  * wave engine's bottom_up (0.04, 0.01, 0.15, never) and split_entries (2^18,
  * 2^20, 2^22), or the pair engine's level_loop. A candidate slower than 1.5x
  * the best so far is abandoned early. Winners are cached per process by graph
@@ -316,6 +324,10 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *                count write) + 8 per units_b (count read)
  *   pair_backward: its persistent backward loop, bytes as backward
  *   level_record: 8 per (vertex, word) read + 36 per record entry written
+ *   wg_pass    : the one-workgroup-per-source engine (whole passes): 36 per
+ *                units_a (vertex reached: distance CAS, list entry, count,
+ *                dependency, reset) + 12 per units_b (arc walked: head, its
+ *                distance)
  *   w_search   : weighted graphs' search rounds: 12 per units_a (arc
  *                relaxed: head, weight, head's distance)
  *   w_counts   : their path-count rounds: 16 per units_a (entry done: count,

@@ -36,6 +36,7 @@ BC_IO_DEVICE, BC_IO_HOST = 0, 1
 BC_PAIR_ALG1, BC_PAIR_EPS = 0, 1
 BC_SCHED_AUTO, BC_SCHED_BATCHED, BC_SCHED_PER_SOURCE, BC_SCHED_THREADED, BC_SCHED_TUNED = \
     0, 1, 2, 3, 4
+BC_SCHED_WORKGROUP = 5
 BC_PAIR_SEARCH_AUTO, BC_PAIR_SEARCH_ONE_SIDED, BC_PAIR_SEARCH_BIDIRECTIONAL = 0, 1, 2
 
 EXPORTS = [

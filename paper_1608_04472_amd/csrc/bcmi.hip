@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "bidir.hpp"
 #include "weighted.hpp"
+#include "wgsource.hpp"
 
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
@@ -203,6 +204,11 @@ struct Work {
     // ([B][n] each; distances, counts, dependencies and the order of the
     // counts' rounds use lv, sig, dlt and ridx)
     DBuf<uint32_t> wpend, wflag, wfa, wfb;
+    // one workgroup per source: per-slot distances (-1 between passes),
+    // counts, exponents, dependencies, visiting lists, level starts, sums
+    DBuf<WgVert> wgv;
+    DBuf<int32_t> wgq, wglo, wgbase;
+    int64_t wgn = 0;        // n the distances were filled for (0: refill)
     int32_t bslots = 0;
     int64_t bn = 0;
     uint32_t bepoch = 0;   // epochs up to this one are used in every slot
@@ -216,6 +222,21 @@ struct Work {
     {
         ctl.ensure(CTL_WORDS);
         if (!h_ctl) HIPX(hipHostMalloc((void **)&h_ctl, CTL_WORDS * sizeof(unsigned long long), 0));
+    }
+    // the engines' per-vertex buffers (not the control block or small arrays)
+    void release_engines()
+    {
+        sig.release(); dlt.release(); sige.release();
+        vis.release(); F0.release(); F1.release(); SG0.release(); SG1.release();
+        vsum.release(); ridx.release(); rmask.release(); rseg.release();
+        lv.release();
+        bst.release(); bval.release(); bq.release(); blo.release();
+        bslots = 0;
+        bn = 0;
+        bepoch = 0;
+        wpend.release(); wflag.release(); wfa.release(); wfb.release();
+        wgv.release(); wgq.release(); wglo.release(); wgbase.release();
+        wgn = 0;
     }
     void release()
     {
@@ -232,6 +253,8 @@ struct Work {
         lane_row.release(); sort_tmp.release(); draw_src.release(); draw_dst.release();
         bst.release(); bval.release(); bq.release(); blo.release();
         wpend.release(); wflag.release(); wfa.release(); wfb.release();
+        wgv.release(); wgq.release(); wglo.release(); wgbase.release();
+        wgn = 0;
         bslots = 0;
         bn = 0;
         bepoch = 0;
@@ -452,6 +475,25 @@ void launch_hot(bc_graph *g, int kernel, int grid, K fn, A... args)
     HIPX(hipEventRecord(p.stop, g->stream));
     g->pending.push_back(p);
     if (g->pending.size() >= 256) prof_flush(g);
+}
+
+// launch_hot for a kernel whose workgroups are `block` threads wide
+template <class K, class... A>
+void launch_wide(bc_graph *g, int kernel, int grid, int block, K fn, A... args)
+{
+    bc_graph::Pending p{kernel, nullptr, nullptr};
+    if (g->prof_on) {
+        p.start = take_event(g);
+        p.stop = take_event(g);
+        HIPX(hipEventRecord(p.start, g->stream));
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, g->stream, args...);
+    HIPX(hipGetLastError());
+    if (g->prof_on) {
+        HIPX(hipEventRecord(p.stop, g->stream));
+        g->pending.push_back(p);
+        if (g->pending.size() >= 256) prof_flush(g);
+    }
 }
 
 // Lay out the record entries and pool segments of the level now in `nxt`
@@ -810,7 +852,7 @@ bool per_source_schedule(const bc_graph *g) { return g->cfg.schedule == BC_SCHED
 
 // ------------------------------------------------------ engine selection
 
-enum Engine { ENG_WAVE = 0, ENG_PAIR = 1 };
+enum Engine { ENG_WAVE = 0, ENG_PAIR = 1, ENG_WG = 2 };
 constexpr int kDeepGraphLevels = 32;
 
 // Wave-per-word batching pays off when a vertex sits at few distinct levels
@@ -841,8 +883,15 @@ Engine engine_for(bc_graph *g)
     if (g->weighted) return ENG_PAIR;   // the layout of the weighted engine
     if (g->cfg.schedule == BC_SCHED_BATCHED) return ENG_WAVE;
     if (g->cfg.schedule == BC_SCHED_THREADED) return ENG_PAIR;
+    if (g->cfg.schedule == BC_SCHED_WORKGROUP) return ENG_WG;
     if (g->engine < 0) g->engine = probe_depth(g) > kDeepGraphLevels ? ENG_PAIR : ENG_WAVE;
     return (Engine)g->engine;
+}
+
+int32_t schedule_of(Engine e)
+{
+    return e == ENG_PAIR ? BC_SCHED_THREADED
+                         : e == ENG_WG ? BC_SCHED_WORKGROUP : BC_SCHED_BATCHED;
 }
 
 // ------------------------------------------------------ pair-per-thread engine
@@ -1188,10 +1237,11 @@ int64_t run_weighted(bc_graph *g, int B, int nvalid, bool pair)
     std::vector<int64_t> off{0, nvalid};
     for (;;) {
         const int64_t s0 = off[off.size() - 2], s1 = off.back();
-        launch_hot(g, PROF_W_COUNTS, grid_for(s1 - s0), k_w_sigma, a, s0, s1);
+        launch(s, grid_for(s1 - s0), k_w_release, a, s0, s1);
         read_ctl(g);
         const int64_t t = (int64_t)w.h_ctl[CTL_TAIL];
         if (t == s1) break;
+        launch_hot(g, PROF_W_COUNTS, grid_for(t - s1), k_w_sigma, a, s1, t);
         off.push_back(t);
     }
     if (w.h_ctl[CTL_SIG_OVERFLOW])
@@ -1237,6 +1287,122 @@ void weighted_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32
         g->stats.batches += 1;
         g->stats.samples_executed += count;
     }
+    HIPX(hipStreamSynchronize(s));
+    prof_flush(g);
+}
+
+// ------------------------------------------------- one workgroup per source
+
+constexpr int kWgSlotsMax = 1024;
+// sources per slot per launch (bounds a launch's duration)
+constexpr int64_t kWgPerSlot = 64;
+
+size_t wg_slot_bytes(int64_t n)
+{
+    // vertex record, list entry, level start; base
+    return (size_t)n * (sizeof(WgVert) + 8) + 8;
+}
+
+// Sources in flight: the configured width or up to kWgSlotsMax, at most the
+// request, within 70 % of the free device memory (held slots count).
+int plan_wg(bc_graph *g, int64_t want, int default_cap)
+{
+    const Work &w = *g->w;
+    const size_t held = w.wgv.bytes() + w.wgq.bytes() + w.wglo.bytes() + w.wgbase.bytes();
+    const size_t budget = (free_device_bytes() + held) / 10 * 7;
+    int S = g->cfg.batch ? g->cfg.batch : std::min(default_cap, kWgSlotsMax);
+    S = (int)std::max<int64_t>(1, std::min<int64_t>(S, want));
+    while (S > 1 && (size_t)S * wg_slot_bytes(g->n) > budget) S /= 2;
+    return S;
+}
+
+void ensure_wg(bc_graph *g, int S, bool ext, bool sum)
+{
+    Work &w = *g->w;
+    const int64_t n = g->n;
+    const size_t cells = (size_t)S * n;
+    if (w.wgv.cap < cells || w.wgn != n) {
+        // distances all below every slot's base (0)
+        w.wgv.release();
+        w.wgv.ensure(cells);
+        launch(g->stream, grid_for((int64_t)cells), k_wg_clear, w.wgv.p, (int64_t)cells);
+        w.wgbase.release();
+        w.wgbase.ensure((size_t)S);
+        launch(g->stream, grid_for(S), k_fill_i32, w.wgbase.p, (int32_t)0, (int64_t)S);
+        w.wgn = n;
+    }
+    w.wgq.ensure(cells);
+    w.wglo.ensure((size_t)S * (n + 1));
+}
+
+// dependencies_impl on the one-workgroup-per-source engine. A pass whose plain
+// counts reach 2^1000 restarts the call with extended counts.
+void wg_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32_t mode, double *out,
+                     int32_t *dist_out, double *sig_m, int32_t *sig_e, bool pair,
+                     const int32_t *dests, const int32_t *targets, int32_t T)
+{
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    Work &w = *g->w;
+    const int S = plan_wg(g, k, g->tuned_batch ? g->tuned_batch : kWgSlotsMax);
+    const bool sum = mode == BC_OUT_SUM;
+    bool ext = g->ext_sticky;
+    int64_t launches = 0;
+    for (;;) {
+        ensure_wg(g, S, ext, sum);
+        if (sum) launch(s, grid_for((int64_t)S * n), k_wg_zero_sum, w.wgv.p, (int64_t)S * n);
+        if (mode == BC_OUT_FULL && out) launch(s, grid_for(k * n), k_fill_f64, out, 0.0, k * n);
+        zero_ctl(g);
+        w.wgn = 0;   // a launch that does not complete leaves the slots unknown
+        for (int64_t c0 = 0; c0 < k; c0 += (int64_t)S * kWgPerSlot) {
+            const int count = (int)std::min<int64_t>((int64_t)S * kWgPerSlot, k - c0);
+            WgArgs a;
+            a.row = g->row.p;
+            a.col = g->col.p;
+            a.rrow = g->rrow();
+            a.rcol = g->rcol();
+            a.n = n;
+            a.srcs = sources + c0;
+            a.dest = pair ? dests + c0 : nullptr;
+            a.count = count;
+            a.vert = w.wgv.p;
+            a.base = w.wgbase.p;
+            a.q = w.wgq.p;
+            a.lo = w.wglo.p;
+            a.sum = sum ? 1 : 0;
+            a.full = mode == BC_OUT_FULL && out ? out + c0 * n : nullptr;
+            a.tgt = mode == BC_OUT_TARGETS ? out + c0 * T : nullptr;
+            a.targets = targets;
+            a.T = mode == BC_OUT_TARGETS ? T : 0;
+            a.dist_out = dist_out ? dist_out + c0 * n : nullptr;
+            a.sig_m = sig_m ? sig_m + c0 * n : nullptr;
+            a.sig_e = sig_e ? sig_e + c0 * n : nullptr;
+            a.ctl = w.ctl.p;
+            a.prof = g->prof_on ? g->prof_dev.p : nullptr;
+            const int grid = std::min(S, count);
+            if (ext) launch_wide(g, PROF_WG, grid, kWgBlock, k_wg<true>, a);
+            else launch_wide(g, PROF_WG, grid, kWgBlock, k_wg<false>, a);
+            ++launches;
+            if (g->timed) {
+                HIPX(hipStreamSynchronize(s));
+                check_deadline(g);
+            }
+        }
+        read_ctl(g);
+        w.wgn = n;
+        if (!ext && w.h_ctl[CTL_SIG_OVERFLOW]) {
+            ext = true;
+            g->ext_sticky = true;
+            continue;
+        }
+        break;
+    }
+    if (sum) launch(s, grid_for(n), k_wg_reduce, (const WgVert *)w.wgv.p, (int32_t)S, n, out);
+    g->stats.schedule = BC_SCHED_WORKGROUP;
+    g->stats.batch_width = S;
+    g->stats.batches = launches;
+    g->stats.samples_executed = k;
+    g->stats.extended = ext ? 1 : 0;
     HIPX(hipStreamSynchronize(s));
     prof_flush(g);
 }
@@ -1501,6 +1667,11 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         return;
     }
 
+    if (!fixed && engine_for(g) == ENG_WG) {
+        wg_dependencies(g, sources, k, mode, out, dist_out, sig_m, sig_e, pair, dests, targets,
+                        T);
+        return;
+    }
     if (!fixed && engine_for(g) == ENG_PAIR) {
         const int B = plan_pairs(g, k, g->tuned_batch ? g->tuned_batch : 512);
         g->stats.batch_width = B;
@@ -1614,7 +1785,7 @@ void pair_dependencies_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, 
         st.batch_width = std::max(st.batch_width, g->stats.batch_width);
         st.pair_search = BC_PAIR_SEARCH_ONE_SIDED;
     }
-    st.schedule = engine_for(g) == ENG_PAIR ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
+    st.schedule = schedule_of(engine_for(g));
     HIPX(hipStreamSynchronize(s));
     prof_flush(g);
     g->stats = st;
@@ -1657,7 +1828,8 @@ int fit_width(bc_graph *g, Engine e, int want)
 {
     bc_config keep = g->cfg;
     g->cfg.batch = want;
-    const int B = e == ENG_PAIR ? plan_pairs(g, want, want) : plan_batch(g, want, want).B;
+    const int B = e == ENG_PAIR ? plan_pairs(g, want, want)
+                  : e == ENG_WG ? plan_wg(g, want, want) : plan_batch(g, want, want).B;
     g->cfg = keep;
     return B;
 }
@@ -1700,6 +1872,8 @@ bc_config tune_plan(bc_graph *g)
             // size the plan's buffers first, so that allocation is not timed
             if (c.schedule == BC_SCHED_THREADED) {
                 ensure_pairs(g, c.batch, g->ext_sticky);
+            } else if (c.schedule == BC_SCHED_WORKGROUP) {
+                ensure_wg(g, plan_wg(g, k, c.batch), g->ext_sticky, true);
             } else {
                 const Plan p = plan_batch(g, k, c.batch);
                 ensure_batch(g, p, g->ext_sticky, start_cap(g), OUT_VSUM);
@@ -1732,7 +1906,7 @@ bc_config tune_plan(bc_graph *g)
     };
     auto make = [&](Engine e, int B) {
         bc_config c{};
-        c.schedule = e == ENG_PAIR ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
+        c.schedule = schedule_of(e);
         c.batch = fit_width(g, e, B);
         return c;
     };
@@ -1743,12 +1917,20 @@ bc_config tune_plan(bc_graph *g)
         const int64_t k_eng = std::min<int64_t>(n, 256);
         trial(make(first, first == ENG_PAIR ? 512 : 2048), k_eng);
         trial(make(second, second == ENG_PAIR ? 512 : 2048), k_eng);
+        trial(make(ENG_WG, 1024), k_eng);
         // 2. batch width, widest first (buffers grow once), up to the first
         // width that holds all n sources; each timed on a batch of its width
-        const Engine e = best.schedule == BC_SCHED_THREADED ? ENG_PAIR : ENG_WAVE;
+        const Engine e = best.schedule == BC_SCHED_THREADED    ? ENG_PAIR
+                         : best.schedule == BC_SCHED_WORKGROUP ? ENG_WG
+                                                               : ENG_WAVE;
         have = false;
         int prev = 0;
-        for (int W : kTuneWidths) {
+        // one workgroup per source: fewer passes in flight keep more of the
+        // slots' records in cache, so narrower widths are candidates too
+        static const int kWgWidths[] = {1024, 512, 256, 128, 64};
+        const bool wg = e == ENG_WG;
+        for (int W : wg ? std::vector<int>(std::begin(kWgWidths), std::end(kWgWidths))
+                        : std::vector<int>(std::begin(kTuneWidths), std::end(kTuneWidths))) {
             if (W > 2 * n && W > 256) continue;
             bc_config c = make(e, W);
             if (c.batch == prev) continue;
@@ -1772,7 +1954,7 @@ bc_config tune_plan(bc_graph *g)
                 c.split_entries = sp;
                 trial(c, 0);
             }
-        } else {
+        } else if (e == ENG_PAIR) {
             // a persistent loop cannot be abandoned mid-launch: it is tried
             // where a batch takes under 50 ms (many short levels)
             int coop = 0;
@@ -1790,6 +1972,8 @@ bc_config tune_plan(bc_graph *g)
     }
     sample.release();
     out.release();
+    // the candidates' buffers go back: the winner sizes its own from free memory
+    g->w->release_engines();
     g->cfg = user;
     g->tuned_batch = user_batch;
     if (!have) fail(BC_E_DEVICE, "no tuning candidate finished");
@@ -1829,7 +2013,8 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
     hipStream_t s = g->stream;
     g->stats = bc_stats{};
     if (T == 0) return;
-    const bool use_pairs = engine_for(g) == ENG_PAIR;
+    // the one-workgroup-per-source engine hands sampler rounds to the pair engine
+    const bool use_pairs = engine_for(g) != ENG_WAVE;
     // round width: the configured one, else 256 source samples or 2048 pair
     // samples (a sampler's stop rule sees samples in draw order, so a round
     // runs ahead of it by up to its width; pair searches stop early, and wider
@@ -2206,7 +2391,7 @@ bc_status bc_graph_configure(bc_graph *g, const bc_config *cfg)
 {
     return guarded([&] {
         need(g && cfg, "null argument");
-        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_TUNED,
+        need(cfg->schedule >= BC_SCHED_AUTO && cfg->schedule <= BC_SCHED_WORKGROUP,
              "unknown schedule");
         const int b = cfg->batch;
         need(b == 0 || (b >= 64 && b <= 4096 && (b & (b - 1)) == 0),
@@ -2245,7 +2430,7 @@ bc_status bc_graph_plan(bc_graph *g, bc_config *out)
         ensure_tuned(g);
         bc_config c = g->cfg;
         if (c.schedule == BC_SCHED_AUTO)
-            c.schedule = engine_for(g) == ENG_PAIR ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
+            c.schedule = schedule_of(engine_for(g));
         if (c.batch == 0) c.batch = g->tuned_batch;
         *out = c;
     });
@@ -2306,13 +2491,13 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
                                                   "sigma_pull", "backward", "level_record",
                                                   "backward_split", "pair_forward",
                                                   "pair_backward", "bidir_pair", "w_search",
-                                                  "w_counts", "w_backward"};
+                                                  "w_counts", "w_backward", "wg_pass"};
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
         static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0,
-                                                   36.0, 12.0, 16.0, 24.0};
+                                                   36.0, 12.0, 16.0, 24.0, 36.0};
         static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0,
-                                                   12.0, 0.0, 20.0, 28.0};
+                                                   12.0, 0.0, 20.0, 28.0, 12.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];

@@ -35,6 +35,30 @@ constexpr int kBiBlock = 256;
 static_assert(kBiBlock == kBlock, "k_bidir runs on the common workgroup size");
 constexpr int kBiSmall = 32;   // rows up to this many arcs are walked by one thread
 
+// long rows a phase queues in LDS; more take a second scan of the range
+constexpr int kRowQ = 512;
+
+// The queue of long rows shared by a workgroup's phases (bi_rows). Its count
+// rotates over three slots: phase k appends to slot k % 3 and clears slot
+// (k+1) % 3 before its barrier; the last read of that slot (phase k-2, after
+// its own barrier) and the next appends (phase k+1, after phase k's barrier)
+// are both ordered with the clear by barriers.
+struct RowQ {
+    int32_t w[kRowQ];
+    int cnt[3];
+    int ovf[3];
+};
+
+// before the first phase; a barrier must follow before the first bi_rows
+__device__ __forceinline__ void rowq_init(RowQ &rq)
+{
+    if (threadIdx.x < 3) {
+        rq.cnt[threadIdx.x] = 0;
+        rq.ovf[threadIdx.x] = 0;
+    }
+}
+
+
 struct BiArgs {
     // adjacency by direction: [0] out-arcs, [1] in-arcs. Side s expands over
     // adj[s] and sums path counts over adj[1 - s].
@@ -59,8 +83,7 @@ struct BiArgs {
 };
 
 struct BiShared {
-    int32_t big[kBiBlock];   // entries of the current chunk with long rows
-    int nbig;
+    RowQ rq;
     int cnt;                 // vertices found by the current expansion
     int meet;                // the expansion found a vertex of the other side
     unsigned long long vol;  // arcs the new frontier will walk
@@ -76,6 +99,21 @@ __device__ __forceinline__ bool bi_held(uint64_t st, uint32_t ep)
     return (uint32_t)(st >> 32) == ep;
 }
 
+// Append among the active lanes of a wavefront: one LDS atomic on *cnt for
+// all lanes with want set; returns each such lane's slot (others: unused).
+// Safe in divergent code (only active lanes take part).
+__device__ __forceinline__ int bi_append(bool want, int *cnt)
+{
+    const uint64_t bal = __ballot(want);
+    if (!want) return 0;
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt, __popcll(bal));
+    base = __shfl(base, leader, kWave);
+    return base + __popcll(bal & ((1ull << lane) - 1ull));
+}
+
 // lane 0 receives the sum over the wavefront, added in a fixed tree
 __device__ __forceinline__ double bi_wave_sum(double x)
 {
@@ -85,34 +123,69 @@ __device__ __forceinline__ double bi_wave_sum(double x)
 }
 
 // For each list entry w = q[i], i in [a, b), that take(w) accepts: a row of at
-// most kBiSmall arcs goes to the entry's thread as small(w, r0, r1), a longer
-// one to a wavefront as big(w, r0, r1, lane). Ends with a barrier; a, b must
-// be uniform over the workgroup.
-template <class Take, class Small, class Big>
-__device__ __forceinline__ void bi_rows(BiShared &sh, const int32_t *q, int a, int b,
+// most kBiSmall arcs goes to one thread as small(w, r0, r1); a longer one to a
+// wavefront as big(w, r0, r1, lane), from the LDS queue (or, when more than
+// kRowQ long rows came up, by a second scan in which each wavefront's ballot
+// finds them 64 entries at a time). A long row is walked the same way either
+// way. Ends with a barrier (two when long rows came up); a, b must be uniform
+// over the workgroup, take(w) must read nothing the phase writes, and every
+// thread passes the same phase counter (from 0, after rowq_init).
+template <int kThreads = kBiBlock, class Take, class Small, class Big>
+__device__ __forceinline__ void bi_rows(RowQ &rq, int &phase, const int32_t *q, int a, int b,
                                         const int64_t *row, Take take, Small small, Big big)
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (int c = a; c < b; c += kBiBlock) {
-        if (threadIdx.x == 0) sh.nbig = 0;
-        __syncthreads();
-        const int i = c + (int)threadIdx.x;
-        if (i < b) {
-            const int32_t w = q[i];
-            if (take(w)) {
-                const int64_t r0 = row[w], r1 = row[w + 1];
-                if (r1 - r0 <= kBiSmall) small(w, r0, r1);
-                else sh.big[atomicAdd(&sh.nbig, 1)] = w;
-            }
+    const int k = phase % 3;
+    phase += 1;
+    if (threadIdx.x == 0) {
+        rq.cnt[(k + 1) % 3] = 0;
+        rq.ovf[(k + 1) % 3] = 0;
+    }
+    for (int i = a + (int)threadIdx.x; i < b; i += kThreads) {
+        const int32_t w = q[i];
+        if (!take(w)) continue;
+        const int64_t r0 = row[w], r1 = row[w + 1];
+        if (r1 - r0 <= kBiSmall) {
+            small(w, r0, r1);
+        } else {
+            const int at = bi_append(true, &rq.cnt[k]);
+            if (at < kRowQ) rq.w[at] = w;
+            else rq.ovf[k] = 1;
         }
-        __syncthreads();
-        const int nbig = sh.nbig;
-        for (int k = wave; k < nbig; k += kBiBlock / kWave) {
-            const int32_t w = sh.big[k];
+    }
+    __syncthreads();
+    const int qc = rq.cnt[k];
+    if (qc == 0) return;
+    if (!rq.ovf[k]) {
+        for (int j = wave; j < qc; j += kThreads / kWave) {
+            const int32_t w = rq.w[j];
             big(w, row[w], row[w + 1], lane);
         }
-        __syncthreads();
+    } else {
+        for (int c = a + wave * kWave; c < b; c += kThreads) {
+            const int i = c + lane;
+            int32_t w = 0;
+            int64_t r0 = 0, r1 = 0;
+            bool longrow = false;
+            if (i < b) {
+                w = q[i];
+                if (take(w)) {
+                    r0 = row[w];
+                    r1 = row[w + 1];
+                    longrow = r1 - r0 > kBiSmall;
+                }
+            }
+            uint64_t m = __ballot(longrow);
+            while (m) {
+                const int src = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const int32_t wb = __shfl(w, src, kWave);
+                const int64_t b0 = __shfl(r0, src, kWave), b1 = __shfl(r1, src, kWave);
+                big(wb, b0, b1, lane);
+            }
+        }
     }
+    __syncthreads();
 }
 
 // Sum of val[x] over the arcs [r0, r1) of `col` whose head x passes ok(x):
@@ -157,6 +230,8 @@ __global__ void __launch_bounds__(kBiBlock) k_bidir(BiArgs a)
     int32_t *lo[2] = {a.lo[0] + (int64_t)blockIdx.x * (a.n + 2),
                       a.lo[1] + (int64_t)blockIdx.x * (a.n + 2)};
     unsigned long long ua = 0, ub = 0;
+    int phase = 0;
+    rowq_init(sh.rq);   // ordered before the first phase by the loop's barriers
 
     uint32_t i = 0;
     for (int p = blockIdx.x; p < a.count; p += gridDim.x, ++i) {
@@ -198,17 +273,20 @@ __global__ void __launch_bounds__(kBiBlock) k_bidir(BiArgs a)
             const int put = f1[s];
             auto visit = [&](int32_t y) {
                 const uint64_t old = st[s][y];
-                if (!bi_held(old, ep) &&
-                    atomicCAS((unsigned long long *)&st[s][y], (unsigned long long)old,
-                              (unsigned long long)nst) == old) {
-                    q[s][put + atomicAdd(&sh.cnt, 1)] = y;
+                const bool got = !bi_held(old, ep) &&
+                                 atomicCAS((unsigned long long *)&st[s][y],
+                                           (unsigned long long)old,
+                                           (unsigned long long)nst) == old;
+                const int at = bi_append(got, &sh.cnt);
+                if (got) {
+                    q[s][put + at] = y;
                     atomicAdd(&sh.vol, (unsigned long long)(erow[y + 1] - erow[y]));
                     ++ua;
                 }
                 if (bi_held(st[o][y], ep)) sh.meet = 1;
             };
             bi_rows(
-                sh, q[s], f0[s], f1[s], erow, [](int32_t) { return true; },
+                sh.rq, phase, q[s], f0[s], f1[s], erow, [](int32_t) { return true; },
                 [&](int32_t, int64_t r0, int64_t r1) {
                     ub += (unsigned long long)(r1 - r0);
                     for (int64_t e = r0; e < r1; ++e) visit(ecol[e]);
@@ -233,7 +311,7 @@ __global__ void __launch_bounds__(kBiBlock) k_bidir(BiArgs a)
             const int32_t *pcol = a.col[o];
             auto from_level = [&](int32_t x) { return st[s][x] == pst; };
             bi_rows(
-                sh, q[s], put, put + cnt, a.row[o],
+                sh.rq, phase, q[s], put, put + cnt, a.row[o],
                 [&](int32_t w) { return !meet || bi_held(st[o][w], ep); },
                 [&](int32_t w, int64_t r0, int64_t r1) {
                     ub += (unsigned long long)(r1 - r0);
@@ -273,7 +351,7 @@ __global__ void __launch_bounds__(kBiBlock) k_bidir(BiArgs a)
                         if (st[s][y] == here) st[o][y] = far_here;
                     };
                     bi_rows(
-                        sh, q[s], lA, lB, a.row[o],
+                        sh.rq, phase, q[s], lA, lB, a.row[o],
                         [&](int32_t x) { return st[o][x] == far_above; },
                         [&](int32_t, int64_t r0, int64_t r1) {
                             ub += (unsigned long long)(r1 - r0);
@@ -291,7 +369,7 @@ __global__ void __launch_bounds__(kBiBlock) k_bidir(BiArgs a)
                         return st[s][x] == above && st[o][x] == far_above;
                     };
                     bi_rows(
-                        sh, q[s], l0, lA, a.row[s],
+                        sh.rq, phase, q[s], l0, lA, a.row[s],
                         [&](int32_t w) { return st[o][w] == far_here; },
                         [&](int32_t w, int64_t r0, int64_t r1) {
                             ub += (unsigned long long)(r1 - r0);

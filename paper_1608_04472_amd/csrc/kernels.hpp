@@ -149,7 +149,8 @@ enum : int {
     PROF_W_SEARCH = 9,   // weighted graphs: search rounds
     PROF_W_COUNTS = 10,  //   path-count rounds
     PROF_W_BACKWARD = 11,  // dependency rounds
-    PROF_KERNELS = 12
+    PROF_WG = 12,        // one workgroup per source
+    PROF_KERNELS = 13
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)

@@ -62,8 +62,8 @@ SMALL = [("dpath12", lambda: gg.directed_path(12)), ("dcycle9", lambda: gg.direc
          ("dg2", lambda: digraph(2, 300))]
 
 
-@pytest.mark.parametrize("sched", SCHEDS + [bc.BC_SCHED_PER_SOURCE],
-                         ids=["wave", "pair", "per-source"])
+@pytest.mark.parametrize("sched", SCHEDS + [bc.BC_SCHED_PER_SOURCE, bc.BC_SCHED_WORKGROUP],
+                         ids=["wave", "pair", "per-source", "wg"])
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
 def test_small_digraphs_all_sources(dev, name, make, sched):
     g = make()

@@ -86,24 +86,32 @@ def test_ba1m_pair_dependencies_from_the_stream(dev, ba):
         assert_close(got[r], O.pair_dependency(g, int(u[r]), int(v[r])), what="pair %d" % j)
 
 
-def test_grid2048_sampled_rows(dev):
+@pytest.mark.parametrize("sched", [bc.BC_SCHED_AUTO, bc.BC_SCHED_WORKGROUP], ids=["auto", "wg"])
+def test_grid2048_sampled_rows(dev, sched):
     """The percolated 2048^2 grid with its 1024 benchmark sources (seed 3):
-    automatic schedule (pair-per-thread, extended counts), rows 0 and 511 of
-    the first batch of 512 against the oracle."""
+    automatic schedule (pair-per-thread) and one workgroup per source, both
+    with extended counts; rows 0 and 511 of the first 512 against the oracle,
+    and the sum over those 512 against the sum of their rows."""
     g = gg.config_graph("grid2048")
     G = bc.Graph(g.row, g.col)
+    G.configure(sched, 0, 0.0)
     src = gg.philox_sources(3, 1024, g.n)
     t = torch.from_numpy(src[:512]).to(dev)
-    say("grid2048 full")
+    say("grid2048 full", sched)
     full, dist, sig = bc.dependencies(G, t, bc.BC_OUT_FULL, dist=True, sigma=True)
     st = G.stats()
-    assert st["schedule"] == bc.BC_SCHED_THREADED and st["extended"] == 1
+    want_sched = bc.BC_SCHED_THREADED if sched == bc.BC_SCHED_AUTO else sched
+    assert st["schedule"] == want_sched and st["extended"] == 1
     for i in (0, 511):
         d, (om, oe), de = O.brandes(g, int(src[i]))
         assert np.array_equal(dist[i].cpu().numpy(), d)
         assert_sigma(sig[0][i].cpu().numpy(), sig[1][i].cpu().numpy(), om, oe, "grid row %d" % i)
         assert_close(full[i].cpu().numpy(), de, what="grid row %d" % i)
         assert (oe > 1024).any()           # counts beyond the FP64 range occur on this row
+    del dist, sig
+    say("grid2048 sum", sched)
+    tot, _, _ = bc.dependencies(G, t, bc.BC_OUT_SUM)
+    assert_close(tot.cpu().numpy(), full.sum(0).cpu().numpy(), rtol=1e-9, what="grid sum")
     G.close()
 
 

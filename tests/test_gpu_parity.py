@@ -129,14 +129,18 @@ SMALL = [
 
 
 SCHEDS = [bc.BC_SCHED_BATCHED, bc.BC_SCHED_THREADED]
-# pair samples: the one-sided search on either engine, and the two-sided search
+# every engine of bc_dependencies: wave per word, thread per pair, workgroup
+# per source
+ENGINES = SCHEDS + [bc.BC_SCHED_WORKGROUP]
+ENGINE_IDS = ["wave", "pair", "wg"]
+# pair samples: the one-sided search on each engine, and the two-sided search
 ONE, BIDIR = bc.BC_PAIR_SEARCH_ONE_SIDED, bc.BC_PAIR_SEARCH_BIDIRECTIONAL
 PAIR_SEARCHES = [(bc.BC_SCHED_BATCHED, ONE), (bc.BC_SCHED_THREADED, ONE),
                  (bc.BC_SCHED_AUTO, BIDIR)]
 PAIR_IDS = ["wave", "pair", "bidir"]
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+@pytest.mark.parametrize("sched", ENGINES, ids=ENGINE_IDS)
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
 def test_small_graphs_all_sources(dev, name, make, sched):
     g = make()
@@ -244,7 +248,7 @@ def test_grid_counts_beyond_2_53(dev):
     G.close()
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+@pytest.mark.parametrize("sched", ENGINES, ids=ENGINE_IDS)
 def test_grid_counts_beyond_fp64_range(dev, sched):
     g = gg.grid(600, 600)
     G = bc.Graph(g.row, g.col)
@@ -254,7 +258,7 @@ def test_grid_counts_beyond_fp64_range(dev, sched):
     G.close()
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+@pytest.mark.parametrize("sched", ENGINES, ids=ENGINE_IDS)
 def test_hub_rows_with_extended_counts(dev, sched):
     # A 600x600 grid plus one hub joined to the 15x20 block of vertices in the
     # far corner: from the near corner the hub sits ~1166 levels deep, where
@@ -394,7 +398,7 @@ def test_pair_dependencies(dev, sched, search):
 
 
 @pytest.mark.parametrize("search", [ONE, BIDIR], ids=["one", "bidir"])
-@pytest.mark.parametrize("sched", SCHEDS, ids=["wave", "pair"])
+@pytest.mark.parametrize("sched", ENGINES, ids=ENGINE_IDS)
 def test_pair_dependencies_grid_extended(dev, sched, search):
     # corner to corner of the 600 x 600 grid: counts beyond 2^1000, so the
     # two-sided search hands the pairs to the one-sided engine
@@ -634,3 +638,37 @@ def test_pair_engine_level_loop_equals_per_level(dev, what):
         G.close()
     for x, y in zip(outs[0], outs[1]):
         assert np.array_equal(x, y), what
+
+
+def test_workgroup_engine_outputs_and_slots(dev):
+    """Workgroup per source: BC_OUT_SUM (per-slot sums reduced in slot order),
+    BC_OUT_TARGETS, one-sided pair rows, and more sources than slots (each
+    workgroup runs several passes, resetting its distances in between)."""
+    g = gg.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_WORKGROUP, 64, 0.0, pair_search=ONE)
+    src = gg.philox_sources(9, 700, g.n)
+    src[:3] = gg.top_degree(g, 3)
+    src[5] = src[0]
+    say("wg rmat11 700 sources on 64 slots")
+    full, want = O.dependencies(g, src, full=True, total=True)
+    tot, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+    assert G.stats()["schedule"] == bc.BC_SCHED_WORKGROUP and G.stats()["batch_width"] == 64
+    assert_close(tot.cpu().numpy(), want, what="wg sum")
+    again, _, _ = bc.dependencies(G, T(src, dev), bc.BC_OUT_SUM)
+    assert torch.equal(tot, again)
+    tg = gg.top_degree(g, 6)
+    got = bc.target_dependencies(G, T(src, dev), T(tg, dev)).cpu().numpy()
+    assert_close(got, full[:, tg], what="wg targets")
+    rows, _, _ = bc.dependencies(G, T(src[:150], dev), bc.BC_OUT_FULL)
+    assert_close(rows.cpu().numpy(), full[:150], what="wg rows")
+    us = torch.empty(120, dtype=torch.int32, device=dev)
+    vs = torch.empty(120, dtype=torch.int32, device=dev)
+    bc.bc_draw_pairs(G, 4, 0, 120, us, vs)
+    say("wg one-sided pairs")
+    p = bc.pair_dependencies(G, us, vs).cpu().numpy()
+    assert G.stats()["pair_search"] == ONE
+    u, v = us.cpu().numpy(), vs.cpu().numpy()
+    for i in range(0, 120, 5):
+        assert_close(p[i], O.pair_dependency(g, int(u[i]), int(v[i])), what="wg pair %d" % i)
+    G.close()

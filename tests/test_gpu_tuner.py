@@ -4,8 +4,9 @@ keeps results equal to the untuned library's.
 
 Candidates (bc_graph_tune): the wave engine at widths 256 .. 4096 with
 bottom_up in {0.04, 0.01, 0.15, never} and split_entries in {2^18, 2^20,
-2^22}, and the pair engine at widths 256 .. 4096 with and without its
-persistent level loop.
+2^22}, the pair engine at widths 256 .. 4096 with and without its
+persistent level loop, and one workgroup per source with 64 .. 1024
+sources in flight.
 """
 import itertools
 import sys
@@ -24,6 +25,7 @@ from test_gpu_parity import assert_close  # noqa: E402
 
 O = oracle.load()
 WIDTHS = [256, 512, 1024, 2048, 4096]
+WG_WIDTHS = [64, 128, 256, 512, 1024]
 BOTTOM_UP = [0.04, 0.01, 0.15, -1.0]
 SPLIT = [1 << 18, 1 << 20, 1 << 22]
 WAVE_PLANS = list(itertools.product(WIDTHS, BOTTOM_UP, SPLIT))
@@ -69,6 +71,15 @@ def test_every_wave_plan(case):
         assert G.stats()["batch_width"] == B
 
 
+def test_every_workgroup_plan(case):
+    g, G, s, full, tot = case
+    for B in WG_WIDTHS:
+        say("workgroup plan", B)
+        G.configure(bc.BC_SCHED_WORKGROUP, B, 0.0)
+        check(G, s, full, tot, "wg B=%d" % B)
+        assert G.stats()["batch_width"] == min(B, s.numel())
+
+
 def test_every_pair_plan(case):
     g, G, s, full, tot = case
     for B, loop in PAIR_PLANS:
@@ -84,9 +95,12 @@ def test_tuned_plan(dev, name):
     G = bc.Graph(g.row, g.col)
     say("tune", name)
     plan = G.tune()
-    assert plan["schedule"] in (bc.BC_SCHED_BATCHED, bc.BC_SCHED_THREADED)
-    assert plan["batch"] in WIDTHS
-    if plan["schedule"] == bc.BC_SCHED_BATCHED:
+    assert plan["schedule"] in (bc.BC_SCHED_BATCHED, bc.BC_SCHED_THREADED,
+                                bc.BC_SCHED_WORKGROUP)
+    assert plan["batch"] in WIDTHS + WG_WIDTHS
+    if plan["schedule"] == bc.BC_SCHED_WORKGROUP:
+        assert plan["batch"] in WG_WIDTHS
+    elif plan["schedule"] == bc.BC_SCHED_BATCHED:
         assert plan["bottom_up"] in BOTTOM_UP + [0.0] and plan["split_entries"] in SPLIT + [0]
     else:
         assert plan["level_loop"] in (0, 1, -1)
