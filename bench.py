@@ -160,6 +160,7 @@ def serving_leg(args, bc, gg):
     log("serving: %d graphs (%d CSR entries) and %d queries generated in %.1fs" % (
         len(graphs), sum(g.nnz for g in graphs), len(qs), time.time() - t))
     S = bc.Server(args.serve_budget_gib << 30, args.serve_batch)
+    S.set_lanes(args.serve_lanes)       # before admission: widths fit one workspace per lane
     for g in graphs:
         S.add_graph(g.row, g.col)
     N = len(qs)
@@ -193,7 +194,7 @@ def serving_leg(args, bc, gg):
         "workload": "%d R-MAT graphs (scale 10-18, edge factor 8-32, seeds 100-%d), %d queries "
                     "at %.0f q/s Poisson (seed 3), half source (c 2/5/10), half pair "
                     "(eps 0.05/0.1)" % (len(graphs), 99 + len(graphs), N, args.serve_rate),
-        "queries": N, "arrival_rate_qps": args.serve_rate,
+        "queries": N, "arrival_rate_qps": args.serve_rate, "lanes": args.serve_lanes,
         "achieved_qps": N / makespan, "makespan_s": makespan,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "max_ms": float(lat.max()), "rounds": st["rounds"],
@@ -214,8 +215,9 @@ def serving_leg(args, bc, gg):
                                         status=r["status"],
                                         latency_ms=(r["done_s"] - r["arrival_s"]) * 1e3)) + "\n")
     S.close()
-    log("serving: p50 %.1f ms, p99 %.1f ms, %.1f q/s achieved over %.1f s, %d rounds" % (
-        out["p50_ms"], out["p99_ms"], out["achieved_qps"], makespan, st["rounds"]))
+    log("serving (%d lanes): p50 %.1f ms, p99 %.1f ms, %.1f q/s achieved over %.1f s, %d rounds, "
+        "capped %.2f" % (args.serve_lanes, out["p50_ms"], out["p99_ms"], out["achieved_qps"],
+                         makespan, st["rounds"], out["capped_fraction"]))
     return out
 
 
@@ -513,7 +515,9 @@ def main():
                     help="prefix of the 20,000-query stream to serve (the whole stream "
                          "exceeds one GPU's capacity)")
     ap.add_argument("--serve-rate", type=float, default=500.0)
-    ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=128)
+    ap.add_argument("--serve-lanes", type=int, default=4,
+                    help="serving rounds of this many graphs at once (own streams)")
     ap.add_argument("--serve-batch", type=int, default=4096,
                     help="samples per server round (power of two, 64..4096)")
     ap.add_argument("--no-serve", action="store_true")

@@ -376,8 +376,13 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
  * Scheduling: shortest job first at graph granularity (the graph whose
  * cheapest unfinished query has the smallest bound (k_max - k) * nnz runs the
  * next round), with every eighth round given to the graph of the oldest
- * unfinished query so that no query starves.
- * Not thread-safe: one host thread drives a server. */
+ * unfinished query so that no query starves. With several lanes
+ * (bc_server_set_lanes) a step runs one round on each of up to that many
+ * graphs at once, the next graphs by the same rule, each on its own stream
+ * and workspace; every query's samples and results are the same as with one
+ * lane (a query's rounds never run concurrently).
+ * Not thread-safe: one host thread drives a server (the lanes' host threads
+ * are the server's own). */
 typedef struct bc_server bc_server;
 
 typedef enum { BC_QUERY_SOURCE = 0, BC_QUERY_PAIR = 1 } bc_query_kind;
@@ -406,16 +411,23 @@ typedef struct {
 } bc_result;
 
 /* hbm_budget_bytes bounds the device memory the server holds: the resident
- * graphs (CSR, lane-order keys) plus the shared engine workspace. alloc as in
- * bc_graph_create (NULL = hipMalloc). */
+ * graphs (CSR, lane-order keys) plus the engine workspace of each lane. alloc
+ * as in bc_graph_create (NULL = hipMalloc). */
 bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch,
                            const bc_allocator *alloc, void *hip_stream, bc_server **out);
 void bc_server_destroy(bc_server *s);
 bc_status bc_server_add_graph(bc_server *s, const bc_csr *csr, int32_t *graph_id);
 bc_status bc_server_submit(bc_server *s, const bc_query *q, int64_t *id);
-/* Run one round; *completed receives the number of queries it finished
- * (0 and no device work when nothing is queued). */
+/* Run one round per lane (on distinct graphs); *completed receives the number
+ * of queries they finished (0 and no device work when nothing is queued). */
 bc_status bc_server_step(bc_server *s, int32_t *completed);
+/* Lanes: rounds of different graphs run concurrently, each lane with its own
+ * stream (created by the server, default priority; lane 0 is the caller's
+ * stream) and its own workspace. 1 <= lanes <= 4 (default 1). The budget then
+ * holds the resident graphs plus one workspace per lane: BC_E_INVALID when
+ * the admitted graphs' widest need times lanes does not fit; graphs added
+ * later are sized for the current number of lanes. */
+bc_status bc_server_set_lanes(bc_server *s, int32_t lanes);
 /* Move up to max finished results (completion order) into out. */
 bc_status bc_server_poll(bc_server *s, bc_result *out, int32_t max, int32_t *count);
 bc_status bc_server_now(const bc_server *s, double *now_s);
@@ -427,7 +439,7 @@ typedef struct {
     int64_t samples_executed; /* slots run, including those past a query's stop */
     int64_t samples_used;     /* samples counted by the stopping rules */
     int64_t resident_bytes;   /* graphs' device CSR and lane-order keys */
-    int64_t workspace_bytes;  /* shared engine workspace held now */
+    int64_t workspace_bytes;  /* the lanes' engine workspaces held now */
     int64_t budget_bytes;     /* the budget: resident + workspace never exceed it */
     int64_t split_rounds;     /* rounds run in halves to stay within the budget */
 } bc_server_stats;

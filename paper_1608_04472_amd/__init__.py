@@ -49,7 +49,7 @@ EXPORTS = [
     "bc_adaptive_source", "bc_adaptive_pair", "bc_draw_sources", "bc_draw_pairs",
     "bc_last_stats", "bc_last_error", "bc_profile_enable", "bc_profile_read",
     "bc_server_create", "bc_server_destroy", "bc_server_add_graph", "bc_server_submit",
-    "bc_server_step", "bc_server_poll", "bc_server_now", "bc_server_stats_get",
+    "bc_server_step", "bc_server_set_lanes", "bc_server_poll", "bc_server_now", "bc_server_stats_get",
     "bc_server_graph_width",
 ]
 BC_QUERY_SOURCE, BC_QUERY_PAIR = 0, 1
@@ -216,6 +216,7 @@ def load_library(path: str | None = None):
         "bc_server_add_graph": [V, c.POINTER(_Csr), c.POINTER(c.c_int32)],
         "bc_server_submit": [V, c.POINTER(_Query), c.POINTER(c.c_int64)],
         "bc_server_step": [V, c.POINTER(c.c_int32)],
+        "bc_server_set_lanes": [V, c.c_int32],
         "bc_server_poll": [V, c.POINTER(_Result), c.c_int32, c.POINTER(c.c_int32)],
         "bc_server_now": [V, c.POINTER(c.c_double)],
         "bc_server_stats_get": [V, c.POINTER(_ServerStats)],
@@ -382,6 +383,10 @@ class Server:
         qid = ctypes.c_int64()
         _check(_lib.bc_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid)))
         return qid.value
+
+    def set_lanes(self, lanes: int):
+        """Rounds of up to `lanes` graphs at once, each on its own stream."""
+        _check(_lib.bc_server_set_lanes(self._h, int(lanes)))
 
     def step(self) -> int:
         done = ctypes.c_int32()

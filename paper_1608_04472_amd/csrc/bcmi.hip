@@ -26,9 +26,12 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <exception>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -82,6 +85,11 @@ struct Alloc {
 // The allocator of the handle the current ABI call works on (one per host
 // thread; null = hipMalloc).
 thread_local const Alloc *tl_alloc = nullptr;
+// A stream whose work may still use buffers this thread frees: set while a
+// server runs rounds on several streams, so that memory the caller's allocator
+// hands out again is idle (buffers freed on one lane are not reused under
+// another lane's pending work).
+thread_local hipStream_t tl_sync = nullptr;
 
 struct UseAlloc {
     const Alloc *prev;
@@ -119,6 +127,7 @@ struct DBuf {
     void release()
     {
         if (p && !borrowed) {
+            if (tl_sync) (void)hipStreamSynchronize(tl_sync);
             if (from) from->put(p);
             else (void)hipFree(p);
         }
@@ -2878,33 +2887,16 @@ int widest_width(Engine e, int64_t n, int max_batch)
 
 }  // namespace
 
-struct bc_server {
-    int device = 0;
+// One lane of a server: a stream and the workspace of the rounds it runs.
+struct ServerLane {
     hipStream_t stream = nullptr;
-    Alloc alloc;
-    size_t budget = 0;
-    size_t resident = 0;               // graphs' CSR and lane-order keys
-    int max_batch = 256;
+    bool own_stream = false;   // created by the server (lanes beyond the first)
     Work work;
-    WsNeed ws;                         // budgeted workspace, per buffer
-    std::vector<bc_graph *> graphs;
-    std::vector<int> width;            // batch width per graph
-    std::deque<ServerQuery> queued;    // arrival order
-    std::vector<std::vector<ServerQuery>> active;
-    std::deque<bc_result> done;
-    int64_t next_id = 0, finished = 0, rounds = 0, samples_exec = 0, samples_used = 0;
-    int64_t split_rounds = 0;
     DBuf<QueryDesc> qd;
     DBuf<int32_t> slotq, tgt;
     DBuf<double> X;
-    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
-    double now() const
-    {
-        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-    // device bytes the shared workspace holds now
-    size_t workspace_bytes() const
+    size_t bytes() const
     {
         const Work &w = work;
         return w.sig.bytes() + w.dlt.bytes() + w.sige.bytes() + w.vis.bytes() + w.F0.bytes() +
@@ -2920,13 +2912,58 @@ struct bc_server {
     }
     void release()
     {
-        for (auto g : graphs) bc_graph_destroy(g);
-        graphs.clear();
+        if (stream) (void)hipStreamSynchronize(stream);
         work.release();
         qd.release();
         slotq.release();
         tgt.release();
         X.release();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+};
+
+// What one lane's round produced, merged by the calling thread.
+struct LaneOut {
+    std::vector<bc_result> done;
+    int64_t samples_exec = 0, samples_used = 0, split_rounds = 0;
+    std::exception_ptr error;
+};
+
+struct bc_server {
+    int device = 0;
+    Alloc alloc;
+    size_t budget = 0;
+    size_t resident = 0;               // graphs' CSR and lane-order keys
+    int max_batch = 256;
+    std::vector<std::unique_ptr<ServerLane>> lanes;   // lane 0: the caller's stream
+    WsNeed ws;                         // budgeted workspace of one lane, per buffer
+    std::vector<bc_graph *> graphs;
+    std::vector<int> width;            // batch width per graph
+    std::deque<ServerQuery> queued;    // arrival order
+    std::vector<std::vector<ServerQuery>> active;
+    std::deque<bc_result> done;
+    int64_t next_id = 0, finished = 0, rounds = 0, samples_exec = 0, samples_used = 0;
+    int64_t split_rounds = 0;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    // device bytes the lanes' workspaces hold now
+    size_t workspace_bytes() const
+    {
+        size_t t = 0;
+        for (const auto &l : lanes) t += l->bytes();
+        return t;
+    }
+    void release()
+    {
+        for (auto g : graphs) bc_graph_destroy(g);
+        graphs.clear();
+        for (auto &l : lanes) l->release();
+        lanes.clear();
     }
 };
 
@@ -2937,55 +2974,54 @@ namespace {
 // X[lo..hi). A batch whose level record would outgrow the budgeted workspace
 // runs as two halves (each sample's arithmetic does not depend on its batch
 // mates, so the values are the same).
-void run_slots(bc_server *sv, bc_graph *g, Engine e, int B, int lo, int hi)
+void run_slots(ServerLane &ln, LaneOut &out, bc_graph *g, Engine e, int B, int lo, int hi)
 {
     const int cnt = hi - lo;
     const int64_t n = g->n;
-    hipStream_t st = sv->stream;
+    hipStream_t st = ln.stream;
     try {
         bool ext = false;
         if (e == ENG_PAIR) {
             ensure_pairs(g, B, false);
-            launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)sv->qd.p,
-                   (const int32_t *)sv->slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
-                   g->w->dest.p, sv->tgt.p);
+            launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)ln.qd.p,
+                   (const int32_t *)ln.slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
+                   g->w->dest.p, ln.tgt.p);
             run_pairs(g, B, cnt, true, &ext, nullptr);
             PairArgs a = make_pair_args(g, B, ext, cnt, true);
-            launch(st, grid_for(cnt), k_p_gather_slots, a, (const int32_t *)sv->tgt.p,
-                   (int32_t)lo, sv->X.p);
+            launch(st, grid_for(cnt), k_p_gather_slots, a, (const int32_t *)ln.tgt.p,
+                   (int32_t)lo, ln.X.p);
         } else {
             Plan p;
             p.B = B;
             while ((64 << p.logW) < B) ++p.logW;
             ensure_batch(g, p, false, start_cap(g), OUT_DELTA);
-            launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)sv->qd.p,
-                   (const int32_t *)sv->slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
-                   g->w->dest.p, sv->tgt.p);
+            launch(st, grid_for(cnt), k_serve_draw, (const QueryDesc *)ln.qd.p,
+                   (const int32_t *)ln.slotq.p, (int32_t)lo, (int32_t)cnt, n, g->w->srcs.p,
+                   g->w->dest.p, ln.tgt.p);
             const int32_t *lane_row = order_round(g, cnt, true, B);
             run_batch(g, p, cnt, true, &ext, nullptr, OUT_DELTA);
             BatchArgs a = make_args(g, p, ext, cnt, true, (int64_t)g->w->ridx.cap, OUT_DELTA);
             a.lane_row = lane_row;
-            launch(st, grid_for(cnt), k_gather_slots, a, (const int32_t *)sv->tgt.p, (int32_t)lo,
-                   sv->X.p);
+            launch(st, grid_for(cnt), k_gather_slots, a, (const int32_t *)ln.tgt.p, (int32_t)lo,
+                   ln.X.p);
         }
     } catch (const RecordLimit &) {
         // a single sample reaches at most n (vertex, word) entries, within the
         // 4 n W entries budgeted for any width, so halving always ends
         if (cnt <= 1) fail(BC_E_NOMEM, "level record exceeds the server's budget");
         (void)hipStreamSynchronize(st);
-        sv->split_rounds += 1;
+        out.split_rounds += 1;
         const int mid = lo + cnt / 2;
-        run_slots(sv, g, e, B, lo, mid);
-        run_slots(sv, g, e, B, mid, hi);
+        run_slots(ln, out, g, e, B, lo, mid);
+        run_slots(ln, out, g, e, B, mid, hi);
     }
 }
 
-void server_round(bc_server *sv, int gi, int32_t *completed)
+// Admit waiting queries of graph gi in arrival order while slots remain.
+void admit(bc_server *sv, int gi)
 {
-    bc_graph *g = sv->graphs[gi];
-    std::vector<ServerQuery> &act = sv->active[gi];
-    const int B = sv->width[gi];
-    // admit waiting queries of this graph in arrival order while slots remain
+    std::vector<ServerQuery> &act = sv->active[(size_t)gi];
+    const int B = sv->width[(size_t)gi];
     for (auto it = sv->queued.begin(); it != sv->queued.end() && (int)act.size() < B;) {
         if (it->q.graph == gi) {
             act.push_back(*it);
@@ -2994,6 +3030,17 @@ void server_round(bc_server *sv, int gi, int32_t *completed)
             ++it;
         }
     }
+}
+
+// One round of graph gi's active queries on lane ln: fill the batch's slots,
+// run them, apply the stop rules. Touches only graph gi's state and the
+// lane's, so rounds of different graphs run on different lanes at once;
+// finished queries and counts go to `out` for the calling thread to merge.
+void server_round(bc_server *sv, ServerLane &ln, int gi, LaneOut &out)
+{
+    bc_graph *g = sv->graphs[(size_t)gi];
+    std::vector<ServerQuery> &act = sv->active[(size_t)gi];
+    const int B = sv->width[(size_t)gi];
     const int A = (int)act.size();
     const int64_t n = g->n;
     std::vector<QueryDesc> hd((size_t)A);
@@ -3022,28 +3069,28 @@ void server_round(bc_server *sv, int gi, int32_t *completed)
         for (int k = 0; k < d.nslots; ++k) hslot.push_back(i);
     }
     const int nb = (int)hslot.size();
-    hipStream_t st = sv->stream;
+    hipStream_t st = ln.stream;
     g->stream = st;
-    sv->qd.ensure((size_t)B);
-    sv->slotq.ensure((size_t)B);
-    sv->tgt.ensure((size_t)B);
-    sv->X.ensure((size_t)B);
-    HIPX(hipMemcpyAsync(sv->qd.p, hd.data(), hd.size() * sizeof(QueryDesc),
+    g->w = &ln.work;
+    ln.qd.ensure((size_t)B);
+    ln.slotq.ensure((size_t)B);
+    ln.tgt.ensure((size_t)B);
+    ln.X.ensure((size_t)B);
+    HIPX(hipMemcpyAsync(ln.qd.p, hd.data(), hd.size() * sizeof(QueryDesc),
                         hipMemcpyHostToDevice, st));
-    HIPX(hipMemcpyAsync(sv->slotq.p, hslot.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st));
-    run_slots(sv, g, engine_for(g), B, 0, nb);
-    launch(st, grid_for(A), k_stop_queries, sv->qd.p, (int32_t)A, (const double *)sv->X.p);
-    HIPX(hipMemcpyAsync(hd.data(), sv->qd.p, hd.size() * sizeof(QueryDesc),
+    HIPX(hipMemcpyAsync(ln.slotq.p, hslot.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st));
+    run_slots(ln, out, g, engine_for(g), B, 0, nb);
+    launch(st, grid_for(A), k_stop_queries, ln.qd.p, (int32_t)A, (const double *)ln.X.p);
+    HIPX(hipMemcpyAsync(hd.data(), ln.qd.p, hd.size() * sizeof(QueryDesc),
                         hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
     const double t = sv->now();
-    int fin = 0;
     std::vector<ServerQuery> keep;
     keep.reserve(act.size());
     for (int i = 0; i < A; ++i) {
         ServerQuery sq = act[(size_t)i];
         const QueryDesc &d = hd[(size_t)i];
-        sv->samples_used += d.K - sq.K;
+        out.samples_used += d.K - sq.K;
         sq.S = d.S;
         sq.K = d.K;
         if (d.status == ST_RUNNING) {
@@ -3059,19 +3106,60 @@ void server_round(bc_server *sv, int gi, int32_t *completed)
         r.S = d.S;
         r.arrival_s = sq.arrival;
         r.done_s = t;
-        sv->done.push_back(r);
-        ++fin;
+        out.done.push_back(r);
     }
     act.swap(keep);
-    sv->finished += fin;
-    sv->rounds += 1;
-    sv->samples_exec += nb;
-    *completed = fin;
+    out.samples_exec += nb;
+}
+
+// Graph of the next round: shortest job first at graph granularity (the
+// graph whose cheapest unfinished query has the least remaining work bound,
+// (k_max - k) samples times the CSR size); every eighth round goes to the
+// graph of the oldest unfinished query, so no query starves. Graphs in
+// `busy` are skipped; -1 when none has work.
+int pick_graph(const bc_server *sv, const std::vector<int> &busy, bool oldest_rule)
+{
+    const int G = (int)sv->graphs.size();
+    auto taken = [&](int g) { return std::find(busy.begin(), busy.end(), g) != busy.end(); };
+    int gi = -1;
+    if (oldest_rule) {
+        double oldest = 0.0;
+        for (int i = 0; i < G; ++i) {
+            if (taken(i)) continue;
+            for (const auto &q : sv->active[(size_t)i])
+                if (gi < 0 || q.arrival < oldest) {
+                    gi = i;
+                    oldest = q.arrival;
+                }
+        }
+        for (const auto &q : sv->queued)
+            if (!taken(q.q.graph) && (gi < 0 || q.arrival < oldest)) {
+                gi = q.q.graph;
+                oldest = q.arrival;
+            }
+        return gi;
+    }
+    double best = 0.0;
+    auto consider = [&](const ServerQuery &q) {
+        if (taken(q.q.graph)) return;
+        const double work = (double)(q.q.k_max - q.K) *
+                            (double)std::max<int64_t>(sv->graphs[(size_t)q.q.graph]->nnz, 1);
+        if (gi < 0 || work < best) {
+            gi = q.q.graph;
+            best = work;
+        }
+    };
+    for (int i = 0; i < G; ++i)
+        for (const auto &q : sv->active[(size_t)i]) consider(q);
+    for (const auto &q : sv->queued) consider(q);
+    return gi;
 }
 
 }  // namespace
 
 extern "C" {
+
+constexpr int kServerLanesMax = 4;
 
 bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, const bc_allocator *alloc,
                            void *hip_stream, bc_server **out)
@@ -3087,12 +3175,13 @@ bc_status bc_server_create(size_t hbm_budget_bytes, int32_t max_batch, const bc_
         UseAlloc ua(&sv->alloc);
         try {
             HIPX(hipGetDevice(&sv->device));
-            sv->stream = (hipStream_t)hip_stream;
             sv->budget = hbm_budget_bytes;
             sv->max_batch = max_batch;
             need(hbm_budget_bytes >= CTL_WORDS * sizeof(unsigned long long), "budget below 128 bytes");
-            sv->work.init();
-            sv->ws.b[WB_CTL] = sv->work.ctl.bytes();
+            sv->lanes.push_back(std::make_unique<ServerLane>());
+            sv->lanes[0]->stream = (hipStream_t)hip_stream;
+            sv->lanes[0]->work.init();
+            sv->ws.b[WB_CTL] = sv->lanes[0]->work.ctl.bytes();
         } catch (...) {
             sv->release();
             delete sv;
@@ -3106,7 +3195,6 @@ void bc_server_destroy(bc_server *sv)
 {
     if (!sv) return;
     (void)hipSetDevice(sv->device);
-    if (sv->stream) (void)hipStreamSynchronize(sv->stream);
     UseAlloc ua(&sv->alloc);
     sv->release();
     delete sv;
@@ -3124,8 +3212,10 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
         // and the handle's own control block
         const size_t res_bytes = (size_t)(n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4 +
                                  (size_t)n * 8 + CTL_WORDS * sizeof(unsigned long long);
+        // every lane may hold the widest need (one workspace per lane)
+        const size_t L = sv->lanes.size();
         auto fits = [&](const WsNeed &w) {
-            return sv->resident + res_bytes + w.total() <= sv->budget;
+            return sv->resident + res_bytes + L * w.total() <= sv->budget;
         };
         // the engine choice runs a depth probe in the shared workspace: it must fit first
         WsNeed probe;
@@ -3136,9 +3226,9 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
             fail(BC_E_NOMEM, "graph does not fit the server's HBM budget");
         bc_graph *g = nullptr;
         bc_allocator *al = sv->alloc.a.alloc ? &sv->alloc.a : nullptr;
-        const bc_status rc = bc_graph_create(csr, al, (void *)sv->stream, &g);
+        const bc_status rc = bc_graph_create(csr, al, (void *)sv->lanes[0]->stream, &g);
         if (rc != BC_OK) fail(rc, tl_error);
-        g->w = &sv->work;
+        g->w = &sv->lanes[0]->work;
         try {
             const Engine e = engine_for(g);
             int B = widest_width(e, n, sv->max_batch);
@@ -3147,7 +3237,7 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
             if (!fits(ws))
                 fail(BC_E_NOMEM, "no batch width fits the server's HBM budget for this graph");
             sv->ws = ws;
-            sv->work.cap_limit = (int64_t)(ws.b[WB_RIDX] / 4);
+            for (auto &ln : sv->lanes) ln->work.cap_limit = (int64_t)(ws.b[WB_RIDX] / 4);
             sv->graphs.push_back(g);
             sv->width.push_back(B);
             sv->active.emplace_back();
@@ -3194,38 +3284,74 @@ bc_status bc_server_step(bc_server *sv, int32_t *completed)
         HIPX(hipSetDevice(sv->device));
         UseAlloc ua(&sv->alloc);
         *completed = 0;
-        // Shortest job first at graph granularity: the graph whose cheapest
-        // unfinished query has the least remaining work bound ((k_max - k)
-        // samples times the CSR size) runs next. Every eighth round goes to
-        // the graph of the oldest unfinished query, so no query starves.
-        const int G = (int)sv->graphs.size();
-        int gi = -1;
-        if (sv->rounds % 8 == 7) {
-            double oldest = 0.0;
-            for (int i = 0; i < G; ++i)
-                for (const auto &q : sv->active[(size_t)i])
-                    if (gi < 0 || q.arrival < oldest) {
-                        gi = i;
-                        oldest = q.arrival;
-                    }
-            if (!sv->queued.empty() && (gi < 0 || sv->queued.front().arrival < oldest))
-                gi = sv->queued.front().q.graph;
-        } else {
-            double best = 0.0;
-            auto consider = [&](const ServerQuery &q) {
-                const double work = (double)(q.q.k_max - q.K) *
-                                    (double)std::max<int64_t>(sv->graphs[(size_t)q.q.graph]->nnz, 1);
-                if (gi < 0 || work < best) {
-                    gi = q.q.graph;
-                    best = work;
-                }
-            };
-            for (int i = 0; i < G; ++i)
-                for (const auto &q : sv->active[(size_t)i]) consider(q);
-            for (const auto &q : sv->queued) consider(q);
+        // one graph per lane, picked in turn by the scheduling rule
+        std::vector<int> pick;
+        for (size_t k = 0; k < sv->lanes.size(); ++k) {
+            const int gi = pick_graph(sv, pick, k == 0 && sv->rounds % 8 == 7);
+            if (gi < 0) break;
+            pick.push_back(gi);
+            admit(sv, gi);
         }
-        if (gi < 0) return;
-        server_round(sv, gi, completed);
+        if (pick.empty()) return;
+        const size_t R = pick.size();
+        std::vector<LaneOut> out(R);
+        auto run = [&](size_t k) {
+            try {
+                HIPX(hipSetDevice(sv->device));
+                UseAlloc lane_alloc(&sv->alloc);
+                tl_sync = R > 1 ? sv->lanes[k]->stream : nullptr;
+                server_round(sv, *sv->lanes[k], pick[k], out[k]);
+            } catch (...) {
+                out[k].error = std::current_exception();
+                (void)hipStreamSynchronize(sv->lanes[k]->stream);
+            }
+            tl_sync = nullptr;
+        };
+        std::vector<std::thread> th;
+        for (size_t k = 1; k < R; ++k) th.emplace_back(run, k);
+        run(0);
+        for (auto &t : th) t.join();
+        for (size_t k = 0; k < R; ++k)
+            if (out[k].error) std::rethrow_exception(out[k].error);
+        // results in lane order
+        for (size_t k = 0; k < R; ++k) {
+            for (const bc_result &r : out[k].done) sv->done.push_back(r);
+            sv->finished += (int64_t)out[k].done.size();
+            *completed += (int32_t)out[k].done.size();
+            sv->samples_exec += out[k].samples_exec;
+            sv->samples_used += out[k].samples_used;
+            sv->split_rounds += out[k].split_rounds;
+            sv->rounds += 1;
+        }
+    });
+}
+
+bc_status bc_server_set_lanes(bc_server *sv, int32_t lanes)
+{
+    return guarded([&] {
+        need(sv, "null argument");
+        need(lanes >= 1 && lanes <= kServerLanesMax, "lanes must be in [1, 4]");
+        HIPX(hipSetDevice(sv->device));
+        UseAlloc ua(&sv->alloc);
+        need(sv->resident + (size_t)lanes * sv->ws.total() <= sv->budget,
+             "the lanes' workspaces do not fit the server's HBM budget");
+        while ((int)sv->lanes.size() > lanes) {
+            sv->lanes.back()->release();
+            sv->lanes.pop_back();
+        }
+        while ((int)sv->lanes.size() < lanes) {
+            auto ln = std::make_unique<ServerLane>();
+            HIPX(hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking));
+            ln->own_stream = true;
+            try {
+                ln->work.init();
+                ln->work.cap_limit = sv->lanes[0]->work.cap_limit;
+            } catch (...) {
+                ln->release();
+                throw;
+            }
+            sv->lanes.push_back(std::move(ln));
+        }
     });
 }
 

@@ -98,10 +98,13 @@ def test_mixed_equals_alone_equals_sampler(dev):
         alone = run(A, [q])[0]
         A.close()
         assert key(alone) == key(mixed[i]), (i, q, alone, mixed[i])
-    # the same queries through the single-target sampler calls
+    # the same queries through the single-target sampler calls (pair samples
+    # one-sided, as the server runs them: the two-sided search sums in
+    # another order)
     for i, (gi, t, kind, rule, c, eps, seed, kmax) in enumerate(qs):
         g = graphs[gi]
         G = bc.Graph(g.row, g.col)
+        G.configure(bc.BC_SCHED_AUTO, 0, 0.0, pair_search=bc.BC_PAIR_SEARCH_ONE_SIDED)
         tt = torch.tensor([t], dtype=torch.int32, device=dev)
         if kind == bc.BC_QUERY_SOURCE:
             est, k, Sx, stt = bc.adaptive_source(G, tt, c, seed, kmax)
@@ -279,3 +282,60 @@ def test_rounds_split_when_the_record_outgrows_the_budget(dev):
         oe, ok, oS, ost = O.adaptive_source(g, [t], c, seed, kmax)
         assert res[i]["samples"] == ok[0] and res[i]["status"] == ost[0]
         assert abs(res[i]["est"] - oe[0]) <= 1e-9 * abs(oe[0])
+
+
+def test_lanes_equal_one_lane(dev):
+    """Rounds of up to four graphs at once (one stream and workspace per
+    lane): every query's result equals the one-lane server's, bit for bit;
+    the budget holds one workspace per lane."""
+    graphs = [m() for _, m in GRAPHS] + [gg.rmat(9, 8, 0.57, 0.19, 0.19, seed=7),
+                                         gg.er(500, 0.01, seed=3)]
+    qs = make_queries(graphs)
+    say("serving one lane", len(qs))
+    S = new_server(graphs)
+    one = run(S, qs)
+    S.close()
+    for lanes in (2, 4):
+        say("serving lanes", lanes)
+        S = new_server(graphs)
+        S.set_lanes(lanes)
+        got = run(S, qs)
+        st = S.stats()
+        assert st["resident_bytes"] + st["workspace_bytes"] <= st["budget_bytes"]
+        assert st["finished"] == len(qs)
+        S.close()
+        for i in range(len(qs)):
+            assert key(got[i]) == key(one[i]), (lanes, i, qs[i], got[i], one[i])
+
+
+def test_lanes_budget(dev):
+    """Lanes need one workspace each within the budget: some budget admits
+    the graph with one lane but refuses four; a large one takes four."""
+    g = gg.er(2000, 0.004, seed=1)
+    say("serving lanes budget")
+    refused = False
+    for kib in (256, 384, 512, 768, 1024, 1536, 2048, 4096, 8192):
+        S = bc.Server(kib << 10, 64)
+        try:
+            S.add_graph(g.row, g.col)
+        except bc.BcError as e:
+            assert e.status == bc.BC_E_NOMEM
+            S.close()
+            continue
+        try:
+            S.set_lanes(4)
+        except bc.BcError as e:
+            assert e.status == bc.BC_E_INVALID
+            refused = True
+            S.set_lanes(1)
+            S.close()
+            break
+        S.close()
+    assert refused
+    S = bc.Server(8 * GIB, 64)
+    S.add_graph(g.row, g.col)
+    S.set_lanes(4)
+    with pytest.raises(bc.BcError):
+        S.set_lanes(5)
+    S.set_lanes(2)
+    S.close()
