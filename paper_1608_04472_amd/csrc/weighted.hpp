@@ -88,6 +88,21 @@ __device__ __forceinline__ void w_rows(int64_t i0, int64_t i1, Get get, Small sm
     }
 }
 
+// Append to a global list among the active lanes of a wavefront: one atomic
+// on *tail for all lanes with want set (a contended counter serialises every
+// atomic on it); returns each such lane's position. Safe in divergent code.
+__device__ __forceinline__ unsigned long long w_append(bool want, unsigned long long *tail)
+{
+    const uint64_t bal = __ballot(want);
+    if (!want) return 0;
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(bal));
+    base = __shfl(base, leader, kWave);
+    return base + (unsigned long long)__popcll(bal & ((1ull << lane) - 1ull));
+}
+
 // lane 0 receives the wavefront's sum, added in a fixed tree
 __device__ __forceinline__ double w_wave_sum(double x)
 {
@@ -105,9 +120,10 @@ __global__ void k_w_relax(WArgs a, const uint32_t *F, int64_t count, uint32_t *n
     auto relax = [&](uint32_t base, int32_t dv, int64_t e) {
         const uint32_t ow = base + (uint32_t)a.col[e];
         const int32_t nd = dv + a.wt[e];
-        if (nd < a.dist[ow] && nd < atomicMin(&a.dist[ow], nd) &&
-            atomicExch(&a.flag[ow], round) != round)
-            next[atomicAdd(&a.ctl[CTL_TAIL], 1ull)] = ow;
+        const bool queue = nd < a.dist[ow] && nd < atomicMin(&a.dist[ow], nd) &&
+                           atomicExch(&a.flag[ow], round) != round;
+        const unsigned long long at = w_append(queue, &a.ctl[CTL_TAIL]);
+        if (queue) next[at] = ow;
     };
     w_rows(
         0, count,
@@ -196,8 +212,9 @@ __global__ void k_w_release(WArgs a, int64_t s0, int64_t s1)
 {
     auto release = [&](uint32_t base, int32_t dv, int64_t e) {
         const uint32_t ow = base + (uint32_t)a.col[e];
-        if (dv + a.wt[e] == a.dist[ow] && atomicSub(&a.pend[ow], 1u) == 1u)
-            a.order[atomicAdd(&a.ctl[CTL_TAIL], 1ull)] = ow;
+        const bool ready = dv + a.wt[e] == a.dist[ow] && atomicSub(&a.pend[ow], 1u) == 1u;
+        const unsigned long long at = w_append(ready, &a.ctl[CTL_TAIL]);
+        if (ready) a.order[at] = ow;
     };
     w_rows(
         s0, s1,
