@@ -180,7 +180,9 @@ struct Work {
     // wave engine
     DBuf<double> sig, dlt;
     DBuf<int32_t> sige;
-    DBuf<uint64_t> vis, F0, F1, SG0, SG1, active, valid;
+    // F0, F1: the two rotating levels' (vertex, word) records, kFS words each
+    // (lane mask, pool segment)
+    DBuf<uint64_t> vis, F0, F1, active, valid;
     DBuf<double> vsum;
     DBuf<uint32_t> ridx;
     DBuf<uint64_t> rmask, rseg;
@@ -236,7 +238,7 @@ struct Work {
     void release_engines()
     {
         sig.release(); dlt.release(); sige.release();
-        vis.release(); F0.release(); F1.release(); SG0.release(); SG1.release();
+        vis.release(); F0.release(); F1.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release();
         lv.release();
         bst.release(); bval.release(); bq.release(); blo.release();
@@ -250,7 +252,7 @@ struct Work {
     void release()
     {
         sig.release(); dlt.release(); sige.release();
-        vis.release(); F0.release(); F1.release(); SG0.release(); SG1.release();
+        vis.release(); F0.release(); F1.release();
         active.release(); valid.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release(); ctl.release();
         bcnt.release(); bpop.release();
@@ -600,10 +602,8 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     else g->w->vsum.ensure((size_t)(n * W));
     if (ext) g->w->sige.ensure((size_t)(n * p.B));
     g->w->vis.ensure((size_t)(n * W));
-    g->w->F0.ensure((size_t)(n * W));
-    g->w->F1.ensure((size_t)(n * W));
-    g->w->SG0.ensure((size_t)(n * W));
-    g->w->SG1.ensure((size_t)(n * W));
+    g->w->F0.ensure((size_t)(kFS * n * W));
+    g->w->F1.ensure((size_t)(kFS * n * W));
     g->w->active.ensure((size_t)W);
     g->w->valid.ensure((size_t)W);
     g->w->srcs.ensure((size_t)p.B);
@@ -702,8 +702,8 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         hipStream_t s = g->stream;
         HIPX(hipMemsetAsync(g->w->vis.p, 0, (size_t)(n * W) * 8, s));
         if (kind == OUT_VSUM) HIPX(hipMemsetAsync(g->w->vsum.p, 0, (size_t)(n * W) * 8, s));
-        HIPX(hipMemsetAsync(g->w->F0.p, 0, (size_t)(n * W) * 8, s));
-        HIPX(hipMemsetAsync(g->w->F1.p, 0, (size_t)(n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->w->F0.p, 0, (size_t)(kFS * n * W) * 8, s));
+        HIPX(hipMemsetAsync(g->w->F1.p, 0, (size_t)(kFS * n * W) * 8, s));
         zero_ctl(g);
         launch(s, 1, k_lane_masks, g->w->valid.p, g->w->active.p, (int32_t)W, nvalid);
         launch(s, grid_for(p.B), k_init_sources, a, g->w->F0.p);
@@ -714,10 +714,10 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
             continue;
         }
         launch(s, grid_for(off[1]), k_init_level0, a, (int64_t)0, off[1],
-               (const uint64_t *)g->w->F0.p, g->w->SG0.p);
+               (const uint64_t *)g->w->F0.p, g->w->F0.p + 1);
 
         uint64_t *cur = g->w->F0.p, *nxt = g->w->F1.p;
-        uint64_t *sgcur = g->w->SG0.p, *sgnxt = g->w->SG1.p;
+        uint64_t *sgcur = g->w->F0.p + 1, *sgnxt = g->w->F1.p + 1;   // segments: word 1
         bool redo = false;
         for (int level = 0;; ++level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
@@ -2617,8 +2617,8 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
         const size_t min_rec = (size_t)std::max<int64_t>(4 * n, 1 << 16);
         bool ok = c.take(nw.sig, N * 64) &&
                   (out_mode == BC_OUT_FULL ? c.take(nw.dlt, N * 64) : c.take(nw.vsum, N)) &&
-                  c.take(nw.vis, N) && c.take(nw.F0, N) && c.take(nw.F1, N) && c.take(nw.SG0, N) &&
-                  c.take(nw.SG1, N) && c.take(nw.active, 1) && c.take(nw.valid, 1) &&
+                  c.take(nw.vis, N) && c.take(nw.F0, kFS * N) && c.take(nw.F1, kFS * N) &&
+                  c.take(nw.active, 1) && c.take(nw.valid, 1) &&
                   c.take(nw.srcs, 64) && c.take(nw.dest, 64) && c.take(nw.bcnt, blocks) &&
                   c.take(nw.bpop, blocks);
         // the level record (4 + 8 + 8 bytes per entry) takes what is left; it
@@ -2803,7 +2803,7 @@ struct ServerQuery {
 // be budgeted buffer by buffer: the workspace keeps, for each buffer, the
 // largest size any admitted graph needs.
 enum WsBuf {
-    WB_SIG, WB_DLT, WB_SIGE, WB_VIS, WB_F0, WB_F1, WB_SG0, WB_SG1, WB_ACTIVE, WB_VALID,
+    WB_SIG, WB_DLT, WB_SIGE, WB_VIS, WB_F0, WB_F1, WB_ACTIVE, WB_VALID,
     WB_RIDX, WB_RMASK, WB_RSEG, WB_BCNT, WB_BPOP, WB_SRCS, WB_DEST, WB_LV, WB_PACTIVE,
     WB_SS_D, WB_SS_Q, WB_SS_SIG, WB_SS_DLT, WB_PROBE, WB_OKEY_IN, WB_OKEY_OUT, WB_OIDX,
     WB_OPERM, WB_LANE_ROW, WB_DRAW_SRC, WB_DRAW_DST, WB_SORT_TMP, WB_KEY_TMP, WB_QD,
@@ -2851,7 +2851,8 @@ WsNeed need_for(Engine e, int64_t n, int B)
         r.b[WB_PACTIVE] = Bs;
     } else {
         const size_t cap = (size_t)server_record_entries(n, (int64_t)W);
-        r.b[WB_VIS] = r.b[WB_F0] = r.b[WB_F1] = r.b[WB_SG0] = r.b[WB_SG1] = N * W * 8;
+        r.b[WB_VIS] = N * W * 8;
+        r.b[WB_F0] = r.b[WB_F1] = N * W * 8 * kFS;
         r.b[WB_ACTIVE] = r.b[WB_VALID] = W * 8;
         r.b[WB_RIDX] = cap * 4;
         r.b[WB_RMASK] = r.b[WB_RSEG] = cap * 8;
@@ -2900,7 +2901,7 @@ struct ServerLane {
     {
         const Work &w = work;
         return w.sig.bytes() + w.dlt.bytes() + w.sige.bytes() + w.vis.bytes() + w.F0.bytes() +
-               w.F1.bytes() + w.SG0.bytes() + w.SG1.bytes() + w.active.bytes() +
+               w.F1.bytes() + w.active.bytes() +
                w.valid.bytes() + w.vsum.bytes() + w.ridx.bytes() + w.rmask.bytes() +
                w.rseg.bytes() + w.bcnt.bytes() + w.bpop.bytes() + w.ctl.bytes() +
                w.srcs.bytes() + w.dest.bytes() + w.X.bytes() + w.S.bytes() + w.K.bytes() +

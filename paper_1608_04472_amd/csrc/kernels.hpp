@@ -102,6 +102,12 @@ __device__ __forceinline__ int64_t wave_append(bool want, unsigned long long *ta
     return want ? (int64_t)base + rank_below(bal) : -1;
 }
 
+// A (vertex, word) of a level is one 16-byte record in the frontier arrays:
+// its lane mask, then its pool segment. Kernels take the two as pointers F
+// and SG = F + 1 into the same array and index both by kFS * (vertex, word),
+// so a pull finds a neighbour's mask and segment on one line.
+constexpr int64_t kFS = 2;
+
 struct BatchArgs {
     const int64_t *row;   // out-neighbours (the search, Theorem 1's successors)
     const int32_t *col;
@@ -245,7 +251,8 @@ __global__ void k_init_sources(BatchArgs a, uint64_t *F0)
         const int64_t o = (int64_t)s * a.B + b;
         if (a.dlt) a.dlt[o] = 0.0;
         idx = ((uint32_t)s << a.logW) + (uint32_t)j;
-        const uint64_t old = atomicOr((unsigned long long *)&F0[idx], (unsigned long long)bit);
+        const uint64_t old = atomicOr((unsigned long long *)&F0[kFS * idx],
+                                      (unsigned long long)bit);
         atomicOr((unsigned long long *)&a.vis[idx], (unsigned long long)bit);
         want = (old == 0);
     }
@@ -260,7 +267,7 @@ __global__ void k_init_level0(BatchArgs a, int64_t e0, int64_t e1, const uint64_
     for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
          e += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t idx = a.ridx[e];
-        const uint64_t m = F0[idx];
+        const uint64_t m = F0[kFS * idx];
         const int c = __popcll(m);
         const uint64_t seg = atomicAdd(&a.ctl[CTL_POOL], (unsigned long long)c);
         for (int r = 0; r < c; ++r) {
@@ -269,7 +276,7 @@ __global__ void k_init_level0(BatchArgs a, int64_t e0, int64_t e1, const uint64_
         }
         a.rmask[e] = m;
         a.rseg[e] = seg;
-        SG0[idx] = seg;
+        SG0[kFS * idx] = seg;
     }
 }
 
@@ -277,7 +284,7 @@ __global__ void k_clear(BatchArgs a, int64_t e0, int64_t e1, uint64_t *F)
 {
     for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
          e += (int64_t)gridDim.x * blockDim.x)
-        F[a.ridx[e]] = 0;
+        F[kFS * a.ridx[e]] = 0;
 }
 
 // ---------------------------------------------------------- forward: discover
@@ -303,7 +310,7 @@ __global__ void k_discover_topdown(BatchArgs a, int64_t e0, int64_t e1, uint64_t
             const uint32_t widx = ((uint32_t)a.col[p] << a.logW) + j;
             const uint64_t fresh = m & ~a.vis[widx];
             if (fresh) {
-                const uint64_t old = atomicOr((unsigned long long *)&nxt[widx],
+                const uint64_t old = atomicOr((unsigned long long *)&nxt[kFS * widx],
                                               (unsigned long long)fresh);
                 found += __popcll(fresh & ~old);
             }
@@ -344,7 +351,7 @@ __global__ void k_discover_bottomup(BatchArgs a_in, const uint64_t *cur, uint64_
                     uint64_t f[8];
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
-                        f[k] = c[k] >= 0 ? cur[((int64_t)c[k] << a.logW) + j] : 0ull;
+                        f[k] = c[k] >= 0 ? cur[kFS * (((int64_t)c[k] << a.logW) + j)] : 0ull;
 #pragma unroll
                     for (int k = 0; k < 8; ++k) c[k] = e + 8 + k < end ? a.col[e + 8 + k] : -1;
 #pragma unroll
@@ -353,7 +360,7 @@ __global__ void k_discover_bottomup(BatchArgs a_in, const uint64_t *cur, uint64_
                 }
                 const uint64_t fresh = acc & want;
                 if (fresh) {
-                    nxt[idx] = fresh;
+                    nxt[kFS * idx] = fresh;
                     found += __popcll(fresh);
                 }
             }
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(256) void k_level_count(const uint64_t *nxt, int64_
     int ce = 0, cs = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const uint64_t m = base + r < total ? nxt[base + r] : 0ull;
+        const uint64_t m = base + r < total ? nxt[kFS * (base + r)] : 0ull;
         ce += m != 0;
         cs += __popcll(m);
     }
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t
     int ce = 0, cs = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        m[r] = base + r < total ? nxt[base + r] : 0ull;
+        m[r] = base + r < total ? nxt[kFS * (base + r)] : 0ull;
         ce += m[r] != 0;
         cs += __popcll(m[r]);
     }
@@ -609,14 +616,14 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t beg, int64_
     };
     int32_t x_next = nb_at(beg + kWave);          // ids of chunk c+1
     int64_t xi = ((int64_t)nb_at(beg) << a.logW) + j;
-    uint64_t f_cur = F[xi], s_cur = SG[xi];       // words of chunk c
+    uint64_t f_cur = F[kFS * xi], s_cur = SG[kFS * xi];   // words of chunk c
     for (int64_t base = beg; base < end; base += kWave) {
         const bool in = base + lane < end;
         const uint64_t fm = in ? f_cur : 0ull;
         const uint64_t sx = (fm & want) ? s_cur : 0ull;
         // issue the next chunk's words and the one after's ids
         const int64_t xin = ((int64_t)x_next << a.logW) + j;
-        const uint64_t f_nxt = F[xin], s_nxt = SG[xin];
+        const uint64_t f_nxt = F[kFS * xin], s_nxt = SG[kFS * xin];
         x_next = nb_at(base + 2 * kWave);
         uint64_t bal = wave_ballot((fm & want) != 0);
         while (bal) {
@@ -909,10 +916,10 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             if (lane < kTile && e < e1) {
                 const uint32_t idx = ((uint32_t)v << a.logW) + j;
                 if (!kBackward) {
-                    SGo[idx] = seg;
+                    SGo[kFS * idx] = seg;
                 } else {
-                    Fo[idx] = m;
-                    SGo[idx] = seg;
+                    Fo[kFS * idx] = m;
+                    SGo[kFS * idx] = seg;
                     if (a.vsum) t.vs[lane] = a.vsum[idx];
                 }
             }
@@ -930,9 +937,10 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             const int i = lo;
             const int32_t x = a.col[t.beg[i] + (p - t.start[i])];
             const int64_t xi = ((int64_t)x << a.logW) + t.j[i];
-            const uint64_t fm = F[xi];
+            // mask and segment share the record's line: both loaded
+            const uint64_t fm = F[kFS * xi], sg = SG[kFS * xi];
             t.fm[p] = fm;
-            t.fs[p] = (fm & t.m[i]) ? SG[xi] : 0;
+            t.fs[p] = (fm & t.m[i]) ? sg : 0;
         }
         __syncthreads();
         // phase 3: value sums, one entry per wavefront at a time (with kSplit,
