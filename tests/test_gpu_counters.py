@@ -107,3 +107,42 @@ def test_work_units_equal_the_oracle_counts(dev, name, make, sched, batch, bu, k
         assert ba == reach, (name, ba, reach)
         assert bb == bwd_dag, (name, bb, bwd_dag)
     G.close()
+
+
+@pytest.mark.parametrize("name,make", [("er2000", lambda: gg.config_graph("er2000")),
+                                       ("grid60", lambda: gg.grid(60, 60)),
+                                       ("rmat12", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19,
+                                                                  seed=9))],
+                         ids=["er2000", "grid60", "rmat12"])
+def test_workgroup_units_equal_the_oracle_counts(dev, name, make):
+    """One workgroup per source counts, per pass, every vertex it reaches
+    besides the source (units_a) and every arc it walks (units_b): the rows of
+    all reached vertices while discovering, and the in- and out-rows of every
+    reached vertex but the source for the counts and the dependencies. On an
+    undirected graph that is 3 * (sum of reached degrees) - 2 * deg(s), and the
+    reached degrees sum to twice the edges of the source's component."""
+    g = make()
+    src = gg.philox_sources(8, 300, g.n)
+    src[:3] = gg.top_degree(g, 3)
+    src[7] = src[0]
+    iso = np.flatnonzero(g.degree() == 0)
+    if iso.size:
+        src[9] = iso[0]
+    deg = g.degree()
+    want_a = want_b = 0
+    for s in src:
+        r, edges, _ = O.source_work(g, int(s))
+        want_a += r - 1
+        want_b += 3 * 2 * edges - 2 * int(deg[s])
+    G = bc.Graph(g.row, g.col)
+    G.configure(bc.BC_SCHED_WORKGROUP, 64, 0.0)
+    for mode in (bc.BC_OUT_SUM, bc.BC_OUT_FULL):
+        say(name, "workgroup mode", mode)
+        G.profile(True)
+        bc.dependencies(G, torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev), mode)
+        prof = {k["name"]: k for k in G.profile_read()}
+        G.profile(False)
+        assert G.stats()["schedule"] == bc.BC_SCHED_WORKGROUP
+        assert prof["wg_pass"]["units_a"] == want_a, (name, prof["wg_pass"]["units_a"], want_a)
+        assert prof["wg_pass"]["units_b"] == want_b, (name, prof["wg_pass"]["units_b"], want_b)
+    G.close()
