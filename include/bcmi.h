@@ -199,8 +199,9 @@ void bc_graph_destroy(bc_graph *g);
 bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
 /* Autotuner: times candidate plans on one seeded batch of sources each and
  * installs the fastest per source, by coordinate descent: the engine
- * (BC_SCHED_BATCHED, BC_SCHED_THREADED or BC_SCHED_WORKGROUP) at its default
- * width, then the batch width (256 .. 4096, within 32-bit indices and free
+ * (BC_SCHED_BATCHED, BC_SCHED_THREADED or BC_SCHED_WORKGROUP, the last one
+ * only on graphs deeper than 32 levels or of at most 2^16 vertices) at its
+ * default width, then the batch width (256 .. 4096, within 32-bit indices and free
  * memory; for BC_SCHED_WORKGROUP the sources in flight, 64 .. 1024), then the
  * wave engine's bottom_up (0.04, 0.01, 0.15, never) and split_entries (2^18,
  * 2^20, 2^22), or the pair engine's level_loop. A candidate slower than 1.5x

@@ -211,10 +211,14 @@ struct Work {
     DBuf<uint64_t> bst;
     DBuf<double> bval;
     DBuf<int32_t> bq, blo;
-    // weighted graphs: predecessors pending, queue stamps, search frontiers
-    // ([B][n] each; distances, counts, dependencies and the order of the
-    // counts' rounds use lv, sig, dlt and ridx)
-    DBuf<uint32_t> wpend, wflag, wfa, wfb;
+    // weighted graphs ([n][B] entries, [n][W] words): rho and predecessors
+    // pending per entry; changed and released lanes per word; the search's
+    // lists (words), their taken lanes and arc tasks; the lanes of the counts'
+    // rounds (distances, counts, dependencies and the rounds' words use lv,
+    // sig, dlt and ridx)
+    DBuf<double> wrho;
+    DBuf<uint32_t> wpend, wfa, wfb;
+    DBuf<uint64_t> wchg, wrdy, wtmask, wtask, womask;
     // one workgroup per source: per-slot distances (-1 between passes),
     // counts, exponents, dependencies, visiting lists, level starts, sums
     DBuf<WgVert> wgv;
@@ -245,7 +249,8 @@ struct Work {
         bslots = 0;
         bn = 0;
         bepoch = 0;
-        wpend.release(); wflag.release(); wfa.release(); wfb.release();
+        wrho.release(); wpend.release(); wfa.release(); wfb.release();
+        wchg.release(); wrdy.release(); wtmask.release(); wtask.release(); womask.release();
         wgv.release(); wgq.release(); wglo.release(); wgbase.release();
         wgn = 0;
     }
@@ -263,7 +268,8 @@ struct Work {
         okey_in.release(); okey_out.release(); oidx_in.release(); operm.release();
         lane_row.release(); sort_tmp.release(); draw_src.release(); draw_dst.release();
         bst.release(); bval.release(); bq.release(); blo.release();
-        wpend.release(); wflag.release(); wfa.release(); wfb.release();
+        wrho.release(); wpend.release(); wfa.release(); wfb.release();
+        wchg.release(); wrdy.release(); wtmask.release(); wtask.release(); womask.release();
         wgv.release(); wgq.release(); wglo.release(); wgbase.release();
         wgn = 0;
         bslots = 0;
@@ -863,6 +869,9 @@ bool per_source_schedule(const bc_graph *g) { return g->cfg.schedule == BC_SCHED
 
 enum Engine { ENG_WAVE = 0, ENG_PAIR = 1, ENG_WG = 2 };
 constexpr int kDeepGraphLevels = 32;
+// the tuner times the workgroup engine on graphs of at most kDeepGraphLevels
+// levels only up to this many vertices
+constexpr int64_t kWgTrialMaxShallow = 1 << 16;
 
 // Wave-per-word batching pays off when a vertex sits at few distinct levels
 // across a batch's sources (small-world graphs); for deep graphs each
@@ -889,7 +898,7 @@ int probe_depth(bc_graph *g)
 
 Engine engine_for(bc_graph *g)
 {
-    if (g->weighted) return ENG_PAIR;   // the layout of the weighted engine
+    if (g->weighted) return ENG_WAVE;   // the weighted engine's 64-source words
     if (g->cfg.schedule == BC_SCHED_BATCHED) return ENG_WAVE;
     if (g->cfg.schedule == BC_SCHED_THREADED) return ENG_PAIR;
     if (g->cfg.schedule == BC_SCHED_WORKGROUP) return ENG_WG;
@@ -1147,8 +1156,27 @@ std::vector<int64_t> run_pairs(bc_graph *g, int B, int nvalid, bool pair, bool *
 
 // ------------------------------------------------------------ weighted graphs
 
-// Width of a weighted batch: as the pair-per-thread engine (32-bit entry
-// indices), 48 bytes per entry.
+// Bytes of a weighted batch of width B (words W = B / 64): per entry the
+// distance, count, dependency, rho and pending predecessors (32) and a slot of
+// the counts' rounds (12: a word appears in a round only with a lane that
+// joins it, so the rounds hold at most n * B words); per word its two masks
+// and the search's two lists and taken lanes (32); the search's tasks (one per
+// list entry and chunk of kWChunk arcs, at most n * W + nnz * W / kWChunk + W).
+size_t weighted_tasks(const bc_graph *g, int B)
+{
+    const size_t W = (size_t)B / 64;
+    return (size_t)g->n * W + (size_t)g->nnz * W / kWChunk + W;
+}
+
+size_t weighted_bytes(const bc_graph *g, int B)
+{
+    const size_t np = (size_t)B * g->n, words = np / 64;
+    return np * 44 + words * 32 + weighted_tasks(g, B) * 8;
+}
+
+// Width of a weighted batch: a power of two from 64, up to the request or
+// default_cap, within 70 % of the free device memory (held buffers count) and
+// with word indices below 2^32.
 int plan_weighted(bc_graph *g, int64_t want, int default_cap)
 {
     int B = g->cfg.batch;
@@ -1156,27 +1184,35 @@ int plan_weighted(bc_graph *g, int64_t want, int default_cap)
         B = 64;
         while (B < want && B < default_cap) B *= 2;
     }
-    while (B > 1 && (int64_t)B * g->n >= (1ll << 32)) B /= 2;
+    B = std::max(B, 64);
+    while (B > 64 && (int64_t)(B / 64) * g->n >= (1ll << 32)) B /= 2;
     const Work &w = *g->w;
     const size_t held = w.sig.bytes() + w.dlt.bytes() + w.lv.bytes() + w.ridx.bytes() +
-                        w.wpend.bytes() + w.wflag.bytes() + w.wfa.bytes() + w.wfb.bytes();
+                        w.wrho.bytes() + w.wpend.bytes() + w.wfa.bytes() + w.wfb.bytes() +
+                        w.wchg.bytes() + w.wrdy.bytes() + w.wtmask.bytes() + w.wtask.bytes() +
+                        w.womask.bytes();
     const size_t budget = (free_device_bytes() + held) / 10 * 7;
-    while (B > 1 && (size_t)g->n * B * 48 > budget) B /= 2;
+    while (B > 64 && weighted_bytes(g, B) > budget) B /= 2;
     return B;
 }
 
 void ensure_weighted(bc_graph *g, int B)
 {
-    const size_t np = (size_t)B * g->n;
+    const size_t np = (size_t)B * g->n, words = np / 64;
     Work &w = *g->w;
     w.lv.ensure(np);
     w.sig.ensure(np);
     w.dlt.ensure(np);
-    w.ridx.ensure(np);
+    w.wrho.ensure(np);
     w.wpend.ensure(np);
-    w.wflag.ensure(np);
-    w.wfa.ensure(np);
-    w.wfb.ensure(np);
+    w.ridx.ensure(np);
+    w.womask.ensure(np);
+    w.wchg.ensure(words);
+    w.wrdy.ensure(words);
+    w.wfa.ensure(words);
+    w.wfb.ensure(words);
+    w.wtmask.ensure(words);
+    w.wtask.ensure(weighted_tasks(g, B));
     w.srcs.ensure((size_t)B);
     w.dest.ensure((size_t)B);
 }
@@ -1190,14 +1226,20 @@ WArgs make_weighted_args(bc_graph *g, int B, int nvalid, bool pair)
     a.rrow = g->rrow();
     a.rcol = g->rcol();
     a.rwt = g->rwt();
-    a.n = (uint32_t)g->n;
-    a.B = B;
+    a.n = g->n;
+    a.logW = 0;
+    while ((64 << a.logW) < B) ++a.logW;
     a.dist = g->w->lv.p;
     a.sig = g->w->sig.p;
     a.dlt = g->w->dlt.p;
+    a.rho = g->w->wrho.p;
     a.pend = g->w->wpend.p;
-    a.flag = g->w->wflag.p;
-    a.order = g->w->ridx.p;
+    a.chg = g->w->wchg.p;
+    a.rdy = g->w->wrdy.p;
+    a.tmask = g->w->wtmask.p;
+    a.task = g->w->wtask.p;
+    a.ord = g->w->ridx.p;
+    a.omask = g->w->womask.p;
     a.ctl = g->w->ctl.p;
     a.srcs = g->w->srcs.p;
     a.dest = pair ? g->w->dest.p : nullptr;
@@ -1206,57 +1248,54 @@ WArgs make_weighted_args(bc_graph *g, int B, int nvalid, bool pair)
     return a;
 }
 
-// The weighted engine's arrays as the pair-per-thread engine's output and
-// gather kernels read them (lv: distance, -1 unreached; plain counts).
-PairArgs weighted_pair_args(bc_graph *g, int B, int nvalid, bool pair)
-{
-    PairArgs a = make_pair_args(g, B, false, nvalid, pair);
-    a.sige = nullptr;
-    return a;
-}
-
 // Brandes' pass (pair mode: toward each lane's destination) for the nvalid
-// sources in g->w->srcs (and destinations in g->w->dest). Returns the rounds
-// of the path counts.
+// sources in g->w->srcs (and destinations in g->w->dest), B lanes wide.
+// Returns the rounds of the path counts.
 int64_t run_weighted(bc_graph *g, int B, int nvalid, bool pair)
 {
     hipStream_t s = g->stream;
     Work &w = *g->w;
-    const int64_t np = (int64_t)nvalid * g->n;
+    const int64_t np = (int64_t)B * g->n, words = np / 64;
     WArgs a = make_weighted_args(g, B, nvalid, pair);
-    launch(s, grid_for(np), k_fill_i32, w.lv.p, kWUnreached, np);
-    launch(s, grid_for(np), k_fill_i32, (int32_t *)w.wflag.p, (int32_t)0, np);
-    launch(s, grid_for(nvalid), k_w_init, a, w.wfa.p);
+    launch(s, grid_for(np), k_fill_i32, a.dist, kWUnreached, np);
+    launch(s, grid_for(2 * words), k_fill_i32, (int32_t *)a.chg, (int32_t)0, 2 * words);
+    launch(s, grid_for(2 * words), k_fill_i32, (int32_t *)a.rdy, (int32_t)0, 2 * words);
+    zero_ctl(g);
+    launch(s, grid_for(nvalid), k_ww_init, a, w.wfa.p);
+    read_ctl(g);
     // the search: rounds until no distance falls
     uint32_t *cur = w.wfa.p, *nxt = w.wfb.p;
-    int64_t count = nvalid;
-    for (uint32_t round = 1; count > 0; ++round) {
+    int64_t count = (int64_t)w.h_ctl[CTL_TAIL];
+    while (count > 0) {
         zero_ctl(g);
-        launch_hot(g, PROF_W_SEARCH, grid_for(count), k_w_relax, a, (const uint32_t *)cur, count,
-                   nxt, round);
+        launch(s, grid_for(count), k_ww_take, a, (const uint32_t *)cur, count);
+        launch_hot(g, PROF_W_SEARCH, grid_waves(count), k_ww_relax, a, (const uint32_t *)cur,
+                   nxt);
         read_ctl(g);
         count = (int64_t)w.h_ctl[CTL_TAIL];
         std::swap(cur, nxt);
         if (g->timed) check_deadline(g);
     }
-    // path counts in rounds; the order list grows behind each round (its
-    // tail starts after the sources, set by k_w_count)
+    // path counts in rounds; ord grows behind each round
     zero_ctl(g);
-    launch(s, grid_for(np), k_w_count, a);
-    std::vector<int64_t> off{0, nvalid};
+    launch(s, grid_waves(words), k_ww_prep, a);
+    read_ctl(g);
+    std::vector<int64_t> off{0, (int64_t)w.h_ctl[CTL_TAIL]};
     for (;;) {
         const int64_t s0 = off[off.size() - 2], s1 = off.back();
-        launch(s, grid_for(s1 - s0), k_w_release, a, s0, s1);
+        launch(s, grid_waves(s1 - s0), k_ww_release, a, s0, s1);
         read_ctl(g);
         const int64_t t = (int64_t)w.h_ctl[CTL_TAIL];
         if (t == s1) break;
-        launch_hot(g, PROF_W_COUNTS, grid_for(t - s1), k_w_sigma, a, s1, t);
+        launch_hot(g, PROF_W_COUNTS, grid_waves(t - s1), k_ww_sigma, a, s1, t);
         off.push_back(t);
     }
+    read_ctl(g);
     if (w.h_ctl[CTL_SIG_OVERFLOW])
         fail(BC_E_UNSUPPORTED, "path counts reach 2^1000 on a weighted graph");
+    // Theorem 1, latest round first (round 0 holds the sources: delta 0)
     for (size_t r = off.size() - 1; r >= 2; --r)
-        launch_hot(g, PROF_W_BACKWARD, grid_for(off[r] - off[r - 1]), k_w_backward, a,
+        launch_hot(g, PROF_W_BACKWARD, grid_waves(off[r] - off[r - 1]), k_ww_backward, a,
                    off[r - 1], off[r]);
     const int64_t rounds = (int64_t)off.size() - 1;
     g->stats.levels += rounds;
@@ -1272,7 +1311,7 @@ void weighted_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32
     hipStream_t s = g->stream;
     const int B = plan_weighted(g, k, g->tuned_batch ? g->tuned_batch : 512);
     g->stats.batch_width = B;
-    g->stats.schedule = BC_SCHED_THREADED;
+    g->stats.schedule = BC_SCHED_BATCHED;
     for (int64_t b0 = 0; b0 < k; b0 += B) {
         const int count = (int)std::min<int64_t>(B, k - b0);
         ensure_weighted(g, B);
@@ -1282,17 +1321,16 @@ void weighted_dependencies(bc_graph *g, const int32_t *sources, int64_t k, int32
             HIPX(hipMemcpyAsync(g->w->dest.p, dests + b0, (size_t)count * 4,
                                 hipMemcpyDeviceToDevice, s));
         run_weighted(g, B, count, pair);
-        PairArgs a = weighted_pair_args(g, B, count, pair);
-        if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_p_out_sum, a, out);
+        const WArgs a = make_weighted_args(g, B, count, pair);
+        if (mode == BC_OUT_SUM) launch(s, grid_waves(n), k_ww_out_sum, a, out);
         else if (mode == BC_OUT_TARGETS)
-            launch(s, grid_for((int64_t)count * T), k_p_out_targets, a, targets, T,
+            launch(s, grid_for((int64_t)count * T), k_ww_out_targets, a, targets, T,
                    (int32_t)count, b0, out);
-        else launch(s, grid_for(n * count), k_p_out_full, a, (int32_t)count, b0, out);
+        else launch(s, grid_for(n * count), k_ww_out_full, a, (int32_t)count, b0, out);
         if (dist_out)
-            HIPX(hipMemcpyAsync(dist_out + b0 * n, g->w->lv.p, (size_t)count * n * 4,
-                                hipMemcpyDeviceToDevice, s));
+            launch(s, grid_for(n * count), k_ww_out_dist, a, (int32_t)count, b0, dist_out);
         if (sig_m || sig_e)
-            launch(s, grid_for(n * count), k_p_out_sigma, a, (int32_t)count, b0, sig_m, sig_e);
+            launch(s, grid_for(n * count), k_ww_out_sigma, a, (int32_t)count, b0, sig_m, sig_e);
         g->stats.batches += 1;
         g->stats.samples_executed += count;
     }
@@ -1750,8 +1788,10 @@ void dependencies_impl(bc_graph *g, const int32_t *sources, int64_t k, int32_t m
         std::vector<int64_t> off = run_batch(g, p, count, pair, &ext, &so, kind);
         BatchArgs a = make_args(g, p, ext, count, pair, (int64_t)g->w->ridx.cap, kind);
         a.lane_row = lane_row;
-        if (mode == BC_OUT_SUM) launch(s, grid_for(n), k_out_vsum, a, out);
-        else if (mode == BC_OUT_TARGETS)
+        if (mode == BC_OUT_SUM) {
+            const int64_t vb = vsum_tile_vertices(a.logW);
+            launch(s, (int)std::min<int64_t>((n + vb - 1) / vb, 1 << 16), k_out_vsum, a, out);
+        } else if (mode == BC_OUT_TARGETS)
             launch(s, grid_for((int64_t)count * T), k_out_targets, a, targets, T, (int32_t)count,
                    b0, out);
         else launch(s, grid_for(n * count), k_out_full, a, (int32_t)count, b0, out);
@@ -1848,7 +1888,7 @@ bc_config tune_plan(bc_graph *g)
     if (g->weighted) {
         // one engine serves weighted graphs: nothing to choose but the width
         bc_config c = g->cfg;
-        c.schedule = BC_SCHED_THREADED;
+        c.schedule = BC_SCHED_BATCHED;
         c.batch = 0;
         return c;
     }
@@ -1926,7 +1966,11 @@ bc_config tune_plan(bc_graph *g)
         const int64_t k_eng = std::min<int64_t>(n, 256);
         trial(make(first, first == ENG_PAIR ? 512 : 2048), k_eng);
         trial(make(second, second == ENG_PAIR ? 512 : 2048), k_eng);
-        trial(make(ENG_WG, 1024), k_eng);
+        // one workgroup per source: a single launch that cannot be abandoned,
+        // and on a large shallow graph one pass walks wide levels with one
+        // workgroup (~0.26 s on 2^20 vertices): tried on deep or small graphs
+        if (probe_depth(g) > kDeepGraphLevels || n <= kWgTrialMaxShallow)
+            trial(make(ENG_WG, 1024), k_eng);
         // 2. batch width, widest first (buffers grow once), up to the first
         // width that holds all n sources; each timed on a batch of its width
         const Engine e = best.schedule == BC_SCHED_THREADED    ? ENG_PAIR
@@ -2090,8 +2134,8 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
         if (done) {
         } else if (g->weighted) {
             run_weighted(g, p.B, nb, pair);
-            PairArgs a = weighted_pair_args(g, p.B, nb, pair);
-            launch(s, grid_for((int64_t)T * p.B), k_p_gather_targets, a, targets, T,
+            const WArgs a = make_weighted_args(g, p.B, nb, pair);
+            launch(s, grid_for((int64_t)T * p.B), k_ww_gather_targets, a, targets, T,
                    (int32_t)p.B, g->w->X.p);
         } else if (use_pairs) {
             run_pairs(g, p.B, nb, pair, &ext, nullptr);

@@ -40,6 +40,7 @@ enum : int {
     CTL_RUNNING = 3,      // targets still sampling
     CTL_POOL = 4,         // value-pool tail
     CTL_LEVELS = 5,       // levels of a pass run by a persistent loop
+    CTL_WTASKS = 6,       // tasks of a weighted search round
     CTL_BAR = 8,          // grid barrier of the persistent loops: arrivals,
                           // generation, failure flag (CTL_BAR .. CTL_BAR + 2)
     CTL_WORDS = 16
@@ -1171,16 +1172,38 @@ __global__ void k_out_targets(BatchArgs a, const int32_t *targets, int32_t T, in
 }
 
 // out[v] += sum over j ascending of vsum[v][j]
-__global__ void k_out_vsum(BatchArgs a, double *out)
+// out[v] += the per-word dependency sums of v, in word order. A block's
+// vertices have their words staged in LDS by coalesced loads (each thread
+// reading its own words would stride a wavefront over 64 lines per word);
+// rows are padded by one double so that the threads' row reads fall in
+// different banks.
+constexpr int kVsumTile = 4096;   // words staged per workgroup
+// vertices per tile: at most 1024, so that a padded tile fits the LDS array
+__host__ __device__ inline int64_t vsum_tile_vertices(int logW)
 {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < a.n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        double acc = out[v];
-        const int W = 1 << a.logW;
-        for (int j = 0; j < W; ++j) acc += a.vsum[(v << a.logW) + j];
-        out[v] = acc;
+    const int64_t v = kVsumTile >> logW;
+    return v < 1024 ? v : 1024;
+}
+__global__ __launch_bounds__(kBlock) void k_out_vsum(BatchArgs a, double *out)
+{
+    __shared__ double t[kVsumTile + kVsumTile / 4];
+    const int W = 1 << a.logW;
+    const int64_t vb = vsum_tile_vertices(a.logW);   // W <= 64
+    for (int64_t v0 = blockIdx.x * vb; v0 < a.n; v0 += (int64_t)gridDim.x * vb) {
+        const int64_t cnt = a.n - v0 < vb ? a.n - v0 : vb;
+        const double *src = a.vsum + (v0 << a.logW);
+        for (int64_t i = threadIdx.x; i < (cnt << a.logW); i += kBlock)
+            t[(i >> a.logW) * (W + 1) + (i & (W - 1))] = src[i];
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < cnt; k += kBlock) {
+            double acc = out[v0 + k];
+            for (int j = 0; j < W; ++j) acc += t[k * (W + 1) + j];
+            out[v0 + k] = acc;
+        }
+        __syncthreads();
     }
 }
+
 
 // per-source distances from the level record: dist[row(b)*n + v] = level
 __global__ void k_out_dist(BatchArgs a, int64_t e0, int64_t e1, int32_t level, int32_t count,

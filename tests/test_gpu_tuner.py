@@ -6,7 +6,8 @@ Candidates (bc_graph_tune): the wave engine at widths 256 .. 4096 with
 bottom_up in {0.04, 0.01, 0.15, never} and split_entries in {2^18, 2^20,
 2^22}, the pair engine at widths 256 .. 4096 with and without its
 persistent level loop, and one workgroup per source with 64 .. 1024
-sources in flight.
+sources in flight (on graphs deeper than 32 levels or of at most 2^16
+vertices).
 """
 import itertools
 import sys

@@ -2,7 +2,8 @@
 weighted oracle (Dijkstra's algorithm, Section 3): distances bit-exact, path
 counts exact below 2^53, dependencies, exact BC, pair dependencies and both
 samplers within the tolerance of the other parity tests; undirected and
-directed; batches of 64 to 512 sources with ragged tails; unit weights give
+directed; batches of 64 to 4096 sources (one to 64 words of 64) with ragged
+tails, rows longer than one search task; unit weights give
 the unweighted library's values; counts beyond 2^1000 are refused."""
 import sys
 from dataclasses import replace
@@ -76,12 +77,12 @@ def test_small_weighted_all_sources(dev, name, g):
     check_sources(G, g, np.arange(g.n, dtype=np.int32), dev, name)
     assert_close(bc.exact(G).cpu().numpy(), O.bc_exact(g, directed=g.directed),
                  what=name + " bc")
-    assert G.stats()["schedule"] == bc.BC_SCHED_THREADED
+    assert G.stats()["schedule"] == bc.BC_SCHED_BATCHED
     G.close()
 
 
 @pytest.mark.parametrize("directed", [False, True], ids=["undirected", "directed"])
-@pytest.mark.parametrize("batch", [64, 512])
+@pytest.mark.parametrize("batch", [64, 512, 4096])
 def test_rmat_weighted_batches(dev, directed, batch):
     base = gg.rmat_directed(11, 8, 0.57, 0.19, 0.19, seed=5) if directed else \
         gg.rmat(11, 8, 0.57, 0.19, 0.19, seed=5)
