@@ -188,8 +188,9 @@ bc_status bc_graph_create_directed(const bc_csr *csr, const bc_allocator *alloc,
  * equal weights on the two arcs of an edge, directed ones (directed != 0) take
  * a CSR of out-arcs as bc_graph_create_directed. Every compute call serves
  * the handle with one engine (a label-correcting search of the batch's
- * sources, then path counts and Theorem 1 over the shortest-path DAG in
- * topological rounds); dist_out holds weighted distances; path counts must
+ * sources, 64 per wavefront word, then path counts and Theorem 1 over the
+ * shortest-path DAG in topological rounds; bc_last_stats reports it as
+ * BC_SCHED_BATCHED); dist_out holds weighted distances; path counts must
  * stay below 2^1000 (BC_E_UNSUPPORTED otherwise); pair samples search from
  * u to the end of the search (no early stop, no two-sided search). Not
  * served: the query server, bc_dependencies_noalloc. */
@@ -329,14 +330,17 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *                units_a (vertex reached: distance CAS, list entry, count,
  *                dependency, reset) + 12 per units_b (arc walked: head, its
  *                distance)
- *   w_search   : weighted graphs' search rounds: 12 per units_a (arc
- *                relaxed: head, weight, head's distance)
- *   w_counts   : their path-count rounds: 16 per units_a (entry done: count,
- *                order entry, pending counter) + 20 per units_b (in-arc read:
- *                tail, weight, distance, count)
- *   w_backward : their dependency rounds: 24 per units_a (entry: order entry,
- *                distance, count, dependency write) + 28 per units_b (out-arc:
- *                head, weight, distance, count, dependency)
+ *   w_search   : weighted graphs' search rounds (64 sources per word):
+ *                4 per units_a (arc relaxed for one source: the head's
+ *                distance) + 8 per units_b (arc walked for a word: head,
+ *                weight)
+ *   w_counts   : their path-count rounds, both halves (successors released,
+ *                counts summed; units from the sums): 16 per units_a (entry
+ *                counted: distance, count, pending counter) + 12 per units_b
+ *                (in-arc read for an entry: the tail's distance and count)
+ *   w_backward : their dependency rounds: 28 per units_a (entry: distance,
+ *                count, dependency and rho written) + 12 per units_b (out-arc
+ *                read for an entry: the head's distance and rho)
  *   bidir_pair : the two-sided pair search (one launch per batch of pairs):
  *                units_a = vertices found by either side, 36 each (row
  *                bounds, stamp, list entry, path count); units_b = arcs

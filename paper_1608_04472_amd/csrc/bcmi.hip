@@ -1283,7 +1283,7 @@ int64_t run_weighted(bc_graph *g, int B, int nvalid, bool pair)
     std::vector<int64_t> off{0, (int64_t)w.h_ctl[CTL_TAIL]};
     for (;;) {
         const int64_t s0 = off[off.size() - 2], s1 = off.back();
-        launch(s, grid_waves(s1 - s0), k_ww_release, a, s0, s1);
+        launch_hot(g, PROF_W_COUNTS, grid_waves(s1 - s0), k_ww_release, a, s0, s1);
         read_ctl(g);
         const int64_t t = (int64_t)w.h_ctl[CTL_TAIL];
         if (t == s1) break;
@@ -2548,9 +2548,9 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
         static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0,
-                                                   36.0, 12.0, 16.0, 24.0, 36.0};
+                                                   36.0, 4.0, 16.0, 28.0, 36.0};
         static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0,
-                                                   12.0, 0.0, 20.0, 28.0, 12.0};
+                                                   12.0, 8.0, 12.0, 12.0, 12.0};
         int32_t c = 0;
         for (int k = 0; k < PROF_KERNELS && c < max; ++k, ++c) {
             bc_kernel_profile &r = out[c];

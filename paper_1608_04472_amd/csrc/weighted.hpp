@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_ww_relax(WArgs a, const uint32_t *li
     const int lane = lane_id();
     const int64_t ntask = (int64_t)a.ctl[CTL_WTASKS];
     const uint32_t jm = (1u << a.logW) - 1u;
-    unsigned long long units = 0;
+    unsigned long long units = 0, arcs = 0;
     WPush q;
     for (int64_t t = w_wave_id(); t < ntask; t += w_waves()) {
         const uint64_t tk = uniform_u64(a.task[t]);
@@ -189,6 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_ww_relax(WArgs a, const uint32_t *li
         const bool on = (m >> lane) & 1ull;
         const int32_t dv = a.dist[((int64_t)wi << 6) + lane];
         units += (unsigned long long)__popcll(m) * (unsigned long long)(r1 - r0);
+        arcs += (unsigned long long)(r1 - r0);
         for (int64_t e = r0; e < r1; e += kWFlight) {
             int32_t xs[kWFlight], ws[kWFlight], old[kWFlight];
 #pragma unroll
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_ww_relax(WArgs a, const uint32_t *li
         }
     }
     q.flush(&a.ctl[CTL_TAIL], next, nullptr, lane);
-    if (a.prof) prof_add_raw(a.prof, PROF_W_SEARCH, units, 0);
+    if (a.prof) prof_add_raw(a.prof, PROF_W_SEARCH, units, arcs);
 }
 
 // After the search, one wavefront per word (all n * W): path count 1 at the

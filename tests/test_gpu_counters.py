@@ -146,3 +146,38 @@ def test_workgroup_units_equal_the_oracle_counts(dev, name, make):
         assert prof["wg_pass"]["units_a"] == want_a, (name, prof["wg_pass"]["units_a"], want_a)
         assert prof["wg_pass"]["units_b"] == want_b, (name, prof["wg_pass"]["units_b"], want_b)
     G.close()
+
+
+@pytest.mark.parametrize("name,make", [("rmat12", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19,
+                                                                  seed=9)),
+                                       ("grid60", lambda: gg.grid(60, 60))],
+                         ids=["rmat12", "grid60"])
+def test_weighted_units_equal_the_oracle_counts(dev, name, make):
+    """The weighted engine's count and dependency rounds each take every
+    reached lane but the source once (units_a) and read its in-row or out-row
+    (units_b); positive weights leave reachability as in the plain graph, so
+    on an undirected graph units_a = sum of (reached - 1) and units_b = 2 *
+    (component edges) - deg(s) per source. The search's units depend on the
+    order in which rounds meet the lanes and are not compared."""
+    g = gg.with_weights(make(), 9, seed=3)
+    src = gg.philox_sources(8, 300, g.n)
+    src[:3] = gg.top_degree(g, 3)
+    src[7] = src[0]
+    deg = g.degree()
+    want_a = want_b = 0
+    for s in src:
+        r, edges, _ = O.source_work(g, int(s))
+        want_a += r - 1
+        want_b += 2 * edges - int(deg[s])
+    G = bc.Graph(g.row, g.col, weights=g.w)
+    G.configure(bc.BC_SCHED_AUTO, 128, 0.0)
+    say(name, "weighted counters")
+    G.profile(True)
+    bc.dependencies(G, torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev), bc.BC_OUT_SUM)
+    prof = {k["name"]: k for k in G.profile_read()}
+    G.profile(False)
+    for k in ("w_counts", "w_backward"):
+        assert prof[k]["units_a"] == want_a, (name, k, prof[k]["units_a"], want_a)
+        assert prof[k]["units_b"] == want_b, (name, k, prof[k]["units_b"], want_b)
+    assert prof["w_search"]["units_a"] >= want_b   # every reached lane's out-row at least once
+    G.close()
