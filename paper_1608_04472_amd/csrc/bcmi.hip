@@ -182,7 +182,7 @@ struct Work {
     DBuf<int32_t> sige;
     // F0, F1: the two rotating levels' (vertex, word) records, kFS words each
     // (lane mask, pool segment)
-    DBuf<uint64_t> vis, F0, F1, active, valid;
+    DBuf<uint64_t> vis, F0, F1, active, valid, live;
     DBuf<double> vsum;
     DBuf<uint32_t> ridx;
     DBuf<uint64_t> rmask, rseg;
@@ -258,7 +258,7 @@ struct Work {
     {
         sig.release(); dlt.release(); sige.release();
         vis.release(); F0.release(); F1.release();
-        active.release(); valid.release();
+        active.release(); valid.release(); live.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release(); ctl.release();
         bcnt.release(); bpop.release();
         srcs.release();
@@ -528,7 +528,7 @@ void build_level(bc_graph *g, const BatchArgs &a, const uint64_t *nxt, int64_t c
     }
     launch(s, (int)nb, k_level_count, nxt, total, g->w->bcnt.p, g->w->bpop.p);
     hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, g->w->bcnt.p, g->w->bpop.p, nb,
-                       g->w->ctl.p, cap);
+                       g->w->ctl.p, cap, g->w->live.p, (int32_t)(1 << a.logW));
     HIPX(hipGetLastError());
     launch(s, (int)nb, k_level_write, a, nxt, (const unsigned long long *)g->w->bcnt.p,
            (const unsigned long long *)g->w->bpop.p);
@@ -612,6 +612,7 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->F1.ensure((size_t)(kFS * n * W));
     g->w->active.ensure((size_t)W);
     g->w->valid.ensure((size_t)W);
+    g->w->live.ensure((size_t)W);
     g->w->srcs.ensure((size_t)p.B);
     g->w->dest.ensure((size_t)p.B);
     g->w->ridx.ensure((size_t)cap);
@@ -621,7 +622,9 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->bpop.ensure((size_t)(((n * W) >> kLevelShift) + 2));
 }
 
-__global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32_t nvalid)
+// valid, active and live (level 0 holds every source) lanes of each word
+__global__ void k_lane_masks(uint64_t *valid, uint64_t *active, uint64_t *live, int32_t W,
+                             int32_t nvalid)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= W) return;
@@ -630,6 +633,7 @@ __global__ void k_lane_masks(uint64_t *valid, uint64_t *active, int32_t W, int32
     const uint64_t m = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
     valid[j] = m;
     active[j] = m;
+    live[j] = m;
 }
 
 BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair, int64_t cap,
@@ -656,6 +660,7 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     a.ctl = g->w->ctl.p;
     a.active = g->w->active.p;
     a.valid = g->w->valid.p;
+    a.live = g->w->live.p;
     a.srcs = g->w->srcs.p;
     a.dest = pair ? g->w->dest.p : nullptr;
     a.lane_row = nullptr;
@@ -711,7 +716,8 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         HIPX(hipMemsetAsync(g->w->F0.p, 0, (size_t)(kFS * n * W) * 8, s));
         HIPX(hipMemsetAsync(g->w->F1.p, 0, (size_t)(kFS * n * W) * 8, s));
         zero_ctl(g);
-        launch(s, 1, k_lane_masks, g->w->valid.p, g->w->active.p, (int32_t)W, nvalid);
+        launch(s, 1, k_lane_masks, g->w->valid.p, g->w->active.p, g->w->live.p, (int32_t)W,
+               nvalid);
         launch(s, grid_for(p.B), k_init_sources, a, g->w->F0.p);
         read_ctl(g);
         std::vector<int64_t> off{0, (int64_t)g->w->h_ctl[CTL_TAIL]};
@@ -2662,7 +2668,7 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
         bool ok = c.take(nw.sig, N * 64) &&
                   (out_mode == BC_OUT_FULL ? c.take(nw.dlt, N * 64) : c.take(nw.vsum, N)) &&
                   c.take(nw.vis, N) && c.take(nw.F0, kFS * N) && c.take(nw.F1, kFS * N) &&
-                  c.take(nw.active, 1) && c.take(nw.valid, 1) &&
+                  c.take(nw.active, 1) && c.take(nw.valid, 1) && c.take(nw.live, 1) &&
                   c.take(nw.srcs, 64) && c.take(nw.dest, 64) && c.take(nw.bcnt, blocks) &&
                   c.take(nw.bpop, blocks);
         // the level record (4 + 8 + 8 bytes per entry) takes what is left; it

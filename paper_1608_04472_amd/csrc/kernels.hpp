@@ -128,6 +128,7 @@ struct BatchArgs {
     unsigned long long *ctl;
     uint64_t *active;    // [W] sources still expanding (pair mode clears finished slots)
     const uint64_t *valid;  // [W] lanes holding a real source
+    uint64_t *live;      // [W] lanes present in the newest level (its masks OR-ed)
     const int32_t *srcs; // [B] source (pair: u)
     const int32_t *dest; // [B] pair destination v, or null in source mode
     double *vsum;        // [n][W] per-(vertex, word) dependency sums, or null
@@ -338,7 +339,9 @@ __global__ void k_discover_bottomup(BatchArgs a_in, const uint64_t *cur, uint64_
         const int64_t idx = i0 + threadIdx.x;
         if (idx < total) {
             const uint32_t j = (uint32_t)idx & wmask;
-            const uint64_t want = ~a.vis[idx] & a.valid[j] & a.active[j];
+            // a lane absent from the current level finds nothing (its search
+            // has ended, e.g. a source outside this vertex's component)
+            const uint64_t want = ~a.vis[idx] & a.valid[j] & a.active[j] & a.live[j];
             if (want) {
                 const int64_t v = idx >> a.logW;
                 uint64_t acc = 0;
@@ -440,12 +443,15 @@ __global__ __launch_bounds__(256) void k_level_count(const uint64_t *nxt, int64_
 // One workgroup of 1024 threads: exclusive scan of the block totals from the
 // record tail (ctl[CTL_TAIL]) and the pool tail (ctl[CTL_POOL]); both tails
 // advance past the level, and a record beyond `cap` raises the overflow flag.
+// The level's live lanes start empty (k_level_write fills them).
 __global__ __launch_bounds__(1024) void k_level_scan(unsigned long long *bcnt,
                                                      unsigned long long *bpop, int64_t nb,
-                                                     unsigned long long *ctl, int64_t cap)
+                                                     unsigned long long *ctl, int64_t cap,
+                                                     uint64_t *live, int32_t W)
 {
     __shared__ unsigned long long we[16], ws[16];
     const int tid = threadIdx.x;
+    for (int j = tid; j < W; j += 1024) live[j] = 0ull;
     const int lane = lane_id();
     const int wv = tid >> 6;
     unsigned long long ce = ctl[CTL_TAIL], cs = ctl[CTL_POOL];
@@ -493,11 +499,15 @@ __global__ __launch_bounds__(1024) void k_level_scan(unsigned long long *bcnt,
 }
 
 // Entries of the level in (vertex, word) order with their masks and pool
-// segments; the words join the visited set.
+// segments; the words join the visited set, and their lanes the level's live
+// lanes (OR-ed per workgroup in LDS, then into a.live only with new bits).
 __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t *nxt,
                                                      const unsigned long long *bcnt,
                                                      const unsigned long long *bpop)
 {
+    __shared__ unsigned long long lw[64];
+    const int W = 1 << a.logW;
+    if ((int)threadIdx.x < W) lw[threadIdx.x] = 0ull;
     const int64_t total = a.n << a.logW;
     const int64_t base = ((int64_t)blockIdx.x << kLevelShift) + (int64_t)threadIdx.x * 4;
     uint64_t m[4];
@@ -525,6 +535,29 @@ __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t
             pos += 1;
             seg += (uint64_t)__popcll(m[r]);
         }
+    }
+    // block_scan2's barriers order the LDS clear before these ORs
+    const uint32_t wmask = (uint32_t)W - 1u;
+    uint64_t own = 0;
+    int jo = -1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (!m[r]) continue;
+        const int j = (int)((uint64_t)(base + r) & wmask);
+        if (j == jo) {
+            own |= m[r];
+        } else {
+            if (own) atomicOr(&lw[jo], (unsigned long long)own);
+            own = m[r];
+            jo = j;
+        }
+    }
+    if (own) atomicOr(&lw[jo], (unsigned long long)own);
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+        const uint64_t x = lw[threadIdx.x];
+        if (x & ~a.live[threadIdx.x])
+            atomicOr((unsigned long long *)&a.live[threadIdx.x], (unsigned long long)x);
     }
 }
 
