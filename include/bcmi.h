@@ -110,10 +110,9 @@ typedef struct {
     int32_t batch;         /* sources per batch, a power of two in [64, 4096]; 0 = auto */
     double bottom_up;      /* run a level bottom-up when its frontier entries exceed
                               bottom_up * (n * batch/64); 0 = auto, < 0 = never */
-    int64_t split_entries; /* a backward level with fewer (vertex, 64-source word)
-                              entries than this sums its rows longer than 256 with a
-                              whole workgroup; 0 = auto (2^20), < 0 = never. Values
-                              are identical either way. */
+    int64_t split_entries; /* ignored (any value): every level sums rows longer
+                              than 256 in parts of 256, one wavefront per part over
+                              the whole device; the field keeps the struct's layout */
     int32_t level_loop;    /* pair-per-thread engine: > 0 runs all levels of a pass in
                               one persistent cooperative launch (grid barriers between
                               phases, each wait bounded in time: BC_E_DEVICE if one
@@ -204,8 +203,8 @@ bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
  * only on graphs deeper than 32 levels or of at most 2^16 vertices) at its
  * default width, then the batch width (256 .. 4096, within 32-bit indices and free
  * memory; for BC_SCHED_WORKGROUP the sources in flight, 64 .. 1024), then the
- * wave engine's bottom_up (0.04, 0.01, 0.15, never) and split_entries (2^18,
- * 2^20, 2^22), or the pair engine's level_loop. A candidate slower than 1.5x
+ * wave engine's bottom_up (0.04, 0.01, 0.15, never), or the pair engine's
+ * level_loop. A candidate slower than 1.5x
  * the best so far is abandoned early. Winners are cached per process by graph
  * signature (n, nnz, log2-degree histogram, BFS depth from a highest-degree
  * vertex). The width applies to bc_dependencies and bc_exact; the samplers keep
@@ -318,9 +317,10 @@ bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
  *   sigma_pull : 8 per units_a (count write) + 8 per units_b (count read)
  *   backward   : 20 per units_a (count read, rho write, level read)
  *                + 8 per units_b (rho read)
- *   backward_split: the backward of levels with fewer than 2^20 record
- *                entries, whose rows longer than 256 are summed by a whole
- *                workgroup (same units and bytes as backward)
+ *   hub_parts  : rows longer than 256 of both pulls, summed in parts of 256
+ *                by a wavefront each before the pull adds the parts in order:
+ *                8 per units_b (count or rho read); the pulls' units_a count
+ *                their entries
  *   pair_forward : the pair engine's persistent forward loop (discovery and
  *                path counts of every level): 12 per units_a (level and
  *                count write) + 8 per units_b (count read)

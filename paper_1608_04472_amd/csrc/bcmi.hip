@@ -152,7 +152,6 @@ int grid_waves(int64_t waves)
 
 // backward levels with fewer record entries than this are narrow enough for
 // their longest rows to set their time: they take the split form
-constexpr int64_t kSplitEntries = 1ll << 20;
 
 // tiled pull kernels: one workgroup per kTile entries, grid-strided
 int grid_tiles(int64_t entries)
@@ -161,9 +160,9 @@ int grid_tiles(int64_t entries)
 }
 
 template <class K, class... A>
-void launch(hipStream_t st, int grid, K kernel, A... args)
+void launch(hipStream_t st, dim3 grid, K kernel, A... args)
 {
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, st, args...);
+    hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, args...);
     HIPX(hipGetLastError());
 }
 
@@ -183,6 +182,10 @@ struct Work {
     // F0, F1: the two rotating levels' (vertex, word) records, kFS words each
     // (lane mask, pool segment)
     DBuf<uint64_t> vis, F0, F1, active, valid, live;
+    // a level's long-row entries and their rows' part sums ([part][B])
+    DBuf<int64_t> hubs;
+    DBuf<double> pm;
+    DBuf<int32_t> pe;
     DBuf<double> vsum;
     DBuf<uint32_t> ridx;
     DBuf<uint64_t> rmask, rseg;
@@ -244,6 +247,7 @@ struct Work {
         sig.release(); dlt.release(); sige.release();
         vis.release(); F0.release(); F1.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release();
+        hubs.release(); pm.release(); pe.release();
         lv.release();
         bst.release(); bval.release(); bq.release(); blo.release();
         bslots = 0;
@@ -259,6 +263,7 @@ struct Work {
         sig.release(); dlt.release(); sige.release();
         vis.release(); F0.release(); F1.release();
         active.release(); valid.release(); live.release();
+        hubs.release(); pm.release(); pe.release();
         vsum.release(); ridx.release(); rmask.release(); rseg.release(); ctl.release();
         bcnt.release(); bpop.release();
         srcs.release();
@@ -296,6 +301,13 @@ struct bc_graph {
     bool weighted = false;    // wt_buf: out-arc weights; rwt_buf: in-arc weights (directed)
     DBuf<int32_t> wt_buf, rwt_buf;
     const int32_t *rwt() const { return directed ? rwt_buf.p : wt_buf.p; }
+    // rows longer than kHub, per direction (out: row/col, in: rrow/rcol): the
+    // first part of each in the part-sum slab (-1 for shorter rows), how many
+    // such rows, their parts, the most parts of one row
+    DBuf<int32_t> hpart_buf, rhpart_buf;
+    int64_t hubs_out = 0, hubs_in = 0, parts_out = 0, parts_in = 0;
+    int32_t most_out = 0, most_in = 0;
+    const int32_t *rhpart() const { return directed ? rhpart_buf.p : hpart_buf.p; }
     bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0, BC_PAIR_SEARCH_AUTO};
     Work own;
     Work *w = &own;
@@ -334,6 +346,7 @@ struct bc_graph {
         row.release(); col.release();
         rrow_buf.release(); rcol_buf.release();
         wt_buf.release(); rwt_buf.release();
+        hpart_buf.release(); rhpart_buf.release();
         skey.release();
         own.release();
         prof_dev.release();
@@ -480,7 +493,7 @@ void prof_flush(bc_graph *g)
 
 // Launch one of the hot kernels, bracketed by events while profiling.
 template <class K, class... A>
-void launch_hot(bc_graph *g, int kernel, int grid, K fn, A... args)
+void launch_hot(bc_graph *g, int kernel, dim3 grid, K fn, A... args)
 {
     if (!g->prof_on) {
         launch(g->stream, grid, fn, args...);
@@ -511,6 +524,27 @@ void launch_wide(bc_graph *g, int kernel, int grid, int block, K fn, A... args)
         g->pending.push_back(p);
         if (g->pending.size() >= 256) prof_flush(g);
     }
+}
+
+// Part sums of the rows longer than kHub among the record entries [e0, e1),
+// for the pull that follows: a's row / col / hpart in the pull's direction,
+// F / SG the pulled level's words, `most` the most parts of one such row.
+void hub_parts(bc_graph *g, const BatchArgs &a, int64_t e0, int64_t e1, const uint64_t *F,
+               const uint64_t *SG, bool ext, int32_t most)
+{
+    if (e1 <= e0 || most <= 0) return;
+    hipStream_t s = g->stream;
+    launch(s, 1, k_fill_i32, (int32_t *)(g->w->ctl.p + CTL_HUBS), (int32_t)0, (int64_t)2);
+    launch(s, grid_for(e1 - e0), k_hub_find, a, e0, e1, g->w->hubs.p);
+    // one wavefront per (entry, part) up to the list's bound, parts along y
+    const int64_t bound = std::min<int64_t>(e1 - e0, (int64_t)g->w->hubs.cap);
+    const dim3 grid((unsigned)grid_waves(bound), (unsigned)std::min(most, 65535));
+    if (ext)
+        launch_hot(g, PROF_HUB_PARTS, grid, k_hub_parts<true>, a, F, SG,
+                   (const int64_t *)g->w->hubs.p);
+    else
+        launch_hot(g, PROF_HUB_PARTS, grid, k_hub_parts<false>, a, F, SG,
+                   (const int64_t *)g->w->hubs.p);
 }
 
 // Lay out the record entries and pool segments of the level now in `nxt`
@@ -613,6 +647,12 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->active.ensure((size_t)W);
     g->w->valid.ensure((size_t)W);
     g->w->live.ensure((size_t)W);
+    if (g->hubs_out || g->hubs_in) {
+        const int64_t pp = std::max(g->parts_out, g->parts_in);
+        g->w->hubs.ensure((size_t)(std::max(g->hubs_out, g->hubs_in) * W));
+        g->w->pm.ensure((size_t)(pp * p.B));
+        if (ext) g->w->pe.ensure((size_t)(pp * p.B));
+    }
     g->w->srcs.ensure((size_t)p.B);
     g->w->dest.ensure((size_t)p.B);
     g->w->ridx.ensure((size_t)cap);
@@ -661,6 +701,10 @@ BatchArgs make_args(bc_graph *g, const Plan &p, bool ext, int nvalid, bool pair,
     a.active = g->w->active.p;
     a.valid = g->w->valid.p;
     a.live = g->w->live.p;
+    a.hpart = g->hpart_buf.p;
+    a.rhpart = g->rhpart();
+    a.pm = g->w->pm.p;
+    a.pe = ext ? g->w->pe.p : nullptr;
     a.srcs = g->w->srcs.p;
     a.dest = pair ? g->w->dest.p : nullptr;
     a.lane_row = nullptr;
@@ -750,6 +794,13 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
                 break;
             }
             if (e2 == e1) break;
+            if (g->hubs_in) {
+                BatchArgs ain = a;
+                ain.row = a.rrow;
+                ain.col = a.rcol;
+                ain.hpart = a.rhpart;
+                hub_parts(g, ain, e1, e2, cur, sgcur, ext, g->most_in);
+            }
             if (ext)
                 launch_hot(g, PROF_SIGMA, grid_tiles(e2 - e1), k_sigma_pull<true>, a, e1, e2,
                            (const uint64_t *)cur, (const uint64_t *)sgcur, sgnxt);
@@ -781,17 +832,13 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
 
         // backward: cur holds the deepest level's masks, nxt is clear
         const int L = (int)off.size() - 1;
-        const int64_t split_entries =
-            g->cfg.split_entries == 0 ? kSplitEntries : g->cfg.split_entries;
         uint64_t *fnext = nxt, *fown = cur;
         uint64_t *sgnext = sgnxt, *sgown = sgcur;
         for (int level = L - 1; level >= 1; --level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
+            if (g->hubs_out) hub_parts(g, a, e0, e1, fnext, sgnext, ext, g->most_out);
             if (ext)
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<true>, a, e0, e1,
-                           (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
-            else if (e1 - e0 < split_entries)
-                launch_hot(g, PROF_BACKWARD_SPLIT, grid_tiles(e1 - e0), k_backward_split, a, e0, e1,
                            (const uint64_t *)fnext, (const uint64_t *)sgnext, fown, sgown);
             else
                 launch_hot(g, PROF_BACKWARD, grid_tiles(e1 - e0), k_backward<false>, a, e0, e1,
@@ -1874,7 +1921,6 @@ std::map<TuneKey, bc_config> tune_cache;
 
 constexpr int kTuneWidths[] = {4096, 2048, 1024, 512, 256};
 constexpr double kTuneBottomUp[] = {0.04, 0.01, 0.15, -1.0};
-constexpr int64_t kTuneSplit[] = {1ll << 20, 1ll << 18, 1ll << 22};
 constexpr uint64_t kTuneSeed = 0x74756e65ull;   // the sample sources' Philox key
 
 // Widest width <= want that an engine serves on this graph (32-bit indices,
@@ -2004,13 +2050,6 @@ bc_config tune_plan(bc_graph *g)
                 if (bu == 0.04) continue;
                 bc_config c = width;
                 c.bottom_up = bu;
-                trial(c, 0);
-            }
-            const bc_config dir = best;
-            for (int64_t sp : kTuneSplit) {
-                if (sp == (1ll << 20)) continue;
-                bc_config c = dir;
-                c.split_entries = sp;
                 trial(c, 0);
             }
         } else if (e == ENG_PAIR) {
@@ -2288,6 +2327,30 @@ void validate_weights(const bc_csr *c, const std::vector<int64_t> &row, const in
         }
 }
 
+// The rows longer than kHub in `row`: the first part (of kPart neighbours)
+// of each in the part-sum slab, rows in vertex order, -1 for shorter rows,
+// uploaded to `out`; their number, their parts and the most parts of one row.
+void hub_table(const std::vector<int64_t> &row, DBuf<int32_t> &out, int64_t &hubs, int64_t &parts,
+               int32_t &most)
+{
+    const size_t n = row.size() - 1;
+    std::vector<int32_t> h(n, -1);
+    hubs = parts = 0;
+    most = 0;
+    for (size_t v = 0; v < n; ++v) {
+        const int64_t d = row[v + 1] - row[v];
+        if (d <= kHub) continue;
+        h[v] = (int32_t)parts;
+        const int64_t q = (d + kPart - 1) / kPart;
+        parts += q;
+        hubs += 1;
+        most = (int32_t)std::max<int64_t>(most, q);
+        need(parts < (1ll << 31), "too many long rows");
+    }
+    out.ensure(n);
+    HIPX(hipMemcpy(out.p, h.data(), n * 4, hipMemcpyHostToDevice));
+}
+
 void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream, bc_graph **out,
                   bool directed, const int32_t *weights = nullptr)
 {
@@ -2350,6 +2413,10 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
             HIPX(hipMemcpy(g->row.p, row.data(), row.size() * 8, hipMemcpyHostToDevice));
             if (csr->nnz)
                 HIPX(hipMemcpy(g->col.p, csr->col, (size_t)csr->nnz * 4, hipMemcpyHostToDevice));
+            hub_table(row, g->hpart_buf, g->hubs_out, g->parts_out, g->most_out);
+            g->hubs_in = g->hubs_out;
+            g->parts_in = g->parts_out;
+            g->most_in = g->most_out;
             if (weights) {
                 g->weighted = true;
                 g->wt_buf.ensure((size_t)std::max<int64_t>(csr->nnz, 1));
@@ -2378,6 +2445,7 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
                                    hipMemcpyHostToDevice));
                 }
                 g->directed = true;
+                hub_table(trow, g->rhpart_buf, g->hubs_in, g->parts_in, g->most_in);
                 g->rrow_buf.ensure(trow.size());
                 g->rcol_buf.ensure((size_t)csr->nnz);
                 HIPX(hipMemcpy(g->rrow_buf.p, trow.data(), trow.size() * 8, hipMemcpyHostToDevice));
@@ -2548,12 +2616,12 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
         for (int k = 0; k < 2 * PROF_KERNELS; ++k) units[k] += (unsigned long long)g->prof_host_units[k];
         static const char *names[PROF_KERNELS] = {"discover_topdown", "discover_bottomup",
                                                   "sigma_pull", "backward", "level_record",
-                                                  "backward_split", "pair_forward",
+                                                  "hub_parts", "pair_forward",
                                                   "pair_backward", "bidir_pair", "w_search",
                                                   "w_counts", "w_backward", "wg_pass"};
         // level_record: each word read once (8 B); per entry the record
         // (4 + 8 + 8 B) and the visited word read and written (16 B)
-        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 20.0, 12.0, 20.0,
+        static const double per_a[PROF_KERNELS] = {4.0, 4.0, 8.0, 20.0, 8.0, 0.0, 12.0, 20.0,
                                                    36.0, 4.0, 16.0, 28.0, 36.0};
         static const double per_b[PROF_KERNELS] = {0.0, 0.0, 8.0, 8.0, 36.0, 8.0, 8.0, 8.0,
                                                    12.0, 8.0, 12.0, 12.0, 12.0};
@@ -2671,6 +2739,10 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
                   c.take(nw.active, 1) && c.take(nw.valid, 1) && c.take(nw.live, 1) &&
                   c.take(nw.srcs, 64) && c.take(nw.dest, 64) && c.take(nw.bcnt, blocks) &&
                   c.take(nw.bpop, blocks);
+        // long rows: the level's list (one word per vertex) and the part sums
+        const size_t hubs = (size_t)std::max(g->hubs_out, g->hubs_in);
+        const size_t parts = (size_t)std::max(g->parts_out, g->parts_in);
+        if (hubs) ok = ok && c.take(nw.hubs, hubs) && c.take(nw.pm, parts * 64);
         // the level record (4 + 8 + 8 bytes per entry) takes what is left; it
         // needs at least 4 entries per vertex
         const size_t rec_bytes = 20, pad = 3 * 256;
@@ -2681,7 +2753,10 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
                                        std::to_string((size_t)BC_NOALLOC_SCRATCH_BYTES) +
                                        "-byte scratch array)");
         // extended path-count exponents when room remains beside that record
-        if (c.left() >= N * 64 * 4 + 256 + min_rec * rec_bytes + pad) (void)c.take(nw.sige, N * 64);
+        if (c.left() >= (N + parts) * 64 * 4 + 512 + min_rec * rec_bytes + pad) {
+            (void)c.take(nw.sige, N * 64);
+            if (hubs) (void)c.take(nw.pe, parts * 64);
+        }
         const size_t rec = (c.left() - pad) / rec_bytes;
         (void)(c.take(nw.ridx, rec) && c.take(nw.rmask, rec) && c.take(nw.rseg, rec));
         nw.cap_limit = (int64_t)rec;
@@ -2857,7 +2932,7 @@ enum WsBuf {
     WB_RIDX, WB_RMASK, WB_RSEG, WB_BCNT, WB_BPOP, WB_SRCS, WB_DEST, WB_LV, WB_PACTIVE,
     WB_SS_D, WB_SS_Q, WB_SS_SIG, WB_SS_DLT, WB_PROBE, WB_OKEY_IN, WB_OKEY_OUT, WB_OIDX,
     WB_OPERM, WB_LANE_ROW, WB_DRAW_SRC, WB_DRAW_DST, WB_SORT_TMP, WB_KEY_TMP, WB_QD,
-    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_LOFF, WB_COUNT
+    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_LOFF, WB_LIVE, WB_HUBS, WB_PM, WB_PE, WB_COUNT
 };
 
 struct WsNeed {
@@ -2883,11 +2958,13 @@ int64_t server_record_entries(int64_t n, int64_t W)
     return std::max<int64_t>(4 * n * W, 1 << 16);
 }
 
-// Upper bound of the device bytes a server round on a graph of n vertices at
-// width B allocates, per buffer (engine slabs and bitmaps, level record,
-// lane-order sort, the one-off depth probe and key bitmaps, round arrays).
-WsNeed need_for(Engine e, int64_t n, int B)
+// Upper bound of the device bytes a server round on graph g at width B
+// allocates with engine e, per buffer (engine slabs and bitmaps, level record,
+// long rows' part sums, lane-order sort, the one-off depth probe and key
+// bitmaps, round arrays).
+WsNeed need_for(const bc_graph *g, Engine e, int B)
 {
+    const int64_t n = g->n;
     WsNeed r;
     const size_t N = (size_t)n, Bs = (size_t)B, W = (size_t)std::max(1, B / 64);
     r.b[WB_SIG] = N * Bs * 8;
@@ -2903,7 +2980,10 @@ WsNeed need_for(Engine e, int64_t n, int B)
         const size_t cap = (size_t)server_record_entries(n, (int64_t)W);
         r.b[WB_VIS] = N * W * 8;
         r.b[WB_F0] = r.b[WB_F1] = N * W * 8 * kFS;
-        r.b[WB_ACTIVE] = r.b[WB_VALID] = W * 8;
+        r.b[WB_ACTIVE] = r.b[WB_VALID] = r.b[WB_LIVE] = W * 8;
+        r.b[WB_HUBS] = (size_t)std::max(g->hubs_out, g->hubs_in) * W * 8;
+        r.b[WB_PM] = (size_t)std::max(g->parts_out, g->parts_in) * Bs * 8;
+        r.b[WB_PE] = (size_t)std::max(g->parts_out, g->parts_in) * Bs * 4;
         r.b[WB_RIDX] = cap * 4;
         r.b[WB_RMASK] = r.b[WB_RSEG] = cap * 8;
         r.b[WB_BCNT] = r.b[WB_BPOP] = (((N * W) >> kLevelShift) + 2) * 8;
@@ -3262,7 +3342,8 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
         // resident: the CSR (int64 rows, int32 columns) and the lane-order key
         // and the handle's own control block
         const size_t res_bytes = (size_t)(n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4 +
-                                 (size_t)n * 8 + CTL_WORDS * sizeof(unsigned long long);
+                                 (size_t)n * 8 + (size_t)n * 4 +
+                                 CTL_WORDS * sizeof(unsigned long long);
         // every lane may hold the widest need (one workspace per lane)
         const size_t L = sv->lanes.size();
         auto fits = [&](const WsNeed &w) {
@@ -3283,8 +3364,8 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
         try {
             const Engine e = engine_for(g);
             int B = widest_width(e, n, sv->max_batch);
-            while (B > 64 && !fits(sv->ws.max_with(need_for(e, n, B)))) B /= 2;
-            const WsNeed ws = sv->ws.max_with(need_for(e, n, B));
+            while (B > 64 && !fits(sv->ws.max_with(need_for(g, e, B)))) B /= 2;
+            const WsNeed ws = sv->ws.max_with(need_for(g, e, B));
             if (!fits(ws))
                 fail(BC_E_NOMEM, "no batch width fits the server's HBM budget for this graph");
             sv->ws = ws;

@@ -41,6 +41,7 @@ enum : int {
     CTL_POOL = 4,         // value-pool tail
     CTL_LEVELS = 5,       // levels of a pass run by a persistent loop
     CTL_WTASKS = 6,       // tasks of a weighted search round
+    CTL_HUBS = 7,         // long-row entries of a level (k_hub_find)
     CTL_BAR = 8,          // grid barrier of the persistent loops: arrivals,
                           // generation, failure flag (CTL_BAR .. CTL_BAR + 2)
     CTL_WORDS = 16
@@ -129,6 +130,10 @@ struct BatchArgs {
     uint64_t *active;    // [W] sources still expanding (pair mode clears finished slots)
     const uint64_t *valid;  // [W] lanes holding a real source
     uint64_t *live;      // [W] lanes present in the newest level (its masks OR-ed)
+    const int32_t *hpart;   // [n] first part of each row longer than kHub (row/col), -1 else
+    const int32_t *rhpart;  // the same for rrow/rcol
+    double *pm;          // [part][B] part sums of the level's long rows
+    int32_t *pe;         // their exponents (extended mode), else null
     const int32_t *srcs; // [B] source (pair: u)
     const int32_t *dest; // [B] pair destination v, or null in source mode
     double *vsum;        // [n][W] per-(vertex, word) dependency sums, or null
@@ -150,7 +155,7 @@ enum : int {
     PROF_SIGMA = 2,
     PROF_BACKWARD = 3,
     PROF_LEVEL = 4,   // record layout of a level (k_level_*), counted on the host
-    PROF_BACKWARD_SPLIT = 5,
+    PROF_HUB_PARTS = 5,  // part sums of rows longer than kHub (both pulls)
     PROF_PAIR_FWD = 6,   // pair engine's persistent forward loop (discovery + path counts)
     PROF_PAIR_BWD = 7,   // pair engine's persistent backward loop
     PROF_BIDIR = 8,      // two-sided pair search
@@ -672,43 +677,45 @@ __device__ __forceinline__ void pull_sum(const BatchArgs &a, int64_t beg, int64_
     }
 }
 
-// Rows longer than kHub are summed in kQuarters parts, each in ascending CSR
-// order, and the part sums are added in part order. The backward of a narrow
-// level spreads the parts of such a row over the workgroup's wavefronts; the
-// grouping is the same in both forms, so a vertex's sums are bit-identical
-// whichever form its level takes.
-constexpr int kQuarters = 4;
-// value loads in flight per wavefront in the split form, whose rows are long
-// and whose levels are narrow (the additions stay in neighbour order)
-constexpr int kSplitInFlight = 16;
+// Rows longer than kHub are summed in parts of kPart neighbours, each part in
+// ascending CSR order by a wavefront of its own (k_hub_parts, all parts of a
+// level's long rows spread over the device), and the part sums are added in
+// part order by the entry's pull: one grouping for every level and kernel.
+constexpr int kPart = 256;
 
-__device__ __forceinline__ int64_t part_begin(int64_t beg, int64_t deg, int q, int parts)
+__device__ __forceinline__ int32_t row_parts(int64_t deg)
 {
-    return beg + deg * q / parts;
+    return (int32_t)((deg + kPart - 1) / kPart);
 }
 
+// The entry's sum from its row's part sums, in part order.
+template <bool kExt>
+__device__ __forceinline__ void parts_sum(const BatchArgs &a, int64_t v, uint32_t j, int64_t deg,
+                                          const int32_t *hpart, int lane, double &accp,
+                                          XNum &accx)
+{
+    const int32_t parts = row_parts(deg);
+    const int64_t first = hpart[v];
+#pragma unroll 1
+    for (int32_t q = 0; q < parts; ++q) {
+        const int64_t o = ((first + q) << (a.logW + 6)) + ((int64_t)j << 6) + lane;
+        if (kExt) {
+            const XNum y{a.pm[o], a.pe[o]};
+            accx = q == 0 ? y : xadd(accx, y);
+        } else {
+            accp = q == 0 ? a.pm[o] : accp + a.pm[o];
+        }
+    }
+}
+
+// A row of at most kHub neighbours that the tile could not stage.
 template <bool kExt>
 __device__ __forceinline__ void row_sum(const BatchArgs &a, int64_t beg, int64_t deg, uint32_t j,
                                         uint64_t want, const uint64_t *F, const uint64_t *SG,
                                         int lane, double &accp, XNum &accx,
                                         unsigned long long &units)
 {
-    const int parts = deg > kHub ? kQuarters : 1;
-#pragma unroll 1
-    for (int q = 0; q < parts; ++q) {
-        double p = 0.0;
-        XNum x{0.0, 0};
-        pull_sum<kExt>(a, part_begin(beg, deg, q, parts), part_begin(beg, deg, q + 1, parts), j,
-                       want, F, SG, lane, p, x, units);
-        if (q == 0) {
-            accp = p;
-            accx = x;
-        } else if (kExt) {
-            accx = xadd(accx, x);
-        } else {
-            accp += p;
-        }
-    }
+    pull_sum<kExt>(a, beg, beg + deg, j, want, F, SG, lane, accp, accx, units);
 }
 
 // x from the lane DPP control `Ctrl` selects (0 where no lane is selected or
@@ -769,7 +776,6 @@ struct TileLds {
     int32_t end[kTile];
     int32_t staged[kTile];
     int32_t total;
-    int32_t nsplit;         // the tile has rows longer than kHub
     double vs[kTile];       // the entry's running dependency sum before this level
     uint64_t fm[kEdgeCap];  // the neighbour's full frontier word for the entry's word
     uint64_t fs[kEdgeCap];  // the neighbour's pool segment for that word
@@ -836,6 +842,8 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
         acc = pre_x;
     } else if (t.staged[i]) {
         pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
+    } else if (t.deg[i] > kHub) {
+        parts_sum<kExt>(a, v, j, t.deg[i], a.hpart, lane, accp, acc);
     } else {
         row_sum<kExt>(a, (int64_t)uniform_u64((uint64_t)t.beg[i]),
                       __builtin_amdgcn_readfirstlane(t.deg[i]), j, m, F, SG, lane, accp, acc, ub);
@@ -884,7 +892,7 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
 // kBackward = true: dependency sweep (F/SG = next-deeper frontier, masks and
 //   segments from the record; the entry's own word and segment are scattered
 //   into Fo/SGo for the next, shallower level).
-template <bool kExt, bool kBackward, bool kSplit>
+template <bool kExt, bool kBackward>
 __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, const uint64_t *F,
                                            const uint64_t *SG, uint64_t *Fo, uint64_t *SGo)
 {
@@ -940,11 +948,7 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
                 t.end[lane] = endp;
                 t.staged[lane] = (fits && de == deg) ? 1 : 0;
             }
-            const uint64_t sp = wave_ballot(deg > kHub);
-            if (lane == 0) {
-                t.total = maxfit;
-                t.nsplit = sp != 0ull;
-            }
+            if (lane == 0) t.total = maxfit;
             // per-entry bookkeeping, one lane per entry (each (v, j) occurs
             // once per level, so these updates do not race)
             if (lane < kTile && e < e1) {
@@ -977,48 +981,15 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
             t.fs[p] = (fm & t.m[i]) ? sg : 0;
         }
         __syncthreads();
-        // phase 3: value sums, one entry per wavefront at a time (with kSplit,
-        // rows longer than kHub are left to the whole workgroup)
+        // phase 3: value sums, one entry per wavefront at a time (a row longer
+        // than kHub from its part sums)
         for (int i = wv; i < kTile; i += nwv) {
             if (tile + i >= e1) break;
-            if (kSplit && t.deg[i] > kHub) continue;
             entry_sum<kExt, kBackward, false>(a, t, i, lane, F, SG, ua, ub);
-        }
-        static_assert(kBlock / kWave == kQuarters, "one part per wavefront");
-        if (kSplit && t.nsplit) {
-            // wavefront q sums part q of the row; the part sums meet in LDS,
-            // where the staged words are no longer needed once every wavefront
-            // is past its own entries, and wavefront 0 adds them in part order
-            double *pm = reinterpret_cast<double *>(t.fm);
-            int32_t *pe = reinterpret_cast<int32_t *>(t.fs);
-            for (int i = 0; i < kTile; ++i) {
-                if (tile + i >= e1) break;
-                const int64_t deg = t.deg[i];
-                if (deg <= kHub) continue;
-                const int64_t beg = t.beg[i];
-                const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
-                const uint64_t m = uniform_u64(t.m[i]);
-                double p = 0.0;
-                XNum x{0.0, 0};
-                pull_sum<kExt, kSplitInFlight>(a, part_begin(beg, deg, wv, kQuarters),
-                               part_begin(beg, deg, wv + 1, kQuarters), j, m, F, SG, lane, p, x,
-                               ub);
-                __syncthreads();
-                pm[wv * kWave + lane] = kExt ? x.m : p;
-                if (kExt) pe[wv * kWave + lane] = x.e;
-                __syncthreads();
-                if (wv == 0) {
-                    for (int q = 1; q < kQuarters; ++q) {
-                        if (kExt) x = xadd(x, XNum{pm[q * kWave + lane], pe[q * kWave + lane]});
-                        else p += pm[q * kWave + lane];
-                    }
-                    entry_sum<kExt, kBackward, true>(a, t, i, lane, F, SG, ua, ub, p, x);
-                }
-            }
         }
         __syncthreads();
     }
-    prof_add(a, kBackward ? (kSplit ? PROF_BACKWARD_SPLIT : PROF_BACKWARD) : PROF_SIGMA, ua, ub,
+    prof_add(a, kBackward ? PROF_BACKWARD : PROF_SIGMA, ua, ub,
              lane);
 }
 
@@ -1036,7 +1007,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
     BatchArgs b = a;
     b.row = a.rrow;
     b.col = a.rcol;
-    pull_tiles<kExt, false, false>(b, e0, e1, cur, sgcur, nullptr, sgnxt);
+    b.hpart = a.rhpart;
+    pull_tiles<kExt, false>(b, e0, e1, cur, sgcur, nullptr, sgnxt);
 }
 
 // Theorem 1 in the rho form: delta(v) = sigma(v) * sum over successors w of
@@ -1050,17 +1022,65 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
                                                      const uint64_t *fnext, const uint64_t *sgnext,
                                                      uint64_t *fown, uint64_t *sgown)
 {
-    pull_tiles<kExt, true, false>(a, e0, e1, fnext, sgnext, fown, sgown);
+    pull_tiles<kExt, true>(a, e0, e1, fnext, sgnext, fown, sgown);
 }
 
-// The same sweep for a narrow level, whose time is set by its longest rows:
-// each row longer than kHub is summed by all wavefronts of the workgroup.
-__global__ __launch_bounds__(kBlock) void k_backward_split(BatchArgs a, int64_t e0, int64_t e1,
-                                                          const uint64_t *fnext,
-                                                          const uint64_t *sgnext, uint64_t *fown,
-                                                          uint64_t *sgown)
+// ------------------------------------------------------- long rows in parts
+//
+// Before a pull over the record entries [e0, e1), the entries whose row (in the
+// pull's direction: a.row / a.col / a.hpart) is longer than kHub are listed,
+// and each part of kPart neighbours of such a row is summed by one wavefront.
+
+// the level's long-row entries, appended at ctl[CTL_HUBS] (zeroed beforehand)
+__global__ void k_hub_find(BatchArgs a, int64_t e0, int64_t e1, int64_t *hubs)
 {
-    pull_tiles<false, true, true>(a, e0, e1, fnext, sgnext, fown, sgown);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = e0 + blockIdx.x * (int64_t)blockDim.x; b < e1; b += stride) {
+        const int64_t e = b + threadIdx.x;
+        bool want = false;
+        if (e < e1) want = a.hpart[a.ridx[e] >> a.logW] >= 0;
+        const int64_t pos = wave_append(want, &a.ctl[CTL_HUBS]);
+        if (want) hubs[pos] = e;
+    }
+}
+
+// Parts blockIdx.y, blockIdx.y + gridDim.y, ... of each listed entry's row:
+// the sum over the part's neighbours of the overlapping lanes' values (as the
+// pulls take them), into the part's slot.
+template <bool kExt>
+__global__ __launch_bounds__(kBlock) void k_hub_parts(BatchArgs a, const uint64_t *F,
+                                                      const uint64_t *SG, const int64_t *hubs)
+{
+    const int lane = lane_id();
+    const int64_t nh = (int64_t)a.ctl[CTL_HUBS];
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long ub = 0;
+    for (int64_t h = wave; h < nh; h += waves) {
+        const int64_t e = (int64_t)uniform_u64((uint64_t)hubs[h]);
+        const uint32_t idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.ridx[e]);
+        const int64_t v = idx >> a.logW;
+        const uint32_t j = idx & wmask;
+        const uint64_t m = uniform_u64(a.rmask[e]);
+        const int64_t beg = a.row[v], end = a.row[v + 1];
+        const int64_t first = a.hpart[v];
+        for (int64_t q = blockIdx.y; beg + q * kPart < end; q += gridDim.y) {
+            const int64_t pb = beg + q * kPart;
+            const int64_t pe = pb + kPart < end ? pb + kPart : end;
+            double p = 0.0;
+            XNum x{0.0, 0};
+            pull_sum<kExt>(a, pb, pe, j, m, F, SG, lane, p, x, ub);
+            const int64_t o = ((first + q) << (a.logW + 6)) + ((int64_t)j << 6) + lane;
+            if (kExt) {
+                a.pm[o] = x.m;
+                a.pe[o] = x.e;
+            } else {
+                a.pm[o] = p;
+            }
+        }
+    }
+    prof_add(a, PROF_HUB_PARTS, 0, ub, lane);
 }
 
 // ------------------------------------------------------------- lane order

@@ -6,10 +6,13 @@ kernels must count exactly the (vertex, source) pairs and shortest-path DAG
 edges that the oracle's plain BFS counts (oracle_source_work):
   discovery (top-down + bottom-up) units_a = sum over sources of (reached - 1)
   sigma_pull units_a = sum of (reached - 1);  units_b = sum of DAG edges
-  backward (both forms) units_a = sum of (reached - 1);
-                        units_b = sum of (DAG edges - deg(s)), the source's own
-                        edges being the only DAG edges the sweep from level 1
-                        up does not read.
+  backward units_a = sum of (reached - 1);
+           units_b = sum of (DAG edges - deg(s)), the source's own edges being
+           the only DAG edges the sweep from level 1 up does not read.
+Rows longer than 256 are summed in parts by their own kernel (hub_parts), whose
+units_b hold those rows' DAG edges for both pulls: the two pulls' units_b and
+hub_parts' add up to the two totals, and each pull alone matches its total on
+a graph without such rows.
 """
 import sys
 
@@ -62,9 +65,9 @@ def counted(G, src, dev, mode):
         fwd["units_a"]
     sa = prof["sigma_pull"]["units_a"] + fwd["units_a"]
     sb = prof["sigma_pull"]["units_b"] + fwd["units_b"]
-    bwd_a = sum(prof[k]["units_a"] for k in ("backward", "backward_split", "pair_backward"))
-    bwd_b = sum(prof[k]["units_b"] for k in ("backward", "backward_split", "pair_backward"))
-    return disc, sa, sb, bwd_a, bwd_b
+    bwd_a = sum(prof[k]["units_a"] for k in ("backward", "pair_backward"))
+    bwd_b = sum(prof[k]["units_b"] for k in ("backward", "pair_backward"))
+    return disc, sa, sb, bwd_a, bwd_b, prof["hub_parts"]["units_b"]
 
 
 CASES = [
@@ -99,13 +102,18 @@ def test_work_units_equal_the_oracle_counts(dev, name, make, sched, batch, bu, k
     sched = abs(sched)
     for mode in (bc.BC_OUT_SUM, bc.BC_OUT_FULL):
         say(name, "mode", mode)
-        disc, sa, sb, ba, bb = counted(G, src, dev, mode)
+        disc, sa, sb, ba, bb, hb = counted(G, src, dev, mode)
         assert G.stats()["schedule"] == sched
         assert disc == reach, (name, disc, reach)
         assert sa == reach, (name, sa, reach)
-        assert sb == dag, (name, sb, dag)
         assert ba == reach, (name, ba, reach)
-        assert bb == bwd_dag, (name, bb, bwd_dag)
+        assert sb + bb + hb == dag + bwd_dag, (name, sb, bb, hb, dag, bwd_dag)
+        if (g.degree() > 256).sum() == 0 or sched == bc.BC_SCHED_THREADED:
+            assert hb == 0, (name, hb)
+            assert sb == dag, (name, sb, dag)
+            assert bb == bwd_dag, (name, bb, bwd_dag)
+        else:
+            assert hb > 0, name
     G.close()
 
 

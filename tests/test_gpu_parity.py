@@ -558,26 +558,28 @@ def test_accuracy_sweep_settings_match_the_oracle(dev):
     G.close()
 
 
-def test_backward_forms_bit_identical(dev):
-    # the wide-level backward (one wavefront per row) and the narrow-level form
-    # (a workgroup per row longer than 256) sum the same parts in the same
-    # order: forcing either form everywhere gives identical bits, and both
+def test_long_rows_in_parts_bit_identical_across_widths(dev):
+    # rows longer than 256 are summed in fixed parts of 256 (each by its own
+    # wavefront, parts added in order) and shorter rows in CSR order, so a
+    # source's values do not depend on the batch it runs in: widths 64, 512
+    # and 4096 (one, eight and 64 words of 64) give identical bits, and they
     # match the oracle
     g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
-    assert (g.degree() > 256).sum() > 20
+    assert (g.degree() > 256).sum() > 20 and g.degree().max() > 4 * 256
     src = np.concatenate([gg.top_degree(g, 4), gg.philox_sources(4, 250, g.n)]).astype(np.int32)
     outs = {}
-    for split in (-1, 0, 1 << 40):
+    for width in (64, 512, 4096):
         G = bc.Graph(g.row, g.col)
-        G.configure(bc.BC_SCHED_BATCHED, 128, 0.0, split)
-        if split == -1:
-            outs[split] = check_sources(G, g, src, dev, "rmat12 backward never split")
+        G.configure(bc.BC_SCHED_BATCHED, width, 0.0)
+        if width == 64:
+            outs[width] = check_sources(G, g, src, dev, "rmat12 parts width 64")
         else:
-            say("rmat12 backward split_entries=%d" % split)
-            outs[split] = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+            say("rmat12 parts width %d" % width)
+            outs[width] = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
+        assert G.stats()["batch_width"] == width
         G.close()
-    assert np.array_equal(outs[-1], outs[0])
-    assert np.array_equal(outs[-1], outs[1 << 40])
+    assert np.array_equal(outs[64], outs[512])
+    assert np.array_equal(outs[64], outs[4096])
 
 
 @pytest.mark.parametrize("what", ["grid600 extended", "rmat12 pairs", "grid90 sampler"])

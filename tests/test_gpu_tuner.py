@@ -3,8 +3,7 @@ it picks comes from its candidate set, is cached per graph signature, and
 keeps results equal to the untuned library's.
 
 Candidates (bc_graph_tune): the wave engine at widths 256 .. 4096 with
-bottom_up in {0.04, 0.01, 0.15, never} and split_entries in {2^18, 2^20,
-2^22}, the pair engine at widths 256 .. 4096 with and without its
+bottom_up in {0.04, 0.01, 0.15, never}, the pair engine at widths 256 .. 4096 with and without its
 persistent level loop, and one workgroup per source with 64 .. 1024
 sources in flight (on graphs deeper than 32 levels or of at most 2^16
 vertices).
@@ -28,8 +27,7 @@ O = oracle.load()
 WIDTHS = [256, 512, 1024, 2048, 4096]
 WG_WIDTHS = [64, 128, 256, 512, 1024]
 BOTTOM_UP = [0.04, 0.01, 0.15, -1.0]
-SPLIT = [1 << 18, 1 << 20, 1 << 22]
-WAVE_PLANS = list(itertools.product(WIDTHS, BOTTOM_UP, SPLIT))
+WAVE_PLANS = list(itertools.product(WIDTHS, BOTTOM_UP))
 PAIR_PLANS = list(itertools.product(WIDTHS, [-1, 1]))
 
 
@@ -65,10 +63,10 @@ def check(G, s, full, tot, what):
 
 def test_every_wave_plan(case):
     g, G, s, full, tot = case
-    for B, bu, sp in WAVE_PLANS:
-        say("wave plan", B, bu, sp)
-        G.configure(bc.BC_SCHED_BATCHED, B, bu, sp)
-        check(G, s, full, tot, "wave B=%d bu=%g split=%d" % (B, bu, sp))
+    for B, bu in WAVE_PLANS:
+        say("wave plan", B, bu)
+        G.configure(bc.BC_SCHED_BATCHED, B, bu)
+        check(G, s, full, tot, "wave B=%d bu=%g" % (B, bu))
         assert G.stats()["batch_width"] == B
 
 
@@ -102,7 +100,7 @@ def test_tuned_plan(dev, name):
     if plan["schedule"] == bc.BC_SCHED_WORKGROUP:
         assert plan["batch"] in WG_WIDTHS
     elif plan["schedule"] == bc.BC_SCHED_BATCHED:
-        assert plan["bottom_up"] in BOTTOM_UP + [0.0] and plan["split_entries"] in SPLIT + [0]
+        assert plan["bottom_up"] in BOTTOM_UP + [0.0] and plan["split_entries"] == 0
     else:
         assert plan["level_loop"] in (0, 1, -1)
     eff = G.plan()
