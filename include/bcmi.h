@@ -369,7 +369,11 @@ bc_status bc_profile_read(bc_graph *g, bc_kernel_profile *out, int32_t max, int3
  * up. A query's samples come from its own seed and each sample's arithmetic
  * does not depend on its batch mates, so a query's result is bit-identical
  * to running it alone, and to bc_adaptive_source / bc_adaptive_pair with T = 1
- * on the same graph, seed and schedule.
+ * on the same graph, seed and schedule. Pair samples take the two-sided
+ * search (one workgroup per pair, up to an eighth of the graph's batch width
+ * at once per lane, at most 512), as the
+ * samplers do by default; on a graph where it once met path counts of 2^1000
+ * they run one-sided from then on.
  * Admission by HBM budget: resident bytes (every graph's CSR and lane-order
  * key) plus the shared workspace never exceed the budget. The workspace is
  * sized per buffer for the widest need of any admitted graph; a new graph

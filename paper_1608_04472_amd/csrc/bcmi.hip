@@ -150,9 +150,6 @@ int grid_waves(int64_t waves)
     return std::min(grid_for(waves * kWave), 16384);
 }
 
-// backward levels with fewer record entries than this are narrow enough for
-// their longest rows to set their time: they take the split form
-
 // tiled pull kernels: one workgroup per kTile entries, grid-strided
 int grid_tiles(int64_t entries)
 {
@@ -235,6 +232,8 @@ struct Work {
     // server sets it from its budget; a batch that would need more raises
     // RecordLimit.
     int64_t cap_limit = 0;
+    // bytes the two-sided search's slots may hold; 0 = no limit (a server sets it)
+    size_t bi_budget = 0;
 
     void init()
     {
@@ -1540,30 +1539,37 @@ int plan_bidir(bc_graph *g, int64_t want)
 }
 
 // The two-sided search of `count` pairs (device arrays us, vs): target values
-// into X[t * stride + i] when X is given, rows into full[i * n + w] (zeroed by
-// the caller) when full is given. Returns false when a path count reached
-// 2^1000 (plain FP64 only): the caller runs those pairs one-sided.
+// into X[t * stride + i] when X is given, or into X[i] for pair i's own target
+// ptgt[i] when ptgt is given; rows into full[i * n + w] (zeroed by the
+// caller) when full is given. Returns false when a path count reached 2^1000
+// (plain FP64 only): the caller runs those pairs one-sided.
 bool run_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, int count,
-               const int32_t *targets, int32_t T, int32_t stride, double *X, double *full)
+               const int32_t *targets, int32_t T, int32_t stride, double *X, double *full,
+               const int32_t *ptgt = nullptr)
 {
     if (count <= 0) return true;
     Work &w = *g->w;
     const int64_t n = g->n;
     hipStream_t s = g->stream;
-    const int want = plan_bidir(g, count);
-    if (want > w.bslots || w.bn != n) {
+    int want = plan_bidir(g, count);
+    if (w.bi_budget)
+        want = (int)std::max<size_t>(1, std::min<size_t>((size_t)want,
+                                                         w.bi_budget / bidir_slot_bytes(n)));
+    // Slots are laid out [side][slot][n] for this graph and width; buffers
+    // large enough are kept across graphs and widths: a stale stamp holds an
+    // older epoch than any pair of this launch, so it never reads as found.
+    const size_t cells = (size_t)2 * want * n, lo_cells = (size_t)2 * want * (n + 2);
+    if (w.bst.cap < cells || w.bval.cap < cells || w.bq.cap < cells || w.blo.cap < lo_cells) {
         w.bst.release(); w.bval.release(); w.bq.release(); w.blo.release();
-        w.bslots = 0;
-        const size_t cells = (size_t)2 * want * n;
         w.bst.ensure(cells);
         w.bval.ensure(cells);
         w.bq.ensure(cells);
-        w.blo.ensure((size_t)2 * want * (n + 2));
+        w.blo.ensure(lo_cells);
         HIPX(hipMemsetAsync(w.bst.p, 0, cells * sizeof(uint64_t), s));
-        w.bslots = want;
-        w.bn = n;
         w.bepoch = 0;
     }
+    w.bslots = want;
+    w.bn = n;
     const int grid = std::min(w.bslots, count);
     const uint32_t per_slot = (uint32_t)((count + grid - 1) / grid);
     if ((uint64_t)w.bepoch + per_slot + 1 >= 0xffffffffull) {
@@ -1596,6 +1602,7 @@ bool run_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, int count,
     a.stride = stride;
     a.X = X;
     a.full = full;
+    a.ptgt = ptgt;
     zero_ctl(g);
     launch_hot(g, PROF_BIDIR, grid, k_bidir, a);
     w.bepoch += per_slot;
@@ -2932,7 +2939,7 @@ enum WsBuf {
     WB_RIDX, WB_RMASK, WB_RSEG, WB_BCNT, WB_BPOP, WB_SRCS, WB_DEST, WB_LV, WB_PACTIVE,
     WB_SS_D, WB_SS_Q, WB_SS_SIG, WB_SS_DLT, WB_PROBE, WB_OKEY_IN, WB_OKEY_OUT, WB_OIDX,
     WB_OPERM, WB_LANE_ROW, WB_DRAW_SRC, WB_DRAW_DST, WB_SORT_TMP, WB_KEY_TMP, WB_QD,
-    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_LOFF, WB_LIVE, WB_HUBS, WB_PM, WB_PE, WB_COUNT
+    WB_SLOTQ, WB_TGT, WB_X, WB_CTL, WB_LOFF, WB_LIVE, WB_HUBS, WB_PM, WB_PE, WB_BI, WB_COUNT
 };
 
 struct WsNeed {
@@ -2950,6 +2957,13 @@ struct WsNeed {
         return r;
     }
 };
+
+// Slots of the two-sided search a server round may use for its pair samples:
+// one per eight slots of the batch, 8 to 512 (each holds ~48 bytes per vertex).
+int server_bi_slots(int B)
+{
+    return std::max(8, std::min(B / 8, 512));
+}
 
 // Record entries a server batch of W words on n vertices starts with, and
 // the most it may grow to (the budgeted size).
@@ -3001,6 +3015,8 @@ WsNeed need_for(const bc_graph *g, Engine e, int B)
     r.b[WB_X] = Bs * 8;
     r.b[WB_CTL] = CTL_WORDS * sizeof(unsigned long long);
     if (e == ENG_PAIR) r.b[WB_LOFF] = (N + 2) * 8;
+    // pair samples: the two-sided search's stamps, counts, lists, level starts
+    r.b[WB_BI] = (size_t)server_bi_slots(B) * bidir_slot_bytes(n);
     return r;
 }
 
@@ -3039,7 +3055,9 @@ struct ServerLane {
                w.ss_q.bytes() + w.ss_sig.bytes() + w.ss_dlt.bytes() + w.probe_src.bytes() +
                w.okey_in.bytes() + w.okey_out.bytes() + w.oidx_in.bytes() + w.operm.bytes() +
                w.lane_row.bytes() + w.draw_src.bytes() + w.draw_dst.bytes() +
-               w.sort_tmp.bytes() + qd.bytes() + slotq.bytes() + tgt.bytes() + X.bytes();
+               w.sort_tmp.bytes() + w.live.bytes() + w.hubs.bytes() + w.pm.bytes() +
+               w.pe.bytes() + w.bst.bytes() + w.bval.bytes() + w.bq.bytes() + w.blo.bytes() +
+               qd.bytes() + slotq.bytes() + tgt.bytes() + X.bytes();
     }
     void release()
     {
@@ -3148,6 +3166,26 @@ void run_slots(ServerLane &ln, LaneOut &out, bc_graph *g, Engine e, int B, int l
     }
 }
 
+// Pair slots [lo, hi) of the round: the two-sided search, each slot's value
+// at its query's target into X[lo..hi); on a graph where it cannot serve
+// (counts once reached 2^1000, now or before) the slots run one-sided.
+void run_pair_slots(ServerLane &ln, LaneOut &out, bc_graph *g, Engine e, int B, int lo, int hi)
+{
+    const int cnt = hi - lo;
+    if (cnt <= 0) return;
+    if (use_bidir(g)) {
+        g->w->srcs.ensure((size_t)B);
+        g->w->dest.ensure((size_t)B);
+        launch(ln.stream, grid_for(cnt), k_serve_draw, (const QueryDesc *)ln.qd.p,
+               (const int32_t *)ln.slotq.p, (int32_t)lo, (int32_t)cnt, g->n, g->w->srcs.p,
+               g->w->dest.p, ln.tgt.p);
+        if (run_bidir(g, g->w->srcs.p, g->w->dest.p, cnt, nullptr, 0, 0, ln.X.p + lo, nullptr,
+                      ln.tgt.p))
+            return;
+    }
+    run_slots(ln, out, g, e, B, lo, hi);
+}
+
 // Admit waiting queries of graph gi in arrival order while slots remain.
 void admit(bc_server *sv, int gi)
 {
@@ -3178,26 +3216,34 @@ void server_round(bc_server *sv, ServerLane &ln, int gi, LaneOut &out)
     std::vector<int32_t> hslot;
     hslot.reserve((size_t)B);
     const int base = B / A, extra = B % A;
-    for (int i = 0; i < A; ++i) {
-        const ServerQuery &sq = act[(size_t)i];
-        const bool pairq = sq.q.kind == BC_QUERY_PAIR;
-        QueryDesc &d = hd[(size_t)i];
-        std::memset(&d, 0, sizeof(d));
-        d.seed = sq.q.seed;
-        d.j0 = sq.K;
-        d.k_max = sq.q.k_max;
-        d.threshold = sq.q.c * (double)n;
-        d.eps_rhs = ((sq.q.eps * sq.q.eps) * sq.q.eps) * ((double)n * (double)n);
-        d.scale = pairq ? (double)n * (double)(n - 1) : (double)n;
-        d.S = sq.S;
-        d.K = sq.K;
-        d.target = sq.q.target;
-        d.rule = !pairq ? RULE_SOURCE : (sq.q.rule == BC_PAIR_EPS ? RULE_PAIR_EPS : RULE_PAIR_ALG1);
-        d.slot0 = (int32_t)hslot.size();
-        const int64_t need = sq.q.k_max - sq.K;
-        d.nslots = (int32_t)std::min<int64_t>(need, base + (i < extra ? 1 : 0));
-        d.status = ST_RUNNING;
-        for (int k = 0; k < d.nslots; ++k) hslot.push_back(i);
+    // the source queries' slots first, then the pair queries' (two engines)
+    int ns = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < A; ++i) {
+            const ServerQuery &sq = act[(size_t)i];
+            const bool pairq = sq.q.kind == BC_QUERY_PAIR;
+            if (pairq != (pass == 1)) continue;
+            QueryDesc &d = hd[(size_t)i];
+            std::memset(&d, 0, sizeof(d));
+            d.seed = sq.q.seed;
+            d.j0 = sq.K;
+            d.k_max = sq.q.k_max;
+            d.threshold = sq.q.c * (double)n;
+            d.eps_rhs = ((sq.q.eps * sq.q.eps) * sq.q.eps) * ((double)n * (double)n);
+            d.scale = pairq ? (double)n * (double)(n - 1) : (double)n;
+            d.S = sq.S;
+            d.K = sq.K;
+            d.target = sq.q.target;
+            d.rule = !pairq                      ? RULE_SOURCE
+                     : sq.q.rule == BC_PAIR_EPS ? RULE_PAIR_EPS
+                                                : RULE_PAIR_ALG1;
+            d.slot0 = (int32_t)hslot.size();
+            const int64_t need = sq.q.k_max - sq.K;
+            d.nslots = (int32_t)std::min<int64_t>(need, base + (i < extra ? 1 : 0));
+            d.status = ST_RUNNING;
+            for (int k = 0; k < d.nslots; ++k) hslot.push_back(i);
+            if (!pairq) ns = (int)hslot.size();
+        }
     }
     const int nb = (int)hslot.size();
     hipStream_t st = ln.stream;
@@ -3210,7 +3256,8 @@ void server_round(bc_server *sv, ServerLane &ln, int gi, LaneOut &out)
     HIPX(hipMemcpyAsync(ln.qd.p, hd.data(), hd.size() * sizeof(QueryDesc),
                         hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(ln.slotq.p, hslot.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st));
-    run_slots(ln, out, g, engine_for(g), B, 0, nb);
+    if (ns > 0) run_slots(ln, out, g, engine_for(g), B, 0, ns);
+    run_pair_slots(ln, out, g, engine_for(g), B, ns, nb);
     launch(st, grid_for(A), k_stop_queries, ln.qd.p, (int32_t)A, (const double *)ln.X.p);
     HIPX(hipMemcpyAsync(hd.data(), ln.qd.p, hd.size() * sizeof(QueryDesc),
                         hipMemcpyDeviceToHost, st));
@@ -3369,7 +3416,10 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
             if (!fits(ws))
                 fail(BC_E_NOMEM, "no batch width fits the server's HBM budget for this graph");
             sv->ws = ws;
-            for (auto &ln : sv->lanes) ln->work.cap_limit = (int64_t)(ws.b[WB_RIDX] / 4);
+            for (auto &ln : sv->lanes) {
+                ln->work.cap_limit = (int64_t)(ws.b[WB_RIDX] / 4);
+                ln->work.bi_budget = ws.b[WB_BI];
+            }
             sv->graphs.push_back(g);
             sv->width.push_back(B);
             sv->active.emplace_back();
@@ -3478,6 +3528,7 @@ bc_status bc_server_set_lanes(bc_server *sv, int32_t lanes)
             try {
                 ln->work.init();
                 ln->work.cap_limit = sv->lanes[0]->work.cap_limit;
+                ln->work.bi_budget = sv->lanes[0]->work.bi_budget;
             } catch (...) {
                 ln->release();
                 throw;

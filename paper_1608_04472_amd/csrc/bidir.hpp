@@ -79,6 +79,7 @@ struct BiArgs {
     int32_t T;
     int32_t stride;
     double *X;             // X[t * stride + pair] for the T targets, or null
+    const int32_t *ptgt;   // [count] one target per pair: X[pair] = its value (T = 0), or null
     double *full;          // full[pair * n + w] (zero on entry), or null
 };
 
@@ -401,6 +402,7 @@ __global__ void __launch_bounds__(kBiBlock) k_bidir(BiArgs a)
         if (a.X)
             for (int t = threadIdx.x; t < a.T; t += kBiBlock)
                 a.X[(int64_t)t * a.stride + p] = value(a.targets[t]);
+        if (a.ptgt && threadIdx.x == 0) a.X[p] = value(a.ptgt[p]);
         if (a.full && met)
             for (int s = 0; s < 2; ++s) {
                 const int end = lo[s][depth[s] + 1];

@@ -99,12 +99,10 @@ def test_mixed_equals_alone_equals_sampler(dev):
         A.close()
         assert key(alone) == key(mixed[i]), (i, q, alone, mixed[i])
     # the same queries through the single-target sampler calls (pair samples
-    # one-sided, as the server runs them: the two-sided search sums in
-    # another order)
+    # by the two-sided search, as the server runs them)
     for i, (gi, t, kind, rule, c, eps, seed, kmax) in enumerate(qs):
         g = graphs[gi]
         G = bc.Graph(g.row, g.col)
-        G.configure(bc.BC_SCHED_AUTO, 0, 0.0, pair_search=bc.BC_PAIR_SEARCH_ONE_SIDED)
         tt = torch.tensor([t], dtype=torch.int32, device=dev)
         if kind == bc.BC_QUERY_SOURCE:
             est, k, Sx, stt = bc.adaptive_source(G, tt, c, seed, kmax)
