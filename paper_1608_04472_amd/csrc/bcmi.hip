@@ -179,8 +179,8 @@ struct Work {
     // F0, F1: the two rotating levels' (vertex, word) records, kFS words each
     // (lane mask, pool segment)
     DBuf<uint64_t> vis, F0, F1, active, valid, live;
-    // a level's long-row entries and their rows' part sums ([part][B])
-    DBuf<int64_t> hubs;
+    // a level's long-row parts (tasks) and their sums ([part][B])
+    DBuf<uint64_t> hubs;
     DBuf<double> pm;
     DBuf<int32_t> pe;
     DBuf<double> vsum;
@@ -535,15 +535,14 @@ void hub_parts(bc_graph *g, const BatchArgs &a, int64_t e0, int64_t e1, const ui
     hipStream_t s = g->stream;
     launch(s, 1, k_fill_i32, (int32_t *)(g->w->ctl.p + CTL_HUBS), (int32_t)0, (int64_t)2);
     launch(s, grid_for(e1 - e0), k_hub_find, a, e0, e1, g->w->hubs.p);
-    // one wavefront per (entry, part) up to the list's bound, parts along y
-    const int64_t bound = std::min<int64_t>(e1 - e0, (int64_t)g->w->hubs.cap);
-    const dim3 grid((unsigned)grid_waves(bound), (unsigned)std::min(most, 65535));
+    // one wavefront per task, at most as many as the level's entries could make
+    const int64_t bound = std::min<int64_t>((e1 - e0) * most, (int64_t)g->w->hubs.cap);
     if (ext)
-        launch_hot(g, PROF_HUB_PARTS, grid, k_hub_parts<true>, a, F, SG,
-                   (const int64_t *)g->w->hubs.p);
+        launch_hot(g, PROF_HUB_PARTS, grid_waves(bound), k_hub_parts<true>, a, F, SG,
+                   (const uint64_t *)g->w->hubs.p);
     else
-        launch_hot(g, PROF_HUB_PARTS, grid, k_hub_parts<false>, a, F, SG,
-                   (const int64_t *)g->w->hubs.p);
+        launch_hot(g, PROF_HUB_PARTS, grid_waves(bound), k_hub_parts<false>, a, F, SG,
+                   (const uint64_t *)g->w->hubs.p);
 }
 
 // Lay out the record entries and pool segments of the level now in `nxt`
@@ -648,7 +647,7 @@ void ensure_batch(bc_graph *g, const Plan &p, bool ext, int64_t cap, OutKind kin
     g->w->live.ensure((size_t)W);
     if (g->hubs_out || g->hubs_in) {
         const int64_t pp = std::max(g->parts_out, g->parts_in);
-        g->w->hubs.ensure((size_t)(std::max(g->hubs_out, g->hubs_in) * W));
+        g->w->hubs.ensure((size_t)(pp * W));
         g->w->pm.ensure((size_t)(pp * p.B));
         if (ext) g->w->pe.ensure((size_t)(pp * p.B));
     }
@@ -2746,10 +2745,10 @@ bc_status bc_dependencies_noalloc(bc_graph *g, const int32_t *sources, int64_t k
                   c.take(nw.active, 1) && c.take(nw.valid, 1) && c.take(nw.live, 1) &&
                   c.take(nw.srcs, 64) && c.take(nw.dest, 64) && c.take(nw.bcnt, blocks) &&
                   c.take(nw.bpop, blocks);
-        // long rows: the level's list (one word per vertex) and the part sums
+        // long rows: the level's part tasks (one word per vertex) and their sums
         const size_t hubs = (size_t)std::max(g->hubs_out, g->hubs_in);
         const size_t parts = (size_t)std::max(g->parts_out, g->parts_in);
-        if (hubs) ok = ok && c.take(nw.hubs, hubs) && c.take(nw.pm, parts * 64);
+        if (hubs) ok = ok && c.take(nw.hubs, parts) && c.take(nw.pm, parts * 64);
         // the level record (4 + 8 + 8 bytes per entry) takes what is left; it
         // needs at least 4 entries per vertex
         const size_t rec_bytes = 20, pad = 3 * 256;
@@ -2995,7 +2994,7 @@ WsNeed need_for(const bc_graph *g, Engine e, int B)
         r.b[WB_VIS] = N * W * 8;
         r.b[WB_F0] = r.b[WB_F1] = N * W * 8 * kFS;
         r.b[WB_ACTIVE] = r.b[WB_VALID] = r.b[WB_LIVE] = W * 8;
-        r.b[WB_HUBS] = (size_t)std::max(g->hubs_out, g->hubs_in) * W * 8;
+        r.b[WB_HUBS] = (size_t)std::max(g->parts_out, g->parts_in) * W * 8;
         r.b[WB_PM] = (size_t)std::max(g->parts_out, g->parts_in) * Bs * 8;
         r.b[WB_PE] = (size_t)std::max(g->parts_out, g->parts_in) * Bs * 4;
         r.b[WB_RIDX] = cap * 4;

@@ -1027,57 +1027,74 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExt ? 1
 
 // ------------------------------------------------------- long rows in parts
 //
-// Before a pull over the record entries [e0, e1), the entries whose row (in the
-// pull's direction: a.row / a.col / a.hpart) is longer than kHub are listed,
-// and each part of kPart neighbours of such a row is summed by one wavefront.
+// Before a pull over the record entries [e0, e1), each part of kPart
+// neighbours of an entry whose row (in the pull's direction: a.row / a.col /
+// a.hpart) is longer than kHub becomes a task, and every task is summed by
+// one wavefront.
 
-// the level's long-row entries, appended at ctl[CTL_HUBS] (zeroed beforehand)
-__global__ void k_hub_find(BatchArgs a, int64_t e0, int64_t e1, int64_t *hubs)
+// task: record entry << kTaskPartBits | part
+constexpr int kTaskPartBits = 24;
+
+// the level's long-row parts as tasks, appended at ctl[CTL_HUBS] (zeroed
+// beforehand), one atomic per wavefront
+__global__ void k_hub_find(BatchArgs a, int64_t e0, int64_t e1, uint64_t *tasks)
 {
+    const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = e0 + blockIdx.x * (int64_t)blockDim.x; b < e1; b += stride) {
         const int64_t e = b + threadIdx.x;
-        bool want = false;
-        if (e < e1) want = a.hpart[a.ridx[e] >> a.logW] >= 0;
-        const int64_t pos = wave_append(want, &a.ctl[CTL_HUBS]);
-        if (want) hubs[pos] = e;
+        int32_t parts = 0;
+        if (e < e1) {
+            const int64_t v = a.ridx[e] >> a.logW;
+            if (a.hpart[v] >= 0) parts = row_parts(a.row[v + 1] - a.row[v]);
+        }
+        int32_t incl = parts;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t y = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += y;
+        }
+        const int32_t total = __shfl(incl, kWave - 1, kWave);
+        unsigned long long base = 0;
+        if (lane == 0 && total) base = atomicAdd(&a.ctl[CTL_HUBS], (unsigned long long)total);
+        base = __shfl(base, 0, kWave) + (unsigned long long)(incl - parts);
+        for (int32_t q = 0; q < parts; ++q)
+            tasks[base + q] = ((uint64_t)e << kTaskPartBits) | (uint64_t)q;
     }
 }
 
-// Parts blockIdx.y, blockIdx.y + gridDim.y, ... of each listed entry's row:
-// the sum over the part's neighbours of the overlapping lanes' values (as the
-// pulls take them), into the part's slot.
+// One wavefront per task: the sum over the part's neighbours of the
+// overlapping lanes' values (as the pulls take them), into the part's slot.
 template <bool kExt>
 __global__ __launch_bounds__(kBlock) void k_hub_parts(BatchArgs a, const uint64_t *F,
-                                                      const uint64_t *SG, const int64_t *hubs)
+                                                      const uint64_t *SG, const uint64_t *tasks)
 {
     const int lane = lane_id();
-    const int64_t nh = (int64_t)a.ctl[CTL_HUBS];
+    const int64_t nt = (int64_t)a.ctl[CTL_HUBS];
     const uint32_t wmask = (1u << a.logW) - 1u;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long ub = 0;
-    for (int64_t h = wave; h < nh; h += waves) {
-        const int64_t e = (int64_t)uniform_u64((uint64_t)hubs[h]);
+    for (int64_t t = wave; t < nt; t += waves) {
+        const uint64_t tk = uniform_u64(tasks[t]);
+        const int64_t e = (int64_t)(tk >> kTaskPartBits);
+        const int64_t q = (int64_t)(tk & ((1ull << kTaskPartBits) - 1ull));
         const uint32_t idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.ridx[e]);
         const int64_t v = idx >> a.logW;
         const uint32_t j = idx & wmask;
         const uint64_t m = uniform_u64(a.rmask[e]);
-        const int64_t beg = a.row[v], end = a.row[v + 1];
-        const int64_t first = a.hpart[v];
-        for (int64_t q = blockIdx.y; beg + q * kPart < end; q += gridDim.y) {
-            const int64_t pb = beg + q * kPart;
-            const int64_t pe = pb + kPart < end ? pb + kPart : end;
-            double p = 0.0;
-            XNum x{0.0, 0};
-            pull_sum<kExt>(a, pb, pe, j, m, F, SG, lane, p, x, ub);
-            const int64_t o = ((first + q) << (a.logW + 6)) + ((int64_t)j << 6) + lane;
-            if (kExt) {
-                a.pm[o] = x.m;
-                a.pe[o] = x.e;
-            } else {
-                a.pm[o] = p;
-            }
+        const int64_t end = a.row[v + 1];
+        const int64_t pb = a.row[v] + q * kPart;
+        const int64_t pe = pb + kPart < end ? pb + kPart : end;
+        double p = 0.0;
+        XNum x{0.0, 0};
+        pull_sum<kExt>(a, pb, pe, j, m, F, SG, lane, p, x, ub);
+        const int64_t o = ((a.hpart[v] + q) << (a.logW + 6)) + ((int64_t)j << 6) + lane;
+        if (kExt) {
+            a.pm[o] = x.m;
+            a.pe[o] = x.e;
+        } else {
+            a.pm[o] = p;
         }
     }
     prof_add(a, PROF_HUB_PARTS, 0, ub, lane);
