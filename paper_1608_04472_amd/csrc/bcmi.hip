@@ -1311,20 +1311,15 @@ int64_t run_weighted(bc_graph *g, int B, int nvalid, bool pair)
     launch(s, grid_for(np), k_fill_i32, a.dist, kWUnreached, np);
     launch(s, grid_for(2 * words), k_fill_i32, (int32_t *)a.chg, (int32_t)0, 2 * words);
     launch(s, grid_for(2 * words), k_fill_i32, (int32_t *)a.rdy, (int32_t)0, 2 * words);
-    zero_ctl(g);
-    launch(s, grid_for(nvalid), k_ww_init, a, w.wfa.p);
-    read_ctl(g);
+    launch(s, grid_for(nvalid), k_ww_init, a);
     // the search: rounds until no distance falls
-    uint32_t *cur = w.wfa.p, *nxt = w.wfb.p;
-    int64_t count = (int64_t)w.h_ctl[CTL_TAIL];
-    while (count > 0) {
+    for (;;) {
         zero_ctl(g);
-        launch(s, grid_for(count), k_ww_take, a, (const uint32_t *)cur, count);
-        launch_hot(g, PROF_W_SEARCH, grid_waves(count), k_ww_relax, a, (const uint32_t *)cur,
-                   nxt);
+        launch(s, grid_for(words), k_ww_collect, a, w.wfa.p);
         read_ctl(g);
-        count = (int64_t)w.h_ctl[CTL_TAIL];
-        std::swap(cur, nxt);
+        if (w.h_ctl[CTL_TAIL] == 0) break;
+        launch_hot(g, PROF_W_SEARCH, grid_waves((int64_t)w.h_ctl[CTL_WTASKS]), k_ww_relax, a,
+                   (const uint32_t *)w.wfa.p);
         if (g->timed) check_deadline(g);
     }
     // path counts in rounds; ord grows behind each round

@@ -6,7 +6,8 @@
 // (one word), so that one arc of a vertex is relaxed for all of them with one
 // coalesced read and coalesced atomicMin's on integer distances (ties are
 // exact). Every round expands the words that have lanes whose distance fell
-// in the previous round, until no distance falls. Path counts (Definition 3
+// in the previous round, until no distance falls; the search's atomics return
+// nothing, so no wavefront waits on one. Path counts (Definition 3
 // with the predecessor condition d(s,u) + w(u,v) = d(s,v)) then follow the
 // shortest-path DAG in rounds: a lane joins the next round once its last DAG
 // predecessor is done, and then sums its predecessors' counts in CSR order (so
@@ -113,69 +114,84 @@ __device__ __forceinline__ bool w_mark(uint64_t *word, uint64_t bal, int lane)
     return __shfl(prev, 0, kWave) == 0ull;
 }
 
-// Round 0 of the search: lane b's source at distance 0; the words holding
-// sources form the first list (ctl[CTL_TAIL] zeroed beforehand).
-__global__ void k_ww_init(WArgs a, uint32_t *list)
+// Round 0 of the search: lane b's source at distance 0, its lane changed.
+__global__ void k_ww_init(WArgs a)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool on = b < a.nvalid;
-    uint32_t wi = 0;
-    bool fresh = false;
-    if (on) {
-        const int64_t s = a.srcs[b];
-        const uint32_t j = (uint32_t)b >> 6;
-        a.dist[w_at(a, s, j, b & 63)] = 0;
-        wi = (uint32_t)((s << a.logW) + j);
-        fresh = atomicOr((unsigned long long *)&a.chg[wi], 1ull << (b & 63)) == 0ull;
-    }
-    const int64_t at = wave_append(fresh, &a.ctl[CTL_TAIL]);
-    if (fresh) list[at] = wi;
+    if (b >= a.nvalid) return;
+    const int64_t s = a.srcs[b];
+    const uint32_t j = (uint32_t)b >> 6;
+    a.dist[w_at(a, s, j, b & 63)] = 0;
+    atomicOr((unsigned long long *)&a.chg[(s << a.logW) + j], 1ull << (b & 63));
 }
 
-// Start of a search round over list[0, count): each entry takes its word's
-// changed lanes (the word leaves the pending set, so later falls queue it
-// again) and is cut into tasks of kWChunk arcs (ctl[CTL_WTASKS] counts them).
-__global__ void k_ww_take(WArgs a, const uint32_t *list, int64_t count)
+// Appends one item per lane with `want` set and `count` items per lane to two
+// lists with one atomic each per wavefront; returns the lane's first position
+// in each (all lanes active).
+__device__ __forceinline__ void w_append2(bool want, int32_t count, unsigned long long *tail1,
+                                          unsigned long long *tail2, int lane,
+                                          unsigned long long &at1, unsigned long long &at2)
+{
+    int32_t i1 = want ? 1 : 0, i2 = count;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y1 = __shfl_up(i1, off, kWave);
+        const int32_t y2 = __shfl_up(i2, off, kWave);
+        if (lane >= off) {
+            i1 += y1;
+            i2 += y2;
+        }
+    }
+    const int32_t t1 = __shfl(i1, kWave - 1, kWave), t2 = __shfl(i2, kWave - 1, kWave);
+    unsigned long long b1 = 0, b2 = 0;
+    if (lane == 0 && t1) b1 = atomicAdd(tail1, (unsigned long long)t1);
+    if (lane == 0 && t2) b2 = atomicAdd(tail2, (unsigned long long)t2);
+    at1 = __shfl(b1, 0, kWave) + (unsigned long long)(i1 - (want ? 1 : 0));
+    at2 = __shfl(b2, 0, kWave) + (unsigned long long)(i2 - count);
+}
+
+// Start of a search round: every word with changed lanes takes them (the
+// word leaves the pending set, so later falls mark it again), joins the
+// round's list (ctl[CTL_TAIL]) and is cut into tasks of kWChunk arcs
+// (ctl[CTL_WTASKS]); both zeroed beforehand.
+__global__ void k_ww_collect(WArgs a, uint32_t *list)
 {
     const int lane = lane_id();
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x; c < count;
+    const int64_t words = a.n << a.logW;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x; c < words;
          c += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = c + threadIdx.x;
+        const int64_t wi = c + threadIdx.x;
+        uint64_t m = 0;
         int32_t chunks = 0;
-        if (i < count) {
-            const uint32_t wi = list[i];
-            const int64_t v = wi >> a.logW;
-            a.tmask[i] = a.chg[wi];
-            a.chg[wi] = 0ull;
-            chunks = (int32_t)((a.row[v + 1] - a.row[v] + kWChunk - 1) / kWChunk);
+        if (wi < words) {
+            m = a.chg[wi];
+            if (m) {
+                a.chg[wi] = 0ull;
+                const int64_t v = wi >> a.logW;
+                chunks = (int32_t)((a.row[v + 1] - a.row[v] + kWChunk - 1) / kWChunk);
+            }
         }
-        // the wavefront's tasks in one block of the task list
-        int32_t incl = chunks;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int32_t y = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += y;
+        unsigned long long at = 0, tb = 0;
+        w_append2(m != 0, chunks, &a.ctl[CTL_TAIL], &a.ctl[CTL_WTASKS], lane, at, tb);
+        if (m) {
+            list[at] = (uint32_t)wi;
+            a.tmask[at] = m;
+            for (int32_t k = 0; k < chunks; ++k)
+                a.task[tb + k] = ((uint64_t)at << 32) | (uint32_t)k;
         }
-        const int32_t total = __shfl(incl, kWave - 1, kWave);
-        unsigned long long base = 0;
-        if (lane == 0 && total) base = atomicAdd(&a.ctl[CTL_WTASKS], (unsigned long long)total);
-        base = __shfl(base, 0, kWave) + (unsigned long long)(incl - chunks);
-        for (int32_t k = 0; k < chunks; ++k)
-            a.task[base + k] = ((uint64_t)i << 32) | (uint32_t)k;
     }
 }
 
 // A search round: one wavefront per task relaxes its arc chunk for the
-// entry's lanes; a word with a lane whose distance fell is queued (once per
-// round) in next at ctl[CTL_TAIL].
-__global__ __launch_bounds__(kBlock) void k_ww_relax(WArgs a, const uint32_t *list,
-                                                     uint32_t *next)
+// entry's lanes. A lane whose candidate beats the distance it read marks its
+// word changed: then its distance falls in this round (to the candidate or
+// below), so every round lowers some distance and the search ends.
+__global__ __launch_bounds__(kBlock) void k_ww_relax(WArgs a, const uint32_t *list)
 {
     const int lane = lane_id();
     const int64_t ntask = (int64_t)a.ctl[CTL_WTASKS];
     const uint32_t jm = (1u << a.logW) - 1u;
     unsigned long long units = 0, arcs = 0;
-    WPush q;
     for (int64_t t = w_wave_id(); t < ntask; t += w_waves()) {
         const uint64_t tk = uniform_u64(a.task[t]);
         const int64_t i = (int64_t)(tk >> 32);
@@ -205,18 +221,15 @@ __global__ __launch_bounds__(kBlock) void k_ww_relax(WArgs a, const uint32_t *li
             for (int f = 0; f < kWFlight; ++f) {
                 if (xs[f] < 0) break;
                 const int32_t nd = dv + ws[f];
-                bool imp = on && nd < old[f];
-                if (imp) imp = nd < atomicMin(&a.dist[w_at(a, xs[f], j, lane)], nd);
+                const bool imp = on && nd < old[f];
+                if (imp) atomicMin(&a.dist[w_at(a, xs[f], j, lane)], nd);
                 const uint64_t bal = wave_ballot(imp);
-                if (bal) {
-                    const uint32_t xw = ((uint32_t)xs[f] << a.logW) + j;
-                    if (w_mark(&a.chg[xw], bal, lane))
-                        q.push(xw, 0ull, &a.ctl[CTL_TAIL], next, nullptr, lane);
-                }
+                if (bal && lane == 0)
+                    atomicOr((unsigned long long *)&a.chg[((int64_t)xs[f] << a.logW) + j],
+                             (unsigned long long)bal);
             }
         }
     }
-    q.flush(&a.ctl[CTL_TAIL], next, nullptr, lane);
     if (a.prof) prof_add_raw(a.prof, PROF_W_SEARCH, units, arcs);
 }
 
