@@ -337,3 +337,44 @@ def test_lanes_budget(dev):
         S.set_lanes(5)
     S.set_lanes(2)
     S.close()
+
+
+def diamond_chain(d):
+    """Vertex 0, then d diamonds: c_{i-1} -> a_i, b_i -> c_i (c_0 = 0), so
+    sigma(0, c_i) = 2^i and pairs more than ~1000 diamonds apart have path
+    counts beyond 2^1000."""
+    src, dst = [], []
+    prev = 0
+    for i in range(d):
+        a, b, c = 1 + 3 * i, 2 + 3 * i, 3 + 3 * i
+        src += [prev, prev, a, b]
+        dst += [a, b, c, c]
+        prev = c
+    return gg.from_edges(1 + 3 * d, np.array(src), np.array(dst), "diamonds%d" % d)
+
+
+def test_pair_queries_past_the_fp64_range(dev):
+    """Pair slots run on the two-sided search, which works in plain FP64: once
+    a round meets a pair whose path count reaches 2^1000, that round's pair
+    slots and the graph's later ones run one-sided (extended counts). Both
+    queries still match the oracle."""
+    g = diamond_chain(1100)
+    qs = [(0, 3, bc.BC_QUERY_PAIR, bc.BC_PAIR_EPS, 1.0, 0.1, 41, 1500),   # capped at k_max
+          (0, 3 * 550 - 1, bc.BC_QUERY_SOURCE, 0, 2.0, 0.1, 43, 200)]
+    G = bc.Graph(g.row, g.col)
+    u = torch.empty(1500, dtype=torch.int32, device=dev)
+    v = torch.empty(1500, dtype=torch.int32, device=dev)
+    bc.bc_draw_pairs(G, 41, 0, 1500, u, v)
+    G.close()
+    apart = np.abs((u.cpu().numpy() - 1) // 3 - (v.cpu().numpy() - 1) // 3)
+    assert (apart > 1010).sum() >= 3       # some drawn pairs count beyond 2^1000
+    say("serving diamond chain")
+    S = new_server([g], budget=8 * GIB, max_batch=512)
+    res = run(S, qs)
+    S.close()
+    oe, ok, oS, ost = O.adaptive_pair(g, [3], oracle.RULE_EPS, 0.1, 1.0, 41, 1500)
+    assert res[0]["samples"] == ok[0] == 1500 and res[0]["status"] == ost[0], (res[0], ok, ost)
+    assert abs(res[0]["est"] - oe[0]) <= 1e-9 * abs(oe[0])
+    oe, ok, oS, ost = O.adaptive_source(g, [3 * 550 - 1], 2.0, 43, 200)
+    assert res[1]["samples"] == ok[0] and res[1]["status"] == ost[0]
+    assert abs(res[1]["est"] - oe[0]) <= 1e-9 * abs(oe[0])
