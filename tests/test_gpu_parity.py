@@ -263,7 +263,7 @@ def test_hub_rows_with_extended_counts(dev, sched):
     # A 600x600 grid plus one hub joined to the 15x20 block of vertices in the
     # far corner: from the near corner the hub sits ~1166 levels deep, where
     # path counts are far beyond FP64's range, and its row (300 neighbours) is
-    # longer than a tile stages, so its sums take the global gather path.
+    # longer than 256, so the wave engine sums it in two parts (extended counts).
     x = y = 600
     ids = np.arange(x * y).reshape(x, y)
     s = np.concatenate([ids[:, :-1].ravel(), ids[:-1, :].ravel()])
