@@ -227,16 +227,20 @@ def test_sum_mode_matches_oracle(dev):
     G.close()
 
 
+@pytest.mark.parametrize("bu", [0.0, 1e-9], ids=["auto", "bottom-up"])
 @pytest.mark.parametrize("batch", [64, 512])
-def test_rmat_isolated_vertices_and_hubs(dev, batch):
+def test_rmat_isolated_vertices_and_hubs(dev, batch, bu):
+    # isolated sources end their search at level 0; bottom-up levels look only
+    # for the lanes still present in the current level (1e-9: every level
+    # bottom-up), which must not change any value
     g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
     assert (g.degree() == 0).any()
     G = bc.Graph(g.row, g.col)
-    G.configure(bc.BC_SCHED_BATCHED, batch, 0.0)
+    G.configure(bc.BC_SCHED_BATCHED, batch, bu)
     iso = np.flatnonzero(g.degree() == 0)[:3]
     hubs = gg.top_degree(g, 3)
     src = np.concatenate([iso, hubs, gg.philox_sources(2, 90, g.n)]).astype(np.int32)
-    check_sources(G, g, src, dev, "rmat12 B=%d" % batch)
+    check_sources(G, g, src, dev, "rmat12 B=%d bu=%g" % (batch, bu))
     G.close()
 
 
