@@ -1897,10 +1897,10 @@ void pair_dependencies_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, 
 // -------------------------------------------------------------- autotuner
 //
 // Times candidate plans on one seeded batch of sources each and keeps the
-// fastest per source, by coordinate descent: the engine (wave per word or
-// thread per pair) at its default width, then the batch width, then, for the
-// wave engine, the bottom-up threshold and the split size of the backward,
-// or, for the pair engine, the persistent level loop. A candidate that runs
+// fastest per source, by coordinate descent: the engine (wave per word,
+// thread per pair, or workgroup per source on deep or small graphs) at its
+// default width, then the batch width, then, for the wave engine, the
+// bottom-up threshold, or, for the pair engine, the persistent level loop. A candidate that runs
 // past 1.5x the best time for its batch is abandoned at a level boundary.
 // Winners are cached per process by graph signature (size, log2-degree
 // histogram, BFS depth from the hub). Every plan only changes how sources

@@ -568,8 +568,8 @@ __global__ __launch_bounds__(256) void k_level_write(BatchArgs a, const uint64_t
 
 // ------------------------------------------------- neighbour pull (shared)
 
-// Rows longer than kHub are never staged in LDS: their neighbours are gathered
-// from global memory.
+// Rows longer than kHub are never staged in LDS: they are summed in parts over
+// the whole device before the pull (k_hub_parts).
 constexpr int kHub = 256;
 
 // Issue the value loads of up to kIF overlapping neighbours, taken from
@@ -708,16 +708,6 @@ __device__ __forceinline__ void parts_sum(const BatchArgs &a, int64_t v, uint32_
     }
 }
 
-// A row of at most kHub neighbours that the tile could not stage.
-template <bool kExt>
-__device__ __forceinline__ void row_sum(const BatchArgs &a, int64_t beg, int64_t deg, uint32_t j,
-                                        uint64_t want, const uint64_t *F, const uint64_t *SG,
-                                        int lane, double &accp, XNum &accx,
-                                        unsigned long long &units)
-{
-    pull_sum<kExt>(a, beg, beg + deg, j, want, F, SG, lane, accp, accx, units);
-}
-
 // x from the lane DPP control `Ctrl` selects (0 where no lane is selected or
 // the row is masked off)
 template <int Ctrl, int RowMask, bool BoundCtrl>
@@ -759,9 +749,9 @@ __device__ __forceinline__ double wave_sum_to_last(double x)
 //   3. each wavefront takes entries in turn: the overlap masks come from LDS,
 //      the slab values of overlapping neighbours are loaded eight at a time
 //      (lanes = sources) and summed in ascending CSR order.
-// Entries whose row is longer than kHub, or that no longer fit the tile's
-// edge budget, skip staging and gather their neighbours from global memory
-// in phase 3 (the same sums; rows longer than kHub are summed in parts).
+// Entries whose row is longer than kHub skip staging and take their row's
+// part sums (k_hub_parts) in phase 3; entries that no longer fit the tile's
+// edge budget gather their neighbours from global memory (the same sums).
 constexpr int kTile = 32;
 constexpr int kEdgeCap = 1024;
 
@@ -806,14 +796,14 @@ __device__ __forceinline__ void pull_sum_lds(const BatchArgs &a, const Lds &t, i
     }
 }
 
-// Phase 3 for entry i of a staged tile: the sum over its overlapping
-// neighbours in ascending CSR order, then sigma (forward) or rho and the
-// dependency (backward) for the entry's lanes.
-template <bool kExt, bool kBackward, bool kPre, class Lds>
+// Phase 3 for entry i of a tile: the sum over its overlapping neighbours in
+// ascending CSR order (a row longer than kHub from its part sums, in part
+// order), then sigma (forward) or rho and the dependency (backward) for the
+// entry's lanes.
+template <bool kExt, bool kBackward, class Lds>
 __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int i, int lane,
                                           const uint64_t *F, const uint64_t *SG,
-                                          unsigned long long &ua, unsigned long long &ub,
-                                          double pre_p = 0.0, XNum pre_x = XNum{0.0, 0})
+                                          unsigned long long &ua, unsigned long long &ub)
 {
     const int64_t v = __builtin_amdgcn_readfirstlane(t.v[i]);
     const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)t.j[i]);
@@ -837,16 +827,15 @@ __device__ __forceinline__ void entry_sum(const BatchArgs &a, const Lds &t, int 
     XNum acc{0.0, 0};
     double accp = 0.0;
     ua += __popcll(m);
-    if (kPre) {
-        accp = pre_p;
-        acc = pre_x;
-    } else if (t.staged[i]) {
+    if (t.staged[i]) {
         pull_sum_lds<kExt>(a, t, t.start[i], t.start[i] + t.deg[i], m, lane, accp, acc, ub);
     } else if (t.deg[i] > kHub) {
         parts_sum<kExt>(a, v, j, t.deg[i], a.hpart, lane, accp, acc);
     } else {
-        row_sum<kExt>(a, (int64_t)uniform_u64((uint64_t)t.beg[i]),
-                      __builtin_amdgcn_readfirstlane(t.deg[i]), j, m, F, SG, lane, accp, acc, ub);
+        // a row the tile could not stage: its neighbours from global memory
+        const int64_t beg = (int64_t)uniform_u64((uint64_t)t.beg[i]);
+        pull_sum<kExt>(a, beg, beg + __builtin_amdgcn_readfirstlane(t.deg[i]), j, m, F, SG,
+                       lane, accp, acc, ub);
     }
     if (!kBackward) {
         if (mine) {
@@ -985,7 +974,7 @@ __device__ __forceinline__ void pull_tiles(BatchArgs a, int64_t e0, int64_t e1, 
         // than kHub from its part sums)
         for (int i = wv; i < kTile; i += nwv) {
             if (tile + i >= e1) break;
-            entry_sum<kExt, kBackward, false>(a, t, i, lane, F, SG, ua, ub);
+            entry_sum<kExt, kBackward>(a, t, i, lane, F, SG, ua, ub);
         }
         __syncthreads();
     }
