@@ -20,6 +20,9 @@ namespace bcmi {
 // threads per workgroup: a pass's levels are walked by all of them, so a wide
 // workgroup keeps more of a level's loads in flight per source
 constexpr int kWgBlock = 1024;
+// arcs of a thread's row whose loads are issued together (a group's heads,
+// then their records, before any is used)
+constexpr int kWgFlight = 8;
 
 // a vertex's state in a slot: the fields a pull reads together share one line
 struct WgVert {
@@ -105,8 +108,7 @@ __global__ void __launch_bounds__(kWgBlock) k_wg(WgArgs a)
             }
             __syncthreads();
             const int32_t nd = b0 + L + 1;
-            auto visit = [&](int32_t w) {
-                const int32_t old = vx[w].dist;
+            auto visit_from = [&](int32_t w, int32_t old) {
                 const bool got = old < b0 && atomicCAS(&vx[w].dist, old, nd) == old;
                 const int at = bi_append(got, &sh.cnt);
                 if (got) {
@@ -119,12 +121,22 @@ __global__ void __launch_bounds__(kWgBlock) k_wg(WgArgs a)
                 sh.rq, phase, q, f0, f1, a.row, [](int32_t) { return true; },
                 [&](int32_t, int64_t r0, int64_t r1) {
                     ub += (unsigned long long)(r1 - r0);
-                    for (int64_t e = r0; e < r1; ++e) visit(a.col[e]);
+                    for (int64_t e = r0; e < r1; e += kWgFlight) {
+                        int32_t y[kWgFlight], old[kWgFlight];
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) y[f] = e + f < r1 ? a.col[e + f] : -1;
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) old[f] = vx[y[f] >= 0 ? y[f] : y[0]].dist;
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f)
+                            if (y[f] >= 0) visit_from(y[f], old[f]);
+                    }
                 },
                 [&](int32_t, int64_t r0, int64_t r1, int lane) {
                     for (int64_t e = r0 + lane; e < r1; e += kWave) {
                         ++ub;
-                        visit(a.col[e]);
+                        const int32_t w = a.col[e];
+                        visit_from(w, vx[w].dist);
                     }
                 });
             const int cnt = sh.cnt;
@@ -137,22 +149,39 @@ __global__ void __launch_bounds__(kWgBlock) k_wg(WgArgs a)
                 sh.rq, phase, q, f1, f1 + cnt, a.rrow, [](int32_t) { return true; },
                 [&](int32_t w, int64_t r0, int64_t r1) {
                     ub += (unsigned long long)(r1 - r0);
-                    if (kExt) {
-                        XNum x{0.0, 0};
-                        for (int64_t e = r0; e < r1; ++e) {
-                            const int32_t u = a.rcol[e];
-                            if (pred(u)) x = xadd(x, XNum{vx[u].sig, vx[u].sige});
+                    // the same additions in CSR order; a group's records are
+                    // loaded together (a non-predecessor adds +0.0 to a
+                    // non-negative sum, or nothing in extended form)
+                    XNum x{0.0, 0};
+                    double xp = 0.0;
+                    for (int64_t e = r0; e < r1; e += kWgFlight) {
+                        int32_t u[kWgFlight], d[kWgFlight], ue[kWgFlight];
+                        double us[kWgFlight];
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) u[f] = e + f < r1 ? a.rcol[e + f] : -1;
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) {
+                            const WgVert &r = vx[u[f] >= 0 ? u[f] : u[0]];
+                            d[f] = r.dist;
+                            us[f] = r.sig;
+                            ue[f] = kExt ? r.sige : 0;
                         }
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) {
+                            const bool p = u[f] >= 0 && d[f] == pl;
+                            if (kExt) {
+                                if (p) x = xadd(x, XNum{us[f], ue[f]});
+                            } else {
+                                xp += p ? us[f] : 0.0;
+                            }
+                        }
+                    }
+                    if (kExt) {
                         vx[w].sig = x.m;
                         vx[w].sige = x.e;
                     } else {
-                        double x = 0.0;
-                        for (int64_t e = r0; e < r1; ++e) {
-                            const int32_t u = a.rcol[e];
-                            if (pred(u)) x += vx[u].sig;
-                        }
-                        vx[w].sig = x;
-                        if (!(x < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
+                        vx[w].sig = xp;
+                        if (!(xp < 0x1p1000)) a.ctl[CTL_SIG_OVERFLOW] = 1ull;
                     }
                 },
                 [&](int32_t w, int64_t r0, int64_t r1, int lane) {
@@ -207,10 +236,31 @@ __global__ void __launch_bounds__(kWgBlock) k_wg(WgArgs a)
                 sh.rq, phase, q, lo[l], lo[l + 1], a.row, [](int32_t) { return true; },
                 [&](int32_t v, int64_t r0, int64_t r1) {
                     ub += (unsigned long long)(r1 - r0);
+                    // contrib(v, w) from a group's records loaded together,
+                    // added in CSR order for the successors only
+                    const double sv = vx[v].sig;
+                    const int32_t ev = kExt ? vx[v].sige : 0;
                     double x = 0.0;
-                    for (int64_t e = r0; e < r1; ++e) {
-                        const int32_t w = a.col[e];
-                        if (vx[w].dist == nl) x += contrib(v, w);
+                    for (int64_t e = r0; e < r1; e += kWgFlight) {
+                        int32_t w[kWgFlight], d[kWgFlight], we[kWgFlight];
+                        double ws[kWgFlight], wd[kWgFlight];
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) w[f] = e + f < r1 ? a.col[e + f] : -1;
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) {
+                            const WgVert &r = vx[w[f] >= 0 ? w[f] : w[0]];
+                            d[f] = r.dist;
+                            ws[f] = r.sig;
+                            wd[f] = r.dlt;
+                            we[f] = kExt ? r.sige : 0;
+                        }
+#pragma unroll
+                        for (int f = 0; f < kWgFlight; ++f) {
+                            if (w[f] < 0 || d[f] != nl) continue;
+                            const double term = dst >= 0 ? (w[f] == dst ? 1.0 : 0.0) : 1.0;
+                            const double rr = kExt ? ldexp(sv / ws[f], ev - we[f]) : sv / ws[f];
+                            x += rr * (term + wd[f]);
+                        }
                     }
                     vx[v].dlt = x;
                     if (a.sum) vx[v].sum += x;
