@@ -253,7 +253,7 @@ def c1_leg(args, bc, gg, dev):
         kk = k.cpu().numpy()
         rec = {"ms": 1e3 * dt, "samples_executed": int(ex), "samples_used": int(kk.max()),
                "capped": int((st.cpu().numpy() == bc.BC_CAPPED).sum()),
-               "samples_per_s": ex / dt}
+               "samples_per_s": ex / dt, "bottom_up": G.stats()["bottom_up"]}
         if name.startswith("source"):
             rec["gteps"] = sampler_gteps(bc, G, gg, ce, 1, ex, False) / dt / 1e9
         out[name] = rec
@@ -289,7 +289,8 @@ def c2_leg(args, bc, gg, dev):
            "ms": 1e3 * dt, "samples_executed": int(ex), "samples_used_sum": int(kk.sum()),
            "samples_used_max": int(kk.max()), "rounds": int(G.stats()["batches"]),
            "capped": int((stt == bc.BC_CAPPED).sum()), "done": int((stt == bc.BC_DONE).sum()),
-           "gteps": sampler_gteps(bc, G, gg, ce, 2, ex, False) / dt / 1e9, "plan": G.plan()}
+           "gteps": sampler_gteps(bc, G, gg, ce, 2, ex, False) / dt / 1e9, "plan": G.plan(),
+           "round_bottom_up": G.stats()["bottom_up"]}
     G.close()
     log("C2: %.1f ms, %d sources executed, %d capped, %.2f GTEPS" % (
         out["ms"], ex, out["capped"], out["gteps"]))

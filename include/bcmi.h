@@ -208,8 +208,12 @@ bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
  * the best so far is abandoned early. Winners are cached per process by graph
  * signature (n, nnz, log2-degree histogram, BFS depth from a highest-degree
  * vertex). The width applies to bc_dependencies and bc_exact; the samplers keep
- * their round widths. Plans change scheduling only: values equal any other
- * plan's (sums up to FP64 summation order). *plan (optional) receives it. */
+ * their round widths, and a source sampler on the wave engine whose round width
+ * differs from the plan's tries the bottom_up candidates once more on four
+ * rounds of that width (the threshold is kept per graph signature and width,
+ * and bc_last_stats reports the one used). Plans change scheduling only:
+ * values equal any other plan's (sums up to FP64 summation order). *plan
+ * (optional) receives it. */
 bc_status bc_graph_tune(bc_graph *g, bc_config *plan);
 /* The plan compute calls on g use now, with the schedule resolved to the
  * engine that runs (BC_SCHED_BATCHED, BC_SCHED_THREADED or PER_SOURCE) and
@@ -304,6 +308,9 @@ typedef struct {
     int32_t pair_search;   /* pair samples: BC_PAIR_SEARCH_BIDIRECTIONAL when every
                               batch took the two-sided search, ONE_SIDED when any
                               ran one-sided, 0 for source samples */
+    double bottom_up;      /* bottom-up threshold the wave engine's levels used
+                              (fraction of (vertex, word) entries; -1 = top-down
+                              only); 0 when that engine did not run */
 } bc_stats;
 bc_status bc_last_stats(const bc_graph *g, bc_stats *out);
 

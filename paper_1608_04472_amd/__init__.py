@@ -89,7 +89,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("samples_executed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("levels", ctypes.c_int64), ("extended", ctypes.c_int32),
                 ("batch_width", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("pair_search", ctypes.c_int32)]
+                ("pair_search", ctypes.c_int32), ("bottom_up", ctypes.c_double)]
 
 
 class _KProf(ctypes.Structure):

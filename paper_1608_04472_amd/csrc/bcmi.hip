@@ -307,6 +307,9 @@ struct bc_graph {
     int64_t hubs_out = 0, hubs_in = 0, parts_out = 0, parts_in = 0;
     int32_t most_out = 0, most_in = 0;
     const int32_t *rhpart() const { return directed ? rhpart_buf.p : hpart_buf.p; }
+    // the vertices of those rows, ascending (hubs_out / hubs_in of them)
+    DBuf<int32_t> hlist_buf, rhlist_buf;
+    const int32_t *rhlist() const { return directed ? rhlist_buf.p : hlist_buf.p; }
     bc_config cfg{BC_SCHED_AUTO, 0, 0.0, 0, 0, 0, BC_PAIR_SEARCH_AUTO};
     Work own;
     Work *w = &own;
@@ -346,6 +349,7 @@ struct bc_graph {
         rrow_buf.release(); rcol_buf.release();
         wt_buf.release(); rwt_buf.release();
         hpart_buf.release(); rhpart_buf.release();
+        hlist_buf.release(); rhlist_buf.release();
         skey.release();
         own.release();
         prof_dev.release();
@@ -749,6 +753,7 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
     int64_t cap = std::max<int64_t>(g->cap_hint, std::max<int64_t>(4 * n * W, 1 << 16));
     if (g->w->cap_limit > 0) cap = std::min(cap, g->w->cap_limit);
     const double bu_frac = bottom_up_fraction(g);
+    g->stats.bottom_up = bu_frac;
     for (;;) {
         ensure_batch(g, p, ext, cap, kind);
         BatchArgs a = make_args(g, p, ext, nvalid, pair, cap, kind);
@@ -776,10 +781,14 @@ std::vector<int64_t> run_batch(bc_graph *g, const Plan &p, int nvalid, bool pair
         for (int level = 0;; ++level) {
             const int64_t e0 = off[level], e1 = off[level + 1];
             const int64_t nent = e1 - e0;
-            if (bu_frac > 0 && (double)nent > bu_frac * (double)(n * W))
+            if (bu_frac > 0 && (double)nent > bu_frac * (double)(n * W)) {
                 launch_hot(g, PROF_BOTTOMUP, grid_for(n * W), k_discover_bottomup, a,
                            (const uint64_t *)cur, nxt);
-            else
+                if (g->hubs_in)
+                    launch_hot(g, PROF_BOTTOMUP, grid_waves(g->hubs_in * W),
+                               k_discover_bottomup_long, a, (const uint64_t *)cur, nxt,
+                               g->rhlist(), g->hubs_in);
+            } else
                 launch_hot(g, PROF_TOPDOWN, grid_waves(nent), k_discover_topdown, a, e0, e1, nxt);
             build_level(g, a, nxt, cap);
             read_ctl(g);
@@ -1886,6 +1895,7 @@ void pair_dependencies_bidir(bc_graph *g, const int32_t *us, const int32_t *vs, 
         st.levels += g->stats.levels;
         st.extended |= g->stats.extended;
         st.batch_width = std::max(st.batch_width, g->stats.batch_width);
+        st.bottom_up = g->stats.bottom_up;
         st.pair_search = BC_PAIR_SEARCH_ONE_SIDED;
     }
     st.schedule = schedule_of(engine_for(g));
@@ -2102,6 +2112,95 @@ void ensure_tuned(bc_graph *g)
     if (g->cfg.schedule == BC_SCHED_TUNED && !g->tuned) apply_plan(g, tune_plan(g));
 }
 
+std::map<std::pair<TuneKey, int>, double> round_bu_cache;
+
+// Bottom-up threshold for the wave engine's source rounds of width B under a
+// tuned plan. The plan's threshold was chosen at the plan's own width; a
+// bottom-up level scans every unvisited (vertex, word) entry while a top-down
+// one follows the frontier, and the balance between them moves with the
+// number of words per vertex, so the candidates are tried again at the round
+// width: each is timed on four rounds of the tuner's seeded sources, the
+// plan's own threshold first, and the choice is kept per graph shape and
+// width. Values do not depend on the threshold, only the time does.
+double round_bottom_up(bc_graph *g, const Plan &p)
+{
+    const double planned = g->cfg.bottom_up;
+    if (p.B == g->tuned_batch) return planned;
+    const TuneKey tk{g->n, g->nnz, probe_depth(g), g->deg_hist};
+    const auto key = std::make_pair(tk, p.B);
+    {
+        std::lock_guard<std::mutex> lock(tune_mu);
+        auto it = round_bu_cache.find(key);
+        if (it != round_bu_cache.end()) return it->second;
+    }
+    const int64_t n = g->n;
+    const int64_t k = std::min<int64_t>(n, 4 * (int64_t)p.B);
+    hipStream_t s = g->stream;
+    DBuf<int32_t> sample;
+    DBuf<double> out;
+    sample.ensure((size_t)k);
+    out.ensure((size_t)n);
+    launch(s, grid_for(k), k_draw_sources, kTuneSeed, (int64_t)0, k, n, sample.p);
+    const bc_config user = g->cfg;
+    const int32_t user_batch = g->tuned_batch;
+    double best_per = 0.0, best = planned;
+    bool have = false;
+    auto restore = [&] {
+        g->timed = false;
+        g->cfg = user;
+        g->tuned_batch = user_batch;
+    };
+    std::vector<double> cand{planned};
+    for (double bu : kTuneBottomUp)
+        if (bu != bottom_up_fraction(g)) cand.push_back(bu);
+    try {
+        // one untimed round first, so that no candidate is timed cold
+        g->cfg.batch = p.B;
+        g->tuned_batch = 0;
+        dependencies_impl(g, sample.p, std::min<int64_t>(k, p.B), BC_OUT_SUM, out.p, nullptr,
+                          nullptr, nullptr, false, nullptr);
+        for (double bu : cand) {
+            g->cfg.batch = p.B;
+            g->cfg.bottom_up = bu;
+            g->tuned_batch = 0;
+            ensure_batch(g, plan_batch(g, k, p.B), g->ext_sticky, start_cap(g), OUT_VSUM);
+            HIPX(hipStreamSynchronize(s));
+            g->timed = have;
+            g->deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double>(std::max(0.05, 1.5 * best_per)));
+            const auto t0 = std::chrono::steady_clock::now();
+            try {
+                dependencies_impl(g, sample.p, k, BC_OUT_SUM, out.p, nullptr, nullptr, nullptr,
+                                  false, nullptr);
+            } catch (const TuneTimeout &) {
+                (void)hipStreamSynchronize(s);
+                continue;
+            }
+            const double per =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (!have || per < best_per) {
+                best_per = per;
+                best = bu;
+                have = true;
+            }
+        }
+    } catch (...) {
+        restore();
+        sample.release();
+        out.release();
+        throw;
+    }
+    restore();
+    sample.release();
+    out.release();
+    {
+        std::lock_guard<std::mutex> lock(tune_mu);
+        round_bu_cache[key] = best;
+    }
+    return best;
+}
+
 // --------------------------------------------------------------- samplers
 
 void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int32_t rule,
@@ -2130,6 +2229,17 @@ void sampler_impl(bc_graph *g, const int32_t *targets, int32_t T, bool pair, int
         p.B = plan_pairs(g, k_max, round);
     }
     g->cfg.batch = keep_batch;
+    // source rounds of a width other than the tuned plan's take a bottom-up
+    // threshold tried at their own width, for this call only
+    struct KeepBottomUp {
+        bc_graph *g;
+        double v;
+        ~KeepBottomUp() { g->cfg.bottom_up = v; }
+    } keep_bu{g, g->cfg.bottom_up};
+    if (g->tuned && !pair && !use_pairs && !g->weighted) {
+        g->cfg.bottom_up = round_bottom_up(g, p);
+        g->stats = bc_stats{};
+    }
     g->stats.batch_width = p.B;
     g->stats.schedule = use_pairs ? BC_SCHED_THREADED : BC_SCHED_BATCHED;
     g->w->X.ensure((size_t)T * p.B);
@@ -2330,18 +2440,20 @@ void validate_weights(const bc_csr *c, const std::vector<int64_t> &row, const in
 
 // The rows longer than kHub in `row`: the first part (of kPart neighbours)
 // of each in the part-sum slab, rows in vertex order, -1 for shorter rows,
-// uploaded to `out`; their number, their parts and the most parts of one row.
-void hub_table(const std::vector<int64_t> &row, DBuf<int32_t> &out, int64_t &hubs, int64_t &parts,
-               int32_t &most)
+// uploaded to `out`; their vertices, ascending, uploaded to `list`; their
+// number, their parts and the most parts of one row.
+void hub_table(const std::vector<int64_t> &row, DBuf<int32_t> &out, DBuf<int32_t> &list,
+               int64_t &hubs, int64_t &parts, int32_t &most)
 {
     const size_t n = row.size() - 1;
-    std::vector<int32_t> h(n, -1);
+    std::vector<int32_t> h(n, -1), vs;
     hubs = parts = 0;
     most = 0;
     for (size_t v = 0; v < n; ++v) {
         const int64_t d = row[v + 1] - row[v];
         if (d <= kHub) continue;
         h[v] = (int32_t)parts;
+        vs.push_back((int32_t)v);
         const int64_t q = (d + kPart - 1) / kPart;
         parts += q;
         hubs += 1;
@@ -2350,6 +2462,9 @@ void hub_table(const std::vector<int64_t> &row, DBuf<int32_t> &out, int64_t &hub
     }
     out.ensure(n);
     HIPX(hipMemcpy(out.p, h.data(), n * 4, hipMemcpyHostToDevice));
+    list.ensure(std::max<size_t>(vs.size(), 1));
+    if (!vs.empty())
+        HIPX(hipMemcpy(list.p, vs.data(), vs.size() * 4, hipMemcpyHostToDevice));
 }
 
 void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream, bc_graph **out,
@@ -2414,7 +2529,7 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
             HIPX(hipMemcpy(g->row.p, row.data(), row.size() * 8, hipMemcpyHostToDevice));
             if (csr->nnz)
                 HIPX(hipMemcpy(g->col.p, csr->col, (size_t)csr->nnz * 4, hipMemcpyHostToDevice));
-            hub_table(row, g->hpart_buf, g->hubs_out, g->parts_out, g->most_out);
+            hub_table(row, g->hpart_buf, g->hlist_buf, g->hubs_out, g->parts_out, g->most_out);
             g->hubs_in = g->hubs_out;
             g->parts_in = g->parts_out;
             g->most_in = g->most_out;
@@ -2446,7 +2561,8 @@ void create_graph(const bc_csr *csr, const bc_allocator *alloc, void *hip_stream
                                    hipMemcpyHostToDevice));
                 }
                 g->directed = true;
-                hub_table(trow, g->rhpart_buf, g->hubs_in, g->parts_in, g->most_in);
+                hub_table(trow, g->rhpart_buf, g->rhlist_buf, g->hubs_in, g->parts_in,
+                          g->most_in);
                 g->rrow_buf.ensure(trow.size());
                 g->rcol_buf.ensure((size_t)csr->nnz);
                 HIPX(hipMemcpy(g->rrow_buf.p, trow.data(), trow.size() * 8, hipMemcpyHostToDevice));
@@ -3380,10 +3496,12 @@ bc_status bc_server_add_graph(bc_server *sv, const bc_csr *csr, int32_t *graph_i
         UseAlloc ua(&sv->alloc);
         need(csr->n >= 1 && csr->n < 0x7fffffffll, "n must be in [1, 2^31 - 1)");
         const int64_t n = csr->n;
-        // resident: the CSR (int64 rows, int32 columns) and the lane-order key
-        // and the handle's own control block
-        const size_t res_bytes = (size_t)(n + 1) * 8 + (size_t)std::max<int64_t>(csr->nnz, 0) * 4 +
-                                 (size_t)n * 8 + (size_t)n * 4 +
+        // resident: the CSR (int64 rows, int32 columns), the lane-order key, the
+        // long-row table and list (at most nnz / (kHub + 1) such rows) and the
+        // handle's own control block
+        const int64_t nnz = std::max<int64_t>(csr->nnz, 0);
+        const size_t res_bytes = (size_t)(n + 1) * 8 + (size_t)nnz * 4 + (size_t)n * 8 +
+                                 (size_t)n * 4 + (size_t)(nnz / (kHub + 1) + 1) * 4 +
                                  CTL_WORDS * sizeof(unsigned long long);
         // every lane may hold the widest need (one workspace per lane)
         const size_t L = sv->lanes.size();

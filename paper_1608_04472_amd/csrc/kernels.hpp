@@ -166,6 +166,13 @@ enum : int {
     PROF_KERNELS = 13
 };
 
+__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x |= __shfl_xor(x, off, 64);
+    return x;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 {
 #pragma unroll
@@ -347,8 +354,9 @@ __global__ void k_discover_bottomup(BatchArgs a_in, const uint64_t *cur, uint64_
             // a lane absent from the current level finds nothing (its search
             // has ended, e.g. a source outside this vertex's component)
             const uint64_t want = ~a.vis[idx] & a.valid[j] & a.active[j] & a.live[j];
-            if (want) {
-                const int64_t v = idx >> a.logW;
+            const int64_t v = idx >> a.logW;
+            // rows longer than kHub take a wavefront each (k_discover_bottomup_long)
+            if (want && a.rhpart[v] < 0) {
                 uint64_t acc = 0;
                 const int64_t beg = a.row[v], end = a.row[v + 1];
                 // eight neighbours per step; the next step's neighbour ids are
@@ -376,6 +384,50 @@ __global__ void k_discover_bottomup(BatchArgs a_in, const uint64_t *cur, uint64_
         }
     }
     if (a.prof) prof_add(a, PROF_BOTTOMUP, wave_sum_u64(found), 0, lane_id());
+}
+
+// Bottom-up for the in-rows longer than kHub: one wavefront per (vertex, word)
+// of the `nlong` listed vertices, 256 neighbours a step (four per lane, their
+// frontier words ORed over the wavefront), stopping once every wanted source
+// is found. A thread alone would walk such a row serially while the rest of
+// its wavefront waits.
+__global__ void k_discover_bottomup_long(BatchArgs a, const uint64_t *cur, uint64_t *nxt,
+                                         const int32_t *longv, int64_t nlong)
+{
+    const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t wmask = (1u << a.logW) - 1u;
+    unsigned long long found = 0;
+    for (int64_t t = wave; t < (nlong << a.logW); t += nwaves) {
+        const int64_t v = longv[t >> a.logW];
+        const uint32_t j = (uint32_t)t & wmask;
+        const int64_t idx = (v << a.logW) + j;
+        const uint64_t want = ~a.vis[idx] & a.valid[j] & a.active[j] & a.live[j];
+        if (want == 0) continue;
+        const int64_t beg = a.rrow[v], end = a.rrow[v + 1];
+        unsigned long long acc = 0;
+        for (int64_t p0 = beg; p0 < end; p0 += 4 * kWave) {
+            int32_t c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t p = p0 + k * kWave + lane;
+                c[k] = p < end ? a.rcol[p] : -1;
+            }
+            unsigned long long f = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                f |= c[k] >= 0 ? cur[kFS * (((int64_t)c[k] << a.logW) + j)] : 0ull;
+            acc |= wave_or_u64(f);
+            if ((acc & want) == want) break;
+        }
+        const uint64_t fresh = acc & want;
+        if (fresh && lane == 0) {
+            nxt[kFS * idx] = fresh;
+            found += __popcll(fresh);
+        }
+    }
+    if (a.prof) prof_add(a, PROF_BOTTOMUP, wave_sum_u64(found), 0, lane);
 }
 
 // ------------------------------------------------------- level record

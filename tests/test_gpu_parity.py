@@ -562,23 +562,25 @@ def test_accuracy_sweep_settings_match_the_oracle(dev):
     G.close()
 
 
-def test_long_rows_in_parts_bit_identical_across_widths(dev):
+@pytest.mark.parametrize("bu", [0.0, 1e-9], ids=["auto", "bottom-up"])
+def test_long_rows_in_parts_bit_identical_across_widths(dev, bu):
     # rows longer than 256 are summed in fixed parts of 256 (each by its own
     # wavefront, parts added in order) and shorter rows in CSR order, so a
     # source's values do not depend on the batch it runs in: widths 64, 512
     # and 4096 (one, eight and 64 words of 64) give identical bits, and they
-    # match the oracle
+    # match the oracle; with every level bottom-up, those rows also look for
+    # their frontier parents with a wavefront each
     g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
     assert (g.degree() > 256).sum() > 20 and g.degree().max() > 4 * 256
     src = np.concatenate([gg.top_degree(g, 4), gg.philox_sources(4, 250, g.n)]).astype(np.int32)
     outs = {}
     for width in (64, 512, 4096):
         G = bc.Graph(g.row, g.col)
-        G.configure(bc.BC_SCHED_BATCHED, width, 0.0)
+        G.configure(bc.BC_SCHED_BATCHED, width, bu)
         if width == 64:
-            outs[width] = check_sources(G, g, src, dev, "rmat12 parts width 64")
+            outs[width] = check_sources(G, g, src, dev, "rmat12 parts width 64 bu=%g" % bu)
         else:
-            say("rmat12 parts width %d" % width)
+            say("rmat12 parts width %d bu=%g" % (width, bu))
             outs[width] = bc.dependencies(G, T(src, dev), bc.BC_OUT_FULL)[0].cpu().numpy()
         assert G.stats()["batch_width"] == width
         G.close()

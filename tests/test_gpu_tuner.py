@@ -119,3 +119,46 @@ def test_tuned_plan(dev, name):
     assert_close(est[0].cpu().numpy(), want[0], what="tuned sampler")
     H.close()
     G.close()
+
+
+@pytest.mark.parametrize("name", ["rmat12", "er2000"])
+def test_sampler_rounds_take_a_threshold_tried_at_their_width(dev, name):
+    """A source sampler whose round width differs from the tuned plan's runs
+    the wave engine with a bottom-up threshold tried at the round width: one of
+    the candidates, the same on a second call (kept per graph and width), the
+    plan itself left as tuned, and the estimates equal to the oracle's."""
+    g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9) if name == "rmat12" else \
+        gg.config_graph("er2000")
+    G = bc.Graph(g.row, g.col)
+    say("tune", name)
+    plan = G.tune()
+    sb = 512 if plan["batch"] == 256 else 256
+    H = bc.Graph(g.row, g.col)
+    H.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, sb)
+    eff = H.plan()
+    tg = gg.top_degree(g, 3)
+    want = O.adaptive_source(g, tg, 2.0, 5, 300)
+    used = []
+    for rep in range(2):
+        say("sampler rounds", name, "width", sb, "call", rep)
+        est = bc.adaptive_source(H, torch.from_numpy(tg).to(dev), 2.0, 5, 300)
+        assert np.array_equal(est[1].cpu().numpy(), want[1])
+        assert_close(est[0].cpu().numpy(), want[0], what="sampler at width %d" % sb)
+        st = H.stats()
+        assert st["batch_width"] == sb
+        used.append(st["bottom_up"])
+        assert H.plan() == eff
+    if eff["schedule"] == bc.BC_SCHED_BATCHED:
+        assert used[0] in BOTTOM_UP, used
+        assert used[1] == used[0], used
+    else:
+        assert used == [0.0, 0.0], used      # the wave engine did not run
+    # the plan's own width keeps the plan's threshold
+    H.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, plan["batch"])
+    H.plan()
+    bc.adaptive_source(H, torch.from_numpy(tg).to(dev), 2.0, 5, 300)
+    if eff["schedule"] == bc.BC_SCHED_BATCHED:
+        planned = plan["bottom_up"] if plan["bottom_up"] != 0 else 0.04
+        assert H.stats()["bottom_up"] == planned
+    H.close()
+    G.close()
