@@ -209,9 +209,9 @@ bc_status bc_graph_set_stream(bc_graph *g, void *hip_stream);
  * signature (n, nnz, log2-degree histogram, BFS depth from a highest-degree
  * vertex). The width applies to bc_dependencies and bc_exact; the samplers keep
  * their round widths, and a source sampler on the wave engine whose round width
- * differs from the plan's tries the bottom_up candidates once more on four
- * rounds of that width (the threshold is kept per graph signature and width,
- * and bc_last_stats reports the one used). Plans change scheduling only:
+ * differs from the plan's tries the bottom_up candidates once more on up to
+ * eight rounds of that width, twice each (the threshold is kept per graph
+ * signature and width, and bc_last_stats reports the one used). Plans change scheduling only:
  * values equal any other plan's (sums up to FP64 summation order). *plan
  * (optional) receives it. */
 bc_status bc_graph_tune(bc_graph *g, bc_config *plan);

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <limits>
 #include <map>
 #include <tuple>
 #include <cmath>
@@ -2119,9 +2120,12 @@ std::map<std::pair<TuneKey, int>, double> round_bu_cache;
 // bottom-up level scans every unvisited (vertex, word) entry while a top-down
 // one follows the frontier, and the balance between them moves with the
 // number of words per vertex, so the candidates are tried again at the round
-// width: each is timed on four rounds of the tuner's seeded sources, the
-// plan's own threshold first, and the choice is kept per graph shape and
-// width. Values do not depend on the threshold, only the time does.
+// width: each is timed on up to eight rounds of the tuner's seeded sources,
+// twice, the candidates alternating (nearby thresholds differ by a few per
+// cent, about what one short trial varies by), and the fastest of each
+// candidate's two times decides, the plan's own threshold winning ties. The
+// choice is kept per graph shape and width. Values do not depend on the
+// threshold, only the time does.
 double round_bottom_up(bc_graph *g, const Plan &p)
 {
     const double planned = g->cfg.bottom_up;
@@ -2134,7 +2138,7 @@ double round_bottom_up(bc_graph *g, const Plan &p)
         if (it != round_bu_cache.end()) return it->second;
     }
     const int64_t n = g->n;
-    const int64_t k = std::min<int64_t>(n, 4 * (int64_t)p.B);
+    const int64_t k = std::min<int64_t>(n, 8 * (int64_t)p.B);
     hipStream_t s = g->stream;
     DBuf<int32_t> sample;
     DBuf<double> out;
@@ -2143,8 +2147,6 @@ double round_bottom_up(bc_graph *g, const Plan &p)
     launch(s, grid_for(k), k_draw_sources, kTuneSeed, (int64_t)0, k, n, sample.p);
     const bc_config user = g->cfg;
     const int32_t user_batch = g->tuned_batch;
-    double best_per = 0.0, best = planned;
-    bool have = false;
     auto restore = [&] {
         g->timed = false;
         g->cfg = user;
@@ -2153,35 +2155,41 @@ double round_bottom_up(bc_graph *g, const Plan &p)
     std::vector<double> cand{planned};
     for (double bu : kTuneBottomUp)
         if (bu != bottom_up_fraction(g)) cand.push_back(bu);
+    // each candidate's fastest time; < 0 until timed, infinite once abandoned
+    std::vector<double> best_t(cand.size(), -1.0);
+    double best_all = 0.0;
+    bool have = false;
     try {
         // one untimed round first, so that no candidate is timed cold
         g->cfg.batch = p.B;
         g->tuned_batch = 0;
         dependencies_impl(g, sample.p, std::min<int64_t>(k, p.B), BC_OUT_SUM, out.p, nullptr,
                           nullptr, nullptr, false, nullptr);
-        for (double bu : cand) {
-            g->cfg.batch = p.B;
-            g->cfg.bottom_up = bu;
-            g->tuned_batch = 0;
-            ensure_batch(g, plan_batch(g, k, p.B), g->ext_sticky, start_cap(g), OUT_VSUM);
-            HIPX(hipStreamSynchronize(s));
-            g->timed = have;
-            g->deadline = std::chrono::steady_clock::now() +
-                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
-                              std::chrono::duration<double>(std::max(0.05, 1.5 * best_per)));
-            const auto t0 = std::chrono::steady_clock::now();
-            try {
-                dependencies_impl(g, sample.p, k, BC_OUT_SUM, out.p, nullptr, nullptr, nullptr,
-                                  false, nullptr);
-            } catch (const TuneTimeout &) {
-                (void)hipStreamSynchronize(s);
-                continue;
-            }
-            const double per =
-                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (!have || per < best_per) {
-                best_per = per;
-                best = bu;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (size_t c = 0; c < cand.size(); ++c) {
+                if (std::isinf(best_t[c])) continue;
+                g->cfg.batch = p.B;
+                g->cfg.bottom_up = cand[c];
+                g->tuned_batch = 0;
+                ensure_batch(g, plan_batch(g, k, p.B), g->ext_sticky, start_cap(g), OUT_VSUM);
+                HIPX(hipStreamSynchronize(s));
+                g->timed = have;
+                g->deadline = std::chrono::steady_clock::now() +
+                              std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                  std::chrono::duration<double>(std::max(0.05, 1.5 * best_all)));
+                const auto t0 = std::chrono::steady_clock::now();
+                try {
+                    dependencies_impl(g, sample.p, k, BC_OUT_SUM, out.p, nullptr, nullptr,
+                                      nullptr, false, nullptr);
+                } catch (const TuneTimeout &) {
+                    (void)hipStreamSynchronize(s);
+                    if (best_t[c] < 0) best_t[c] = std::numeric_limits<double>::infinity();
+                    continue;
+                }
+                const double t =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (best_t[c] < 0 || t < best_t[c]) best_t[c] = t;
+                if (!have || t < best_all) best_all = t;
                 have = true;
             }
         }
@@ -2194,6 +2202,12 @@ double round_bottom_up(bc_graph *g, const Plan &p)
     restore();
     sample.release();
     out.release();
+    double best = planned, bt = std::numeric_limits<double>::infinity();
+    for (size_t c = 0; c < cand.size(); ++c)
+        if (best_t[c] >= 0 && best_t[c] < bt) {
+            bt = best_t[c];
+            best = cand[c];
+        }
     {
         std::lock_guard<std::mutex> lock(tune_mu);
         round_bu_cache[key] = best;
