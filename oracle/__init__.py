@@ -22,6 +22,10 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
                       counts, planted mistakes
   pair_work           closed forms (paths, stars, adjacent and unreachable
                       pairs), scipy BFS distances, planted mistakes
+  bidir_work          the two-sided search's walks (the library's design, a
+                      measurement check): closed forms worked by hand (stars,
+                      paths, directed paths, unreachable pairs), bounds by
+                      the components' sizes and arcs, planted mistakes
   *_weighted          the same functions on graphs with positive integer arc
                       weights (Dijkstra's algorithm): brute-force enumeration
                       of weighted shortest paths, networkx's weighted
@@ -94,6 +98,9 @@ def _declare(lib):
                                        c.c_void_p, c.c_void_p, c.c_void_p]
     lib.oracle_pair_work.argtypes = [c.c_int64, c.c_void_p, c.c_void_p, c.c_int32,
                                      c.c_int32, c.c_void_p]
+    lib.oracle_bidir_work.argtypes = [c.c_int64, c.c_void_p, c.c_void_p, c.c_int, c.c_int32,
+                                      c.c_int32, c.c_void_p, c.c_void_p]
+    lib.oracle_bidir_work.restype = c.c_int
     for name in ("oracle_brandes", "oracle_bc_exact", "oracle_dependencies",
                  "oracle_pair_dependency", "oracle_adaptive_source", "oracle_adaptive_pair"):
         d = getattr(lib, name + "_directed")
@@ -248,6 +255,15 @@ class Oracle:
         _ok(self.lib.oracle_pair_work(n, _p(row), _p(col), int(u), int(v), _p(a)),
             "oracle_pair_work")
         return int(a[0])
+
+    def bidir_work(self, g, u, v, directed=False):
+        """(vertices found, arcs read) by the two-sided search for (u, v)."""
+        n, row, col = _csr(g)
+        a = np.zeros(2, np.int64)
+        _ok(self.lib.oracle_bidir_work(n, _p(row), _p(col), 1 if directed else 0, int(u), int(v),
+                                       a[0:].ctypes.data, a[1:].ctypes.data),
+            "oracle_bidir_work")
+        return int(a[0]), int(a[1])
 
 
 def sigma_value(mant, exp):

@@ -865,3 +865,129 @@ int oracle_pair_work(int64_t n, const int64_t *row, const int32_t *col, int32_t 
     pass_free(&p);
     return 0;
 }
+
+/* Work of the two-sided pair search, counted over the walks the library's
+ * search takes. Section 6.2 stops a pair's search once the destination is
+ * reached; growing it from both ends in this balanced order is the
+ * library's design, not the paper's, and this count is a measurement check
+ * only. The rules, step by step:
+ *   - side 0 grows from u over out-arcs, side 1 from v over in-arcs; each
+ *     step the side whose frontier has fewer arcs to walk (side 0 on ties)
+ *     walks every arc of its frontier, adding each vertex it had not held as
+ *     its next level; the step meets the other side when any arc's head is
+ *     held by the other side;
+ *   - a step also reads, over the other direction, the row of each vertex it
+ *     added (after a meeting step: only those the other side holds);
+ *   - the search ends without a meeting when the chosen side has no arcs to
+ *     walk or adds no vertex;
+ *   - after a meeting, with D the sum of the two depths, side 0's levels and
+ *     then side 1's are swept from the deepest up: at level L, every vertex
+ *     of level L+1 that the other side holds at distance D-L-1 reads its row
+ *     over the other direction and gives each neighbour of this side's level
+ *     L the other side's distance D-L; then every level-L vertex the other
+ *     side now holds at D-L reads its row over this side's direction.
+ * found = vertices the steps add (the two ends excluded); arcs = the arcs of
+ * every row read. */
+static int bidir_work_g(const graph_t *g, int32_t u, int32_t v, int64_t *found, int64_t *arcs)
+{
+    const int64_t n = g->n;
+    const int64_t *row[2] = {g->row, g->rrow};
+    const int32_t *col[2] = {g->col, g->rcol};
+    int32_t *dist[2] = {NULL, NULL}, *list[2] = {NULL, NULL};
+    int64_t *lo[2] = {NULL, NULL};
+    int rc = 0;
+    for (int s = 0; s < 2; ++s) {
+        dist[s] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        list[s] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        lo[s] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 2));
+        if (!dist[s] || !list[s] || !lo[s]) rc = -2;
+    }
+    if (rc == 0) {
+        for (int s = 0; s < 2; ++s)
+            for (int64_t x = 0; x < n; ++x) dist[s][x] = -1;
+        const int32_t end[2] = {u, v};
+        int depth[2] = {0, 0};
+        int64_t f0[2] = {0, 0}, f1[2] = {1, 1}, vol[2];
+        for (int s = 0; s < 2; ++s) {
+            dist[s][end[s]] = 0;
+            list[s][0] = end[s];
+            lo[s][0] = 0;
+            lo[s][1] = 1;
+            vol[s] = row[s][end[s] + 1] - row[s][end[s]];
+        }
+        int64_t nf = 0, na = 0;
+        int met = 0;
+        for (;;) {
+            const int s = vol[0] <= vol[1] ? 0 : 1, o = 1 - s;
+            if (vol[s] == 0) break;
+            int meet = 0;
+            int64_t put = f1[s], cnt = 0, nv = 0;
+            for (int64_t i = f0[s]; i < f1[s]; ++i) {
+                const int32_t x = list[s][i];
+                na += row[s][x + 1] - row[s][x];
+                for (int64_t e = row[s][x]; e < row[s][x + 1]; ++e) {
+                    const int32_t y = col[s][e];
+                    if (dist[s][y] < 0) {
+                        dist[s][y] = depth[s] + 1;
+                        list[s][put + cnt++] = y;
+                        nv += row[s][y + 1] - row[s][y];
+                        ++nf;
+                    }
+                    if (dist[o][y] >= 0) meet = 1;
+                }
+            }
+            vol[s] = nv;
+            if (cnt == 0) break;
+            depth[s] += 1;
+            f0[s] = put;
+            f1[s] = put + cnt;
+            lo[s][depth[s] + 1] = put + cnt;
+            for (int64_t i = put; i < put + cnt; ++i) {
+                const int32_t w = list[s][i];
+                if (!meet || dist[o][w] >= 0) na += row[o][w + 1] - row[o][w];
+            }
+            if (meet) {
+                met = 1;
+                break;
+            }
+        }
+        if (met) {
+            const int D = depth[0] + depth[1];
+            for (int s = 0; s < 2; ++s) {
+                const int o = 1 - s;
+                for (int L = depth[s] - 1; L >= 0; --L) {
+                    for (int64_t i = lo[s][L + 1]; i < lo[s][L + 2]; ++i) {
+                        const int32_t x = list[s][i];
+                        if (dist[o][x] != D - L - 1) continue;
+                        na += row[o][x + 1] - row[o][x];
+                        for (int64_t e = row[o][x]; e < row[o][x + 1]; ++e)
+                            if (dist[s][col[o][e]] == L) dist[o][col[o][e]] = D - L;
+                    }
+                    for (int64_t i = lo[s][L]; i < lo[s][L + 1]; ++i) {
+                        const int32_t w = list[s][i];
+                        if (dist[o][w] == D - L) na += row[s][w + 1] - row[s][w];
+                    }
+                }
+            }
+        }
+        *found = nf;
+        *arcs = na;
+    }
+    for (int s = 0; s < 2; ++s) {
+        free(dist[s]);
+        free(list[s]);
+        free(lo[s]);
+    }
+    return rc;
+}
+
+int oracle_bidir_work(int64_t n, const int64_t *row, const int32_t *col, int directed, int32_t u,
+                      int32_t v, int64_t *found, int64_t *arcs)
+{
+    if (check_graph(n, row, col) || u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
+    if (!directed) {
+        const graph_t g = undirected(n, row, col);
+        return bidir_work_g(&g, u, v, found, arcs);
+    }
+    WITH_DIRECTED(n, row, col, bidir_work_g(&g, u, v, found, arcs));
+}

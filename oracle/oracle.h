@@ -139,6 +139,12 @@ int oracle_source_work(int64_t n, const int64_t *row, const int32_t *col, int32_
                        int64_t *reached, int64_t *edges_undirected, int64_t *dag_edges);
 int oracle_pair_work(int64_t n, const int64_t *row, const int32_t *col, int32_t u, int32_t v,
                      int64_t *edges_undirected);
+/* Work of the library's two-sided search for the pair (u, v), u != v, over
+ * the same walks (the balanced order is the library's design; a measurement
+ * check, not the paper's arithmetic): vertices the search adds and arcs of
+ * the rows it reads. directed != 0: col lists out-neighbours. */
+int oracle_bidir_work(int64_t n, const int64_t *row, const int32_t *col, int directed, int32_t u,
+                      int32_t v, int64_t *found, int64_t *arcs);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,9 @@ edges that the oracle's plain BFS counts (oracle_source_work):
   backward units_a = sum of (reached - 1);
            units_b = sum of (DAG edges - deg(s)), the source's own edges being
            the only DAG edges the sweep from level 1 up does not read.
+The two-sided pair search counts (bidir_pair) the vertices it adds (units_a)
+and the arcs of every row it reads (units_b); both must equal the oracle's
+count of the same walks (oracle_bidir_work) summed over the pairs.
 Rows longer than 256 are summed in parts by their own kernel (hub_parts), whose
 units_b hold those rows' DAG edges for both pulls: the two pulls' units_b and
 hub_parts' add up to the two totals, and each pull alone matches its total on
@@ -188,4 +191,44 @@ def test_weighted_units_equal_the_oracle_counts(dev, name, make):
         assert prof[k]["units_a"] == want_a, (name, k, prof[k]["units_a"], want_a)
         assert prof[k]["units_b"] == want_b, (name, k, prof[k]["units_b"], want_b)
     assert prof["w_search"]["units_a"] >= want_b   # every reached lane's out-row at least once
+    G.close()
+
+
+BIDIR_CASES = [
+    ("er2000", lambda: gg.config_graph("er2000"), False),
+    ("rmat12", lambda: gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9), False),
+    ("grid60", lambda: gg.grid(60, 60), False),
+    ("drmat11", lambda: gg.rmat_directed(11, 8, 0.57, 0.19, 0.19, seed=4), True),
+]
+
+
+@pytest.mark.parametrize("name,make,directed", BIDIR_CASES, ids=[c[0] for c in BIDIR_CASES])
+def test_bidir_units_equal_the_oracle_counts(dev, name, make, directed):
+    g = make()
+    rng = np.random.default_rng(31)
+    us = rng.integers(0, g.n, 300).astype(np.int32)
+    vs = rng.integers(0, g.n, 300).astype(np.int32)
+    vs = np.where(vs == us, (vs + 1) % g.n, vs).astype(np.int32)
+    top = gg.top_degree(g, 2)
+    us[:2], vs[:2] = top, top[::-1]                       # hub to hub, both ways
+    us[2], vs[2] = top[0], int(g.col[g.row[top[0]]])       # an arc's two ends
+    iso = np.flatnonzero(g.degree() == 0)
+    if iso.size:
+        us[3], vs[3] = iso[0], top[0]                      # nothing to walk from u
+        us[4], vs[4] = top[0], iso[0]
+    want_a = want_b = 0
+    for u, v in zip(us, vs):
+        a, b = O.bidir_work(g, int(u), int(v), directed=directed)
+        want_a += a
+        want_b += b
+    G = bc.Graph(g.row, g.col, directed=directed)
+    G.configure(bc.BC_SCHED_AUTO, 0, 0.0, pair_search=bc.BC_PAIR_SEARCH_BIDIRECTIONAL)
+    say(name, "two-sided search counters")
+    G.profile(True)
+    bc.pair_dependencies(G, torch.from_numpy(us).to(dev), torch.from_numpy(vs).to(dev))
+    prof = {k["name"]: k for k in G.profile_read()}
+    G.profile(False)
+    assert G.stats()["pair_search"] == bc.BC_PAIR_SEARCH_BIDIRECTIONAL
+    assert prof["bidir_pair"]["units_a"] == want_a, (name, prof["bidir_pair"]["units_a"], want_a)
+    assert prof["bidir_pair"]["units_b"] == want_b, (name, prof["bidir_pair"]["units_b"], want_b)
     G.close()

@@ -62,6 +62,15 @@ WORK_MUTANTS = {
                               "int lead = (da <= db);"),
     "reached_without_source": ("if (reached) *reached = p.reached;",
                                "if (reached) *reached = p.reached - 1;"),
+    "bidir_ties_to_side_one": ("const int s = vol[0] <= vol[1] ? 0 : 1, o = 1 - s;",
+                               "const int s = vol[0] < vol[1] ? 0 : 1, o = 1 - s;"),
+    "bidir_frontier_by_vertices": ("nv += row[s][y + 1] - row[s][y];", "nv += 1;"),
+    "bidir_counts_every_new_vertex": ("if (!meet || dist[o][w] >= 0) na += row[o][w + 1] - row[o][w];",
+                                      "na += row[o][w + 1] - row[o][w];"),
+    "bidir_sweep_stops_above_level_zero": ("for (int L = depth[s] - 1; L >= 0; --L) {",
+                                           "for (int L = depth[s] - 1; L >= 1; --L) {"),
+    "bidir_sweep_pull_wrong_direction": ("if (dist[o][w] == D - L) na += row[s][w + 1] - row[s][w];",
+                                         "if (dist[o][w] == D - L) na += row[o][w + 1] - row[o][w];"),
 }
 
 
@@ -177,6 +186,19 @@ def work_pins_pass(O):
             k = abs(u - v)
             if O.pair_work(p, u, v) != min(u, k) + min(k, n - 1 - u):
                 return False
+        # the two-sided search's walks, worked by hand (tests/test_oracle_work.py)
+        if O.bidir_work(gg.star(6), 1, 2) != (2, 24) or O.bidir_work(gg.star(6), 0, 1) != (1, 12):
+            return False
+        if O.bidir_work(gg.path(9), 0, 8) != (8, 60):
+            return False
+        if O.bidir_work(gg.directed_path(5), 0, 4, directed=True) != (4, 16):
+            return False
+        if O.bidir_work(gg.from_edges(8, [0, 1, 0, 3, 4, 5], [1, 2, 2, 4, 5, 6]), 0, 5) != (5, 16):
+            return False
+        if O.bidir_work(gg.from_edges(5, [0, 0, 1, 2], [1, 2, 3, 4]), 0, 1) != (2, 8):
+            return False
+        if O.bidir_work(gg.from_edges(4, [0, 3, 1], [3, 1, 2]), 0, 1) != (2, 14):
+            return False
         g = gg.er(300, 0.012, seed=3)
         a = sp.csr_matrix((np.ones(g.nnz), g.col, g.row), shape=(g.n, g.n))
         src = np.repeat(np.arange(g.n), np.diff(g.row))

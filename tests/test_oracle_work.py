@@ -181,3 +181,92 @@ def test_pair_work_bounded_by_the_component():
         u, v = (int(x) for x in r.choice(g.n, 2, replace=False))
         _, comp, _ = O.source_work(g, u)
         assert O.pair_work(g, u, v) <= comp
+
+
+# ----------------------------------------- the two-sided search's walk counts
+#
+# oracle_bidir_work(u, v) -> (vertices the search adds, arcs of the rows it
+# reads), for the library's balanced two-sided search (side 0 from u over
+# out-arcs, side 1 from v over in-arcs, the side with fewer frontier arcs
+# expanding, ties to side 0; count pulls after each step; two sweeps after the
+# meeting). Every expected value below was worked out by hand from those rules.
+
+@pytest.mark.parametrize("n", [3, 5, 12])
+def test_star_bidir_work(n):
+    k = n - 1
+    g = gg.star(n)
+    # two leaves: each side walks its leaf's arc and the centre's row (count
+    # pull), then each sweep reads the centre's row and its own leaf's arc
+    assert O.bidir_work(g, 1, 2) == (2, 4 * k + 4)
+    # centre and leaf, either order: one step from the leaf meets the centre
+    assert O.bidir_work(g, 0, 1) == (1, 2 * k + 2)
+    assert O.bidir_work(g, 1, 0) == (1, 2 * k + 2)
+
+
+@pytest.mark.parametrize("n", [4, 6, 25])
+def test_path_bidir_work(n):
+    # ends of a path: side 0 steps first (tie), side 1 once (its frontier has
+    # fewer arcs), then side 0 on every tie until it finds n-2; rows read:
+    # 3 + 2(n-3) + 2(n-3) by side 0's steps and counts, 3 by side 1's, then
+    # 2(n-2) + 2(n-3) + 1 and 3 by the sweeps: 8n - 12 arcs, n - 1 vertices
+    g = gg.path(n)
+    assert O.bidir_work(g, 0, n - 1) == (n - 1, 8 * n - 12)
+    assert O.bidir_work(g, n - 1, 0) == (n - 1, 8 * n - 12)
+
+
+@pytest.mark.parametrize("n", [2, 5, 30])
+def test_directed_path_bidir_work(n):
+    # side 0 walks the whole path on ties (n-1 steps of one arc, one in-arc
+    # each for the counts), its sweep reads one in-arc and one out-arc per
+    # level; backwards nothing is reachable
+    g = gg.directed_path(n)
+    assert O.bidir_work(g, 0, n - 1, directed=True) == (n - 1, 4 * (n - 1))
+    assert O.bidir_work(g, n - 1, 0, directed=True) == (0, 0)
+
+
+def test_unreachable_pair_bidir_work():
+    # components {0,1,2} (a triangle) and {3,4,5,6} (a path), 7 isolated:
+    # side 0 steps once (2 arcs, 2 found, counts 4), then side 1 three times
+    # (2 + 3, 3 + 1, 1 arcs; 2 and 1 found), its last step adds nothing
+    g = gg.from_edges(8, [0, 1, 0, 3, 4, 5], [1, 2, 2, 4, 5, 6])
+    assert O.bidir_work(g, 0, 5) == (5, 16)
+    assert O.bidir_work(g, 7, 0) == (0, 0)
+    assert O.bidir_work(g, 0, 7) == (0, 0)
+
+
+def test_meeting_step_counts_only_vertices_the_other_side_holds():
+    # 0-1 adjacent, 0-2, 1-3, 2-4: the first step (side 0, a tie) adds 1 and 2
+    # and meets at 1; only 1's row is read for the counts, and only 1's row
+    # (not 2's) is marked in the sweep: 2 + 2 + 2 + 2 arcs
+    g = gg.from_edges(5, [0, 0, 1, 2], [1, 2, 3, 4])
+    assert O.bidir_work(g, 0, 1) == (2, 8)
+
+
+def test_bidir_work_bounds():
+    # every vertex is added at most once per side, and a side reads each of
+    # its vertices' rows at most four times (its step, a count, a mark, a
+    # sweep pull); a reachable pair adds at least d(u, v) vertices
+    g = gg.rmat(10, 6, 0.57, 0.19, 0.19, seed=4)
+    r = np.random.default_rng(2)
+    deg = g.degree()
+    for _ in range(40):
+        u, v = (int(x) for x in r.choice(g.n, 2, replace=False))
+        found, arcs = O.bidir_work(g, u, v)
+        du, dv = scipy_dist(g, u), scipy_dist(g, v)
+        assert found <= int((du >= 0).sum()) - 1 + int((dv >= 0).sum()) - 1
+        assert arcs <= 4 * int(deg[du >= 0].sum() + deg[dv >= 0].sum())
+        if du[v] > 0:
+            assert found >= du[v]
+        else:
+            assert arcs <= int(deg[du >= 0].sum() + deg[dv >= 0].sum()) * 2
+
+
+def test_ties_go_to_side_zero():
+    # the path 0-3-1-2 and the pair (0, 1): side 0 steps first (1 arc against
+    # 2) and finds 3; then 2 arcs against 2, a tie, so side 0 steps again and
+    # meets at 1 (counts: 3's row, then 1's); side 1 never steps. The sweep
+    # reads 1's and 3's rows at level 1, 3's and 0's at level 0: 2 vertices
+    # found and 1 + 2 + 2 + 2 + 2 + 2 + 2 + 1 = 14 arcs (side 1 stepping on
+    # the tie would add 2 and 3 instead: 3 vertices)
+    g = gg.from_edges(4, [0, 3, 1], [3, 1, 2])
+    assert O.bidir_work(g, 0, 1) == (2, 14)
