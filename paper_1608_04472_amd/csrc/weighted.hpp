@@ -305,12 +305,19 @@ __global__ __launch_bounds__(kBlock) void k_ww_release(WArgs a, int64_t s0, int6
 #pragma unroll
             for (int f = 0; f < kWFlight; ++f)
                 dx[f] = xs[f] >= 0 ? a.dist[w_at(a, xs[f], j, lane)] : kWUnreached;
+            // the batch's decrements are issued together; a lane whose
+            // decrement took the last predecessor (left 1) is released
+            uint32_t left[kWFlight];
+#pragma unroll
+            for (int f = 0; f < kWFlight; ++f) {
+                left[f] = 0u;
+                if (xs[f] >= 0 && on && dv + ws[f] == dx[f])
+                    left[f] = atomicSub(&a.pend[w_at(a, xs[f], j, lane)], 1u);
+            }
 #pragma unroll
             for (int f = 0; f < kWFlight; ++f) {
                 if (xs[f] < 0) break;
-                bool ready = on && dv + ws[f] == dx[f];
-                if (ready) ready = atomicSub(&a.pend[w_at(a, xs[f], j, lane)], 1u) == 1u;
-                const uint64_t bal = wave_ballot(ready);
+                const uint64_t bal = wave_ballot(left[f] == 1u);
                 if (bal) {
                     const uint32_t xw = ((uint32_t)xs[f] << a.logW) + j;
                     if (w_mark(&a.rdy[xw], bal, lane))
