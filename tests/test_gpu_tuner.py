@@ -162,3 +162,34 @@ def test_sampler_rounds_take_a_threshold_tried_at_their_width(dev, name):
         assert H.stats()["bottom_up"] == planned
     H.close()
     G.close()
+
+
+def test_round_thresholds_are_kept_per_width(dev):
+    """The same handle's sampler at widths 256, 512 and 256 again: each width's
+    threshold is one of the candidates, the second call at 256 reuses the
+    first's, and the estimates equal the oracle's at every width."""
+    g = gg.rmat(12, 16, 0.57, 0.19, 0.19, seed=9)
+    G = bc.Graph(g.row, g.col)
+    plan = G.tune()
+    tg = gg.top_degree(g, 3)
+    want = O.adaptive_source(g, tg, 2.0, 5, 300)
+    seen = {}
+    for sb in (256, 512, 256):
+        say("round threshold, width", sb)
+        G.configure(bc.BC_SCHED_TUNED, 0, 0.0, 0, 0, sb)
+        est = bc.adaptive_source(G, torch.from_numpy(tg).to(dev), 2.0, 5, 300)
+        assert np.array_equal(est[1].cpu().numpy(), want[1])
+        assert_close(est[0].cpu().numpy(), want[0], what="sampler at width %d" % sb)
+        st = G.stats()
+        assert st["batch_width"] == sb
+        if G.plan()["schedule"] != bc.BC_SCHED_BATCHED:
+            assert st["bottom_up"] == 0.0
+            continue
+        if sb == plan["batch"]:
+            assert st["bottom_up"] == (plan["bottom_up"] if plan["bottom_up"] != 0 else 0.04)
+        else:
+            assert st["bottom_up"] in BOTTOM_UP
+        if sb in seen:
+            assert st["bottom_up"] == seen[sb]
+        seen[sb] = st["bottom_up"]
+    G.close()
